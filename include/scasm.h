@@ -1,0 +1,180 @@
+/*
+ * scasm -- sparsity-aware assembly of FETI dual Schur complements on AMD
+ * MI355X (gfx950).  C ABI of libscasm.so.
+ *
+ * The library assembles, for a batch of subdomains i, the dense local dual
+ * operator (paper, Sec. 2.1 eq. (9) and Sec. 2.2 eq. (10))
+ *
+ *     F_i = B_i K_i^+ B_i^T = B_i K_reg,i^{-1} B_i^T = Y_i^T Y_i,
+ *     Y_i = L_i^{-1} P_i B_i^T,   L_i L_i^T = P_i K_reg,i P_i^T,
+ *
+ * (the SYRK form of Sec. 3.1, eq. (14)), from a CPU-computed sparse Cholesky
+ * factor L_i and the signed-boolean gluing matrix B_i, and applies it
+ * (Sec. 2.2, eqs. (11)-(12)).  The three solver stages of Sec. 2.2 map to
+ *     initialisation  -> sc_plan_create   (ordering, symbolic factorisation,
+ *                                          staircase plan, device buffers)
+ *     preprocessing   -> sc_factor + sc_assemble
+ *     solution        -> sc_apply (explicit, eq. (12)) or
+ *                        sc_apply_implicit (eq. (11))
+ *
+ * Conventions
+ *   - Host arrays passed in are borrowed for the duration of the call only.
+ *   - Device pointers (p_dev, q_dev, ...) are caller-owned HIP device memory.
+ *   - `stream` is a hipStream_t passed as void*; NULL = the null stream.
+ *   - Every function returns an sc_status_t; no C++ exception crosses the ABI.
+ *     sc_last_error() returns a thread-local message for the last failure.
+ *   - Asynchronous calls report launch errors at once; execution errors
+ *     surface at the next synchronising call.
+ *   - A plan is not thread-safe; distinct plans are independent.
+ */
+#ifndef SCASM_H
+#define SCASM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sc_plan_s* sc_plan_t;
+
+typedef enum {
+    SC_OK = 0,
+    SC_ERR_INVALID_ARG = 1,   /* bad size, index, sign, pointer or option      */
+    SC_ERR_NOT_SPD = 2,       /* a Cholesky pivot of K_reg was not positive    */
+    SC_ERR_OOM = 3,           /* device or host allocation failed              */
+    SC_ERR_DEVICE = 4,        /* a HIP call failed (message in sc_last_error)  */
+    SC_ERR_UNSUPPORTED = 5,   /* option combination not implemented            */
+    SC_ERR_STATE = 6          /* call out of order (e.g. assemble before factor) */
+} sc_status_t;
+
+typedef enum {
+    SC_PREC_FP64 = 0,         /* every step in FP64; F stored FP64 */
+    SC_PREC_MIXED = 1         /* FP64 diagonal-block solves; FP32 off-diagonal
+                                 updates, X and SYRK (FP32 MFMA, FP32 accumulate);
+                                 F stored FP32 */
+} sc_precision_t;
+
+/*
+ * One subdomain (paper, Sec. 3: "the input for the algorithm is B^T together
+ * with the factor L", L of the fill-reduced K_reg).
+ *   n              DOFs (> 0)
+ *   kreg_rowptr    [n+1] int64 CSR row pointers of K_reg (both triangles)
+ *   kreg_col       column indices; the pattern is fixed for the plan's life
+ *   m              multipliers = columns of B^T (>= 0)
+ *   bt_dof         [m] DOF (original numbering) of column j's single nonzero
+ *   bt_sign        [m] its value, +1 or -1
+ *   perm           optional [n] fill-reducing order, perm[new] = old; NULL =
+ *                  the library's nested dissection
+ *   coords         optional [n/dofs_per_node][dim] node coordinates for the
+ *                  geometric nested dissection; NULL = graph (BFS) dissection
+ *   dim            coordinate dimension (with coords)
+ *   dofs_per_node  1 (heat) or 3 (elasticity); DOFs of a node are contiguous
+ */
+typedef struct {
+    int32_t n;
+    const int64_t* kreg_rowptr;
+    const int32_t* kreg_col;
+    int32_t m;
+    const int32_t* bt_dof;
+    const int8_t* bt_sign;
+    const int32_t* perm;
+    const double* coords;
+    int32_t dim;
+    int32_t dofs_per_node;
+} sc_subdomain_desc_t;
+
+/*
+ * Options; zero-initialised = defaults.
+ *   precision        SC_PREC_FP64 / SC_PREC_MIXED
+ *   staircase        1 (default when 0 is not forced) = sort the columns of
+ *                    B^T by pivot and skip the zero trapezoid of X (Sec. 3.2,
+ *                    3.3); set disable_staircase = 1 for the plain ("orig",
+ *                    Sec. 3.1) assembly that skips nothing
+ *   panel_width      GPU factor blocks: supernodes split into panels of at
+ *                    most this many columns (Sec. 3.2, factor splitting;
+ *                    default 64)
+ *   relax_width      relaxed supernode amalgamation bound (default 64)
+ *   leaf_nodes       nested-dissection leaf size in nodes (default 64)
+ *   n_threads        host threads for sc_factor (0 = all cores)
+ */
+typedef struct {
+    int32_t precision;
+    int32_t disable_staircase;
+    int32_t panel_width;
+    int32_t relax_width;
+    int32_t leaf_nodes;
+    int32_t n_threads;
+    int32_t reserved[8];
+} sc_options_t;
+
+/* Initialisation stage (Sec. 2.2): ordering, symbolic factorisation, staircase
+ * plan (Sec. 3, column pivots and stable sort), GPU block and tile lists, and
+ * allocation of every persistent device buffer (factor values, X, F, tables)
+ * on the current HIP device.  `stream` is used for the table uploads.
+ * Errors: SC_ERR_INVALID_ARG (bad descriptor: index out of range, sign not
+ * +-1, n <= 0, perm not a permutation), SC_ERR_OOM, SC_ERR_DEVICE. */
+sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub,
+                           const sc_options_t* opt, void* stream, sc_plan_t* out);
+
+/* Preprocessing, part 1: numeric Cholesky of every P K_reg P^T on the host
+ * (FP64, threads over subdomains), then an asynchronous upload of the factor
+ * values on `stream` (plus the FP32 copy used by SC_PREC_MIXED).
+ *   kreg_vals   [nsub] host pointers to the CSR values of each K_reg, same
+ *               pattern as at plan creation
+ *   failed_sub, failed_col  optional out: on SC_ERR_NOT_SPD the subdomain and
+ *               permuted column of the first non-positive pivot */
+sc_status_t sc_factor(sc_plan_t plan, const double* const* kreg_vals, void* stream,
+                      int32_t* failed_sub, int32_t* failed_col);
+
+/* Preprocessing, part 2 (the hot path, Sec. 3): on `stream`, for every
+ * subdomain, X = L^{-1} P B^T with the staircase TRSM (factor splitting with
+ * pruned row lists, Sec. 3.2) and F = X^T X with the staircase SYRK (Sec. 3.3),
+ * written back in the original multiplier order (Sec. 3, permutation back).
+ * Asynchronous; F stays on the device.  SC_ERR_STATE before sc_factor. */
+sc_status_t sc_assemble(sc_plan_t plan, void* stream);
+
+/* Solution stage, explicit apply (eq. (12)): q_i = F_i p_i for every
+ * subdomain, on `stream`.  p_dev, q_dev: device FP64 vectors of length
+ * sc_query(...)->dual total, concatenated per subdomain in the original
+ * multiplier order (offsets from sc_query).  FP32-stored F (mixed) is read
+ * as FP32 and accumulated in FP64.  SC_ERR_STATE before sc_assemble. */
+sc_status_t sc_apply(sc_plan_t plan, const double* p_dev, double* q_dev, void* stream);
+
+/* Solution stage, implicit apply (eq. (11)): q_i = B_i P^T L^{-T} L^{-1} P B_i^T
+ * p_i with two sparse triangular solves on the device, same vector layout as
+ * sc_apply.  SC_ERR_STATE before sc_factor. */
+sc_status_t sc_apply_implicit(sc_plan_t plan, const double* p_dev, double* q_dev, void* stream);
+
+/* Copy F_i (m_i x m_i, column-major, leading dimension ld >= m_i, original
+ * multiplier order) to `out` (host memory when on_device == 0, else device
+ * memory), converted to FP64.  Synchronises `stream`. */
+sc_status_t sc_get_F(sc_plan_t plan, int32_t sub, double* out, int32_t ld, int32_t on_device,
+                     void* stream);
+
+/* Sizes and statistics of subdomain `sub` (any out pointer may be NULL):
+ *   n, m, dual_offset (offset of its multipliers in the concatenated dual
+ *   vectors), nnzL (exact structural nonzeros of L), useful_flops (staircase
+ *   TRSM + SYRK flop count: sum_i a(i)(2c_i - 1) + a(i)(a(i) + 1), with a(i)
+ *   the number of columns whose pivot is <= i and c_i = nnz(L[:, i])). */
+sc_status_t sc_query(sc_plan_t plan, int32_t sub, int64_t* n, int64_t* m, int64_t* dual_offset,
+                     int64_t* nnzL, double* useful_flops);
+
+/* Plan-wide totals: number of subdomains, total dual length, useful TRSM and
+ * SYRK flops (as in sc_query), the same counts without the staircase
+ * ("orig"), and the device bytes held by the plan. */
+sc_status_t sc_plan_stats(sc_plan_t plan, int32_t* nsub, int64_t* dual_total,
+                          double* trsm_useful, double* syrk_useful, double* trsm_dense,
+                          double* syrk_dense, int64_t* device_bytes);
+
+/* Release every device and host buffer of the plan.  NULL is accepted. */
+sc_status_t sc_plan_destroy(sc_plan_t plan);
+
+/* Thread-local message describing the last failure ("" if none). */
+const char* sc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SCASM_H */

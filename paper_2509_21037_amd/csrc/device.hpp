@@ -1,0 +1,45 @@
+// Device-side tables shared by the kernels and the host code that builds them.
+#pragma once
+#include <cstdint>
+
+namespace scasm {
+
+// Width of a column tile of X (and of an F output tile): 4 stripes of 16
+// columns, one stripe per wavefront in the TRSM.
+constexpr int kTile = 64;
+constexpr int kStripe = 16;
+constexpr int kMaxPanel = 64;      // GPU panel width bound the TRSM kernel is built for
+
+struct SubDev {
+    int32_t n, m, nblocks, ntiles;
+    int64_t blk_off;     // first block in the global block table
+    int64_t rows_off;    // first entry of this subdomain's row array
+    int64_t lval_off;    // first factor value
+    int64_t col_off;     // first entry of piv / pi / sign (sorted order)
+    int64_t tile_off;    // first tile in the global tile table
+    int64_t F_off;       // first element of F (m*m, column-major, original order)
+    int64_t dual_off;    // offset of the subdomain's multipliers in dual vectors
+};
+
+// One column tile of X: sorted columns [64*tile, 64*tile + ncols) of subdomain
+// `sub`.  Its slab holds rows [kstart, n) x 64 columns, row-major.
+struct TileDev {
+    int32_t sub, tile, kstart, ncols;
+    int64_t x_off;
+    int32_t start_block[4];   // first factor block each 16-column stripe visits
+};
+
+// One lower-triangle F tile (I >= J) of a subdomain.
+struct SyrkItem {
+    int32_t sub;
+    int32_t I, J;
+    int32_t pad;
+};
+
+struct BlockDev {
+    int32_t row0, w, nbelow, ld;
+    int64_t lval_off;    // relative to the subdomain's lval_off
+    int64_t rows_off;    // relative to the subdomain's rows_off
+};
+
+}  // namespace scasm

@@ -1,0 +1,577 @@
+// Host planner: nested-dissection ordering, symbolic factorisation with
+// relaxed supernodes, numeric supernodal Cholesky (FP64) and the staircase
+// plan of the Schur-complement assembly.
+#include "planner.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <numeric>
+
+namespace scasm {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// node graph (K's pattern compressed by DOFs per node)
+// ---------------------------------------------------------------------------
+struct Graph {
+    int32_t nv = 0;
+    std::vector<int64_t> ptr;
+    std::vector<int32_t> adj;
+};
+
+Graph node_graph(const SubdomainInput& in) {
+    const int32_t dpn = in.dofs_per_node;
+    Graph g;
+    g.nv = in.n / dpn;
+    std::vector<std::vector<int32_t>> nb(g.nv);
+    for (int32_t r = 0; r < in.n; ++r) {
+        const int32_t u = r / dpn;
+        for (int64_t p = in.rowptr[r]; p < in.rowptr[r + 1]; ++p) {
+            const int32_t v = in.col[p] / dpn;
+            if (v != u) nb[u].push_back(v);
+        }
+    }
+    g.ptr.assign(g.nv + 1, 0);
+    for (int32_t u = 0; u < g.nv; ++u) {
+        auto& v = nb[u];
+        std::sort(v.begin(), v.end());
+        v.erase(std::unique(v.begin(), v.end()), v.end());
+        g.ptr[u + 1] = g.ptr[u] + (int64_t)v.size();
+    }
+    g.adj.resize(g.ptr[g.nv]);
+    for (int32_t u = 0; u < g.nv; ++u)
+        std::copy(nb[u].begin(), nb[u].end(), g.adj.begin() + g.ptr[u]);
+    return g;
+}
+
+// ---------------------------------------------------------------------------
+// nested dissection: order(A), order(B), then the separator S.  With node
+// coordinates the split is the middle plane (among the distinct coordinate
+// values) of the axis of largest extent; without them it is the middle BFS
+// level from a pseudo-peripheral node.  Any edge left between A and B moves
+// its B end into S, so S always separates.
+// ---------------------------------------------------------------------------
+class Dissector {
+public:
+    Dissector(const Graph& g, const double* coords, int dim, int leaf)
+        : g_(g), coords_(coords), dim_(dim), leaf_(std::max(1, leaf)),
+          side_(g.nv, -1), stamp_(g.nv, 0), level_(g.nv, -1) {}
+
+    void run(std::vector<int32_t>& order) {
+        std::vector<int32_t> all(g_.nv);
+        std::iota(all.begin(), all.end(), 0);
+        order.clear();
+        order.reserve(g_.nv);
+        dissect(all, order);
+    }
+
+private:
+    const Graph& g_;
+    const double* coords_;
+    int dim_, leaf_;
+    std::vector<int8_t> side_;
+    std::vector<int32_t> stamp_;
+    std::vector<int32_t> level_;
+    int32_t tick_ = 0;
+
+    void dissect(std::vector<int32_t>& sub, std::vector<int32_t>& order) {
+        if ((int)sub.size() <= leaf_) {
+            std::sort(sub.begin(), sub.end());
+            order.insert(order.end(), sub.begin(), sub.end());
+            return;
+        }
+        std::vector<int32_t> A, B, S;
+        bool ok = coords_ ? split_plane(sub, A, B, S) : split_bfs(sub, A, B, S);
+        if (!ok || S.size() == sub.size()) {
+            std::sort(sub.begin(), sub.end());
+            order.insert(order.end(), sub.begin(), sub.end());
+            return;
+        }
+        fix_separator(A, B, S);
+        std::vector<int32_t>().swap(sub);
+        dissect(A, order);
+        dissect(B, order);
+        std::sort(S.begin(), S.end());
+        order.insert(order.end(), S.begin(), S.end());
+    }
+
+    bool split_plane(const std::vector<int32_t>& sub, std::vector<int32_t>& A,
+                     std::vector<int32_t>& B, std::vector<int32_t>& S) {
+        int axis = -1;
+        double best = 0;
+        for (int d = 0; d < dim_; ++d) {
+            double lo = coords_[(size_t)sub[0] * dim_ + d], hi = lo;
+            for (int32_t v : sub) {
+                const double x = coords_[(size_t)v * dim_ + d];
+                lo = std::min(lo, x);
+                hi = std::max(hi, x);
+            }
+            if (hi - lo > best) { best = hi - lo; axis = d; }
+        }
+        if (axis < 0) return false;
+        std::vector<double> vals;
+        vals.reserve(sub.size());
+        for (int32_t v : sub) vals.push_back(coords_[(size_t)v * dim_ + axis]);
+        std::sort(vals.begin(), vals.end());
+        vals.erase(std::unique(vals.begin(), vals.end()), vals.end());
+        const double plane = vals[(vals.size() - 1) / 2];
+        for (int32_t v : sub) {
+            const double x = coords_[(size_t)v * dim_ + axis];
+            if (x < plane) A.push_back(v);
+            else if (x > plane) B.push_back(v);
+            else S.push_back(v);
+        }
+        return true;
+    }
+
+    bool split_bfs(const std::vector<int32_t>& sub, std::vector<int32_t>& A,
+                   std::vector<int32_t>& B, std::vector<int32_t>& S) {
+        ++tick_;
+        for (int32_t v : sub) stamp_[v] = tick_;
+        int32_t root = sub[0];
+        int32_t depth = 0;
+        std::vector<int32_t> q;
+        for (int it = 0; it < 4; ++it) {          // pseudo-peripheral node search
+            int32_t far = bfs(root, q, depth);
+            if (it > 0 && level_[far] <= depth && far == root) break;
+            if (it == 3) break;
+            root = far;
+        }
+        bfs(root, q, depth);
+        if (depth < 2) return false;
+        const int32_t mid = depth / 2;
+        std::vector<int8_t> seen(0);
+        for (int32_t v : sub) {
+            const int32_t lv = level_[v];
+            if (lv < 0) B.push_back(v);           // other components
+            else if (lv < mid) A.push_back(v);
+            else if (lv > mid) B.push_back(v);
+            else S.push_back(v);
+        }
+        return true;
+    }
+
+    // BFS restricted to the current subset; fills level_, returns the last node.
+    int32_t bfs(int32_t root, std::vector<int32_t>& q, int32_t& depth) {
+        q.clear();
+        for (int32_t i = 0; i < (int32_t)level_.size(); ++i)
+            if (stamp_[i] == tick_) level_[i] = -1;
+        level_[root] = 0;
+        q.push_back(root);
+        size_t h = 0;
+        int32_t last = root;
+        while (h < q.size()) {
+            const int32_t u = q[h++];
+            last = u;
+            for (int64_t p = g_.ptr[u]; p < g_.ptr[u + 1]; ++p) {
+                const int32_t v = g_.adj[p];
+                if (stamp_[v] == tick_ && level_[v] < 0) {
+                    level_[v] = level_[u] + 1;
+                    q.push_back(v);
+                }
+            }
+        }
+        depth = level_[last];
+        return last;
+    }
+
+    void fix_separator(std::vector<int32_t>& A, std::vector<int32_t>& B, std::vector<int32_t>& S) {
+        for (int32_t v : A) side_[v] = 0;
+        for (int32_t v : B) side_[v] = 1;
+        for (int32_t v : S) side_[v] = 2;
+        for (int32_t a : A)
+            for (int64_t p = g_.ptr[a]; p < g_.ptr[a + 1]; ++p) {
+                const int32_t b = g_.adj[p];
+                if (side_[b] == 1) side_[b] = 2;
+            }
+        std::vector<int32_t> B2;
+        for (int32_t b : B) {
+            if (side_[b] == 2) S.push_back(b);
+            else B2.push_back(b);
+        }
+        B.swap(B2);
+        for (int32_t v : A) side_[v] = -1;
+        for (int32_t v : B) side_[v] = -1;
+        for (int32_t v : S) side_[v] = -1;
+    }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+std::string build_plan(const SubdomainInput& in, const PlanOptions& opt, SubPlan& P, int& code) {
+    code = 1;
+    const int32_t n = in.n;
+    if (n <= 0) return "n must be positive";
+    if (!in.rowptr || !in.col) return "K_reg pattern missing";
+    if (in.m < 0) return "m must be non-negative";
+    if (in.m > 0 && (!in.dof || !in.sign)) return "B^T columns missing";
+    const int32_t dpn = in.dofs_per_node > 0 ? in.dofs_per_node : 1;
+    if (n % dpn != 0) return "n is not a multiple of dofs_per_node";
+    if (in.rowptr[0] != 0) return "rowptr[0] must be 0";
+    for (int32_t r = 0; r < n; ++r) {
+        if (in.rowptr[r + 1] < in.rowptr[r]) return "rowptr not monotone";
+        for (int64_t p = in.rowptr[r]; p < in.rowptr[r + 1]; ++p)
+            if (in.col[p] < 0 || in.col[p] >= n) return "column index out of range";
+    }
+    for (int32_t j = 0; j < in.m; ++j) {
+        if (in.dof[j] < 0 || in.dof[j] >= n) return "B^T dof out of range";
+        if (in.sign[j] != 1 && in.sign[j] != -1) return "B^T sign must be +1 or -1";
+    }
+    if (in.coords && in.dim <= 0) return "coords given without dim";
+
+    P = SubPlan();
+    P.n = n;
+    P.m = in.m;
+    P.dpn = dpn;
+
+    // ---- ordering
+    P.perm.resize(n);
+    if (in.perm) {
+        std::vector<char> seen(n, 0);
+        for (int32_t i = 0; i < n; ++i) {
+            const int32_t v = in.perm[i];
+            if (v < 0 || v >= n || seen[v]) return "perm is not a permutation";
+            seen[v] = 1;
+            P.perm[i] = v;
+        }
+    } else {
+        Graph g = node_graph(in);
+        std::vector<int32_t> norder;
+        Dissector d(g, in.coords, in.dim, opt.leaf_nodes);
+        d.run(norder);
+        for (int32_t k = 0; k < g.nv; ++k)
+            for (int32_t c = 0; c < dpn; ++c) P.perm[(size_t)k * dpn + c] = norder[k] * dpn + c;
+    }
+    P.iperm.resize(n);
+    for (int32_t i = 0; i < n; ++i) P.iperm[P.perm[i]] = i;
+    const auto& iperm = P.iperm;
+
+    // ---- lower pattern of P K P^T by columns (rows > j)
+    std::vector<int64_t> cptr(n + 1, 0);
+    for (int32_t r = 0; r < n; ++r) {
+        const int32_t i = iperm[r];
+        for (int64_t p = in.rowptr[r]; p < in.rowptr[r + 1]; ++p) {
+            const int32_t j = iperm[in.col[p]];
+            if (i > j) ++cptr[j + 1];
+        }
+    }
+    for (int32_t j = 0; j < n; ++j) cptr[j + 1] += cptr[j];
+    std::vector<int32_t> crow(cptr[n]);
+    {
+        std::vector<int64_t> fill(cptr.begin(), cptr.end() - 1);
+        for (int32_t r = 0; r < n; ++r) {
+            const int32_t i = iperm[r];
+            for (int64_t p = in.rowptr[r]; p < in.rowptr[r + 1]; ++p) {
+                const int32_t j = iperm[in.col[p]];
+                if (i > j) crow[fill[j]++] = i;
+            }
+        }
+        for (int32_t j = 0; j < n; ++j) {
+            std::sort(crow.begin() + cptr[j], crow.begin() + cptr[j + 1]);
+            // duplicates (repeated CSR entries) are harmless for the symbolic
+            // phase; they are removed when structures are merged
+        }
+    }
+
+    // ---- elimination tree (Liu, with path compression) from rows of the lower part
+    P.parent.assign(n, -1);
+    {
+        std::vector<int32_t> anc(n, -1);
+        for (int32_t i = 0; i < n; ++i) {          // rows in increasing permuted order
+            const int32_t r = P.perm[i];
+            for (int64_t p = in.rowptr[r]; p < in.rowptr[r + 1]; ++p) {
+                int32_t j = iperm[in.col[p]];
+                if (j >= i) continue;
+                while (anc[j] != -1 && anc[j] != i) {
+                    const int32_t nx = anc[j];
+                    anc[j] = i;
+                    j = nx;
+                }
+                if (anc[j] == -1) {
+                    anc[j] = i;
+                    P.parent[j] = i;
+                }
+            }
+        }
+    }
+    // the column ordering must be topological for the tree (children < parent);
+    // Liu's algorithm guarantees parent[j] > j.
+
+    // ---- exact column structures (counts) by merging children
+    std::vector<int32_t> nchild(n, 0);
+    std::vector<std::vector<int32_t>> kids(n);
+    for (int32_t j = 0; j < n; ++j)
+        if (P.parent[j] >= 0) {
+            ++nchild[P.parent[j]];
+            kids[P.parent[j]].push_back(j);
+        }
+    P.colcount.assign(n, 0);
+    {
+        std::vector<std::vector<int32_t>> st(n);
+        std::vector<int32_t> mark(n, -1);
+        for (int32_t j = 0; j < n; ++j) {
+            std::vector<int32_t> s;
+            for (int64_t p = cptr[j]; p < cptr[j + 1]; ++p) {
+                const int32_t i = crow[p];
+                if (mark[i] != j) { mark[i] = j; s.push_back(i); }
+            }
+            for (int32_t c : kids[j]) {
+                for (int32_t i : st[c])
+                    if (i > j && mark[i] != j) { mark[i] = j; s.push_back(i); }
+                std::vector<int32_t>().swap(st[c]);
+            }
+            std::sort(s.begin(), s.end());
+            P.colcount[j] = 1 + (int32_t)s.size();
+            st[j].swap(s);
+        }
+    }
+    P.nnzL = 0;
+    for (int32_t j = 0; j < n; ++j) P.nnzL += P.colcount[j];
+
+    // ---- fundamental supernodes
+    std::vector<int32_t> fstart;
+    for (int32_t j = 0; j < n; ++j) {
+        const bool cont = j > 0 && P.parent[j - 1] == j && nchild[j] == 1 &&
+                          P.colcount[j - 1] == P.colcount[j] + 1;
+        if (!cont) fstart.push_back(j);
+    }
+    fstart.push_back(n);
+    const int32_t nf = (int32_t)fstart.size() - 1;
+
+    // ---- relaxed amalgamation: merge a supernode into its parent when the
+    // child ends right before the parent, the merged width stays below
+    // relax_width and the explicit zeros stay below relax_zero_frac.
+    std::vector<int32_t> fcol2s(n);
+    for (int32_t s = 0; s < nf; ++s)
+        for (int32_t j = fstart[s]; j < fstart[s + 1]; ++j) fcol2s[j] = s;
+    std::vector<int32_t> gstart;          // group starts (in columns)
+    {
+        // group g covers fundamental supernodes [gfirst, glast]; stats kept per group
+        std::vector<int32_t> grp_of(nf);
+        std::vector<int64_t> g_exact;
+        std::vector<int32_t> g_first_col, g_width;
+        for (int32_t s = 0; s < nf; ++s) {
+            const int32_t f = fstart[s], w = fstart[s + 1] - f;
+            int64_t exact = 0;
+            for (int32_t j = f; j < f + w; ++j) exact += P.colcount[j];
+            const int32_t r = P.colcount[f] - w;      // rows below the fundamental supernode
+            bool merged = false;
+            if (s > 0 && !g_first_col.empty()) {
+                const int32_t gc = (int32_t)g_first_col.size() - 1;   // group ending at f-1
+                const int32_t lastc = f - 1;
+                if (P.parent[lastc] >= f && P.parent[lastc] < f + w) {
+                    const int64_t W = (int64_t)g_width[gc] + w;
+                    const int64_t stored = W * (W + 1) / 2 + W * (int64_t)r;
+                    const int64_t ex = g_exact[gc] + exact;
+                    const double zf = stored > 0 ? double(stored - ex) / double(stored) : 0.0;
+                    if (W <= opt.relax_width && (W <= 4 || zf <= opt.relax_zero_frac)) {
+                        g_width[gc] = (int32_t)W;
+                        g_exact[gc] = ex;
+                        merged = true;
+                    }
+                }
+            }
+            if (!merged) {
+                g_first_col.push_back(f);
+                g_width.push_back(w);
+                g_exact.push_back(exact);
+            }
+        }
+        gstart = g_first_col;
+        gstart.push_back(n);
+    }
+    P.nsuper = (int32_t)gstart.size() - 1;
+    P.sfirst = gstart;
+    P.col2super.resize(n);
+    for (int32_t s = 0; s < P.nsuper; ++s)
+        for (int32_t j = P.sfirst[s]; j < P.sfirst[s + 1]; ++j) P.col2super[j] = s;
+
+    // ---- supernodal row structures: own columns, then the union of the
+    // columns' lower entries and the children's structures below the supernode
+    {
+        std::vector<std::vector<int32_t>> below(P.nsuper);
+        std::vector<std::vector<int32_t>> skids(P.nsuper);
+        std::vector<int32_t> mark(n, -1);
+        for (int32_t s = 0; s < P.nsuper; ++s) {
+            const int32_t f = P.sfirst[s], l = P.sfirst[s + 1] - 1;
+            std::vector<int32_t> rows;
+            for (int32_t j = f; j <= l; ++j)
+                for (int64_t p = cptr[j]; p < cptr[j + 1]; ++p) {
+                    const int32_t i = crow[p];
+                    if (i > l && mark[i] != s) { mark[i] = s; rows.push_back(i); }
+                }
+            for (int32_t c : skids[s])
+                for (int32_t i : below[c])
+                    if (i > l && mark[i] != s) { mark[i] = s; rows.push_back(i); }
+            std::sort(rows.begin(), rows.end());
+            if (!rows.empty()) skids[P.col2super[rows[0]]].push_back(s);
+            below[s].swap(rows);
+        }
+        P.srow_ptr.assign(P.nsuper + 1, 0);
+        P.spanel_off.assign(P.nsuper + 1, 0);
+        for (int32_t s = 0; s < P.nsuper; ++s) {
+            const int64_t w = P.sfirst[s + 1] - P.sfirst[s];
+            const int64_t ld = w + (int64_t)below[s].size();
+            P.srow_ptr[s + 1] = P.srow_ptr[s] + ld;
+            P.spanel_off[s + 1] = P.spanel_off[s] + ld * w;
+        }
+        P.srows.resize(P.srow_ptr[P.nsuper]);
+        P.nnzL_stored = 0;
+        for (int32_t s = 0; s < P.nsuper; ++s) {
+            int64_t o = P.srow_ptr[s];
+            const int32_t f = P.sfirst[s], l = P.sfirst[s + 1] - 1;
+            for (int32_t j = f; j <= l; ++j) P.srows[o++] = j;
+            for (int32_t i : below[s]) P.srows[o++] = i;
+            const int64_t w = l - f + 1;
+            P.nnzL_stored += w * (w + 1) / 2 + w * (int64_t)below[s].size();
+        }
+        P.nval = P.spanel_off[P.nsuper];
+    }
+
+    // ---- CSR entry -> panel slot
+    P.kmap.assign(in.rowptr[n], -1);
+    for (int32_t r = 0; r < n; ++r) {
+        const int32_t i = iperm[r];
+        for (int64_t p = in.rowptr[r]; p < in.rowptr[r + 1]; ++p) {
+            const int32_t j = iperm[in.col[p]];
+            if (i < j) continue;
+            const int32_t s = P.col2super[j];
+            const int32_t* rb = P.srows.data() + P.srow_ptr[s];
+            const int32_t* re = P.srows.data() + P.srow_ptr[s + 1];
+            const int32_t* it = std::lower_bound(rb, re, i);
+            const int64_t ld = re - rb;
+            P.kmap[p] = P.spanel_off[s] + (int64_t)(j - P.sfirst[s]) * ld + (it - rb);
+        }
+    }
+
+    // ---- factor flop estimate (exact structure)
+    P.factor_flops = 0;
+    for (int32_t j = 0; j < n; ++j) {
+        const double c = P.colcount[j];
+        P.factor_flops += c * c;
+    }
+
+    // ---- staircase: pivots, stable sort by (pivot, original index)
+    const int32_t m = in.m;
+    std::vector<int32_t> pv(m);
+    for (int32_t j = 0; j < m; ++j) pv[j] = iperm[in.dof[j]];
+    P.pi.resize(m);
+    std::iota(P.pi.begin(), P.pi.end(), 0);
+    if (opt.staircase)
+        std::stable_sort(P.pi.begin(), P.pi.end(), [&](int32_t a, int32_t b) { return pv[a] < pv[b]; });
+    P.piv.resize(m);
+    P.sign_sorted.resize(m);
+    for (int32_t k = 0; k < m; ++k) {
+        P.piv[k] = pv[P.pi[k]];
+        P.sign_sorted[k] = in.sign[P.pi[k]];
+    }
+    P.active.assign(n, 0);
+    for (int32_t j = 0; j < m; ++j) P.active[pv[j]] += 1;
+    for (int32_t i = 1; i < n; ++i) P.active[i] += P.active[i - 1];
+    P.trsm_useful = P.syrk_useful = P.trsm_dense = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        const double a = P.active[i], c = P.colcount[i];
+        P.trsm_useful += a * (2 * c - 1);
+        P.syrk_useful += a * (a + 1);
+        P.trsm_dense += (double)m * (2 * c - 1);
+    }
+    P.syrk_dense = (double)n * (double)m * (double)(m + 1);
+
+    // ---- GPU blocks: panels of width <= panel_width (multiples of 16 but the last)
+    const int32_t pw = std::max(16, (opt.panel_width / 16) * 16);
+    P.block_of_row.assign(n, -1);
+    for (int32_t s = 0; s < P.nsuper; ++s) {
+        const int32_t f = P.sfirst[s];
+        const int32_t w = P.sfirst[s + 1] - f;
+        const int32_t ld = (int32_t)(P.srow_ptr[s + 1] - P.srow_ptr[s]);
+        const int32_t np = (w + pw - 1) / pw;
+        int32_t base = (w + np - 1) / np;
+        base = std::min(pw, (base + 15) / 16 * 16);
+        for (int32_t c0 = 0; c0 < w; c0 += base) {
+            BlockDesc b;
+            b.row0 = f + c0;
+            b.w = std::min(base, w - c0);
+            b.nbelow = ld - c0 - b.w;
+            b.ld = ld;
+            b.lval_off = P.spanel_off[s] + (int64_t)c0 * ld + c0;
+            b.rows_off = P.srow_ptr[s] + c0 + b.w;
+            for (int32_t i = b.row0; i < b.row0 + b.w; ++i) P.block_of_row[i] = (int32_t)P.blocks.size();
+            P.blocks.push_back(b);
+        }
+    }
+    code = 0;
+    return "";
+}
+
+// ---------------------------------------------------------------------------
+// numeric supernodal Cholesky: for each supernode in order, factor its panel
+// (left-looking column Cholesky of the (w+r) x w panel = diagonal Cholesky +
+// triangular solve of the rows below), then subtract its outer-product
+// contribution from every later supernode its rows touch.
+// ---------------------------------------------------------------------------
+int64_t factor_numeric(const SubPlan& P, const double* kvals, double* vals) {
+    std::memset(vals, 0, sizeof(double) * (size_t)P.nval);
+    for (size_t e = 0; e < P.kmap.size(); ++e)
+        if (P.kmap[e] >= 0) vals[P.kmap[e]] += kvals[e];
+    std::vector<int32_t> pos(P.n, -1);
+    std::vector<double> tmp;
+    for (int32_t s = 0; s < P.nsuper; ++s) {
+        const int32_t f = P.sfirst[s];
+        const int32_t w = P.sfirst[s + 1] - f;
+        const int64_t ld = P.srow_ptr[s + 1] - P.srow_ptr[s];
+        double* A = vals + P.spanel_off[s];
+        const int32_t* rows = P.srows.data() + P.srow_ptr[s];
+        for (int32_t c = 0; c < w; ++c) {
+            double* colc = A + (size_t)c * ld;
+            for (int32_t k = 0; k < c; ++k) {
+                const double* colk = A + (size_t)k * ld;
+                const double lck = colk[c];
+                if (lck == 0.0) continue;
+                for (int64_t i = c; i < ld; ++i) colc[i] -= colk[i] * lck;
+            }
+            const double d = colc[c];
+            if (!(d > 0.0)) return f + c;
+            const double sd = std::sqrt(d);
+            colc[c] = sd;
+            const double inv = 1.0 / sd;
+            for (int64_t i = c + 1; i < ld; ++i) colc[i] *= inv;
+        }
+        // contributions to later supernodes
+        int64_t q = w;
+        while (q < ld) {
+            const int32_t t = P.col2super[rows[q]];
+            const int32_t tf = P.sfirst[t];
+            const int32_t tl = P.sfirst[t + 1] - 1;
+            int64_t q1 = q;
+            while (q1 < ld && rows[q1] <= tl) ++q1;
+            const int64_t ldt = P.srow_ptr[t + 1] - P.srow_ptr[t];
+            const int32_t* trows = P.srows.data() + P.srow_ptr[t];
+            for (int64_t k = 0; k < ldt; ++k) pos[trows[k]] = (int32_t)k;
+            double* T = vals + P.spanel_off[t];
+            const int64_t nr = ld - q;
+            tmp.resize((size_t)nr);
+            for (int64_t b = q; b < q1; ++b) {
+                // tmp[a] = sum_k L[q+a][k] * L[b][k] for rows a >= b - q
+                const int64_t a0 = b - q;
+                std::fill(tmp.begin() + a0, tmp.end(), 0.0);
+                for (int32_t k = 0; k < w; ++k) {
+                    const double* colk = A + (size_t)k * ld;
+                    const double lb = colk[b];
+                    if (lb == 0.0) continue;
+                    const double* src = colk + q;
+                    for (int64_t a = a0; a < nr; ++a) tmp[a] += src[a] * lb;
+                }
+                double* tcol = T + (size_t)(rows[b] - tf) * ldt;
+                for (int64_t a = a0; a < nr; ++a) tcol[pos[rows[q + a]]] -= tmp[a];
+            }
+            q = q1;
+        }
+    }
+    return -1;
+}
+
+}  // namespace scasm

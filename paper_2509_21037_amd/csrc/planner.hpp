@@ -1,0 +1,92 @@
+// Host planner: ordering, symbolic and numeric sparse Cholesky, staircase plan.
+//
+// The factor L of the permuted regularised stiffness P K_reg P^T (paper,
+// Sec. 2.2 eq. (10) and the two-stage factorisation it describes) is held in
+// supernodal form: supernode s owns the contiguous permuted columns
+// [first_s, first_s + w_s) and a sorted row list whose first w_s entries are
+// its own columns and whose remaining r_s entries are the rows below it; the
+// values are a dense column-major panel of (w_s + r_s) x w_s doubles.
+//
+// The staircase plan follows Sec. 3: the pivot of multiplier column j is
+// p_j = iperm[dof_j]; columns are stably sorted by (p_j, j) so that pivots
+// descend left to right (the "stepped" shape), and the solution X = L^{-1}
+// P B^T is zero above each pivot.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace scasm {
+
+struct SubdomainInput {
+    int32_t n = 0;
+    const int64_t* rowptr = nullptr;   // K_reg CSR (both triangles), n+1
+    const int32_t* col = nullptr;
+    int32_t m = 0;
+    const int32_t* dof = nullptr;      // [m]
+    const int8_t* sign = nullptr;      // [m]
+    const int32_t* perm = nullptr;     // optional [n], new -> old
+    const double* coords = nullptr;    // optional [n / dofs_per_node][dim]
+    int32_t dim = 0;
+    int32_t dofs_per_node = 1;
+};
+
+struct PlanOptions {
+    int32_t leaf_nodes = 64;          // nested-dissection leaf size (nodes)
+    int32_t relax_width = 64;         // relaxed amalgamation merges up to this width
+    double relax_zero_frac = 0.5;     // ... if the merged zero fraction stays below this
+    int32_t panel_width = 64;         // GPU blocks: supernodes split into panels <= this
+    int32_t staircase = 1;            // 0 = every column treated as pivot 0 ("orig")
+};
+
+// One GPU block: a panel of a supernode.  Its diagonal triangle is rows
+// [row0, row0+w) of columns [row0, row0+w); below it are `nbelow` rows whose
+// global indices start at rows_off in the plan's row array.
+struct BlockDesc {
+    int32_t row0;
+    int32_t w;
+    int32_t nbelow;
+    int32_t ld;            // leading dimension of the supernode panel
+    int64_t lval_off;      // offset of L[row0][row0] in the subdomain's value array
+    int64_t rows_off;      // offset of the first below-row in the subdomain's row array
+};
+
+struct SubPlan {
+    int32_t n = 0, m = 0, dpn = 1;
+    std::vector<int32_t> perm, iperm;          // perm[new] = old
+    std::vector<int32_t> parent;               // column elimination tree
+    std::vector<int32_t> colcount;             // exact nnz(L[:, j]) incl. diagonal
+    // supernodes
+    int32_t nsuper = 0;
+    std::vector<int32_t> sfirst;               // nsuper + 1
+    std::vector<int64_t> srow_ptr;             // nsuper + 1
+    std::vector<int32_t> srows;                // own columns then rows below
+    std::vector<int64_t> spanel_off;           // nsuper + 1, doubles
+    int64_t nval = 0;
+    std::vector<int32_t> col2super;
+    std::vector<int64_t> kmap;                 // CSR entry -> panel slot, -1 = upper part
+    // staircase
+    std::vector<int32_t> piv;                  // [m] pivots in sorted order
+    std::vector<int32_t> pi;                   // [m] sorted position -> original column
+    std::vector<int8_t> sign_sorted;           // [m]
+    std::vector<int32_t> active;               // a(i) for i in [0, n)
+    // GPU blocks
+    std::vector<BlockDesc> blocks;
+    std::vector<int32_t> block_of_row;         // row -> block index
+    // statistics
+    int64_t nnzL = 0;                          // exact
+    int64_t nnzL_stored = 0;                   // supernodal storage incl. explicit zeros
+    double trsm_useful = 0, syrk_useful = 0;   // element-granular staircase counts
+    double trsm_dense = 0, syrk_dense = 0;     // same factor, no staircase ("orig")
+    double factor_flops = 0;
+};
+
+// Returns "" on success, else an error message; `code` receives 1 for a bad
+// argument.
+std::string build_plan(const SubdomainInput& in, const PlanOptions& opt, SubPlan& out, int& code);
+
+// Numeric supernodal Cholesky into `vals` (plan.nval doubles).  Returns -1 on
+// success, else the permuted column whose pivot is not positive.
+int64_t factor_numeric(const SubPlan& plan, const double* kvals, double* vals);
+
+}  // namespace scasm

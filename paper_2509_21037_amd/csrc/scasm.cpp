@@ -1,0 +1,465 @@
+// C ABI of libscasm.so (declared in include/scasm.h).
+#include "scasm.h"
+#include "scasm_host.h"
+
+#include <hip/hip_runtime.h>
+#include <omp.h>
+
+#include <algorithm>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "device.hpp"
+#include "kernels.hpp"
+#include "planner.hpp"
+
+using namespace scasm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+sc_status_t fail(sc_status_t st, const std::string& msg) {
+    g_last_error = msg;
+    return st;
+}
+
+SubdomainInput to_input(const sc_subdomain_desc_t& d) {
+    SubdomainInput in;
+    in.n = d.n;
+    in.rowptr = d.kreg_rowptr;
+    in.col = d.kreg_col;
+    in.m = d.m;
+    in.dof = d.bt_dof;
+    in.sign = d.bt_sign;
+    in.perm = d.perm;
+    in.coords = d.coords;
+    in.dim = d.dim;
+    in.dofs_per_node = d.dofs_per_node > 0 ? d.dofs_per_node : 1;
+    return in;
+}
+
+// Fills `po` from the ABI options; returns "" or an error message.
+std::string to_plan_options(const sc_options_t& o, PlanOptions& po) {
+    if (o.precision != SC_PREC_FP64 && o.precision != SC_PREC_MIXED) return "unknown precision";
+    if (o.panel_width < 0 || o.relax_width < 0 || o.leaf_nodes < 0 || o.n_threads < 0)
+        return "negative option";
+    if (o.panel_width) po.panel_width = o.panel_width;
+    if (po.panel_width > kMaxPanel || po.panel_width < 16) return "panel_width must be in [16, 64]";
+    if (o.relax_width) po.relax_width = o.relax_width;
+    if (o.leaf_nodes) po.leaf_nodes = o.leaf_nodes;
+    po.staircase = o.disable_staircase ? 0 : 1;
+    return "";
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(e_ == hipErrorOutOfMemory ? SC_ERR_OOM : SC_ERR_DEVICE,              \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                  \
+    } while (0)
+
+template <class T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t count = 0;
+    hipError_t alloc(size_t n) {
+        count = n;
+        if (n == 0) return hipSuccess;
+        return hipMalloc((void**)&p, n * sizeof(T));
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        count = 0;
+    }
+};
+
+}  // namespace
+
+struct sc_plan_s {
+    int32_t nsub = 0;
+    sc_options_t opt{};
+    PlanOptions popt{};
+    int device = 0;
+    std::vector<SubPlan> plans;
+    std::vector<int64_t> kval_count;          // CSR entries per subdomain
+    // host mirrors of the tables
+    std::vector<SubDev> h_subs;
+    std::vector<TileDev> h_tiles;
+    std::vector<BlockDev> h_blocks;
+    std::vector<SyrkItem> h_syrk;
+    int64_t nval_total = 0, nrows_total = 0, ncol_total = 0, X_total = 0, F_total = 0, dual_total = 0;
+    double* h_lval = nullptr;                 // pinned
+    // device
+    DevBuf<SubDev> d_subs;
+    DevBuf<TileDev> d_tiles;
+    DevBuf<BlockDev> d_blocks;
+    DevBuf<SyrkItem> d_syrk;
+    DevBuf<int32_t> d_rows, d_piv, d_pi;
+    DevBuf<int8_t> d_sgn;
+    DevBuf<double> d_lval, d_X, d_F;
+    bool factored = false, assembled = false;
+    double trsm_u = 0, syrk_u = 0, trsm_d = 0, syrk_d = 0;
+
+    int64_t device_bytes() const {
+        return (int64_t)(d_subs.count * sizeof(SubDev) + d_tiles.count * sizeof(TileDev) +
+                         d_blocks.count * sizeof(BlockDev) + d_syrk.count * sizeof(SyrkItem) +
+                         (d_rows.count + d_piv.count + d_pi.count) * 4 + d_sgn.count +
+                         (d_lval.count + d_X.count + d_F.count) * 8);
+    }
+    void release() {
+        d_subs.release(); d_tiles.release(); d_blocks.release(); d_syrk.release();
+        d_rows.release(); d_piv.release(); d_pi.release(); d_sgn.release();
+        d_lval.release(); d_X.release(); d_F.release();
+        if (h_lval) (void)hipHostFree(h_lval);
+        h_lval = nullptr;
+    }
+    DevTables tables() const {
+        DevTables t;
+        t.subs = d_subs.p; t.tiles = d_tiles.p; t.blocks = d_blocks.p; t.rows = d_rows.p;
+        t.lval = d_lval.p; t.piv = d_piv.p; t.pi = d_pi.p; t.sgn = d_sgn.p; t.syrk = d_syrk.p;
+        t.X = d_X.p; t.F = d_F.p;
+        t.ntiles = (int64_t)h_tiles.size();
+        t.nsyrk = (int64_t)h_syrk.size();
+        return t;
+    }
+};
+
+extern "C" {
+
+const char* sc_last_error(void) { return g_last_error.c_str(); }
+
+sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc_options_t* opt,
+                           void* stream, sc_plan_t* out) {
+    g_last_error.clear();
+    if (!out) return fail(SC_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (nsub < 0 || (nsub > 0 && !sd)) return fail(SC_ERR_INVALID_ARG, "bad subdomain array");
+    std::unique_ptr<sc_plan_s> P(new (std::nothrow) sc_plan_s());
+    if (!P) return fail(SC_ERR_OOM, "host allocation failed");
+    if (opt) P->opt = *opt;
+    PlanOptions& po = P->popt;
+    {
+        const std::string err = to_plan_options(P->opt, po);
+        if (!err.empty()) return fail(SC_ERR_INVALID_ARG, err);
+    }
+    if (P->opt.precision == SC_PREC_MIXED)
+        return fail(SC_ERR_UNSUPPORTED, "mixed precision is not built yet");
+    P->nsub = nsub;
+    P->plans.resize(nsub);
+    P->kval_count.resize(nsub);
+    std::vector<std::string> errs(nsub);
+    std::vector<int> codes(nsub, 0);
+    const int nthr = P->opt.n_threads > 0 ? P->opt.n_threads : omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthr)
+    for (int32_t i = 0; i < nsub; ++i) {
+        const SubdomainInput in = to_input(sd[i]);
+        try {
+            errs[i] = build_plan(in, po, P->plans[i], codes[i]);
+        } catch (const std::bad_alloc&) {
+            errs[i] = "host allocation failed";
+            codes[i] = 3;
+        } catch (...) {
+            errs[i] = "planner failed";
+            codes[i] = 1;
+        }
+        if (errs[i].empty() && sd[i].n > 0) P->kval_count[i] = sd[i].kreg_rowptr[sd[i].n];
+    }
+    for (int32_t i = 0; i < nsub; ++i)
+        if (!errs[i].empty())
+            return fail(codes[i] == 3 ? SC_ERR_OOM : SC_ERR_INVALID_ARG,
+                        "subdomain " + std::to_string(i) + ": " + errs[i]);
+
+    // ---- tables
+    int64_t blk = 0, rows = 0, lv = 0, colo = 0, xo = 0, fo = 0, dual = 0;
+    for (int32_t i = 0; i < nsub; ++i) {
+        const SubPlan& sp = P->plans[i];
+        SubDev s{};
+        s.n = sp.n;
+        s.m = sp.m;
+        s.nblocks = (int32_t)sp.blocks.size();
+        s.ntiles = (sp.m + kTile - 1) / kTile;
+        s.blk_off = blk;
+        s.rows_off = rows;
+        s.lval_off = lv;
+        s.col_off = colo;
+        s.tile_off = (int64_t)P->h_tiles.size();
+        s.F_off = fo;
+        s.dual_off = dual;
+        for (const BlockDesc& b : sp.blocks)
+            P->h_blocks.push_back(BlockDev{b.row0, b.w, b.nbelow, b.ld, b.lval_off, b.rows_off});
+        for (int32_t t = 0; t < s.ntiles; ++t) {
+            TileDev T{};
+            T.sub = i;
+            T.tile = t;
+            T.ncols = std::min(kTile, sp.m - t * kTile);
+            T.kstart = po.staircase ? sp.piv[(size_t)t * kTile] : 0;
+            T.x_off = xo;
+            xo += (int64_t)(sp.n - T.kstart) * kTile;
+            for (int w = 0; w < 4; ++w) {
+                const int c = t * kTile + w * kStripe;
+                if (w * kStripe >= T.ncols) T.start_block[w] = s.nblocks;
+                else T.start_block[w] = po.staircase ? sp.block_of_row[sp.piv[c]] : 0;
+            }
+            P->h_tiles.push_back(T);
+        }
+        for (int32_t I = 0; I < s.ntiles; ++I)
+            for (int32_t J = 0; J <= I; ++J) P->h_syrk.push_back(SyrkItem{i, I, J, 0});
+        blk += s.nblocks;
+        rows += (int64_t)sp.srows.size();
+        lv += sp.nval;
+        colo += sp.m;
+        fo += (int64_t)sp.m * sp.m;
+        dual += sp.m;
+        P->h_subs.push_back(s);
+        P->trsm_u += sp.trsm_useful;
+        P->syrk_u += sp.syrk_useful;
+        P->trsm_d += sp.trsm_dense;
+        P->syrk_d += sp.syrk_dense;
+    }
+    P->nval_total = lv;
+    P->nrows_total = rows;
+    P->ncol_total = colo;
+    P->X_total = xo;
+    P->F_total = fo;
+    P->dual_total = dual;
+
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(hipGetDevice(&P->device));
+    sc_plan_s* p = P.get();
+    auto cleanup_fail = [&](sc_status_t s, const std::string& m) { p->release(); return fail(s, m); };
+#define ALLOC(buf, n)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (buf).alloc(n);                                                      \
+        if (e_ != hipSuccess)                                                                \
+            return cleanup_fail(e_ == hipErrorOutOfMemory ? SC_ERR_OOM : SC_ERR_DEVICE,      \
+                                std::string("hipMalloc ") + #buf + ": " + hipGetErrorString(e_)); \
+    } while (0)
+    ALLOC(p->d_subs, p->h_subs.size());
+    ALLOC(p->d_tiles, p->h_tiles.size());
+    ALLOC(p->d_blocks, p->h_blocks.size());
+    ALLOC(p->d_syrk, p->h_syrk.size());
+    ALLOC(p->d_rows, (size_t)rows);
+    ALLOC(p->d_piv, (size_t)colo);
+    ALLOC(p->d_pi, (size_t)colo);
+    ALLOC(p->d_sgn, (size_t)colo);
+    ALLOC(p->d_lval, (size_t)lv);
+    ALLOC(p->d_X, (size_t)xo);
+    ALLOC(p->d_F, (size_t)fo);
+#undef ALLOC
+    {
+        hipError_t e = hipHostMalloc((void**)&p->h_lval, std::max<size_t>(1, (size_t)lv) * sizeof(double),
+                                     hipHostMallocDefault);
+        if (e != hipSuccess) return cleanup_fail(SC_ERR_OOM, "pinned host allocation failed");
+    }
+    // flatten per-subdomain arrays
+    std::vector<int32_t> h_rows((size_t)rows), h_piv((size_t)colo), h_pi((size_t)colo);
+    std::vector<int8_t> h_sgn((size_t)colo);
+    for (int32_t i = 0; i < nsub; ++i) {
+        const SubPlan& sp = P->plans[i];
+        const SubDev& s = P->h_subs[i];
+        std::copy(sp.srows.begin(), sp.srows.end(), h_rows.begin() + s.rows_off);
+        std::copy(sp.piv.begin(), sp.piv.end(), h_piv.begin() + s.col_off);
+        std::copy(sp.pi.begin(), sp.pi.end(), h_pi.begin() + s.col_off);
+        std::copy(sp.sign_sorted.begin(), sp.sign_sorted.end(), h_sgn.begin() + s.col_off);
+    }
+    auto up = [&](void* d, const void* h, size_t bytes) -> hipError_t {
+        if (bytes == 0) return hipSuccess;
+        return hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, st);
+    };
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = up(p->d_subs.p, p->h_subs.data(), p->h_subs.size() * sizeof(SubDev));
+    if (e == hipSuccess) e = up(p->d_tiles.p, p->h_tiles.data(), p->h_tiles.size() * sizeof(TileDev));
+    if (e == hipSuccess) e = up(p->d_blocks.p, p->h_blocks.data(), p->h_blocks.size() * sizeof(BlockDev));
+    if (e == hipSuccess) e = up(p->d_syrk.p, p->h_syrk.data(), p->h_syrk.size() * sizeof(SyrkItem));
+    if (e == hipSuccess) e = up(p->d_rows.p, h_rows.data(), h_rows.size() * 4);
+    if (e == hipSuccess) e = up(p->d_piv.p, h_piv.data(), h_piv.size() * 4);
+    if (e == hipSuccess) e = up(p->d_pi.p, h_pi.data(), h_pi.size() * 4);
+    if (e == hipSuccess) e = up(p->d_sgn.p, h_sgn.data(), h_sgn.size());
+    if (e == hipSuccess) e = hipStreamSynchronize(st);   // host vectors go out of scope
+    if (e != hipSuccess) return cleanup_fail(SC_ERR_DEVICE, std::string("table upload: ") + hipGetErrorString(e));
+    *out = P.release();
+    return SC_OK;
+}
+
+sc_status_t sc_factor(sc_plan_t P, const double* const* kreg_vals, void* stream, int32_t* failed_sub,
+                      int32_t* failed_col) {
+    g_last_error.clear();
+    if (!P) return fail(SC_ERR_INVALID_ARG, "plan is NULL");
+    if (P->nsub > 0 && !kreg_vals) return fail(SC_ERR_INVALID_ARG, "kreg_vals is NULL");
+    for (int32_t i = 0; i < P->nsub; ++i)
+        if (!kreg_vals[i] && P->kval_count[i] > 0)
+            return fail(SC_ERR_INVALID_ARG, "kreg_vals[" + std::to_string(i) + "] is NULL");
+    HIP_TRY(hipSetDevice(P->device));
+    hipStream_t st = (hipStream_t)stream;
+    // the previous upload may still read h_lval
+    HIP_TRY(hipStreamSynchronize(st));
+    P->factored = false;
+    P->assembled = false;
+    std::vector<int64_t> bad(P->nsub, -1);
+    const int nthr = P->opt.n_threads > 0 ? P->opt.n_threads : omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthr)
+    for (int32_t i = 0; i < P->nsub; ++i)
+        bad[i] = factor_numeric(P->plans[i], kreg_vals[i], P->h_lval + P->h_subs[i].lval_off);
+    for (int32_t i = 0; i < P->nsub; ++i)
+        if (bad[i] >= 0) {
+            if (failed_sub) *failed_sub = i;
+            if (failed_col) *failed_col = (int32_t)bad[i];
+            return fail(SC_ERR_NOT_SPD, "subdomain " + std::to_string(i) + ": pivot of permuted column " +
+                                            std::to_string(bad[i]) + " is not positive");
+        }
+    if (P->nval_total > 0)
+        HIP_TRY(hipMemcpyAsync(P->d_lval.p, P->h_lval, (size_t)P->nval_total * sizeof(double),
+                               hipMemcpyHostToDevice, st));
+    P->factored = true;
+    return SC_OK;
+}
+
+sc_status_t sc_assemble(sc_plan_t P, void* stream) {
+    g_last_error.clear();
+    if (!P) return fail(SC_ERR_INVALID_ARG, "plan is NULL");
+    if (!P->factored) return fail(SC_ERR_STATE, "sc_assemble before sc_factor");
+    HIP_TRY(hipSetDevice(P->device));
+    HIP_TRY(launch_assemble_f64(P->tables(), (hipStream_t)stream));
+    P->assembled = true;
+    return SC_OK;
+}
+
+sc_status_t sc_apply(sc_plan_t P, const double* p_dev, double* q_dev, void* stream) {
+    (void)p_dev; (void)q_dev; (void)stream;
+    if (!P) return fail(SC_ERR_INVALID_ARG, "plan is NULL");
+    if (!P->assembled) return fail(SC_ERR_STATE, "sc_apply before sc_assemble");
+    return fail(SC_ERR_UNSUPPORTED, "sc_apply is not built yet");
+}
+
+sc_status_t sc_apply_implicit(sc_plan_t P, const double* p_dev, double* q_dev, void* stream) {
+    (void)p_dev; (void)q_dev; (void)stream;
+    if (!P) return fail(SC_ERR_INVALID_ARG, "plan is NULL");
+    if (!P->factored) return fail(SC_ERR_STATE, "sc_apply_implicit before sc_factor");
+    return fail(SC_ERR_UNSUPPORTED, "sc_apply_implicit is not built yet");
+}
+
+sc_status_t sc_get_F(sc_plan_t P, int32_t sub, double* out, int32_t ld, int32_t on_device, void* stream) {
+    g_last_error.clear();
+    if (!P) return fail(SC_ERR_INVALID_ARG, "plan is NULL");
+    if (sub < 0 || sub >= P->nsub) return fail(SC_ERR_INVALID_ARG, "subdomain index out of range");
+    if (!P->assembled) return fail(SC_ERR_STATE, "sc_get_F before sc_assemble");
+    const SubDev& s = P->h_subs[sub];
+    if (s.m == 0) return SC_OK;
+    if (!out || ld < s.m) return fail(SC_ERR_INVALID_ARG, "bad output buffer or ld");
+    HIP_TRY(hipSetDevice(P->device));
+    hipStream_t st = (hipStream_t)stream;
+    const double* src = P->d_F.p + s.F_off;
+    HIP_TRY(hipMemcpy2DAsync(out, (size_t)ld * sizeof(double), src, (size_t)s.m * sizeof(double),
+                             (size_t)s.m * sizeof(double), (size_t)s.m,
+                             on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return SC_OK;
+}
+
+sc_status_t sc_query(sc_plan_t P, int32_t sub, int64_t* n, int64_t* m, int64_t* dual_offset, int64_t* nnzL,
+                     double* useful_flops) {
+    g_last_error.clear();
+    if (!P) return fail(SC_ERR_INVALID_ARG, "plan is NULL");
+    if (sub < 0 || sub >= P->nsub) return fail(SC_ERR_INVALID_ARG, "subdomain index out of range");
+    const SubPlan& sp = P->plans[sub];
+    if (n) *n = sp.n;
+    if (m) *m = sp.m;
+    if (dual_offset) *dual_offset = P->h_subs[sub].dual_off;
+    if (nnzL) *nnzL = sp.nnzL;
+    if (useful_flops) *useful_flops = sp.trsm_useful + sp.syrk_useful;
+    return SC_OK;
+}
+
+sc_status_t sc_plan_stats(sc_plan_t P, int32_t* nsub, int64_t* dual_total, double* trsm_useful,
+                          double* syrk_useful, double* trsm_dense, double* syrk_dense,
+                          int64_t* device_bytes) {
+    g_last_error.clear();
+    if (!P) return fail(SC_ERR_INVALID_ARG, "plan is NULL");
+    if (nsub) *nsub = P->nsub;
+    if (dual_total) *dual_total = P->dual_total;
+    if (trsm_useful) *trsm_useful = P->trsm_u;
+    if (syrk_useful) *syrk_useful = P->syrk_u;
+    if (trsm_dense) *trsm_dense = P->trsm_d;
+    if (syrk_dense) *syrk_dense = P->syrk_d;
+    if (device_bytes) *device_bytes = P->device_bytes();
+    return SC_OK;
+}
+
+sc_status_t sc_host_analyze(const sc_subdomain_desc_t* sd, const sc_options_t* opt, const double* kreg_vals,
+                            int32_t* perm_out, double* L_out, int32_t* piv_out, int32_t* pi_out,
+                            sc_host_info_t* info, int32_t* failed_col) {
+    g_last_error.clear();
+    if (!sd) return fail(SC_ERR_INVALID_ARG, "descriptor is NULL");
+    sc_options_t o{};
+    if (opt) o = *opt;
+    PlanOptions po;
+    std::string err = to_plan_options(o, po);
+    if (!err.empty()) return fail(SC_ERR_INVALID_ARG, err);
+    if (L_out && (!kreg_vals || sd->n > 4096)) return fail(SC_ERR_INVALID_ARG, "dense L needs values and n <= 4096");
+    SubPlan sp;
+    int code = 0;
+    try {
+        err = build_plan(to_input(*sd), po, sp, code);
+    } catch (const std::bad_alloc&) {
+        return fail(SC_ERR_OOM, "host allocation failed");
+    }
+    if (!err.empty()) return fail(SC_ERR_INVALID_ARG, err);
+    if (perm_out) std::copy(sp.perm.begin(), sp.perm.end(), perm_out);
+    if (piv_out) std::copy(sp.piv.begin(), sp.piv.end(), piv_out);
+    if (pi_out) std::copy(sp.pi.begin(), sp.pi.end(), pi_out);
+    if (info) {
+        sc_host_info_t h{};
+        h.n = sp.n;
+        h.m = sp.m;
+        h.nnzL = sp.nnzL;
+        h.nnzL_stored = sp.nnzL_stored;
+        h.nsuper = sp.nsuper;
+        h.nblocks = (int64_t)sp.blocks.size();
+        for (int32_t s = 0; s < sp.nsuper; ++s)
+            h.max_width = std::max<int64_t>(h.max_width, sp.sfirst[s + 1] - sp.sfirst[s]);
+        for (const BlockDesc& b : sp.blocks) h.sum_below += b.nbelow;
+        h.trsm_useful = sp.trsm_useful;
+        h.syrk_useful = sp.syrk_useful;
+        h.trsm_dense = sp.trsm_dense;
+        h.syrk_dense = sp.syrk_dense;
+        h.factor_flops = sp.factor_flops;
+        *info = h;
+    }
+    if (kreg_vals) {
+        std::vector<double> vals((size_t)std::max<int64_t>(1, sp.nval));
+        const int64_t bad = factor_numeric(sp, kreg_vals, vals.data());
+        if (bad >= 0) {
+            if (failed_col) *failed_col = (int32_t)bad;
+            return fail(SC_ERR_NOT_SPD, "pivot of permuted column " + std::to_string(bad) + " is not positive");
+        }
+        if (L_out) {
+            const int64_t n = sp.n;
+            std::fill(L_out, L_out + n * n, 0.0);
+            for (int32_t s = 0; s < sp.nsuper; ++s) {
+                const int32_t f = sp.sfirst[s], w = sp.sfirst[s + 1] - f;
+                const int64_t ld = sp.srow_ptr[s + 1] - sp.srow_ptr[s];
+                const int32_t* rows = sp.srows.data() + sp.srow_ptr[s];
+                const double* A = vals.data() + sp.spanel_off[s];
+                for (int32_t c = 0; c < w; ++c)
+                    for (int64_t q = c; q < ld; ++q) L_out[(int64_t)rows[q] * n + f + c] = A[c * ld + q];
+            }
+        }
+    }
+    return SC_OK;
+}
+
+sc_status_t sc_plan_destroy(sc_plan_t P) {
+    if (!P) return SC_OK;
+    (void)hipSetDevice(P->device);
+    P->release();
+    delete P;
+    return SC_OK;
+}
+
+}  // extern "C"

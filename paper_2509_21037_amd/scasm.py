@@ -1,0 +1,259 @@
+"""ctypes binding of libscasm.so: argument marshalling only; every step of the
+assembly and of the iteration phase runs in the library (host planner and
+HIP kernels).  Loading fails loudly when the library is missing."""
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libscasm.so")
+
+SC_OK, SC_ERR_INVALID_ARG, SC_ERR_NOT_SPD, SC_ERR_OOM, SC_ERR_DEVICE, SC_ERR_UNSUPPORTED, SC_ERR_STATE = range(7)
+SC_PREC_FP64, SC_PREC_MIXED = 0, 1
+STATUS_NAMES = {0: "SC_OK", 1: "SC_ERR_INVALID_ARG", 2: "SC_ERR_NOT_SPD", 3: "SC_ERR_OOM",
+                4: "SC_ERR_DEVICE", 5: "SC_ERR_UNSUPPORTED", 6: "SC_ERR_STATE"}
+
+EXPORTED = ["sc_plan_create", "sc_factor", "sc_assemble", "sc_apply", "sc_apply_implicit",
+            "sc_get_F", "sc_query", "sc_plan_stats", "sc_plan_destroy", "sc_host_analyze",
+            "sc_last_error"]
+
+
+class ScasmError(RuntimeError):
+    def __init__(self, status, message, failed_sub=None, failed_col=None):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+        self.failed_sub = failed_sub
+        self.failed_col = failed_col
+
+
+class SubdomainDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("kreg_rowptr", ctypes.c_void_p), ("kreg_col", ctypes.c_void_p),
+                ("m", ctypes.c_int32), ("bt_dof", ctypes.c_void_p), ("bt_sign", ctypes.c_void_p),
+                ("perm", ctypes.c_void_p), ("coords", ctypes.c_void_p), ("dim", ctypes.c_int32),
+                ("dofs_per_node", ctypes.c_int32)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("disable_staircase", ctypes.c_int32),
+                ("panel_width", ctypes.c_int32), ("relax_width", ctypes.c_int32),
+                ("leaf_nodes", ctypes.c_int32), ("n_threads", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 8)]
+
+
+class HostInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("nnzL", ctypes.c_int64),
+                ("nnzL_stored", ctypes.c_int64), ("nsuper", ctypes.c_int64), ("nblocks", ctypes.c_int64),
+                ("max_width", ctypes.c_int64), ("sum_below", ctypes.c_int64),
+                ("trsm_useful", ctypes.c_double), ("syrk_useful", ctypes.c_double),
+                ("trsm_dense", ctypes.c_double), ("syrk_dense", ctypes.c_double),
+                ("factor_flops", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load():
+    """The shared library; raises if it was not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_2509_21037_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64p, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)
+        lib.sc_plan_create.argtypes = [ctypes.POINTER(SubdomainDesc), i32, ctypes.POINTER(Options), vp,
+                                       ctypes.POINTER(vp)]
+        lib.sc_factor.argtypes = [vp, ctypes.POINTER(vp), vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        lib.sc_assemble.argtypes = [vp, vp]
+        lib.sc_apply.argtypes = [vp, vp, vp, vp]
+        lib.sc_apply_implicit.argtypes = [vp, vp, vp, vp]
+        lib.sc_get_F.argtypes = [vp, i32, vp, i32, i32, vp]
+        lib.sc_query.argtypes = [vp, i32, i64p, i64p, i64p, i64p, dp]
+        lib.sc_plan_stats.argtypes = [vp, ctypes.POINTER(i32), i64p, dp, dp, dp, dp, i64p]
+        lib.sc_plan_destroy.argtypes = [vp]
+        lib.sc_host_analyze.argtypes = [ctypes.POINTER(SubdomainDesc), ctypes.POINTER(Options), vp, vp, vp,
+                                         vp, vp, ctypes.POINTER(HostInfo), ctypes.POINTER(i32)]
+        lib.sc_last_error.argtypes = []
+        lib.sc_last_error.restype = ctypes.c_char_p
+        for name in EXPORTED[:-1]:
+            getattr(lib, name).restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _check(status, **kw):
+    if status != SC_OK:
+        msg = load().sc_last_error().decode(errors="replace")
+        raise ScasmError(status, msg, **kw)
+
+
+def _stream_handle(stream):
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        except Exception:
+            pass
+        return ctypes.c_void_p(0)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _fill_desc(d, s, keep, use_coords=True):
+    rowptr = np.ascontiguousarray(s.rowptr, dtype=np.int64)
+    col = np.ascontiguousarray(s.col, dtype=np.int32)
+    dof = np.ascontiguousarray(s.dof, dtype=np.int32)
+    sign = np.ascontiguousarray(s.sign, dtype=np.int8)
+    coords = getattr(s, "coords", None) if use_coords else None
+    perm = getattr(s, "perm", None)
+    d.n = int(s.n)
+    d.kreg_rowptr = rowptr.ctypes.data
+    d.kreg_col = col.ctypes.data
+    d.m = int(dof.shape[0])
+    d.bt_dof = dof.ctypes.data if dof.size else None
+    d.bt_sign = sign.ctypes.data if sign.size else None
+    keep += [rowptr, col, dof, sign]
+    if perm is not None:
+        perm = np.ascontiguousarray(perm, dtype=np.int32)
+        d.perm = perm.ctypes.data
+        keep.append(perm)
+    if coords is not None:
+        coords = np.ascontiguousarray(coords, dtype=np.float64)
+        d.coords = coords.ctypes.data
+        d.dim = int(coords.shape[1])
+        keep.append(coords)
+    d.dofs_per_node = int(getattr(s, "dofs_per_node", 1))
+
+
+def _options(precision="fp64", staircase=True, panel_width=0, relax_width=0, leaf_nodes=0, n_threads=0):
+    opt = Options()
+    opt.precision = {"fp64": SC_PREC_FP64, "mixed": SC_PREC_MIXED}.get(precision, precision) \
+        if isinstance(precision, str) else int(precision)
+    opt.disable_staircase = 0 if staircase else 1
+    opt.panel_width = panel_width
+    opt.relax_width = relax_width
+    opt.leaf_nodes = leaf_nodes
+    opt.n_threads = n_threads
+    return opt
+
+
+def host_analyze(s, values=True, want_L=False, use_coords=True, **opts):
+    """Host-only planner run for one subdomain (no device needed).  Returns a
+    dict with perm, pivots (sorted), pi (sorted -> original), statistics and,
+    when want_L, the dense factor L (row-major, n <= 4096)."""
+    lib = load()
+    keep = []
+    d = SubdomainDesc()
+    _fill_desc(d, s, keep, use_coords)
+    opt = _options(**opts)
+    n, m = int(s.n), int(np.asarray(s.dof).shape[0])
+    perm = np.zeros(n, dtype=np.int32)
+    piv = np.zeros(max(1, m), dtype=np.int32)
+    pi = np.zeros(max(1, m), dtype=np.int32)
+    L = np.zeros((n, n)) if want_L else None
+    vals = np.ascontiguousarray(s.val, dtype=np.float64) if values else None
+    info = HostInfo()
+    fc = ctypes.c_int32(-1)
+    st = lib.sc_host_analyze(ctypes.byref(d), ctypes.byref(opt), vals.ctypes.data if vals is not None else None,
+                             perm.ctypes.data, L.ctypes.data if L is not None else None, piv.ctypes.data,
+                             pi.ctypes.data, ctypes.byref(info), ctypes.byref(fc))
+    if st != SC_OK:
+        _check(st, failed_col=fc.value)
+    out = {f: getattr(info, f) for f, _ in HostInfo._fields_}
+    out.update(perm=perm, piv=piv[:m], pi=pi[:m], L=L)
+    return out
+
+
+class Plan:
+    """A batch of subdomains (objects with n, rowptr, col, val, dof, sign and
+    optional coords, dim, dofs_per_node, perm attributes)."""
+
+    def __init__(self, subdomains: Sequence, precision: str = "fp64", staircase: bool = True,
+                 panel_width: int = 0, relax_width: int = 0, leaf_nodes: int = 0, n_threads: int = 0,
+                 use_coords: bool = True, stream=None):
+        lib = load()
+        self._lib = lib
+        self._h = ctypes.c_void_p(0)
+        self.subdomains = list(subdomains)
+        self.precision = precision
+        keep = []
+        descs = (SubdomainDesc * max(1, len(self.subdomains)))()
+        for i, s in enumerate(self.subdomains):
+            _fill_desc(descs[i], s, keep, use_coords)
+        opt = _options(precision, staircase, panel_width, relax_width, leaf_nodes, n_threads)
+        _check(lib.sc_plan_create(descs, len(self.subdomains), ctypes.byref(opt), _stream_handle(stream),
+                                  ctypes.byref(self._h)))
+        del keep
+
+    # ---------------------------------------------------------------- stages
+    def factor(self, kvals: Optional[List[np.ndarray]] = None, stream=None):
+        if kvals is None:
+            kvals = [s.val for s in self.subdomains]
+        arrs = [np.ascontiguousarray(v, dtype=np.float64) for v in kvals]
+        ptrs = (ctypes.c_void_p * max(1, len(arrs)))(*[a.ctypes.data for a in arrs])
+        fs, fc = ctypes.c_int32(-1), ctypes.c_int32(-1)
+        st = self._lib.sc_factor(self._h, ptrs, _stream_handle(stream), ctypes.byref(fs), ctypes.byref(fc))
+        if st != SC_OK:
+            _check(st, failed_sub=fs.value, failed_col=fc.value)
+        # the upload is asynchronous and reads pinned memory owned by the plan
+        return self
+
+    def assemble(self, stream=None):
+        _check(self._lib.sc_assemble(self._h, _stream_handle(stream)))
+        return self
+
+    def apply(self, p, q, stream=None):
+        """q = F p on device FP64 tensors of length dual_total."""
+        _check(self._lib.sc_apply(self._h, ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(q.data_ptr()),
+                                  _stream_handle(stream)))
+        return q
+
+    def apply_implicit(self, p, q, stream=None):
+        _check(self._lib.sc_apply_implicit(self._h, ctypes.c_void_p(p.data_ptr()),
+                                           ctypes.c_void_p(q.data_ptr()), _stream_handle(stream)))
+        return q
+
+    # ---------------------------------------------------------------- queries
+    def get_F(self, i: int, stream=None) -> np.ndarray:
+        m = self.query(i)["m"]
+        out = np.zeros((m, m), dtype=np.float64, order="F")
+        _check(self._lib.sc_get_F(self._h, i, out.ctypes.data, max(1, m), 0, _stream_handle(stream)))
+        return out
+
+    def query(self, i: int) -> dict:
+        n, m, off, nnz = (ctypes.c_int64() for _ in range(4))
+        fl = ctypes.c_double()
+        _check(self._lib.sc_query(self._h, i, ctypes.byref(n), ctypes.byref(m), ctypes.byref(off),
+                                  ctypes.byref(nnz), ctypes.byref(fl)))
+        return {"n": n.value, "m": m.value, "dual_offset": off.value, "nnzL": nnz.value,
+                "useful_flops": fl.value}
+
+    def stats(self) -> dict:
+        ns = ctypes.c_int32()
+        dt, db = ctypes.c_int64(), ctypes.c_int64()
+        tu, su, td, sd = (ctypes.c_double() for _ in range(4))
+        _check(self._lib.sc_plan_stats(self._h, ctypes.byref(ns), ctypes.byref(dt), ctypes.byref(tu),
+                                       ctypes.byref(su), ctypes.byref(td), ctypes.byref(sd), ctypes.byref(db)))
+        return {"nsub": ns.value, "dual_total": dt.value, "trsm_useful": tu.value, "syrk_useful": su.value,
+                "trsm_dense": td.value, "syrk_dense": sd.value, "device_bytes": db.value}
+
+    def destroy(self):
+        if self._h and self._h.value:
+            self._lib.sc_plan_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.destroy()

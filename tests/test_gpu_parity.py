@@ -1,0 +1,184 @@
+"""Parity of the HIP assembly (through the C ABI) with the CPU oracle.
+
+F_gpu from sc_assemble (FP64 path) is compared element by element with the
+long-double oracle F = B K_reg^{-1} B^T on the same seeded inputs; the bar is
+a relative Frobenius error <= 1e-12 per subdomain.  At the full workload sizes
+the comparison uses seeded column subsets S (F[S, S]) the oracle computes on
+its own."""
+import numpy as np
+import pytest
+
+import oracle
+import scgen
+from scgen.mesh import Subdomain
+
+P = pytest.importorskip("paper_2509_21037_amd")
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-12
+
+
+def _torch_init():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.init()
+    return torch
+
+
+def _assemble(subs, **kw):
+    _torch_init()
+    plan = P.Plan(subs, **kw)
+    plan.factor()
+    plan.assemble()
+    return plan
+
+
+def _check_against_oracle(plan, subs, max_full=3000, nsel=192, seed=0):
+    errs = []
+    for i, s in enumerate(subs):
+        F = plan.get_F(i)
+        assert F.shape == (s.m, s.m)
+        if s.m == 0:
+            continue
+        assert np.array_equal(F, F.T)
+        if s.n <= max_full:
+            ref = oracle.schur(s)
+            e = oracle.relF(F, ref)
+        else:
+            sel = np.sort(np.random.default_rng(seed + i).choice(s.m, size=min(nsel, s.m), replace=False))
+            ref = oracle.schur(s, sel=sel)
+            e = oracle.relF(F[np.ix_(sel, sel)], ref)
+        errs.append(e)
+        assert e <= TOL_FP64, (i, s.elems, e)
+    return errs
+
+
+def test_heat2d_matches_golden_and_oracle():
+    s = scgen.config_subdomains(1)[0]
+    plan = _assemble([s])
+    F = plan.get_F(0)
+    import os
+    golden = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "heat2d_q1_16x16_F.txt"),
+                        comments="#").reshape(s.m, s.m, order="F")
+    assert oracle.relF(F, golden) <= TOL_FP64
+    _check_against_oracle(plan, [s])
+
+
+def test_heat3d_batch_matches_oracle():
+    subs = scgen.config_subdomains(2, count=3)
+    plan = _assemble(subs)
+    _check_against_oracle(plan, subs)
+
+
+def test_elasticity_uneven_batch_matches_oracle():
+    subs = scgen.config_subdomains(3, count=6)
+    plan = _assemble(subs)
+    _check_against_oracle(plan, subs, max_full=3000)
+
+
+@pytest.mark.parametrize("panel_width", [16, 32, 48, 64])
+def test_panel_widths(panel_width):
+    subs = [scgen.box_subdomain("elasticity", (4, 5, 3), 0.25, seed=5),
+            scgen.box_subdomain("heat", (7, 6, 5), 0.2, seed=6)]
+    plan = _assemble(subs, panel_width=panel_width, relax_width=96)
+    _check_against_oracle(plan, subs)
+
+
+def test_staircase_off_matches_on():
+    subs = [scgen.config_subdomains(1)[0], scgen.box_subdomain("elasticity", (4, 3, 5), 0.25, seed=8)]
+    on = _assemble(subs)
+    off = _assemble(subs, staircase=False)
+    for i in range(len(subs)):
+        a, b = on.get_F(i), off.get_F(i)
+        assert oracle.relF(a, b) <= 1e-14
+    _check_against_oracle(off, subs)
+
+
+def test_sign_flip_is_exact():
+    s = scgen.box_subdomain("heat", (6, 6, 6), 1 / 6, seed=11)
+    flip = scgen.rng.signs_from_seed(5, s.m).astype(np.int8)
+    plan = _assemble([s, s.with_signs(s.sign * flip)])
+    F0, F1 = plan.get_F(0), plan.get_F(1)
+    S = flip.astype(float)
+    assert np.array_equal(F1, S[:, None] * F0 * S[None, :])
+
+
+def test_column_permutation():
+    s = scgen.box_subdomain("elasticity", (3, 4, 4), 0.25, seed=12)
+    perm = np.random.default_rng(1).permutation(s.m)
+    plan = _assemble([s, s.with_columns(s.dof[perm], s.sign[perm])])
+    F0, F1 = plan.get_F(0), plan.get_F(1)
+    assert oracle.relF(F1, F0[np.ix_(perm, perm)]) <= 1e-14
+
+
+def test_run_to_run_deterministic():
+    subs = scgen.config_subdomains(3, count=2)
+    plan = _assemble(subs)
+    a = [plan.get_F(i) for i in range(2)]
+    plan.assemble()
+    b = [plan.get_F(i) for i in range(2)]
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_edge_cases_in_one_batch():
+    base = scgen.box_subdomain("heat", (4, 4, 3), 0.25, seed=13)
+    tiny = scgen.box_subdomain("heat", (1, 1), 1.0, seed=14)            # n = 4, m = 4
+    empty = base.with_columns(np.zeros(0, np.int32), np.zeros(0, np.int8))
+    one = base.with_columns(base.dof[:1], base.sign[:1])
+    ragged = base.with_columns(base.dof[:17], base.sign[:17])
+    same_pivot = base.with_columns(np.full(70, base.dof[5], np.int32),
+                                   scgen.rng.signs_from_seed(3, 70))   # 70 columns, one DOF
+    interior = base.with_columns(np.arange(0, base.n, 7, dtype=np.int32),
+                                 scgen.rng.signs_from_seed(4, len(range(0, base.n, 7))))
+    subs = [base, tiny, empty, one, ragged, same_pivot, interior]
+    plan = _assemble(subs)
+    _check_against_oracle(plan, subs)
+
+
+def test_state_errors():
+    _torch_init()
+    s = scgen.config_subdomains(1)[0]
+    plan = P.Plan([s])
+    with pytest.raises(P.ScasmError) as e:
+        plan.assemble()
+    assert e.value.status == P.SC_ERR_STATE
+    with pytest.raises(P.ScasmError) as e:
+        plan.get_F(0)
+    assert e.value.status == P.SC_ERR_STATE
+    with pytest.raises(P.ScasmError) as e:
+        plan.get_F(5)
+    assert e.value.status == P.SC_ERR_INVALID_ARG
+
+
+def test_not_spd_from_factor():
+    _torch_init()
+    s = scgen.box_subdomain("heat", (3, 3, 3), 0.3, seed=1)
+    plan = P.Plan([s, s])
+    with pytest.raises(P.ScasmError) as e:
+        plan.factor([s.val, np.where(np.arange(len(s.val)) == 0, -1.0, s.val)])
+    assert e.value.status == P.SC_ERR_NOT_SPD and e.value.failed_sub == 1
+
+
+def test_full_heat_workload_sampled():
+    """All 1024 subdomains of the 12^3 heat workload in one assembly (the
+    launch the benchmark times); three subdomains checked in full."""
+    subs = scgen.config_subdomains(2)
+    plan = _assemble(subs)
+    for i in (0, 511, 1023):
+        F = plan.get_F(i)
+        assert oracle.relF(F, oracle.schur(subs[i])) <= TOL_FP64
+
+
+def test_full_elasticity_workload_sampled():
+    """All 512 uneven elasticity subdomains in one assembly; seeded column
+    samples of four subdomains (the largest included) against the oracle."""
+    subs = scgen.config_subdomains(3)
+    plan = _assemble(subs)
+    sizes = np.array([s.n for s in subs])
+    picks = [0, int(np.argmax(sizes)), int(np.argmin(sizes)), 300]
+    for i in picks:
+        s = subs[i]
+        sel = np.sort(np.random.default_rng(i).choice(s.m, size=min(128, s.m), replace=False))
+        F = plan.get_F(i)
+        assert oracle.relF(F[np.ix_(sel, sel)], oracle.schur(s, sel=sel)) <= TOL_FP64

@@ -1,0 +1,218 @@
+"""CPU tests of the host planner (through the host-only C entry point) and of
+the C ABI surface: symbols, argument validation, error codes."""
+import ctypes
+import glob
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import scgen
+from scgen.mesh import Subdomain
+
+P = pytest.importorskip("paper_2509_21037_amd")
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        txt = open(h).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        names |= set(re.findall(r"\b(sc_[A-Za-z_]+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared_symbols()
+    assert {"sc_plan_create", "sc_factor", "sc_assemble", "sc_apply", "sc_apply_implicit", "sc_get_F",
+            "sc_query", "sc_plan_destroy", "sc_last_error", "sc_host_analyze"} <= names
+    lib = P.load()
+    for name in names:
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", P.LIB_PATH], stdout=subprocess.PIPE, text=True).stdout
+    exported = set(re.findall(r"\bT (sc_\w+)", out))
+    assert names <= exported
+
+
+def _structural_nnz(A):
+    pat = np.tril(A != 0)
+    n = A.shape[0]
+    for j in range(n):
+        rows = np.nonzero(pat[j + 1:, j])[0] + j + 1
+        if len(rows):
+            pat[np.ix_(rows, rows)] |= np.tril(np.ones((len(rows), len(rows)), bool))
+    return int(pat.sum())
+
+
+CASES = [
+    ("heat2d", lambda: scgen.config_subdomains(1)[0]),
+    ("heat3d", lambda: scgen.box_subdomain("heat", (5, 6, 4), 0.2, seed=1)),
+    ("elast", lambda: scgen.box_subdomain("elasticity", (3, 4, 3), 0.25, seed=2)),
+    ("elast_flat", lambda: scgen.box_subdomain("elasticity", (6, 2, 3), 0.25, seed=3)),
+]
+
+
+@pytest.mark.parametrize("name,make", CASES)
+@pytest.mark.parametrize("use_coords", [True, False])
+def test_factor_is_cholesky_of_permuted_matrix(name, make, use_coords):
+    s = make()
+    r = P.host_analyze(s, want_L=True, use_coords=use_coords)
+    perm = r["perm"]
+    assert np.array_equal(np.sort(perm), np.arange(s.n))
+    A = s.Kreg_csr().toarray()[np.ix_(perm, perm)]
+    L = r["L"]
+    assert np.abs(np.triu(L, 1)).max() == 0
+    assert np.linalg.norm(L @ L.T - A) / np.linalg.norm(A) < 1e-15
+    assert r["nnzL"] == _structural_nnz(A)
+    assert r["nnzL_stored"] >= r["nnzL"]
+
+
+def test_nested_dissection_beats_natural_order():
+    s = scgen.box_subdomain("heat", (12, 12, 12), 1 / 12, seed=0)
+    nd = P.host_analyze(s, values=False)
+    s.perm = np.arange(s.n, dtype=np.int32)
+    nat = P.host_analyze(s, values=False)
+    assert nd["nnzL"] < 0.6 * nat["nnzL"]
+
+
+def test_dof_blocks_stay_together_for_elasticity():
+    s = scgen.box_subdomain("elasticity", (4, 3, 5), 0.25, seed=4)
+    perm = P.host_analyze(s, values=False)["perm"]
+    assert np.array_equal(perm.reshape(-1, 3) % 3, np.tile([0, 1, 2], (s.n // 3, 1)))
+    assert np.all(perm.reshape(-1, 3)[:, 0] // 3 == perm.reshape(-1, 3)[:, 2] // 3)
+
+
+@pytest.mark.parametrize("staircase", [True, False])
+def test_pivots_and_column_sort(staircase):
+    s = scgen.box_subdomain("heat", (6, 5, 4), 0.2, seed=7)
+    r = P.host_analyze(s, values=False, staircase=staircase)
+    perm, piv, pi = r["perm"], r["piv"], r["pi"]
+    iperm = np.argsort(perm)
+    assert np.array_equal(np.sort(pi), np.arange(s.m))
+    assert np.array_equal(piv, iperm[s.dof[pi]])
+    if staircase:
+        assert np.all(np.diff(piv) >= 0)
+        # stable: equal pivots keep the original column order
+        eq = np.diff(piv) == 0
+        assert np.all(np.diff(pi)[eq] > 0)
+    else:
+        assert np.array_equal(pi, np.arange(s.m))
+
+
+def _flop_counts(L, piv, m):
+    n = L.shape[0]
+    c = (L != 0).sum(axis=0)
+    a = np.zeros(n)
+    np.add.at(a, piv, 1)
+    a = np.cumsum(a)
+    return float((a * (2 * c - 1)).sum()), float((a * (a + 1)).sum()), float(m * (2 * c - 1).sum()), \
+        float(n * m * (m + 1))
+
+
+def test_useful_flop_model_matches_definition():
+    s = scgen.box_subdomain("heat", (5, 5, 5), 0.2, seed=9)
+    r = P.host_analyze(s, want_L=True)
+    perm = r["perm"]
+    A = s.Kreg_csr().toarray()[np.ix_(perm, perm)]
+    pat = np.tril(A != 0)
+    for j in range(s.n):                       # structural pattern, not numerical
+        rows = np.nonzero(pat[j + 1:, j])[0] + j + 1
+        if len(rows):
+            pat[np.ix_(rows, rows)] |= np.tril(np.ones((len(rows), len(rows)), bool))
+    t, sy, td, sd = _flop_counts(pat.astype(float), r["piv"], s.m)
+    assert abs(r["trsm_useful"] - t) < 1e-9 * t
+    assert abs(r["syrk_useful"] - sy) < 1e-9 * sy
+    assert abs(r["trsm_dense"] - td) < 1e-9 * td
+    assert abs(r["syrk_dense"] - sd) < 1e-9 * sd
+
+
+def test_triangular_rhs_gives_threefold_saving():
+    # Sec. 4.3: pivot of column j at row j*n/m with a dense factor -> 1/3 of the work
+    golden = {}
+    for line in open(os.path.join(ROOT, "tests", "golden", "paper_values.txt")):
+        if line.strip() and not line.startswith("#"):
+            k, v, _ = line.split()
+            golden[k] = float(v)
+    n = m = 1000
+    rng = np.random.default_rng(0)
+    M = rng.standard_normal((n, n))
+    Kd = M @ M.T + n * np.eye(n)
+    rowptr = np.arange(0, n * n + 1, n, dtype=np.int64)
+    col = np.tile(np.arange(n, dtype=np.int32), n)
+    sd = Subdomain(kind="dense", dim=0, elems=(), h=1.0, dofs_per_node=1, n=n, k_rowptr=rowptr, k_col=col,
+                   k_val=Kd.ravel(), rowptr=rowptr, col=col, val=Kd.ravel(), coords=None, R=np.zeros((n, 0)),
+                   fix_dofs=np.zeros(0, int), Q=np.zeros((0, 0)), rho=0.0,
+                   dof=(np.arange(m) * n // m).astype(np.int32), sign=np.ones(m, np.int8))
+    sd.perm = np.arange(n, dtype=np.int32)
+    r = P.host_analyze(sd, values=False)
+    ratio_trsm = r["trsm_dense"] / r["trsm_useful"]
+    ratio_syrk = r["syrk_dense"] / r["syrk_useful"]
+    assert abs(ratio_trsm - golden["triangular_rhs_speedup"]) < 0.1
+    assert abs(ratio_syrk - golden["triangular_rhs_speedup"]) < 0.1
+
+
+def test_not_spd_reported_with_column():
+    s = scgen.box_subdomain("heat", (3, 3, 3), 0.3, seed=1)
+    bad = Subdomain(**{**s.__dict__})
+    bad.val = s.k_val            # K itself is singular (floating subdomain)
+    bad.rowptr, bad.col = s.k_rowptr, s.k_col
+    with pytest.raises(P.ScasmError) as e:
+        P.host_analyze(bad)
+    assert e.value.status == P.SC_ERR_NOT_SPD
+    assert 0 <= e.value.failed_col < s.n
+
+
+@pytest.mark.parametrize("mutate,msg", [
+    (lambda s: setattr(s, "dof", np.concatenate([s.dof[:-1], [s.n]]).astype(np.int32)), "dof"),
+    (lambda s: setattr(s, "dof", np.concatenate([s.dof[:-1], [-1]]).astype(np.int32)), "dof"),
+    (lambda s: setattr(s, "sign", np.concatenate([s.sign[:-1], [2]]).astype(np.int8)), "sign"),
+    (lambda s: setattr(s, "sign", np.concatenate([s.sign[:-1], [0]]).astype(np.int8)), "sign"),
+    (lambda s: setattr(s, "perm", np.zeros(s.n, np.int32)), "perm"),
+    (lambda s: setattr(s, "col", np.where(np.arange(len(s.col)) == 3, s.n, s.col).astype(np.int32)), "column"),
+])
+def test_invalid_arguments(mutate, msg):
+    s = scgen.box_subdomain("heat", (3, 3), 0.3, seed=1)
+    bad = Subdomain(**{**s.__dict__})
+    mutate(bad)
+    with pytest.raises(P.ScasmError) as e:
+        P.host_analyze(bad, values=False)
+    assert e.value.status == P.SC_ERR_INVALID_ARG
+    assert msg in e.value.message
+
+
+def test_invalid_options_and_sizes():
+    s = scgen.box_subdomain("heat", (3, 3), 0.3, seed=1)
+    for kw in ({"panel_width": 8}, {"panel_width": 128}, {"precision": 7}, {"relax_width": -1}):
+        with pytest.raises(P.ScasmError) as e:
+            P.host_analyze(s, values=False, **kw)
+        assert e.value.status == P.SC_ERR_INVALID_ARG
+    bad = Subdomain(**{**s.__dict__})
+    bad.n = 0
+    with pytest.raises(P.ScasmError):
+        P.host_analyze(bad, values=False)
+
+
+def test_plan_create_validates_before_touching_the_device():
+    lib = P.load()
+    from paper_2509_21037_amd.scasm import Options
+    h = ctypes.c_void_p(0)
+    assert lib.sc_plan_create(None, 1, ctypes.byref(Options()), None, ctypes.byref(h)) == P.SC_ERR_INVALID_ARG
+    assert lib.sc_plan_create(None, -1, None, None, ctypes.byref(h)) == P.SC_ERR_INVALID_ARG
+    assert lib.sc_plan_create(None, 0, None, None, None) == P.SC_ERR_INVALID_ARG
+    assert lib.sc_assemble(None, None) == P.SC_ERR_INVALID_ARG
+    assert lib.sc_plan_destroy(None) == P.SC_OK
+    assert b"NULL" in lib.sc_last_error() or lib.sc_last_error() == b""
+
+
+def test_zero_multipliers_and_tiny_subdomain():
+    s = scgen.box_subdomain("heat", (1, 1), 1.0, seed=1)
+    r = P.host_analyze(s, want_L=True)
+    assert r["n"] == 4
+    e = Subdomain(**{**s.__dict__})
+    e.dof = np.zeros(0, np.int32)
+    e.sign = np.zeros(0, np.int8)
+    r = P.host_analyze(e)
+    assert r["m"] == 0 and r["trsm_useful"] == 0 and r["syrk_useful"] == 0
