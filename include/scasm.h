@@ -167,6 +167,17 @@ sc_status_t sc_plan_stats(sc_plan_t plan, int32_t* nsub, int64_t* dual_total,
                           double* trsm_useful, double* syrk_useful, double* trsm_dense,
                           double* syrk_dense, int64_t* device_bytes);
 
+/* Kernel timing.  While enabled, sc_assemble and sc_apply record HIP events
+ * on their stream around each kernel they launch; sc_kernel_times adds up the
+ * elapsed milliseconds of every completed launch since the last reset
+ * (synchronising on the recorded events):
+ *   ms[0] staircase TRSM, ms[1] staircase SYRK + permute-back,
+ *   ms[2] explicit apply (GEMV), ms[3] implicit apply;
+ *   counts[k] = number of launches of kernel k summed into ms[k].
+ * `reset` != 0 clears the sums after reading.  Arrays hold 4 entries. */
+sc_status_t sc_set_timing(sc_plan_t plan, int32_t enable);
+sc_status_t sc_kernel_times(sc_plan_t plan, double* ms, int64_t* counts, int32_t reset);
+
 /* Release every device and host buffer of the plan.  NULL is accepted. */
 sc_status_t sc_plan_destroy(sc_plan_t plan);
 

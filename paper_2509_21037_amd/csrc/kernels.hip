@@ -32,26 +32,57 @@ __device__ __forceinline__ void wave_sync() {
 
 // ---------------------------------------------------------------------------
 // Staircase TRSM, X = L^{-1} P B^T (Sec. 3.2, factor splitting with pruning).
-// One workgroup = one 64-column tile of one subdomain; each wavefront owns a
-// 16-column stripe and sweeps the factor blocks from the block holding the
-// stripe's first pivot (rows above it are zero and stay zero: forward
-// substitution only propagates downwards).  Per block:
-//   1. the block's w (<= 64) rows of the stripe are loaded into registers;
-//   2. diagonal solve in FP64: 16-row sub-blocks by substitution (division by
-//      the diagonal, column-wise elimination), each followed by an MFMA
-//      update of the sub-blocks below it inside the diagonal block;
-//   3. the solved rows are stored and the pruned rows below the block are
-//      updated, X[R_b] -= L[R_b, b] X[b], with FP64 MFMA, 16 rows at a time.
-// The stripes never interact (columns of X are independent), so there is no
-// workgroup barrier after initialisation.
+// One workgroup = one 64-column tile of one subdomain; wavefront w owns the
+// 16-column stripe w.  The four wavefronts walk the factor blocks together,
+// from the block holding the tile's first pivot (rows above it are zero and
+// stay zero: forward substitution only propagates downwards); a stripe whose
+// first pivot lies further down joins at its own first block.  Per block:
+//   1. the dense diagonal block (<= 64 x 64) is staged in LDS once for the
+//      workgroup; each wavefront loads its stripe's block rows into registers
+//      (MFMA accumulator layout);
+//   2. diagonal solve in FP64: 16-row sub-blocks by substitution (scaling by
+//      the reciprocal of the diagonal, column-wise elimination), each followed
+//      by an MFMA update of the sub-blocks below it inside the diagonal block;
+//   3. the solved rows are stored, then the pruned rows below the block are
+//      updated in chunks of 64, X[R_b] -= L[R_b, b] X[b], with FP64 MFMA:
+//      each chunk of the factor panel is loaded once into LDS for all four
+//      wavefronts (the next chunk is prefetched into registers meanwhile).
 // ---------------------------------------------------------------------------
+constexpr int kLdsLd = 64 + 2;            // LDS leading dimension (doubles) of a staged chunk
+
+// Loads rows [r0, r0 + 64) x columns [0, w) of a column-major panel (leading
+// dimension ld, nrows valid rows) into 16 registers per thread, negated when
+// `neg` (the update subtracts).
+__device__ __forceinline__ void load_chunk(const double* __restrict__ panel, int ld, int nrows, int w,
+                                           int r0, bool neg, double (&reg)[16]) {
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+        const int e = threadIdx.x + 256 * it;
+        const int row = e & 63;
+        const int k = e >> 6;
+        const int gr = r0 + row;
+        double v = 0.0;
+        if (k < w && gr < nrows) v = panel[(int64_t)k * ld + gr];
+        reg[it] = neg ? -v : v;
+    }
+}
+
+__device__ __forceinline__ void store_chunk(double* __restrict__ sL, const double (&reg)[16]) {
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+        const int e = threadIdx.x + 256 * it;
+        sL[(e >> 6) * kLdsLd + (e & 63)] = reg[it];
+    }
+}
+
 __global__ __launch_bounds__(256) void trsm_stair_f64(
     const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
     const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows,
     const double* __restrict__ lval, const int32_t* __restrict__ piv,
     const int8_t* __restrict__ sgn, double* __restrict__ X)
 {
-    __shared__ double ldiag[4][16 * 17];
+    __shared__ double sL[64 * kLdsLd];
+    __shared__ double sRd[64];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int g = lane >> 4;
@@ -70,123 +101,120 @@ __global__ __launch_bounds__(256) void trsm_stair_f64(
     __threadfence_block();
     if (g == 0 && col < T.ncols)
         Xs[(int64_t)(piv[cbase + col] - kstart) * kTile + col] = (double)sgn[cbase + col];
-    __threadfence_block();
-    if (wv * kStripe >= T.ncols) return;
+    __syncthreads();
 
     const BlockDev* __restrict__ B = blocks + S.blk_off;
     const int32_t* __restrict__ R = rows + S.rows_off;
     const double* __restrict__ L = lval + S.lval_off;
-    double* __restrict__ ld_s = ldiag[wv];
+    const int my_start = tiles[blockIdx.x].start_block[wv];
+    const int first_block = tiles[blockIdx.x].start_block[0];
 
-    for (int b = T.start_block[wv]; b < S.nblocks; ++b) {
+    double pre[16];
+    for (int b = first_block; b < S.nblocks; ++b) {
         const BlockDev bd = B[b];
         const int w = bd.w;
         const int ld = bd.ld;
         const int row0 = bd.row0;
+        const int nb = bd.nbelow;
         const double* __restrict__ Lb = L + bd.lval_off;
+        const bool act = b >= my_start;
+
+        // ---- stage the diagonal block (rows [0, w) of the panel)
+        load_chunk(Lb, ld, w, w, 0, false, pre);
+        __syncthreads();                 // previous users of sL are done
+        store_chunk(sL, pre);
+        __syncthreads();
+        if (threadIdx.x < 64) sRd[threadIdx.x] = threadIdx.x < w ? 1.0 / sL[threadIdx.x * (kLdsLd + 1)] : 0.0;
+        if (nb > 0) load_chunk(Lb, ld, w + nb, w, w, true, pre);     // prefetch first below chunk
+        __syncthreads();
 
         v4d xr[4];
+        if (act) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = 16 * t + 4 * r + g;
-                const int row = row0 + i;
-                xr[t][r] = (i < w && row >= kstart) ? Xs[(int64_t)(row - kstart) * kTile + col] : 0.0;
-            }
-
-        // ---- diagonal block
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            if (16 * t < w) {
-            wave_sync();
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int ii = 4 * r + g;
-                double v = 0.0;
-                if (16 * t + ii < w && 16 * t + j < w)
-                    v = Lb[(int64_t)(16 * t + j) * ld + 16 * t + ii];
-                ld_s[ii * 17 + j] = v;
-            }
-            wave_sync();
-#pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                if (16 * t + k < w) {
-                const int gk = k & 3;
-                const int rk = k >> 2;
-                const double xk_own = xr[t][rk] / ld_s[k * 17 + k];
-                if (g == gk) xr[t][rk] = xk_own;
-                const double xk = __shfl(xk_own, j + 16 * gk, 64);
+            for (int t = 0; t < 4; ++t)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int ii = 4 * r + g;
-                    const double lik = ld_s[ii * 17 + k];
-                    if (ii > k) xr[t][r] -= lik * xk;
+                    const int i = 16 * t + 4 * r + g;
+                    const int row = row0 + i;
+                    xr[t][r] = (i < w && row >= kstart) ? Xs[(int64_t)(row - kstart) * kTile + col] : 0.0;
                 }
-                }
-            }
-#pragma unroll
-            for (int t2 = t + 1; t2 < 4; ++t2) {
-                if (16 * t2 < w) {
-#pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    const int kc = 16 * t + 4 * s + g;
-                    const int ir = 16 * t2 + j;
-                    const double a = (kc < w && ir < w) ? -Lb[(int64_t)kc * ld + ir] : 0.0;
-                    xr[t2] = mfma_f64(a, xr[t][s], xr[t2]);
-                }
-                }
-            }
-            }
-        }
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = 16 * t + 4 * r + g;
-                const int row = row0 + i;
-                if (i < w && row >= kstart) Xs[(int64_t)(row - kstart) * kTile + col] = xr[t][r];
-            }
-
-        // ---- pruned rows below the block
-        const int nb = bd.nbelow;
-        const int32_t* __restrict__ rw = R + bd.rows_off;
-        const double* __restrict__ Lq = Lb + w;      // element (q, k) at Lq[k * ld + q]
-        for (int q0 = 0; q0 < nb; q0 += 32) {
-            v4d acc0, acc1;
-            int64_t off0[4], off1[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int qa = q0 + 4 * r + g;
-                const int qb = qa + 16;
-                off0[r] = qa < nb ? (int64_t)(rw[qa] - kstart) * kTile + col : -1;
-                off1[r] = qb < nb ? (int64_t)(rw[qb] - kstart) * kTile + col : -1;
-                acc0[r] = off0[r] >= 0 ? Xs[off0[r]] : 0.0;
-                acc1[r] = off1[r] >= 0 ? Xs[off1[r]] : 0.0;
-            }
-            const int qa = q0 + j;
-            const int qb = qa + 16;
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 if (16 * t < w) {
 #pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    const int kc = 16 * t + 4 * s + g;
-                    const bool kok = kc < w;
-                    const double a0 = (kok && qa < nb) ? -Lq[(int64_t)kc * ld + qa] : 0.0;
-                    const double a1 = (kok && qb < nb) ? -Lq[(int64_t)kc * ld + qb] : 0.0;
-                    acc0 = mfma_f64(a0, xr[t][s], acc0);
-                    acc1 = mfma_f64(a1, xr[t][s], acc1);
-                }
+                    for (int k = 0; k < 16; ++k) {
+                        if (16 * t + k < w) {
+                            const int gk = k & 3;
+                            const int rk = k >> 2;
+                            const double xk_own = xr[t][rk] * sRd[16 * t + k];
+                            if (g == gk) xr[t][rk] = xk_own;
+                            const double xk = __shfl(xk_own, j + 16 * gk, 64);
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                const int ii = 4 * r + g;
+                                const double lik = sL[(16 * t + k) * kLdsLd + 16 * t + ii];
+                                if (ii > k) xr[t][r] -= lik * xk;
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int t2 = t + 1; t2 < 4; ++t2) {
+                        if (16 * t2 < w) {
+#pragma unroll
+                            for (int s = 0; s < 4; ++s) {
+                                const double a = -sL[(16 * t + 4 * s + g) * kLdsLd + 16 * t2 + j];
+                                xr[t2] = mfma_f64(a, xr[t][s], xr[t2]);
+                            }
+                        }
+                    }
                 }
             }
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                if (off0[r] >= 0) Xs[off0[r]] = acc0[r];
-                if (off1[r] >= 0) Xs[off1[r]] = acc1[r];
-            }
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = 16 * t + 4 * r + g;
+                    const int row = row0 + i;
+                    if (i < w && row >= kstart) Xs[(int64_t)(row - kstart) * kTile + col] = xr[t][r];
+                }
         }
-        __threadfence_block();
+
+        // ---- pruned rows below the block, 64 at a time
+        const int32_t* __restrict__ rw = R + bd.rows_off;
+        for (int q0 = 0; q0 < nb; q0 += 64) {
+            __syncthreads();             // sL free (diagonal block or previous chunk)
+            store_chunk(sL, pre);
+            if (q0 + 64 < nb) load_chunk(Lb, ld, w + nb, w, w + q0 + 64, true, pre);
+            __syncthreads();
+            if (!act) continue;
+            v4d acc[4];
+            int32_t off[4][4];
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int q = q0 + 16 * rt + 4 * r + g;
+                    off[rt][r] = q < nb ? (rw[q] - kstart) * kTile + col : -1;
+                    acc[rt][r] = off[rt][r] >= 0 ? Xs[off[rt][r]] : 0.0;
+                }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if (16 * t < w) {
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const double* sk = sL + (16 * t + 4 * s + g) * kLdsLd + j;
+#pragma unroll
+                        for (int rt = 0; rt < 4; ++rt)
+                            acc[rt] = mfma_f64(sk[16 * rt], xr[t][s], acc[rt]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (off[rt][r] >= 0) Xs[off[rt][r]] = acc[rt][r];
+        }
     }
 }
 
@@ -278,16 +306,21 @@ __global__ __launch_bounds__(256) void syrk_stair_f64(
 }
 
 // ---------------------------------------------------------------------------
-hipError_t launch_assemble_f64(const DevTables& t, hipStream_t stream) {
+hipError_t launch_assemble_f64(const DevTables& t, hipStream_t stream, hipEvent_t* ev) {
+    hipError_t e = hipSuccess;
+    if (ev && (e = hipEventRecord(ev[0], stream)) != hipSuccess) return e;
     if (t.ntiles > 0)
         hipLaunchKernelGGL(trsm_stair_f64, dim3((unsigned)t.ntiles), dim3(256), 0, stream, t.subs,
                            t.tiles, t.blocks, t.rows, t.lval, t.piv, t.sgn, t.X);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[1], stream)) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[2], stream)) != hipSuccess) return e;
     if (t.nsyrk > 0)
         hipLaunchKernelGGL(syrk_stair_f64, dim3((unsigned)t.nsyrk), dim3(256), 0, stream, t.subs,
                            t.tiles, t.syrk, t.X, t.pi, t.F);
-    return hipGetLastError();
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[3], stream)) != hipSuccess) return e;
+    return hipSuccess;
 }
 
 }  // namespace scasm

@@ -25,6 +25,8 @@ struct DevTables {
     int64_t nsyrk = 0;
 };
 
-hipError_t launch_assemble_f64(const DevTables& t, hipStream_t stream);
+// Optional per-kernel events: ev[2k] before and ev[2k+1] after kernel k
+// (0 = TRSM, 1 = SYRK); null = no timing.
+hipError_t launch_assemble_f64(const DevTables& t, hipStream_t stream, hipEvent_t* ev);
 
 }  // namespace scasm

@@ -481,27 +481,37 @@ std::string build_plan(const SubdomainInput& in, const PlanOptions& opt, SubPlan
     }
     P.syrk_dense = (double)n * (double)m * (double)(m + 1);
 
-    // ---- GPU blocks: panels of width <= panel_width (multiples of 16 but the last)
-    const int32_t pw = std::max(16, (opt.panel_width / 16) * 16);
+    // ---- GPU blocks: uniform column ranges of width bs; pruned rows = rows
+    // >= the block end that hold a nonzero in any of the block's columns
+    const int32_t bs = std::max(16, (opt.panel_width / 16) * 16);
+    P.block_width = bs;
     P.block_of_row.assign(n, -1);
-    for (int32_t s = 0; s < P.nsuper; ++s) {
-        const int32_t f = P.sfirst[s];
-        const int32_t w = P.sfirst[s + 1] - f;
-        const int32_t ld = (int32_t)(P.srow_ptr[s + 1] - P.srow_ptr[s]);
-        const int32_t np = (w + pw - 1) / pw;
-        int32_t base = (w + np - 1) / np;
-        base = std::min(pw, (base + 15) / 16 * 16);
-        for (int32_t c0 = 0; c0 < w; c0 += base) {
-            BlockDesc b;
-            b.row0 = f + c0;
-            b.w = std::min(base, w - c0);
-            b.nbelow = ld - c0 - b.w;
-            b.ld = ld;
-            b.lval_off = P.spanel_off[s] + (int64_t)c0 * ld + c0;
-            b.rows_off = P.srow_ptr[s] + c0 + b.w;
-            for (int32_t i = b.row0; i < b.row0 + b.w; ++i) P.block_of_row[i] = (int32_t)P.blocks.size();
-            P.blocks.push_back(b);
+    {
+        std::vector<int32_t> mark(n, -1);
+        int64_t voff = 0;
+        for (int32_t c0 = 0; c0 < n; c0 += bs) {
+            const int32_t c1 = std::min(n, c0 + bs);
+            const int32_t b = (int32_t)P.blocks.size();
+            std::vector<int32_t> rows;
+            for (int32_t s = P.col2super[c0]; s < P.nsuper && P.sfirst[s] < c1; ++s)
+                for (int64_t q = P.srow_ptr[s]; q < P.srow_ptr[s + 1]; ++q) {
+                    const int32_t i = P.srows[q];
+                    if (i >= c1 && mark[i] != b) { mark[i] = b; rows.push_back(i); }
+                }
+            std::sort(rows.begin(), rows.end());
+            BlockDesc d;
+            d.row0 = c0;
+            d.w = c1 - c0;
+            d.nbelow = (int32_t)rows.size();
+            d.ld = d.w + d.nbelow;
+            d.lval_off = voff;
+            d.rows_off = (int64_t)P.brows.size();
+            voff += (int64_t)d.ld * d.w;
+            P.brows.insert(P.brows.end(), rows.begin(), rows.end());
+            for (int32_t i = c0; i < c1; ++i) P.block_of_row[i] = b;
+            P.blocks.push_back(d);
         }
+        P.bval = voff;
     }
     code = 0;
     return "";
@@ -572,6 +582,29 @@ int64_t factor_numeric(const SubPlan& P, const double* kvals, double* vals) {
         }
     }
     return -1;
+}
+
+void repack_blocks(const SubPlan& P, const double* vals, double* bvals) {
+    std::memset(bvals, 0, sizeof(double) * (size_t)P.bval);
+    std::vector<int32_t> pos(P.n, -1);
+    for (const BlockDesc& b : P.blocks) {
+        const int32_t c0 = b.row0, c1 = b.row0 + b.w;
+        for (int32_t q = 0; q < b.nbelow; ++q) pos[P.brows[b.rows_off + q]] = b.w + q;
+        for (int32_t i = c0; i < c1; ++i) pos[i] = i - c0;
+        double* panel = bvals + b.lval_off;
+        for (int32_t s = P.col2super[c0]; s < P.nsuper && P.sfirst[s] < c1; ++s) {
+            const int32_t f = P.sfirst[s];
+            const int64_t ld = P.srow_ptr[s + 1] - P.srow_ptr[s];
+            const int32_t* rows = P.srows.data() + P.srow_ptr[s];
+            const double* A = vals + P.spanel_off[s];
+            const int32_t j0 = std::max(c0, f), j1 = std::min(c1, P.sfirst[s + 1]);
+            for (int32_t j = j0; j < j1; ++j) {
+                const int32_t cj = j - f;
+                double* dst = panel + (size_t)(j - c0) * b.ld;
+                for (int64_t q = cj; q < ld; ++q) dst[pos[rows[q]]] = A[(size_t)cj * ld + q];
+            }
+        }
+    }
 }
 
 }  // namespace scasm

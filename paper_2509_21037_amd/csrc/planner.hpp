@@ -35,20 +35,23 @@ struct PlanOptions {
     int32_t leaf_nodes = 64;          // nested-dissection leaf size (nodes)
     int32_t relax_width = 64;         // relaxed amalgamation merges up to this width
     double relax_zero_frac = 0.5;     // ... if the merged zero fraction stays below this
-    int32_t panel_width = 64;         // GPU blocks: supernodes split into panels <= this
+    int32_t panel_width = 64;         // GPU factor block width (uniform blocks)
     int32_t staircase = 1;            // 0 = every column treated as pivot 0 ("orig")
 };
 
-// One GPU block: a panel of a supernode.  Its diagonal triangle is rows
-// [row0, row0+w) of columns [row0, row0+w); below it are `nbelow` rows whose
-// global indices start at rows_off in the plan's row array.
+// One GPU factor block (Sec. 3.2, factor splitting with pruning): the column
+// range [row0, row0 + w) of L, uniform width except the last.  Its dense
+// panel of (w + nbelow) x w values (column-major, leading dimension ld =
+// w + nbelow) holds the diagonal triangle in its first w rows and, below,
+// only the `nbelow` non-empty rows of L[row0 + w :, block] (pruning), whose
+// global indices start at rows_off in the block row array.
 struct BlockDesc {
     int32_t row0;
     int32_t w;
     int32_t nbelow;
-    int32_t ld;            // leading dimension of the supernode panel
-    int64_t lval_off;      // offset of L[row0][row0] in the subdomain's value array
-    int64_t rows_off;      // offset of the first below-row in the subdomain's row array
+    int32_t ld;
+    int64_t lval_off;      // offset of the panel in the subdomain's block-value array
+    int64_t rows_off;      // offset of the first pruned row in the block row array
 };
 
 struct SubPlan {
@@ -71,7 +74,10 @@ struct SubPlan {
     std::vector<int8_t> sign_sorted;           // [m]
     std::vector<int32_t> active;               // a(i) for i in [0, n)
     // GPU blocks
+    int32_t block_width = 64;
     std::vector<BlockDesc> blocks;
+    std::vector<int32_t> brows;                // pruned rows of every block
+    int64_t bval = 0;                          // values in all block panels
     std::vector<int32_t> block_of_row;         // row -> block index
     // statistics
     int64_t nnzL = 0;                          // exact
@@ -88,5 +94,10 @@ std::string build_plan(const SubdomainInput& in, const PlanOptions& opt, SubPlan
 // Numeric supernodal Cholesky into `vals` (plan.nval doubles).  Returns -1 on
 // success, else the permuted column whose pivot is not positive.
 int64_t factor_numeric(const SubPlan& plan, const double* kvals, double* vals);
+
+// Copies the supernodal factor values into the GPU block panels (plan.bval
+// doubles): the extraction of the dense diagonal blocks and of the non-empty
+// sub-diagonal rows.
+void repack_blocks(const SubPlan& plan, const double* vals, double* bvals);
 
 }  // namespace scasm

@@ -105,6 +105,44 @@ struct sc_plan_s {
     DevBuf<double> d_lval, d_X, d_F;
     bool factored = false, assembled = false;
     double trsm_u = 0, syrk_u = 0, trsm_d = 0, syrk_d = 0;
+    // kernel timing: event pairs per kernel, pending until read
+    bool timing = false;
+    struct PendingTiming { int kernel; hipEvent_t a, b; };
+    std::vector<PendingTiming> pending;
+    std::vector<hipEvent_t> event_pool;
+    double ms_sum[4] = {0, 0, 0, 0};
+    int64_t ms_count[4] = {0, 0, 0, 0};
+
+    hipError_t take_events(int k, hipEvent_t* out) {
+        for (int i = 0; i < k; ++i) {
+            if (event_pool.empty()) {
+                hipEvent_t e;
+                hipError_t err = hipEventCreate(&e);
+                if (err != hipSuccess) return err;
+                event_pool.push_back(e);
+            }
+            out[i] = event_pool.back();
+            event_pool.pop_back();
+        }
+        return hipSuccess;
+    }
+    hipError_t drain_timing(bool wait) {
+        std::vector<PendingTiming> keep;
+        for (auto& p : pending) {
+            if (!wait && hipEventQuery(p.b) != hipSuccess) { keep.push_back(p); continue; }
+            hipError_t e = hipEventSynchronize(p.b);
+            if (e != hipSuccess) return e;
+            float ms = 0;
+            e = hipEventElapsedTime(&ms, p.a, p.b);
+            if (e != hipSuccess) return e;
+            ms_sum[p.kernel] += ms;
+            ms_count[p.kernel] += 1;
+            event_pool.push_back(p.a);
+            event_pool.push_back(p.b);
+        }
+        pending.swap(keep);
+        return hipSuccess;
+    }
 
     int64_t device_bytes() const {
         return (int64_t)(d_subs.count * sizeof(SubDev) + d_tiles.count * sizeof(TileDev) +
@@ -118,6 +156,10 @@ struct sc_plan_s {
         d_lval.release(); d_X.release(); d_F.release();
         if (h_lval) (void)hipHostFree(h_lval);
         h_lval = nullptr;
+        for (auto& p : pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+        for (auto& e : event_pool) (void)hipEventDestroy(e);
+        pending.clear();
+        event_pool.clear();
     }
     DevTables tables() const {
         DevTables t;
@@ -211,8 +253,8 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
         for (int32_t I = 0; I < s.ntiles; ++I)
             for (int32_t J = 0; J <= I; ++J) P->h_syrk.push_back(SyrkItem{i, I, J, 0});
         blk += s.nblocks;
-        rows += (int64_t)sp.srows.size();
-        lv += sp.nval;
+        rows += (int64_t)sp.brows.size();
+        lv += sp.bval;
         colo += sp.m;
         fo += (int64_t)sp.m * sp.m;
         dual += sp.m;
@@ -263,7 +305,7 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
     for (int32_t i = 0; i < nsub; ++i) {
         const SubPlan& sp = P->plans[i];
         const SubDev& s = P->h_subs[i];
-        std::copy(sp.srows.begin(), sp.srows.end(), h_rows.begin() + s.rows_off);
+        std::copy(sp.brows.begin(), sp.brows.end(), h_rows.begin() + s.rows_off);
         std::copy(sp.piv.begin(), sp.piv.end(), h_piv.begin() + s.col_off);
         std::copy(sp.pi.begin(), sp.pi.end(), h_pi.begin() + s.col_off);
         std::copy(sp.sign_sorted.begin(), sp.sign_sorted.end(), h_sgn.begin() + s.col_off);
@@ -303,9 +345,25 @@ sc_status_t sc_factor(sc_plan_t P, const double* const* kreg_vals, void* stream,
     P->assembled = false;
     std::vector<int64_t> bad(P->nsub, -1);
     const int nthr = P->opt.n_threads > 0 ? P->opt.n_threads : omp_get_max_threads();
-#pragma omp parallel for schedule(dynamic, 1) num_threads(nthr)
-    for (int32_t i = 0; i < P->nsub; ++i)
-        bad[i] = factor_numeric(P->plans[i], kreg_vals[i], P->h_lval + P->h_subs[i].lval_off);
+    bool oom = false;
+#pragma omp parallel num_threads(nthr)
+    {
+        std::vector<double> sn;     // supernodal values of the subdomain being factored
+#pragma omp for schedule(dynamic, 1)
+        for (int32_t i = 0; i < P->nsub; ++i) {
+            const SubPlan& sp = P->plans[i];
+            try {
+                sn.resize((size_t)std::max<int64_t>(1, sp.nval));
+            } catch (const std::bad_alloc&) {
+#pragma omp atomic write
+                oom = true;
+                continue;
+            }
+            bad[i] = factor_numeric(sp, kreg_vals[i], sn.data());
+            if (bad[i] < 0) repack_blocks(sp, sn.data(), P->h_lval + P->h_subs[i].lval_off);
+        }
+    }
+    if (oom) return fail(SC_ERR_OOM, "host allocation failed in sc_factor");
     for (int32_t i = 0; i < P->nsub; ++i)
         if (bad[i] >= 0) {
             if (failed_sub) *failed_sub = i;
@@ -325,7 +383,17 @@ sc_status_t sc_assemble(sc_plan_t P, void* stream) {
     if (!P) return fail(SC_ERR_INVALID_ARG, "plan is NULL");
     if (!P->factored) return fail(SC_ERR_STATE, "sc_assemble before sc_factor");
     HIP_TRY(hipSetDevice(P->device));
-    HIP_TRY(launch_assemble_f64(P->tables(), (hipStream_t)stream));
+    hipEvent_t ev[4];
+    hipEvent_t* evp = nullptr;
+    if (P->timing) {
+        HIP_TRY(P->take_events(4, ev));
+        evp = ev;
+    }
+    HIP_TRY(launch_assemble_f64(P->tables(), (hipStream_t)stream, evp));
+    if (evp) {
+        P->pending.push_back({0, ev[0], ev[1]});
+        P->pending.push_back({1, ev[2], ev[3]});
+    }
     P->assembled = true;
     return SC_OK;
 }
@@ -450,6 +518,26 @@ sc_status_t sc_host_analyze(const sc_subdomain_desc_t* sd, const sc_options_t* o
                     for (int64_t q = c; q < ld; ++q) L_out[(int64_t)rows[q] * n + f + c] = A[c * ld + q];
             }
         }
+    }
+    return SC_OK;
+}
+
+sc_status_t sc_set_timing(sc_plan_t P, int32_t enable) {
+    g_last_error.clear();
+    if (!P) return fail(SC_ERR_INVALID_ARG, "plan is NULL");
+    P->timing = enable != 0;
+    return SC_OK;
+}
+
+sc_status_t sc_kernel_times(sc_plan_t P, double* ms, int64_t* counts, int32_t reset) {
+    g_last_error.clear();
+    if (!P) return fail(SC_ERR_INVALID_ARG, "plan is NULL");
+    HIP_TRY(hipSetDevice(P->device));
+    HIP_TRY(P->drain_timing(true));
+    for (int k = 0; k < 4; ++k) {
+        if (ms) ms[k] = P->ms_sum[k];
+        if (counts) counts[k] = P->ms_count[k];
+        if (reset) { P->ms_sum[k] = 0; P->ms_count[k] = 0; }
     }
     return SC_OK;
 }

@@ -17,7 +17,7 @@ STATUS_NAMES = {0: "SC_OK", 1: "SC_ERR_INVALID_ARG", 2: "SC_ERR_NOT_SPD", 3: "SC
 
 EXPORTED = ["sc_plan_create", "sc_factor", "sc_assemble", "sc_apply", "sc_apply_implicit",
             "sc_get_F", "sc_query", "sc_plan_stats", "sc_plan_destroy", "sc_host_analyze",
-            "sc_last_error"]
+            "sc_set_timing", "sc_kernel_times", "sc_last_error"]
 
 
 class ScasmError(RuntimeError):
@@ -75,6 +75,8 @@ def load():
         lib.sc_plan_destroy.argtypes = [vp]
         lib.sc_host_analyze.argtypes = [ctypes.POINTER(SubdomainDesc), ctypes.POINTER(Options), vp, vp, vp,
                                          vp, vp, ctypes.POINTER(HostInfo), ctypes.POINTER(i32)]
+        lib.sc_set_timing.argtypes = [vp, i32]
+        lib.sc_kernel_times.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), i32]
         lib.sc_last_error.argtypes = []
         lib.sc_last_error.restype = ctypes.c_char_p
         for name in EXPORTED[:-1]:
@@ -240,6 +242,18 @@ class Plan:
                                        ctypes.byref(su), ctypes.byref(td), ctypes.byref(sd), ctypes.byref(db)))
         return {"nsub": ns.value, "dual_total": dt.value, "trsm_useful": tu.value, "syrk_useful": su.value,
                 "trsm_dense": td.value, "syrk_dense": sd.value, "device_bytes": db.value}
+
+    def set_timing(self, enable: bool = True):
+        _check(self._lib.sc_set_timing(self._h, 1 if enable else 0))
+
+    KERNELS = ("trsm", "syrk", "apply", "apply_implicit")
+
+    def kernel_times(self, reset: bool = True) -> dict:
+        """Accumulated kernel milliseconds and launch counts (HIP events)."""
+        ms = (ctypes.c_double * 4)()
+        cnt = (ctypes.c_int64 * 4)()
+        _check(self._lib.sc_kernel_times(self._h, ms, cnt, 1 if reset else 0))
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(self.KERNELS)}
 
     def destroy(self):
         if self._h and self._h.value:
