@@ -9,6 +9,7 @@ namespace scasm {
 constexpr int kTile = 64;
 constexpr int kStripe = 16;
 constexpr int kMaxPanel = 64;      // GPU panel width bound the TRSM kernel is built for
+constexpr int kSyrkTile = 128;     // edge of an F output tile (two X column tiles)
 
 struct SubDev {
     int32_t n, m, nblocks, ntiles;
@@ -29,7 +30,7 @@ struct TileDev {
     int32_t start_block[4];   // first factor block each 16-column stripe visits
 };
 
-// One lower-triangle F tile (I >= J) of a subdomain.
+// One lower-triangle F output tile (I >= J, in units of kSyrkTile columns).
 struct SyrkItem {
     int32_t sub;
     int32_t I, J;

@@ -220,24 +220,26 @@ __global__ __launch_bounds__(256) void trsm_stair_f64(
 
 // ---------------------------------------------------------------------------
 // Staircase SYRK, F = X^T X (Sec. 3.3, output splitting): one workgroup per
-// lower 64 x 64 tile (I >= J) of the sorted F; its k-range starts at the first
-// pivot of tile I, which bounds the nonzero rows of both operands.  The
-// result is written straight to the original multiplier order,
+// lower 128 x 128 tile (I >= J) of the column-sorted F, each wavefront a
+// 64 x 64 quadrant (4 x 4 MFMA tiles).  The k-range starts at the first pivot
+// of tile I, which bounds the nonzero rows of both operands (rows of a slab
+// above its own first pivot are zero and are not stored).  X rows are staged
+// through double-buffered LDS, 16 rows per step, the next step prefetched into
+// registers.  The result goes straight to the original multiplier order:
 // F[pi(a), pi(b)] = F[pi(b), pi(a)] = sum_k X[k, a] X[k, b].
 // ---------------------------------------------------------------------------
+constexpr int kSyrkKC = 16;
+constexpr int kSyrkLd = kSyrkTile + 4;
+
 __global__ __launch_bounds__(256) void syrk_stair_f64(
     const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
     const SyrkItem* __restrict__ items, const double* __restrict__ X,
     const int32_t* __restrict__ pi, double* __restrict__ F)
 {
-    constexpr int KC = 16;
-    constexpr int LDP = kTile + 2;
-    __shared__ double sI[KC * LDP];
-    __shared__ double sJ[KC * LDP];
+    __shared__ double sI[2][kSyrkKC * kSyrkLd];
+    __shared__ double sJ[2][kSyrkKC * kSyrkLd];
     const SyrkItem it = items[blockIdx.x];
     const SubDev S = subs[it.sub];
-    const TileDev TI = tiles[S.tile_off + it.I];
-    const TileDev TJ = tiles[S.tile_off + it.J];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int g = lane >> 4;
@@ -247,40 +249,86 @@ __global__ __launch_bounds__(256) void syrk_stair_f64(
     const bool diag = it.I == it.J;
     const bool active = !(diag && wi < wj);
     const int n = S.n;
-    const double* __restrict__ XI = X + TI.x_off;
-    const double* __restrict__ XJ = X + TJ.x_off;
 
-    v4d acc[2][2];
+    // the two 64-column slabs of each 128-column tile (the second may not exist)
+    const double* xs[4];
+    int ks[4];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+    for (int q = 0; q < 4; ++q) {
+        const int t64 = 2 * (q < 2 ? it.I : it.J) + (q & 1);
+        if (t64 < S.ntiles) {
+            const TileDev& T = tiles[S.tile_off + t64];
+            xs[q] = X + T.x_off;
+            ks[q] = T.kstart;
+        } else {
+            xs[q] = nullptr;
+            ks[q] = INT_MAX;
+        }
+    }
+    const int kbeg = ks[0];
 
-    for (int kb = TI.kstart; kb < n; kb += KC) {
+    v4d acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+
+    // thread -> (row, column pair) of a 16 x 128 step, 4 pairs per operand
+    double2 rI[4], rJ[4];
+    auto load_step = [&](int kb) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int idx = threadIdx.x + 256 * e;
             const int rr = idx >> 6;
-            const int cc = idx & 63;
+            const int cc = 2 * (idx & 63);
+            const int half = cc >> 6;
+            const int c = cc & 63;
             const int k = kb + rr;
-            sI[rr * LDP + cc] = k < n ? XI[(int64_t)(k - TI.kstart) * kTile + cc] : 0.0;
-            sJ[rr * LDP + cc] = k < n ? XJ[(int64_t)(k - TJ.kstart) * kTile + cc] : 0.0;
+            const int qi = half, qj = 2 + half;
+            rI[e] = (k < n && k >= ks[qi]) ? *reinterpret_cast<const double2*>(xs[qi] + (int64_t)(k - ks[qi]) * kTile + c)
+                                           : make_double2(0.0, 0.0);
+            rJ[e] = (k < n && k >= ks[qj]) ? *reinterpret_cast<const double2*>(xs[qj] + (int64_t)(k - ks[qj]) * kTile + c)
+                                           : make_double2(0.0, 0.0);
         }
-        __syncthreads();
+    };
+    auto store_step = [&](int buf) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int idx = threadIdx.x + 256 * e;
+            const int rr = idx >> 6;
+            const int cc = 2 * (idx & 63);
+            *reinterpret_cast<double2*>(&sI[buf][rr * kSyrkLd + cc]) = rI[e];
+            *reinterpret_cast<double2*>(&sJ[buf][rr * kSyrkLd + cc]) = rJ[e];
+        }
+    };
+
+    const int nsteps = kbeg < n ? (n - kbeg + kSyrkKC - 1) / kSyrkKC : 0;
+    if (nsteps > 0) {
+        load_step(kbeg);
+        store_step(0);
+    }
+    __syncthreads();
+    for (int st = 0; st < nsteps; ++st) {
+        const int buf = st & 1;
+        if (st + 1 < nsteps) load_step(kbeg + (st + 1) * kSyrkKC);
         if (active) {
 #pragma unroll
-            for (int s = 0; s < KC / 4; ++s) {
-                const int kr = (4 * s + g) * LDP;
-                const double a0 = sI[kr + 32 * wi + j];
-                const double a1 = sI[kr + 32 * wi + 16 + j];
-                const double b0 = sJ[kr + 32 * wj + j];
-                const double b1 = sJ[kr + 32 * wj + 16 + j];
-                acc[0][0] = mfma_f64(a0, b0, acc[0][0]);
-                acc[0][1] = mfma_f64(a0, b1, acc[0][1]);
-                acc[1][0] = mfma_f64(a1, b0, acc[1][0]);
-                acc[1][1] = mfma_f64(a1, b1, acc[1][1]);
+            for (int s = 0; s < kSyrkKC / 4; ++s) {
+                const double* ai = &sI[buf][(4 * s + g) * kSyrkLd + 64 * wi + j];
+                const double* bj = &sJ[buf][(4 * s + g) * kSyrkLd + 64 * wj + j];
+                double a[4], b[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    a[t] = ai[16 * t];
+                    b[t] = bj[16 * t];
+                }
+#pragma unroll
+                for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < 4; ++tj) acc[ti][tj] = mfma_f64(a[ti], b[tj], acc[ti][tj]);
             }
         }
+        if (st + 1 < nsteps) store_step(buf ^ 1);
         __syncthreads();
     }
     if (!active) return;
@@ -288,13 +336,13 @@ __global__ __launch_bounds__(256) void syrk_stair_f64(
     const int32_t* __restrict__ pis = pi + S.col_off;
     double* __restrict__ Fs = F + S.F_off;
 #pragma unroll
-    for (int ti = 0; ti < 2; ++ti)
+    for (int ti = 0; ti < 4; ++ti)
 #pragma unroll
-        for (int tj = 0; tj < 2; ++tj)
+        for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int a = it.I * kTile + 32 * wi + 16 * ti + 4 * r + g;
-                const int b = it.J * kTile + 32 * wj + 16 * tj + j;
+                const int a = it.I * kSyrkTile + 64 * wi + 16 * ti + 4 * r + g;
+                const int b = it.J * kSyrkTile + 64 * wj + 16 * tj + j;
                 if (a < m && b < m && (!diag || a >= b)) {
                     const int64_t pa = pis[a];
                     const int64_t pb = pis[b];

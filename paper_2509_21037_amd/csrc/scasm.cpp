@@ -250,7 +250,8 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
             }
             P->h_tiles.push_back(T);
         }
-        for (int32_t I = 0; I < s.ntiles; ++I)
+        const int32_t nst = (sp.m + kSyrkTile - 1) / kSyrkTile;
+        for (int32_t I = 0; I < nst; ++I)
             for (int32_t J = 0; J <= I; ++J) P->h_syrk.push_back(SyrkItem{i, I, J, 0});
         blk += s.nblocks;
         rows += (int64_t)sp.brows.size();
