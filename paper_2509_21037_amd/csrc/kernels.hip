@@ -9,6 +9,7 @@
 // of k-slice r of the same tile used as a right-hand side.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cstdint>
 
@@ -354,6 +355,408 @@ __global__ __launch_bounds__(256) void syrk_stair_f64(
 }
 
 // ---------------------------------------------------------------------------
+// Mixed precision (FP64 diagonal solves; FP32 X, off-diagonal updates and
+// SYRK with FP32 MFMA and FP32 accumulation).
+//
+// v_mfma_f32_16x16x4f32 takes A and B in the same lane layout as the FP64
+// instruction, but its accumulator is laid out differently:
+//   C/D (16x16): lane l, register r holds D[4 (l / 16) + r][l % 16].
+// ---------------------------------------------------------------------------
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4f mfma_f32(float a, float b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// FP64 factor values -> FP32 copy (round to nearest even).
+__global__ __launch_bounds__(256) void convert_f64_f32(const double* __restrict__ a, float* __restrict__ b,
+                                                       int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) b[i] = (float)a[i];
+}
+
+constexpr int kLdsLdF = 64 + 4;           // LDS leading dimension (floats) of an FP32 chunk
+
+__device__ __forceinline__ void load_chunk_f32(const float* __restrict__ panel, int ld, int nrows, int w,
+                                               int r0, float (&reg)[16]) {
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+        const int e = threadIdx.x + 256 * it;
+        const int row = e & 63;
+        const int k = e >> 6;
+        const int gr = r0 + row;
+        float v = 0.0f;
+        if (k < w && gr < nrows) v = panel[(int64_t)k * ld + gr];
+        reg[it] = -v;
+    }
+}
+
+__global__ __launch_bounds__(256) void trsm_stair_mixed(
+    const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
+    const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows,
+    const double* __restrict__ lval, const float* __restrict__ lval32, const int32_t* __restrict__ piv,
+    const int8_t* __restrict__ sgn, float* __restrict__ X)
+{
+    __shared__ double sL[64 * kLdsLd];        // FP64 diagonal block, reused as the FP32 chunk
+    __shared__ double sRd[64];
+    float* sLf = reinterpret_cast<float*>(sL);
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int g = lane >> 4;
+    const int j = lane & 15;
+    const TileDev T = tiles[blockIdx.x];
+    const SubDev S = subs[T.sub];
+    const int n = S.n;
+    const int kstart = T.kstart;
+    float* __restrict__ Xs = X + T.x_off;
+    const int col = wv * kStripe + j;
+    const int64_t cbase = S.col_off + (int64_t)T.tile * kTile;
+
+    const int nrows = n - kstart;
+    for (int r = g; r < nrows; r += 4) Xs[(int64_t)r * kTile + col] = 0.0f;
+    __threadfence_block();
+    if (g == 0 && col < T.ncols)
+        Xs[(int64_t)(piv[cbase + col] - kstart) * kTile + col] = (float)sgn[cbase + col];
+    __syncthreads();
+
+    const BlockDev* __restrict__ B = blocks + S.blk_off;
+    const int32_t* __restrict__ R = rows + S.rows_off;
+    const double* __restrict__ L = lval + S.lval_off;
+    const float* __restrict__ L32 = lval32 + S.lval_off;
+    const int my_start = tiles[blockIdx.x].start_block[wv];
+    const int first_block = tiles[blockIdx.x].start_block[0];
+
+    double pre[16];
+    float pref[16];
+    for (int b = first_block; b < S.nblocks; ++b) {
+        const BlockDev bd = B[b];
+        const int w = bd.w;
+        const int ld = bd.ld;
+        const int row0 = bd.row0;
+        const int nb = bd.nbelow;
+        const double* __restrict__ Lb = L + bd.lval_off;
+        const float* __restrict__ Lb32 = L32 + bd.lval_off;
+        const bool act = b >= my_start;
+
+        load_chunk(Lb, ld, w, w, 0, false, pre);
+        __syncthreads();
+        store_chunk(sL, pre);
+        __syncthreads();
+        if (threadIdx.x < 64) sRd[threadIdx.x] = threadIdx.x < w ? 1.0 / sL[threadIdx.x * (kLdsLd + 1)] : 0.0;
+        if (nb > 0) load_chunk_f32(Lb32, ld, w + nb, w, w, pref);
+        __syncthreads();
+
+        v4d xr[4];
+        float xb[4][4];
+        if (act) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = 16 * t + 4 * r + g;
+                    const int row = row0 + i;
+                    xr[t][r] = (i < w && row >= kstart) ? (double)Xs[(int64_t)(row - kstart) * kTile + col] : 0.0;
+                }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if (16 * t < w) {
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) {
+                        if (16 * t + k < w) {
+                            const int gk = k & 3;
+                            const int rk = k >> 2;
+                            const double xk_own = xr[t][rk] * sRd[16 * t + k];
+                            if (g == gk) xr[t][rk] = xk_own;
+                            const double xk = __shfl(xk_own, j + 16 * gk, 64);
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                const int ii = 4 * r + g;
+                                const double lik = sL[(16 * t + k) * kLdsLd + 16 * t + ii];
+                                if (ii > k) xr[t][r] -= lik * xk;
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int t2 = t + 1; t2 < 4; ++t2) {
+                        if (16 * t2 < w) {
+#pragma unroll
+                            for (int s = 0; s < 4; ++s) {
+                                const double a = -sL[(16 * t + 4 * s + g) * kLdsLd + 16 * t2 + j];
+                                xr[t2] = mfma_f64(a, xr[t][s], xr[t2]);
+                            }
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = 16 * t + 4 * r + g;
+                    const int row = row0 + i;
+                    xb[t][r] = (float)xr[t][r];
+                    if (i < w && row >= kstart) Xs[(int64_t)(row - kstart) * kTile + col] = xb[t][r];
+                }
+        }
+
+        const int32_t* __restrict__ rw = R + bd.rows_off;
+        for (int q0 = 0; q0 < nb; q0 += 64) {
+            __syncthreads();
+#pragma unroll
+            for (int it = 0; it < 16; ++it) {
+                const int e = threadIdx.x + 256 * it;
+                sLf[(e >> 6) * kLdsLdF + (e & 63)] = pref[it];
+            }
+            if (q0 + 64 < nb) load_chunk_f32(Lb32, ld, w + nb, w, w + q0 + 64, pref);
+            __syncthreads();
+            if (!act) continue;
+            v4f acc[4];
+            int32_t off[4][4];
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int q = q0 + 16 * rt + 4 * g + r;
+                    off[rt][r] = q < nb ? (rw[q] - kstart) * kTile + col : -1;
+                    acc[rt][r] = off[rt][r] >= 0 ? Xs[off[rt][r]] : 0.0f;
+                }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if (16 * t < w) {
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const float* sk = sLf + (16 * t + 4 * s + g) * kLdsLdF + j;
+#pragma unroll
+                        for (int rt = 0; rt < 4; ++rt) acc[rt] = mfma_f32(sk[16 * rt], xb[t][s], acc[rt]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (off[rt][r] >= 0) Xs[off[rt][r]] = acc[rt][r];
+        }
+    }
+}
+
+// FP32 staircase SYRK: as syrk_stair_f64 with FP32 X, FP32 MFMA and FP32
+// accumulation, 32 rows per LDS step; F stored FP32.
+constexpr int kSyrkKCF = 32;
+constexpr int kSyrkLdF = kSyrkTile + 4;
+
+__global__ __launch_bounds__(256) void syrk_stair_f32(
+    const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
+    const SyrkItem* __restrict__ items, const float* __restrict__ X,
+    const int32_t* __restrict__ pi, float* __restrict__ F)
+{
+    __shared__ float sI[2][kSyrkKCF * kSyrkLdF];
+    __shared__ float sJ[2][kSyrkKCF * kSyrkLdF];
+    const SyrkItem it = items[blockIdx.x];
+    const SubDev S = subs[it.sub];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int g = lane >> 4;
+    const int j = lane & 15;
+    const int wi = wv >> 1;
+    const int wj = wv & 1;
+    const bool diag = it.I == it.J;
+    const bool active = !(diag && wi < wj);
+    const int n = S.n;
+
+    const float* xs[4];
+    int ks[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int t64 = 2 * (q < 2 ? it.I : it.J) + (q & 1);
+        if (t64 < S.ntiles) {
+            const TileDev& T = tiles[S.tile_off + t64];
+            xs[q] = X + T.x_off;
+            ks[q] = T.kstart;
+        } else {
+            xs[q] = nullptr;
+            ks[q] = INT_MAX;
+        }
+    }
+    const int kbeg = ks[0];
+
+    v4f acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
+
+    // thread -> (row, 4 columns) of a 32 x 128 step, 4 per operand
+    float4 rI[4], rJ[4];
+    auto load_step = [&](int kb) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int idx = threadIdx.x + 256 * e;
+            const int rr = idx >> 5;
+            const int cc = 4 * (idx & 31);
+            const int half = cc >> 6;
+            const int c = cc & 63;
+            const int k = kb + rr;
+            const int qi = half, qj = 2 + half;
+            rI[e] = (k < n && k >= ks[qi]) ? *reinterpret_cast<const float4*>(xs[qi] + (int64_t)(k - ks[qi]) * kTile + c)
+                                           : make_float4(0.f, 0.f, 0.f, 0.f);
+            rJ[e] = (k < n && k >= ks[qj]) ? *reinterpret_cast<const float4*>(xs[qj] + (int64_t)(k - ks[qj]) * kTile + c)
+                                           : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    };
+    auto store_step = [&](int buf) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int idx = threadIdx.x + 256 * e;
+            const int rr = idx >> 5;
+            const int cc = 4 * (idx & 31);
+            *reinterpret_cast<float4*>(&sI[buf][rr * kSyrkLdF + cc]) = rI[e];
+            *reinterpret_cast<float4*>(&sJ[buf][rr * kSyrkLdF + cc]) = rJ[e];
+        }
+    };
+
+    const int nsteps = kbeg < n ? (n - kbeg + kSyrkKCF - 1) / kSyrkKCF : 0;
+    if (nsteps > 0) {
+        load_step(kbeg);
+        store_step(0);
+    }
+    __syncthreads();
+    for (int st = 0; st < nsteps; ++st) {
+        const int buf = st & 1;
+        if (st + 1 < nsteps) load_step(kbeg + (st + 1) * kSyrkKCF);
+        if (active) {
+#pragma unroll
+            for (int s = 0; s < kSyrkKCF / 4; ++s) {
+                const float* ai = &sI[buf][(4 * s + g) * kSyrkLdF + 64 * wi + j];
+                const float* bj = &sJ[buf][(4 * s + g) * kSyrkLdF + 64 * wj + j];
+                float a[4], b[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    a[t] = ai[16 * t];
+                    b[t] = bj[16 * t];
+                }
+#pragma unroll
+                for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < 4; ++tj) acc[ti][tj] = mfma_f32(a[ti], b[tj], acc[ti][tj]);
+            }
+        }
+        if (st + 1 < nsteps) store_step(buf ^ 1);
+        __syncthreads();
+    }
+    if (!active) return;
+    const int m = S.m;
+    const int32_t* __restrict__ pis = pi + S.col_off;
+    float* __restrict__ Fs = F + S.F_off;
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int a = it.I * kSyrkTile + 64 * wi + 16 * ti + 4 * g + r;
+                const int b = it.J * kSyrkTile + 64 * wj + 16 * tj + j;
+                if (a < m && b < m && (!diag || a >= b)) {
+                    const int64_t pa = pis[a];
+                    const int64_t pb = pis[b];
+                    const float v = acc[ti][tj][r];
+                    Fs[pa + pb * m] = v;
+                    Fs[pb + pa * m] = v;
+                }
+            }
+}
+
+// ---------------------------------------------------------------------------
+// Explicit apply, q_i = F_i p_i (Sec. 2.2, eq. (12)), all subdomains at once.
+// F_i is symmetric and stored column-major in the original multiplier order,
+// so q[c] = sum_r F[r, c] p[r] is a dot product with one contiguous column.
+// One workgroup per 32 columns of one subdomain; each wavefront reduces 8
+// columns, reading them with 16-byte loads (FP64 F) or 16-byte loads of four
+// values (FP32 F), accumulating in FP64.
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(256) void apply_gemv(
+    const SubDev* __restrict__ subs, const int2* __restrict__ items, const T* __restrict__ F,
+    const double* __restrict__ p, double* __restrict__ q)
+{
+    const int2 it = items[blockIdx.x];          // (subdomain, first column)
+    const SubDev S = subs[it.x];
+    const int m = S.m;
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const T* __restrict__ Fs = F + S.F_off;
+    const double* __restrict__ ps = p + S.dual_off;
+    constexpr int V = 16 / sizeof(T);            // values per 16-byte load
+    const int c0 = it.y + 8 * wv;
+    double sum[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) sum[c] = 0.0;
+    // main part: aligned vector loads when the column start allows it
+    const bool vec = (m % V) == 0;
+    if (vec) {
+        for (int r = V * lane; r < m; r += 64 * V) {
+            double pv[V];
+#pragma unroll
+            for (int e = 0; e < V; ++e) pv[e] = ps[r + e];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const int cc = c0 + c;
+                if (cc < m) {
+                    const T* col = Fs + (int64_t)cc * m + r;
+                    if constexpr (V == 2) {
+                        const double2 f = *reinterpret_cast<const double2*>(col);
+                        sum[c] += f.x * pv[0] + f.y * pv[1];
+                    } else {
+                        const float4 f = *reinterpret_cast<const float4*>(col);
+                        sum[c] += (double)f.x * pv[0] + (double)f.y * pv[1] + (double)f.z * pv[2] +
+                                  (double)f.w * pv[3];
+                    }
+                }
+            }
+        }
+    } else {
+        for (int r = lane; r < m; r += 64) {
+            const double pr = ps[r];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const int cc = c0 + c;
+                if (cc < m) sum[c] += (double)Fs[(int64_t)cc * m + r] * pr;
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        double v = sum[c];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        sum[c] = v;
+    }
+    if (lane < 8 && c0 + lane < m) {
+        double v = 0.0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            if (c == lane) v = sum[c];
+        q[S.dual_off + c0 + lane] = v;
+    }
+}
+
+hipError_t launch_apply(const DevTables& t, const double* p, double* q, hipStream_t stream, hipEvent_t* ev) {
+    hipError_t e = hipSuccess;
+    if (ev && (e = hipEventRecord(ev[0], stream)) != hipSuccess) return e;
+    if (t.napply > 0) {
+        if (t.F32)
+            hipLaunchKernelGGL(apply_gemv<float>, dim3((unsigned)t.napply), dim3(256), 0, stream, t.subs,
+                               t.apply_items, (const float*)t.F32, p, q);
+        else
+            hipLaunchKernelGGL(apply_gemv<double>, dim3((unsigned)t.napply), dim3(256), 0, stream, t.subs,
+                               t.apply_items, (const double*)t.F, p, q);
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[1], stream)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
 hipError_t launch_assemble_f64(const DevTables& t, hipStream_t stream, hipEvent_t* ev) {
     hipError_t e = hipSuccess;
     if (ev && (e = hipEventRecord(ev[0], stream)) != hipSuccess) return e;
@@ -366,6 +769,30 @@ hipError_t launch_assemble_f64(const DevTables& t, hipStream_t stream, hipEvent_
     if (t.nsyrk > 0)
         hipLaunchKernelGGL(syrk_stair_f64, dim3((unsigned)t.nsyrk), dim3(256), 0, stream, t.subs,
                            t.tiles, t.syrk, t.X, t.pi, t.F);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[3], stream)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+hipError_t launch_convert_f32(const double* a, float* b, int64_t n, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(convert_f64_f32, dim3((unsigned)blocks), dim3(256), 0, stream, a, b, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_assemble_mixed(const DevTables& t, hipStream_t stream, hipEvent_t* ev) {
+    hipError_t e = hipSuccess;
+    if (ev && (e = hipEventRecord(ev[0], stream)) != hipSuccess) return e;
+    if (t.ntiles > 0)
+        hipLaunchKernelGGL(trsm_stair_mixed, dim3((unsigned)t.ntiles), dim3(256), 0, stream, t.subs,
+                           t.tiles, t.blocks, t.rows, t.lval, t.lval32, t.piv, t.sgn, t.X32);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[1], stream)) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[2], stream)) != hipSuccess) return e;
+    if (t.nsyrk > 0)
+        hipLaunchKernelGGL(syrk_stair_f32, dim3((unsigned)t.nsyrk), dim3(256), 0, stream, t.subs,
+                           t.tiles, t.syrk, t.X32, t.pi, t.F32);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[3], stream)) != hipSuccess) return e;
     return hipSuccess;

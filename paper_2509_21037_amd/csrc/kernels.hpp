@@ -21,12 +21,23 @@ struct DevTables {
     float* X32 = nullptr;
     double* F = nullptr;
     float* F32 = nullptr;
+    const int2* apply_items = nullptr;     // (subdomain, first column) per GEMV workgroup
     int64_t ntiles = 0;
     int64_t nsyrk = 0;
+    int64_t napply = 0;
 };
 
 // Optional per-kernel events: ev[2k] before and ev[2k+1] after kernel k
 // (0 = TRSM, 1 = SYRK); null = no timing.
 hipError_t launch_assemble_f64(const DevTables& t, hipStream_t stream, hipEvent_t* ev);
+
+// Mixed precision: FP64 factor -> FP32 copy, and the assembly with FP64
+// diagonal solves, FP32 X / updates / SYRK and FP32 F.
+hipError_t launch_convert_f32(const double* a, float* b, int64_t n, hipStream_t stream);
+hipError_t launch_assemble_mixed(const DevTables& t, hipStream_t stream, hipEvent_t* ev);
+
+// q = F p for every subdomain (FP32 F when t.F32 is set, else FP64 F);
+// optional events ev[0] before, ev[1] after.
+hipError_t launch_apply(const DevTables& t, const double* p, double* q, hipStream_t stream, hipEvent_t* ev);
 
 }  // namespace scasm

@@ -93,6 +93,7 @@ struct sc_plan_s {
     std::vector<TileDev> h_tiles;
     std::vector<BlockDev> h_blocks;
     std::vector<SyrkItem> h_syrk;
+    std::vector<int2> h_apply;
     int64_t nval_total = 0, nrows_total = 0, ncol_total = 0, X_total = 0, F_total = 0, dual_total = 0;
     double* h_lval = nullptr;                 // pinned
     // device
@@ -100,9 +101,12 @@ struct sc_plan_s {
     DevBuf<TileDev> d_tiles;
     DevBuf<BlockDev> d_blocks;
     DevBuf<SyrkItem> d_syrk;
+    DevBuf<int2> d_apply;
     DevBuf<int32_t> d_rows, d_piv, d_pi;
     DevBuf<int8_t> d_sgn;
     DevBuf<double> d_lval, d_X, d_F;
+    DevBuf<float> d_lval32, d_X32, d_F32;
+    bool mixed = false;
     bool factored = false, assembled = false;
     double trsm_u = 0, syrk_u = 0, trsm_d = 0, syrk_d = 0;
     // kernel timing: event pairs per kernel, pending until read
@@ -147,13 +151,16 @@ struct sc_plan_s {
     int64_t device_bytes() const {
         return (int64_t)(d_subs.count * sizeof(SubDev) + d_tiles.count * sizeof(TileDev) +
                          d_blocks.count * sizeof(BlockDev) + d_syrk.count * sizeof(SyrkItem) +
+                         d_apply.count * sizeof(int2) +
                          (d_rows.count + d_piv.count + d_pi.count) * 4 + d_sgn.count +
-                         (d_lval.count + d_X.count + d_F.count) * 8);
+                         (d_lval.count + d_X.count + d_F.count) * 8 +
+                         (d_lval32.count + d_X32.count + d_F32.count) * 4);
     }
     void release() {
-        d_subs.release(); d_tiles.release(); d_blocks.release(); d_syrk.release();
+        d_subs.release(); d_tiles.release(); d_blocks.release(); d_syrk.release(); d_apply.release();
         d_rows.release(); d_piv.release(); d_pi.release(); d_sgn.release();
         d_lval.release(); d_X.release(); d_F.release();
+        d_lval32.release(); d_X32.release(); d_F32.release();
         if (h_lval) (void)hipHostFree(h_lval);
         h_lval = nullptr;
         for (auto& p : pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
@@ -166,8 +173,11 @@ struct sc_plan_s {
         t.subs = d_subs.p; t.tiles = d_tiles.p; t.blocks = d_blocks.p; t.rows = d_rows.p;
         t.lval = d_lval.p; t.piv = d_piv.p; t.pi = d_pi.p; t.sgn = d_sgn.p; t.syrk = d_syrk.p;
         t.X = d_X.p; t.F = d_F.p;
+        t.lval32 = d_lval32.p; t.X32 = d_X32.p; t.F32 = d_F32.p;
+        t.apply_items = d_apply.p;
         t.ntiles = (int64_t)h_tiles.size();
         t.nsyrk = (int64_t)h_syrk.size();
+        t.napply = (int64_t)h_apply.size();
         return t;
     }
 };
@@ -190,8 +200,7 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
         const std::string err = to_plan_options(P->opt, po);
         if (!err.empty()) return fail(SC_ERR_INVALID_ARG, err);
     }
-    if (P->opt.precision == SC_PREC_MIXED)
-        return fail(SC_ERR_UNSUPPORTED, "mixed precision is not built yet");
+    P->mixed = P->opt.precision == SC_PREC_MIXED;
     P->nsub = nsub;
     P->plans.resize(nsub);
     P->kval_count.resize(nsub);
@@ -250,6 +259,7 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
             }
             P->h_tiles.push_back(T);
         }
+        for (int32_t c = 0; c < sp.m; c += 32) P->h_apply.push_back(make_int2(i, c));
         const int32_t nst = (sp.m + kSyrkTile - 1) / kSyrkTile;
         for (int32_t I = 0; I < nst; ++I)
             for (int32_t J = 0; J <= I; ++J) P->h_syrk.push_back(SyrkItem{i, I, J, 0});
@@ -257,7 +267,7 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
         rows += (int64_t)sp.brows.size();
         lv += sp.bval;
         colo += sp.m;
-        fo += (int64_t)sp.m * sp.m;
+        fo += ((int64_t)sp.m * sp.m + 3) / 4 * 4;      // 32-byte aligned F blocks
         dual += sp.m;
         P->h_subs.push_back(s);
         P->trsm_u += sp.trsm_useful;
@@ -287,13 +297,20 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
     ALLOC(p->d_tiles, p->h_tiles.size());
     ALLOC(p->d_blocks, p->h_blocks.size());
     ALLOC(p->d_syrk, p->h_syrk.size());
+    ALLOC(p->d_apply, p->h_apply.size());
     ALLOC(p->d_rows, (size_t)rows);
     ALLOC(p->d_piv, (size_t)colo);
     ALLOC(p->d_pi, (size_t)colo);
     ALLOC(p->d_sgn, (size_t)colo);
     ALLOC(p->d_lval, (size_t)lv);
-    ALLOC(p->d_X, (size_t)xo);
-    ALLOC(p->d_F, (size_t)fo);
+    if (p->mixed) {
+        ALLOC(p->d_lval32, (size_t)lv);
+        ALLOC(p->d_X32, (size_t)xo);
+        ALLOC(p->d_F32, (size_t)fo);
+    } else {
+        ALLOC(p->d_X, (size_t)xo);
+        ALLOC(p->d_F, (size_t)fo);
+    }
 #undef ALLOC
     {
         hipError_t e = hipHostMalloc((void**)&p->h_lval, std::max<size_t>(1, (size_t)lv) * sizeof(double),
@@ -320,6 +337,7 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
     if (e == hipSuccess) e = up(p->d_tiles.p, p->h_tiles.data(), p->h_tiles.size() * sizeof(TileDev));
     if (e == hipSuccess) e = up(p->d_blocks.p, p->h_blocks.data(), p->h_blocks.size() * sizeof(BlockDev));
     if (e == hipSuccess) e = up(p->d_syrk.p, p->h_syrk.data(), p->h_syrk.size() * sizeof(SyrkItem));
+    if (e == hipSuccess) e = up(p->d_apply.p, p->h_apply.data(), p->h_apply.size() * sizeof(int2));
     if (e == hipSuccess) e = up(p->d_rows.p, h_rows.data(), h_rows.size() * 4);
     if (e == hipSuccess) e = up(p->d_piv.p, h_piv.data(), h_piv.size() * 4);
     if (e == hipSuccess) e = up(p->d_pi.p, h_pi.data(), h_pi.size() * 4);
@@ -375,6 +393,7 @@ sc_status_t sc_factor(sc_plan_t P, const double* const* kreg_vals, void* stream,
     if (P->nval_total > 0)
         HIP_TRY(hipMemcpyAsync(P->d_lval.p, P->h_lval, (size_t)P->nval_total * sizeof(double),
                                hipMemcpyHostToDevice, st));
+    if (P->mixed) HIP_TRY(launch_convert_f32(P->d_lval.p, P->d_lval32.p, P->nval_total, st));
     P->factored = true;
     return SC_OK;
 }
@@ -390,7 +409,8 @@ sc_status_t sc_assemble(sc_plan_t P, void* stream) {
         HIP_TRY(P->take_events(4, ev));
         evp = ev;
     }
-    HIP_TRY(launch_assemble_f64(P->tables(), (hipStream_t)stream, evp));
+    if (P->mixed) HIP_TRY(launch_assemble_mixed(P->tables(), (hipStream_t)stream, evp));
+    else HIP_TRY(launch_assemble_f64(P->tables(), (hipStream_t)stream, evp));
     if (evp) {
         P->pending.push_back({0, ev[0], ev[1]});
         P->pending.push_back({1, ev[2], ev[3]});
@@ -400,10 +420,21 @@ sc_status_t sc_assemble(sc_plan_t P, void* stream) {
 }
 
 sc_status_t sc_apply(sc_plan_t P, const double* p_dev, double* q_dev, void* stream) {
-    (void)p_dev; (void)q_dev; (void)stream;
+    g_last_error.clear();
     if (!P) return fail(SC_ERR_INVALID_ARG, "plan is NULL");
     if (!P->assembled) return fail(SC_ERR_STATE, "sc_apply before sc_assemble");
-    return fail(SC_ERR_UNSUPPORTED, "sc_apply is not built yet");
+    if (P->dual_total > 0 && (!p_dev || !q_dev)) return fail(SC_ERR_INVALID_ARG, "p or q is NULL");
+    if (P->dual_total > 0 && p_dev == q_dev) return fail(SC_ERR_INVALID_ARG, "p and q must not alias");
+    HIP_TRY(hipSetDevice(P->device));
+    hipEvent_t ev[2];
+    hipEvent_t* evp = nullptr;
+    if (P->timing) {
+        HIP_TRY(P->take_events(2, ev));
+        evp = ev;
+    }
+    HIP_TRY(launch_apply(P->tables(), p_dev, q_dev, (hipStream_t)stream, evp));
+    if (evp) P->pending.push_back({2, ev[0], ev[1]});
+    return SC_OK;
 }
 
 sc_status_t sc_apply_implicit(sc_plan_t P, const double* p_dev, double* q_dev, void* stream) {
@@ -423,11 +454,28 @@ sc_status_t sc_get_F(sc_plan_t P, int32_t sub, double* out, int32_t ld, int32_t 
     if (!out || ld < s.m) return fail(SC_ERR_INVALID_ARG, "bad output buffer or ld");
     HIP_TRY(hipSetDevice(P->device));
     hipStream_t st = (hipStream_t)stream;
-    const double* src = P->d_F.p + s.F_off;
-    HIP_TRY(hipMemcpy2DAsync(out, (size_t)ld * sizeof(double), src, (size_t)s.m * sizeof(double),
-                             (size_t)s.m * sizeof(double), (size_t)s.m,
-                             on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+    if (!P->mixed) {
+        const double* src = P->d_F.p + s.F_off;
+        HIP_TRY(hipMemcpy2DAsync(out, (size_t)ld * sizeof(double), src, (size_t)s.m * sizeof(double),
+                                 (size_t)s.m * sizeof(double), (size_t)s.m,
+                                 on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        return SC_OK;
+    }
+    // FP32-stored F: copy to the host, widen, and place with the caller's ld
+    std::vector<float> tmp((size_t)s.m * s.m);
+    HIP_TRY(hipMemcpyAsync(tmp.data(), P->d_F32.p + s.F_off, tmp.size() * sizeof(float), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    std::vector<double> wide((size_t)ld * s.m, 0.0);
+    for (int64_t c = 0; c < s.m; ++c)
+        for (int64_t r = 0; r < s.m; ++r) wide[(size_t)c * ld + r] = (double)tmp[(size_t)c * s.m + r];
+    if (on_device) {
+        HIP_TRY(hipMemcpyAsync(out, wide.data(), wide.size() * sizeof(double), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    } else {
+        for (int64_t c = 0; c < s.m; ++c)
+            std::copy(wide.begin() + c * ld, wide.begin() + c * ld + s.m, out + c * ld);
+    }
     return SC_OK;
 }
 

@@ -182,3 +182,77 @@ def test_full_elasticity_workload_sampled():
         sel = np.sort(np.random.default_rng(i).choice(s.m, size=min(128, s.m), replace=False))
         F = plan.get_F(i)
         assert oracle.relF(F[np.ix_(sel, sel)], oracle.schur(s, sel=sel)) <= TOL_FP64
+
+
+def _dual_vectors(plan, subs, seed=0):
+    import torch
+    st = plan.stats()
+    p = torch.from_numpy(scgen.splitmix64_uniform(seed, st["dual_total"])).cuda()
+    q = torch.zeros_like(p)
+    return p, q
+
+
+@pytest.mark.parametrize("cfg,count", [(1, 1), (2, 3), (3, 5)])
+def test_explicit_apply_matches_dense_product(cfg, count):
+    subs = scgen.config_subdomains(cfg, count=count)
+    odd = scgen.box_subdomain("heat", (3, 4, 2), 0.25, seed=3)
+    odd = odd.with_columns(odd.dof[:33], odd.sign[:33])          # odd m: unaligned column starts
+    subs = subs + [odd]
+    plan = _assemble(subs)
+    p, q = _dual_vectors(plan, subs)
+    plan.apply(p, q)
+    qh = q.cpu().numpy()
+    ph = p.cpu().numpy()
+    for i, s in enumerate(subs):
+        o = plan.query(i)["dual_offset"]
+        ref = oracle.schur(s) @ ph[o:o + s.m]
+        got = qh[o:o + s.m]
+        assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref), i
+
+
+def test_apply_state_and_alias_errors():
+    torch = _torch_init()
+    s = scgen.config_subdomains(1)[0]
+    plan = P.Plan([s])
+    plan.factor()
+    p = torch.zeros(s.m, dtype=torch.float64, device="cuda")
+    with pytest.raises(P.ScasmError) as e:
+        plan.apply(p, torch.zeros_like(p))
+    assert e.value.status == P.SC_ERR_STATE
+    plan.assemble()
+    with pytest.raises(P.ScasmError) as e:
+        plan.apply(p, p)
+    assert e.value.status == P.SC_ERR_INVALID_ARG
+
+
+# ---------------------------------------------------------------- mixed precision
+
+TOL_MIXED = 1e-5
+
+
+@pytest.mark.parametrize("cfg,count", [(1, 1), (2, 3), (3, 6)])
+def test_mixed_precision_matches_oracle(cfg, count):
+    subs = scgen.config_subdomains(cfg, count=count)
+    plan = _assemble(subs, precision="mixed")
+    for i, s in enumerate(subs):
+        F = plan.get_F(i)
+        assert np.array_equal(F, F.T)
+        if s.n <= 3000:
+            e = oracle.relF(F, oracle.schur(s))
+        else:
+            sel = np.sort(np.random.default_rng(i).choice(s.m, size=192, replace=False))
+            e = oracle.relF(F[np.ix_(sel, sel)], oracle.schur(s, sel=sel))
+        assert e <= TOL_MIXED, (i, s.elems, e)
+
+
+def test_mixed_apply_reads_fp32_accumulates_fp64():
+    subs = scgen.config_subdomains(3, count=3)
+    plan = _assemble(subs, precision="mixed")
+    p, q = _dual_vectors(plan, subs, seed=7)
+    plan.apply(p, q)
+    qh, ph = q.cpu().numpy(), p.cpu().numpy()
+    for i, s in enumerate(subs):
+        o = plan.query(i)["dual_offset"]
+        F = plan.get_F(i)                      # the stored FP32 values, widened
+        ref = F @ ph[o:o + s.m]
+        assert np.linalg.norm(qh[o:o + s.m] - ref) <= 1e-13 * np.linalg.norm(ref)
