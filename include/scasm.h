@@ -146,6 +146,28 @@ sc_status_t sc_apply(sc_plan_t plan, const double* p_dev, double* q_dev, void* s
  * sc_apply.  SC_ERR_STATE before sc_factor. */
 sc_status_t sc_apply_implicit(sc_plan_t plan, const double* p_dev, double* q_dev, void* stream);
 
+/* Solution stage: projected conjugate gradients (Sec. 2.1: the dual problem
+ * (7), solved by PCPG, applying F once per iteration) on every subdomain's own
+ * dual problem, e = 0, identity preconditioner, FP64 vectors and scalars, F
+ * applied as in sc_apply (FP32-stored F read as FP32, accumulated in FP64):
+ *   lambda_0 = 0, r_0 = d, w_0 = P r_0, p_0 = w_0, P = I - G (G^T G)^{-1} G^T,
+ *   q = F p, alpha = (w.w)/(p.q), lambda += alpha p, r -= alpha q,
+ *   w' = P r, beta = (w'.w')/(w.w), p = w' + beta p.
+ * G_i = B_i R_i is formed by the library from the kernel basis:
+ *   R_host      [nsub] host pointers, R_i is n_i x k_i column-major (original
+ *               DOF numbering); k_host [nsub], 0 <= k_i <= 8, G_i^T G_i must be
+ *               nonsingular (SC_ERR_INVALID_ARG otherwise)
+ *   d_dev       device FP64 right-hand side, dual layout (see sc_apply)
+ *   lambda_dev  device FP64 output, dual layout
+ *   iters       number of iterations (>= 0)
+ *   wnorm_hist  optional host array [(iters + 1) * nsub]: ||w_k|| of every
+ *               subdomain after iteration k (row k)
+ * A subdomain whose w or p.q reaches zero keeps its iterate.  Synchronises
+ * `stream` when wnorm_hist is given.  SC_ERR_STATE before sc_assemble. */
+sc_status_t sc_pcpg(sc_plan_t plan, const double* const* R_host, const int32_t* k_host,
+                    const double* d_dev, double* lambda_dev, int32_t iters, double* wnorm_hist,
+                    void* stream);
+
 /* Copy F_i (m_i x m_i, column-major, leading dimension ld >= m_i, original
  * multiplier order) to `out` (host memory when on_device == 0, else device
  * memory), converted to FP64.  Synchronises `stream`. */

@@ -774,6 +774,265 @@ hipError_t launch_assemble_f64(const DevTables& t, hipStream_t stream, hipEvent_
     return hipSuccess;
 }
 
+// ---------------------------------------------------------------------------
+// Projected conjugate gradients on each subdomain's dual problem (Sec. 2.1,
+// eq. (7), with e = 0 and the identity preconditioner), FP64 vectors; the
+// per-subdomain scalars stay on the device.  One workgroup per subdomain.
+//   lambda_0 = 0, r_0 = d, w_0 = P r_0, p_0 = w_0,  P = I - G (G^T G)^{-1} G^T
+//   q = F p;  alpha = (w.w)/(p.q);  lambda += alpha p;  r -= alpha q
+//   w' = P r;  beta = (w'.w')/(w.w);  p = w' + beta p
+// ---------------------------------------------------------------------------
+constexpr int kMaxKer = 8;
+
+struct PcpgDev {
+    const double* G;        // per subdomain m x k, column-major, at g_off
+    const int64_t* g_off;
+    const int32_t* kdim;
+    const double* GtGinv;   // per subdomain k x k at 64 * sub
+    double* r;
+    double* w;
+    double* pvec;
+    double* q;
+    double* ww;             // per subdomain w.w
+    double* hist;           // (iters + 1) x nsub or null
+    int32_t nsub;
+};
+
+__device__ double block_sum(double v, double* red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) t += red[i];
+    return t;
+}
+
+// w = r - G (G^T G)^{-1} G^T r over one subdomain; returns w.w
+__device__ double project(const SubDev& S, const PcpgDev& D, int sub, const double* r, double* w, double* red,
+                          double* su) {
+    const int m = S.m;
+    const int k = D.kdim[sub];
+    const double* G = D.G + D.g_off[sub];
+    for (int c = 0; c < k; ++c) {
+        double t = 0.0;
+        for (int i = threadIdx.x; i < m; i += 256) t += G[(int64_t)c * m + i] * r[i];
+        t = block_sum(t, red);
+        if (threadIdx.x == 0) su[c] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < k) {
+        double u = 0.0;
+        for (int c = 0; c < k; ++c) u += D.GtGinv[64 * sub + threadIdx.x * k + c] * su[c];
+        su[kMaxKer + threadIdx.x] = u;
+    }
+    __syncthreads();
+    double ww = 0.0;
+    for (int i = threadIdx.x; i < m; i += 256) {
+        double v = r[i];
+        for (int c = 0; c < k; ++c) v -= G[(int64_t)c * m + i] * su[kMaxKer + c];
+        w[i] = v;
+        ww += v * v;
+    }
+    return block_sum(ww, red);
+}
+
+__global__ __launch_bounds__(256) void pcpg_init(const SubDev* __restrict__ subs, PcpgDev D,
+                                                 const double* __restrict__ d, double* __restrict__ lambda) {
+    __shared__ double red[4];
+    __shared__ double su[2 * kMaxKer];
+    const int sub = blockIdx.x;
+    const SubDev S = subs[sub];
+    const int64_t o = S.dual_off;
+    for (int i = threadIdx.x; i < S.m; i += 256) {
+        lambda[o + i] = 0.0;
+        D.r[o + i] = d[o + i];
+    }
+    __syncthreads();
+    const double ww = project(S, D, sub, D.r + o, D.w + o, red, su);
+    for (int i = threadIdx.x; i < S.m; i += 256) D.pvec[o + i] = D.w[o + i];
+    if (threadIdx.x == 0) {
+        D.ww[sub] = ww;
+        if (D.hist) D.hist[sub] = sqrt(ww);
+    }
+}
+
+__global__ __launch_bounds__(256) void pcpg_step(const SubDev* __restrict__ subs, PcpgDev D,
+                                                 double* __restrict__ lambda, int iter) {
+    __shared__ double red[4];
+    __shared__ double su[2 * kMaxKer];
+    const int sub = blockIdx.x;
+    const SubDev S = subs[sub];
+    const int64_t o = S.dual_off;
+    const int m = S.m;
+    double* r = D.r + o;
+    double* w = D.w + o;
+    double* pv = D.pvec + o;
+    const double* q = D.q + o;
+    const double ww = D.ww[sub];
+    double pq = 0.0;
+    for (int i = threadIdx.x; i < m; i += 256) pq += pv[i] * q[i];
+    pq = block_sum(pq, red);
+    const bool go = pq > 0.0 && ww > 0.0;       // converged (or breakdown): keep the iterate
+    const double alpha = go ? ww / pq : 0.0;
+    for (int i = threadIdx.x; i < m; i += 256) {
+        lambda[o + i] += alpha * pv[i];
+        r[i] -= alpha * q[i];
+    }
+    __syncthreads();
+    const double ww2 = go ? project(S, D, sub, r, w, red, su) : ww;
+    const double beta = go ? ww2 / ww : 0.0;
+    if (go)
+        for (int i = threadIdx.x; i < m; i += 256) pv[i] = w[i] + beta * pv[i];
+    if (threadIdx.x == 0) {
+        D.ww[sub] = ww2;
+        if (D.hist) D.hist[(int64_t)(iter + 1) * D.nsub + sub] = sqrt(ww2);
+    }
+}
+
+hipError_t launch_pcpg(const DevTables& t, const PcpgArgs& a, hipStream_t stream) {
+    PcpgDev D;
+    D.G = a.G; D.g_off = a.g_off; D.kdim = a.kdim; D.GtGinv = a.GtGinv;
+    D.r = a.r; D.w = a.w; D.pvec = a.p; D.q = a.q; D.ww = a.ww; D.hist = a.hist; D.nsub = a.nsub;
+    if (a.nsub <= 0) return hipSuccess;
+    hipLaunchKernelGGL(pcpg_init, dim3((unsigned)a.nsub), dim3(256), 0, stream, t.subs, D, a.d, a.lambda);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    for (int it = 0; it < a.iters; ++it) {
+        if ((e = launch_apply(t, a.p, a.q, stream, nullptr)) != hipSuccess) return e;
+        hipLaunchKernelGGL(pcpg_step, dim3((unsigned)a.nsub), dim3(256), 0, stream, t.subs, D, a.lambda, it);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// Implicit apply (Sec. 2.2, eq. (11)): q = B P^T L^{-T} L^{-1} P B^T p, one
+// workgroup per subdomain sweeping the factor blocks (forward, then backward),
+// FP64.  x (n doubles per subdomain, global workspace) carries P B^T p, then
+// y = L^{-1} x, then z = L^{-T} y in place.
+//   forward, block b:  y_b = L_bb^{-1} x_b;  x[R_b] -= L[R_b, b] y_b
+//   backward, block b: z_b = L_bb^{-T} (y_b - L[R_b, b]^T z[R_b])
+// Repeated DOFs (several multipliers on one DOF) are summed by one thread per
+// run of equal pivots (sorted), so the result does not depend on scheduling.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void implicit_apply(
+    const SubDev* __restrict__ subs, const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows,
+    const double* __restrict__ lval, const int32_t* __restrict__ piv, const int32_t* __restrict__ pi,
+    const int8_t* __restrict__ sgn, const int64_t* __restrict__ xoff, const double* __restrict__ p,
+    double* __restrict__ q, double* __restrict__ xwork)
+{
+    __shared__ double sL[64 * 65];
+    __shared__ double sv[64];
+    __shared__ double sz[64];
+    const int sub = blockIdx.x;
+    const SubDev S = subs[sub];
+    const int n = S.n;
+    const int m = S.m;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wv = tid >> 6;
+    double* __restrict__ x = xwork + xoff[sub];
+    const int32_t* __restrict__ pv = piv + S.col_off;
+    const int32_t* __restrict__ pis = pi + S.col_off;
+    const int8_t* __restrict__ sg = sgn + S.col_off;
+    const double* __restrict__ ps = p + S.dual_off;
+    const BlockDev* __restrict__ B = blocks + S.blk_off;
+    const int32_t* __restrict__ R = rows + S.rows_off;
+    const double* __restrict__ L = lval + S.lval_off;
+
+    for (int i = tid; i < n; i += 256) x[i] = 0.0;
+    __syncthreads();
+    for (int a = tid; a < m; a += 256) {
+        if (a > 0 && pv[a - 1] == pv[a]) continue;
+        double v = 0.0;
+        for (int b = a; b < m && pv[b] == pv[a]; ++b) v += (double)sg[b] * ps[pis[b]];
+        x[pv[a]] = v;
+    }
+    __syncthreads();
+
+    // ---- forward
+    for (int b = 0; b < S.nblocks; ++b) {
+        const BlockDev bd = B[b];
+        const int w = bd.w, ld = bd.ld, nb = bd.nbelow, row0 = bd.row0;
+        const double* __restrict__ Lb = L + bd.lval_off;
+        for (int e = tid; e < 64 * 64; e += 256) {
+            const int r = e & 63, k = e >> 6;
+            sL[k * 65 + r] = (r < w && k < w) ? Lb[(int64_t)k * ld + r] : 0.0;
+        }
+        __syncthreads();
+        if (wv == 0) {
+            double xi = lane < w ? x[row0 + lane] : 0.0;
+            for (int k = 0; k < w; ++k) {
+                const double xk = __shfl(xi, k, 64) / sL[k * 65 + k];
+                if (lane == k) xi = xk;
+                if (lane > k) xi -= sL[k * 65 + lane] * xk;
+            }
+            if (lane < w) {
+                x[row0 + lane] = xi;
+                sv[lane] = xi;
+            }
+        }
+        __syncthreads();
+        const int32_t* __restrict__ rw = R + bd.rows_off;
+        for (int qq = tid; qq < nb; qq += 256) {
+            double t = 0.0;
+            for (int k = 0; k < w; ++k) t += Lb[(int64_t)k * ld + w + qq] * sv[k];
+            x[rw[qq]] -= t;
+        }
+        __syncthreads();
+    }
+    // ---- backward
+    for (int b = S.nblocks - 1; b >= 0; --b) {
+        const BlockDev bd = B[b];
+        const int w = bd.w, ld = bd.ld, nb = bd.nbelow, row0 = bd.row0;
+        const double* __restrict__ Lb = L + bd.lval_off;
+        const int32_t* __restrict__ rw = R + bd.rows_off;
+        double acc = 0.0;                      // lane k of wavefront 0: sum_q L[q][k] z[R[q]]
+        for (int c0 = 0; c0 < nb; c0 += 64) {
+            for (int e = tid; e < 64 * 64; e += 256) {
+                const int r = e & 63, k = e >> 6;
+                sL[k * 65 + r] = (c0 + r < nb && k < w) ? Lb[(int64_t)k * ld + w + c0 + r] : 0.0;
+            }
+            if (tid < 64) sz[tid] = c0 + tid < nb ? x[rw[c0 + tid]] : 0.0;
+            __syncthreads();
+            if (wv == 0 && lane < w)
+                for (int r = 0; r < 64; ++r) acc += sL[lane * 65 + r] * sz[r];
+            __syncthreads();
+        }
+        for (int e = tid; e < 64 * 64; e += 256) {
+            const int r = e & 63, k = e >> 6;
+            sL[k * 65 + r] = (r < w && k < w) ? Lb[(int64_t)k * ld + r] : 0.0;
+        }
+        __syncthreads();
+        if (wv == 0) {
+            double vk = lane < w ? x[row0 + lane] - acc : 0.0;
+            for (int i = w - 1; i >= 0; --i) {
+                const double zi = __shfl(vk, i, 64) / sL[i * 65 + i];
+                if (lane == i) vk = zi;
+                if (lane < i) vk -= sL[lane * 65 + i] * zi;
+            }
+            if (lane < w) x[row0 + lane] = vk;
+        }
+        __syncthreads();
+    }
+    for (int a = tid; a < m; a += 256) q[S.dual_off + pis[a]] = (double)sg[a] * x[pv[a]];
+}
+
+hipError_t launch_apply_implicit(const DevTables& t, const int64_t* xoff, double* xwork, const double* p,
+                                 double* q, int32_t nsub, hipStream_t stream, hipEvent_t* ev) {
+    hipError_t e = hipSuccess;
+    if (ev && (e = hipEventRecord(ev[0], stream)) != hipSuccess) return e;
+    if (nsub > 0)
+        hipLaunchKernelGGL(implicit_apply, dim3((unsigned)nsub), dim3(256), 0, stream, t.subs, t.blocks, t.rows,
+                           t.lval, t.piv, t.pi, t.sgn, xoff, p, q, xwork);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[1], stream)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
 hipError_t launch_convert_f32(const double* a, float* b, int64_t n, hipStream_t stream) {
     if (n <= 0) return hipSuccess;
     const int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);

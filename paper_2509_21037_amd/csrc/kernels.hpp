@@ -36,6 +36,28 @@ hipError_t launch_assemble_f64(const DevTables& t, hipStream_t stream, hipEvent_
 hipError_t launch_convert_f32(const double* a, float* b, int64_t n, hipStream_t stream);
 hipError_t launch_assemble_mixed(const DevTables& t, hipStream_t stream, hipEvent_t* ev);
 
+struct PcpgArgs {
+    const double* G;        // concatenated m_i x k_i column-major blocks
+    const int64_t* g_off;   // [nsub] offsets into G
+    const int32_t* kdim;    // [nsub] kernel dimension k_i (<= 8)
+    const double* GtGinv;   // [nsub][64] (G^T G)^{-1}, k_i x k_i row-major
+    const double* d;        // right-hand side (dual layout)
+    double* lambda;         // solution (dual layout)
+    double *r, *w, *p, *q;  // workspace (dual layout)
+    double* ww;             // [nsub]
+    double* hist;           // [(iters + 1) * nsub] or null
+    int32_t nsub;
+    int32_t iters;
+};
+
+// Projected CG on every subdomain, `iters` iterations (explicit F apply).
+hipError_t launch_pcpg(const DevTables& t, const PcpgArgs& a, hipStream_t stream);
+
+// Implicit apply q = B P^T L^{-T} L^{-1} P B^T p; xwork holds n_i doubles per
+// subdomain at xoff[i].
+hipError_t launch_apply_implicit(const DevTables& t, const int64_t* xoff, double* xwork, const double* p,
+                                 double* q, int32_t nsub, hipStream_t stream, hipEvent_t* ev);
+
 // q = F p for every subdomain (FP32 F when t.F32 is set, else FP64 F);
 // optional events ev[0] before, ev[1] after.
 hipError_t launch_apply(const DevTables& t, const double* p, double* q, hipStream_t stream, hipEvent_t* ev);

@@ -457,6 +457,8 @@ std::string build_plan(const SubdomainInput& in, const PlanOptions& opt, SubPlan
 
     // ---- staircase: pivots, stable sort by (pivot, original index)
     const int32_t m = in.m;
+    P.dof.assign(in.dof, in.dof + m);
+    P.sign.assign(in.sign, in.sign + m);
     std::vector<int32_t> pv(m);
     for (int32_t j = 0; j < m; ++j) pv[j] = iperm[in.dof[j]];
     P.pi.resize(m);

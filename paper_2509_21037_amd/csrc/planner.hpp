@@ -68,6 +68,8 @@ struct SubPlan {
     int64_t nval = 0;
     std::vector<int32_t> col2super;
     std::vector<int64_t> kmap;                 // CSR entry -> panel slot, -1 = upper part
+    std::vector<int32_t> dof;                  // [m] B^T columns as given (original order)
+    std::vector<int8_t> sign;                  // [m]
     // staircase
     std::vector<int32_t> piv;                  // [m] pivots in sorted order
     std::vector<int32_t> pi;                   // [m] sorted position -> original column

@@ -6,6 +6,7 @@
 #include <omp.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -106,6 +107,8 @@ struct sc_plan_s {
     DevBuf<int8_t> d_sgn;
     DevBuf<double> d_lval, d_X, d_F;
     DevBuf<float> d_lval32, d_X32, d_F32;
+    DevBuf<double> d_xwork;                   // implicit apply: n_i doubles per subdomain
+    DevBuf<int64_t> d_xoff;
     bool mixed = false;
     bool factored = false, assembled = false;
     double trsm_u = 0, syrk_u = 0, trsm_d = 0, syrk_d = 0;
@@ -154,13 +157,15 @@ struct sc_plan_s {
                          d_apply.count * sizeof(int2) +
                          (d_rows.count + d_piv.count + d_pi.count) * 4 + d_sgn.count +
                          (d_lval.count + d_X.count + d_F.count) * 8 +
-                         (d_lval32.count + d_X32.count + d_F32.count) * 4);
+                         (d_lval32.count + d_X32.count + d_F32.count) * 4 +
+                         (d_xwork.count + d_xoff.count) * 8);
     }
     void release() {
         d_subs.release(); d_tiles.release(); d_blocks.release(); d_syrk.release(); d_apply.release();
         d_rows.release(); d_piv.release(); d_pi.release(); d_sgn.release();
         d_lval.release(); d_X.release(); d_F.release();
         d_lval32.release(); d_X32.release(); d_F32.release();
+        d_xwork.release(); d_xoff.release();
         if (h_lval) (void)hipHostFree(h_lval);
         h_lval = nullptr;
         for (auto& p : pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
@@ -437,11 +442,123 @@ sc_status_t sc_apply(sc_plan_t P, const double* p_dev, double* q_dev, void* stre
     return SC_OK;
 }
 
+sc_status_t sc_pcpg(sc_plan_t P, const double* const* R_host, const int32_t* k_host, const double* d_dev,
+                    double* lambda_dev, int32_t iters, double* wnorm_hist, void* stream) {
+    g_last_error.clear();
+    if (!P) return fail(SC_ERR_INVALID_ARG, "plan is NULL");
+    if (!P->assembled) return fail(SC_ERR_STATE, "sc_pcpg before sc_assemble");
+    if (iters < 0) return fail(SC_ERR_INVALID_ARG, "iters must be >= 0");
+    if (P->nsub > 0 && (!R_host || !k_host)) return fail(SC_ERR_INVALID_ARG, "R or k is NULL");
+    if (P->dual_total > 0 && (!d_dev || !lambda_dev)) return fail(SC_ERR_INVALID_ARG, "d or lambda is NULL");
+    // G_i = B_i R_i and (G_i^T G_i)^{-1} on the host (k_i <= 8)
+    std::vector<int64_t> g_off(P->nsub + 1, 0);
+    for (int32_t i = 0; i < P->nsub; ++i) {
+        if (k_host[i] < 0 || k_host[i] > 8) return fail(SC_ERR_INVALID_ARG, "k_i must be in [0, 8]");
+        if (k_host[i] > 0 && !R_host[i]) return fail(SC_ERR_INVALID_ARG, "R_i is NULL");
+        g_off[i + 1] = g_off[i] + (int64_t)P->plans[i].m * k_host[i];
+    }
+    std::vector<double> G((size_t)std::max<int64_t>(1, g_off[P->nsub]));
+    std::vector<double> Ginv((size_t)std::max(1, P->nsub) * 64, 0.0);
+    for (int32_t i = 0; i < P->nsub; ++i) {
+        const SubPlan& sp = P->plans[i];
+        const int k = k_host[i];
+        const int64_t m = sp.m, n = sp.n;
+        double* Gi = G.data() + g_off[i];
+        for (int c = 0; c < k; ++c)
+            for (int64_t j = 0; j < m; ++j) Gi[c * m + j] = sp.sign[j] * R_host[i][c * n + sp.dof[j]];
+        // Gram matrix and its inverse by Gauss-Jordan with partial pivoting
+        double A[8][16];
+        for (int a = 0; a < k; ++a)
+            for (int b = 0; b < k; ++b) {
+                double t = 0.0;
+                for (int64_t j = 0; j < m; ++j) t += Gi[a * m + j] * Gi[b * m + j];
+                A[a][b] = t;
+                A[a][k + b] = (a == b) ? 1.0 : 0.0;
+            }
+        double scale = 0.0;
+        for (int a = 0; a < k; ++a) scale = std::max(scale, std::abs(A[a][a]));
+        for (int c = 0; c < k; ++c) {
+            int piv = c;
+            for (int a = c + 1; a < k; ++a)
+                if (std::abs(A[a][c]) > std::abs(A[piv][c])) piv = a;
+            if (!(std::abs(A[piv][c]) > 1e-13 * scale))
+                return fail(SC_ERR_INVALID_ARG, "G^T G of subdomain " + std::to_string(i) + " is singular");
+            if (piv != c)
+                for (int b = 0; b < 2 * k; ++b) std::swap(A[c][b], A[piv][b]);
+            const double inv = 1.0 / A[c][c];
+            for (int b = 0; b < 2 * k; ++b) A[c][b] *= inv;
+            for (int a = 0; a < k; ++a)
+                if (a != c) {
+                    const double f = A[a][c];
+                    for (int b = 0; b < 2 * k; ++b) A[a][b] -= f * A[c][b];
+                }
+        }
+        for (int a = 0; a < k; ++a)
+            for (int b = 0; b < k; ++b) Ginv[(size_t)64 * i + a * k + b] = A[a][k + b];
+    }
+    HIP_TRY(hipSetDevice(P->device));
+    hipStream_t st = (hipStream_t)stream;
+    // workspace
+    const size_t nd = (size_t)std::max<int64_t>(1, P->dual_total);
+    DevBuf<double> dG, dGi, dwork, dww, dhist;
+    DevBuf<int64_t> doff;
+    DevBuf<int32_t> dk;
+    auto cleanup = [&]() { dG.release(); dGi.release(); dwork.release(); dww.release(); dhist.release();
+                           doff.release(); dk.release(); };
+    hipError_t e = dG.alloc(G.size());
+    if (e == hipSuccess) e = dGi.alloc(Ginv.size());
+    if (e == hipSuccess) e = dwork.alloc(4 * nd);
+    if (e == hipSuccess) e = dww.alloc((size_t)std::max(1, P->nsub));
+    if (e == hipSuccess && wnorm_hist) e = dhist.alloc((size_t)(iters + 1) * std::max(1, P->nsub));
+    if (e == hipSuccess) e = doff.alloc(g_off.size());
+    if (e == hipSuccess) e = dk.alloc((size_t)std::max(1, P->nsub));
+    if (e == hipSuccess) e = hipMemcpyAsync(dG.p, G.data(), G.size() * 8, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(dGi.p, Ginv.data(), Ginv.size() * 8, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(doff.p, g_off.data(), g_off.size() * 8, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && P->nsub > 0) e = hipMemcpyAsync(dk.p, k_host, (size_t)P->nsub * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+        PcpgArgs a;
+        a.G = dG.p; a.g_off = doff.p; a.kdim = dk.p; a.GtGinv = dGi.p;
+        a.d = d_dev; a.lambda = lambda_dev;
+        a.r = dwork.p; a.w = dwork.p + nd; a.p = dwork.p + 2 * nd; a.q = dwork.p + 3 * nd;
+        a.ww = dww.p; a.hist = dhist.p; a.nsub = P->nsub; a.iters = iters;
+        e = launch_pcpg(P->tables(), a, st);
+    }
+    if (e == hipSuccess && wnorm_hist)
+        e = hipMemcpyAsync(wnorm_hist, dhist.p, (size_t)(iters + 1) * P->nsub * 8, hipMemcpyDeviceToHost, st);
+    // the workspace is released after the queued work has finished
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    cleanup();
+    if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? SC_ERR_OOM : SC_ERR_DEVICE,
+                                     std::string("sc_pcpg: ") + hipGetErrorString(e));
+    return SC_OK;
+}
+
 sc_status_t sc_apply_implicit(sc_plan_t P, const double* p_dev, double* q_dev, void* stream) {
-    (void)p_dev; (void)q_dev; (void)stream;
+    g_last_error.clear();
     if (!P) return fail(SC_ERR_INVALID_ARG, "plan is NULL");
     if (!P->factored) return fail(SC_ERR_STATE, "sc_apply_implicit before sc_factor");
-    return fail(SC_ERR_UNSUPPORTED, "sc_apply_implicit is not built yet");
+    if (P->dual_total > 0 && (!p_dev || !q_dev)) return fail(SC_ERR_INVALID_ARG, "p or q is NULL");
+    if (P->dual_total > 0 && p_dev == q_dev) return fail(SC_ERR_INVALID_ARG, "p and q must not alias");
+    HIP_TRY(hipSetDevice(P->device));
+    hipStream_t st = (hipStream_t)stream;
+    if (!P->d_xoff.p && P->nsub > 0) {           // workspace, allocated on first use
+        std::vector<int64_t> off(P->nsub + 1, 0);
+        for (int32_t i = 0; i < P->nsub; ++i) off[i + 1] = off[i] + P->plans[i].n;
+        HIP_TRY(P->d_xwork.alloc((size_t)off[P->nsub]));
+        HIP_TRY(P->d_xoff.alloc(off.size()));
+        HIP_TRY(hipMemcpyAsync(P->d_xoff.p, off.data(), off.size() * 8, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    hipEvent_t ev[2];
+    hipEvent_t* evp = nullptr;
+    if (P->timing) {
+        HIP_TRY(P->take_events(2, ev));
+        evp = ev;
+    }
+    HIP_TRY(launch_apply_implicit(P->tables(), P->d_xoff.p, P->d_xwork.p, p_dev, q_dev, P->nsub, st, evp));
+    if (evp) P->pending.push_back({3, ev[0], ev[1]});
+    return SC_OK;
 }
 
 sc_status_t sc_get_F(sc_plan_t P, int32_t sub, double* out, int32_t ld, int32_t on_device, void* stream) {

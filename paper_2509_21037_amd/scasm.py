@@ -17,7 +17,7 @@ STATUS_NAMES = {0: "SC_OK", 1: "SC_ERR_INVALID_ARG", 2: "SC_ERR_NOT_SPD", 3: "SC
 
 EXPORTED = ["sc_plan_create", "sc_factor", "sc_assemble", "sc_apply", "sc_apply_implicit",
             "sc_get_F", "sc_query", "sc_plan_stats", "sc_plan_destroy", "sc_host_analyze",
-            "sc_set_timing", "sc_kernel_times", "sc_last_error"]
+            "sc_set_timing", "sc_kernel_times", "sc_pcpg", "sc_last_error"]
 
 
 class ScasmError(RuntimeError):
@@ -75,6 +75,7 @@ def load():
         lib.sc_plan_destroy.argtypes = [vp]
         lib.sc_host_analyze.argtypes = [ctypes.POINTER(SubdomainDesc), ctypes.POINTER(Options), vp, vp, vp,
                                          vp, vp, ctypes.POINTER(HostInfo), ctypes.POINTER(i32)]
+        lib.sc_pcpg.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(i32), vp, vp, i32, vp, vp]
         lib.sc_set_timing.argtypes = [vp, i32]
         lib.sc_kernel_times.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), i32]
         lib.sc_last_error.argtypes = []
@@ -218,6 +219,22 @@ class Plan:
         _check(self._lib.sc_apply_implicit(self._h, ctypes.c_void_p(p.data_ptr()),
                                            ctypes.c_void_p(q.data_ptr()), _stream_handle(stream)))
         return q
+
+    def pcpg(self, d, lam, iters: int, R_list=None, history: bool = False, stream=None):
+        """Projected CG on every subdomain's dual problem; d, lam: device FP64
+        tensors of length dual_total.  R_list: per-subdomain kernel bases
+        (n_i x k_i); default: the subdomains' `R` attributes.  Returns the
+        ||w_k|| history ((iters + 1) x nsub) when `history`."""
+        if R_list is None:
+            R_list = [s.R for s in self.subdomains]
+        Rs = [np.asfortranarray(np.asarray(R, dtype=np.float64)) for R in R_list]
+        ks = (ctypes.c_int32 * max(1, len(Rs)))(*[R.shape[1] for R in Rs])
+        ptrs = (ctypes.c_void_p * max(1, len(Rs)))(*[R.ctypes.data for R in Rs])
+        hist = np.zeros((iters + 1, len(Rs))) if history else None
+        _check(self._lib.sc_pcpg(self._h, ptrs, ks, ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(lam.data_ptr()),
+                                 int(iters), hist.ctypes.data if hist is not None else None,
+                                 _stream_handle(stream)))
+        return hist
 
     # ---------------------------------------------------------------- queries
     def get_F(self, i: int, stream=None) -> np.ndarray:

@@ -256,3 +256,64 @@ def test_mixed_apply_reads_fp32_accumulates_fp64():
         F = plan.get_F(i)                      # the stored FP32 values, widened
         ref = F @ ph[o:o + s.m]
         assert np.linalg.norm(qh[o:o + s.m] - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
+# ---------------------------------------------------------------- PCPG
+
+def _pcpg_case(precision, cfg=3, count=4, iters=30):
+    import torch
+    subs = scgen.config_subdomains(cfg, count=count)
+    plan = _assemble(subs, precision=precision)
+    st = plan.stats()
+    d = torch.from_numpy(scgen.splitmix64_uniform(scgen.BASE_SEED + 4, st["dual_total"])).cuda()
+    lam = torch.zeros_like(d)
+    hist = plan.pcpg(d, lam, iters, history=True)
+    return subs, plan, d.cpu().numpy(), lam.cpu().numpy(), hist
+
+
+def test_pcpg_fp64_matches_oracle():
+    # Compared at convergence (100 iterations, as in the mixed workload): in
+    # mid-run, CG amplifies round-off-level differences of F by many orders
+    # (two oracle F differing by 2e-14 give lambda 5e-8..1e-5 apart at 30
+    # iterations, 2e-14 apart at 100).
+    iters = 100
+    subs, plan, d, lam, hist = _pcpg_case("fp64", iters=iters)
+    for i, s in enumerate(subs):
+        o = plan.query(i)["dual_offset"]
+        F = oracle.schur(s)
+        ref, href = oracle.pcpg(F, oracle.gluing_G(s), d[o:o + s.m], iters)
+        assert np.linalg.norm(lam[o:o + s.m] - ref) <= 1e-10 * np.linalg.norm(ref), i
+        assert abs(hist[0, i] - href[0]) <= 1e-12 * href[0]
+        assert hist[-1, i] < 1e-10 * hist[0, i]
+
+
+def test_pcpg_mixed_close_to_fp64():
+    iters = 100
+    _, plan64, d, lam64, _ = _pcpg_case("fp64", iters=iters)
+    _, plan32, _, lam32, _ = _pcpg_case("mixed", iters=iters)
+    err = np.linalg.norm(lam32 - lam64) / np.linalg.norm(lam64)
+    assert err < 1e-3, err
+
+
+# ---------------------------------------------------------------- implicit apply
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_implicit_apply_matches_oracle(precision):
+    base = scgen.box_subdomain("heat", (4, 4, 3), 0.25, seed=13)
+    per_face = scgen.box_subdomain("elasticity", (3, 2, 3), 0.25, seed=15, gluing="per_face")
+    subs = scgen.config_subdomains(1) + scgen.config_subdomains(3, count=3) + [base, per_face]
+    _torch_init()
+    plan = P.Plan(subs, precision=precision)
+    plan.factor()
+    p, q = _dual_vectors(plan, subs, seed=11)
+    plan.apply_implicit(p, q)            # needs only the factor (before sc_assemble)
+    qh, ph = q.cpu().numpy(), p.cpu().numpy()
+    for i, s in enumerate(subs):
+        o = plan.query(i)["dual_offset"]
+        if s.n <= 3000:
+            ref = oracle.schur(s) @ ph[o:o + s.m]
+        else:
+            import scipy.sparse.linalg as spla
+            Bt = s.Bt_dense()
+            ref = Bt.T @ spla.spsolve(s.Kreg_csr().tocsc(), Bt @ ph[o:o + s.m])
+        assert np.linalg.norm(qh[o:o + s.m] - ref) <= 1e-12 * np.linalg.norm(ref), i
