@@ -1,19 +1,29 @@
 #!/usr/bin/env python3
 """Benchmark of the Schur-complement assembly on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload heat|elast]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload heat|elast|large]
+                    [--pcpg ITERS] [--no-mixed] [--no-cpu-baseline] [--compare-orig]
 
 A step is one sc_assemble over the whole batch: staircase TRSM X = L^{-1} P B^T
 and staircase SYRK F = X^T X with the permutation back, for every subdomain.
 Inputs (factor values, tables) are resident in HBM before the timed region:
 the host factorisation and its upload happen in sc_factor, untimed.
 
+Workloads: heat  = 1024 x 12^3 hex8 heat subdomains (default; the headline),
+           elast = 512 uneven hex8 elasticity boxes (6..16 elements per axis);
+                   with --pcpg both assemblies run that many PCPG iterations,
+           large = 64 x 20^3 hex8 elasticity, per-face gluing, with the
+                   explicit-vs-implicit apply and the amortisation point.
+
 Prints ONE JSON line on stdout (progress goes to stderr):
-  value         subdomains/s over the K timed steps (wall clock, synchronised)
+  value         subdomains/s of the FP64 assembly over the K timed steps
+                (wall clock, synchronised)
   useful_gflops staircase TRSM + SYRK flop count / time
-  roofline      dominant kernel: its useful flops per launch / its mean launch
-                duration from HIP events on the launch stream, against the
-                FP64 matrix peak of the chip
+  mixed         the same assembly in mixed precision, with its error vs the
+                oracle on sampled subdomains
+  roofline      dominant kernel of the FP64 assembly: useful flops per launch /
+                mean launch duration (HIP events on the launch stream), against
+                the chip's published FP64 matrix peak
   cpu_baseline  the CPU oracle on a bounded sample of the same workload
 """
 import argparse
@@ -26,34 +36,114 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "SC assembly subdomains/s and useful GFLOP/s per GPU, mixed vs FP64 at stated error"
-PEAK_FP64_MATRIX_TFLOPS = 78.6
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
 PEAK_HBM_GBS = 8000.0
-WORKLOADS = {"heat": 2, "elast": 3}
+WORKLOADS = {"heat": 2, "elast": 3, "large": 5}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(subs, gpu_F, seconds):
-    """Times the oracle (long double, as it stands) on subdomains 0, 1, ...
-    until `seconds` have elapsed; returns the baseline object and the parity
-    errors of the GPU F on the same subdomains."""
+def kernels_digest():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2509_21037_amd", "csrc", "kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(workload, precision, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when it was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{precision}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernels_sha256") != kernels_digest():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k["fetch_bytes"] + k["write_bytes"]
+
+
+def time_assembly(torch, plan, steps, warmup):
+    for _ in range(warmup):
+        plan.assemble()
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    plan.kernel_times(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.assemble()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kt = plan.kernel_times(reset=True)
+    plan.set_timing(False)
+    return 1e3 * elapsed / steps, {k: kt[k][0] / max(1, kt[k][1]) for k in ("trsm", "syrk")}
+
+
+def time_apply(torch, plan, which, iters=20):
+    st = plan.stats()
+    p = torch.rand(st["dual_total"], dtype=torch.float64, device="cuda")
+    q = torch.zeros_like(p)
+    f = plan.apply if which == "explicit" else plan.apply_implicit
+    f(p, q)
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    plan.kernel_times(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        f(p, q)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kt = plan.kernel_times(reset=True)
+    plan.set_timing(False)
+    key = "apply" if which == "explicit" else "apply_implicit"
+    return 1e3 * el / iters, kt[key][0] / max(1, kt[key][1])
+
+
+def sampled_error(plan, subs, picks, nsel=192):
+    import numpy as np
+    import oracle
+    errs = []
+    for i in picks:
+        s = subs[i]
+        F = plan.get_F(i)
+        if s.n <= 3000:
+            errs.append(oracle.relF(F, oracle.schur(s)))
+        else:
+            sel = np.sort(np.random.default_rng(i).choice(s.m, size=min(nsel, s.m), replace=False))
+            errs.append(oracle.relF(F[np.ix_(sel, sel)], oracle.schur(s, sel=sel)))
+    return errs
+
+
+def cpu_baseline(subs, seconds):
+    """The oracle (long double, as it stands) on subdomains 0, 1, ... until
+    `seconds` have elapsed."""
+    import numpy as np
     import oracle
     nthreads = max(1, min(16, os.cpu_count() or 1))
     t0 = time.perf_counter()
     done = 0
-    errs = []
+    big = subs[0].n > 3000
     while done < len(subs):
-        F = oracle.schur(subs[done], prec="ld", nthreads=nthreads)
-        errs.append(oracle.relF(gpu_F(done), F))
+        s = subs[done]
+        if big:
+            sel = np.arange(0, s.m, max(1, s.m // 256))[:256]
+            oracle.schur(s, sel=sel, prec="ld", nthreads=nthreads)
+        else:
+            oracle.schur(s, prec="ld", nthreads=nthreads)
         done += 1
         if time.perf_counter() - t0 >= seconds:
             break
     el = time.perf_counter() - t0
+    if big:
+        return {"value": None, "unit": "subdomains/s", "cores": nthreads, "kind": "oracle",
+                "sample": f"{done} subdomains, 256-column subsets only, {el:.1f} s "
+                          f"({el / done:.2f} s per 256-column subset)"}
     return {"value": done / el, "unit": "subdomains/s", "cores": nthreads, "kind": "oracle",
             "sample": f"first {done} subdomains of the batch, long-double oracle (Cholesky in natural "
-                      f"order, full forward substitution, Y^T Y), {el:.1f} s"}, errs
+                      f"order, full forward substitution, Y^T Y), {el:.1f} s"}
 
 
 def main():
@@ -64,6 +154,8 @@ def main():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="heat")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--pcpg", type=int, default=0, help="PCPG iterations on the FP64 and the mixed F")
     ap.add_argument("--compare-orig", action="store_true", help="also time the assembly without the staircase")
     ap.add_argument("--panel-width", type=int, default=0, help="GPU factor block width (0 = library default)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -74,6 +166,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
     import scgen
     import paper_2509_21037_amd as P
@@ -91,64 +184,90 @@ def main():
     t0 = time.perf_counter()
     subs = scgen.config_subdomains(cfg)
     log(f"bench: generated {len(subs)} subdomains in {time.perf_counter() - t0:.1f}s")
+    picks = sorted({0, len(subs) // 2, len(subs) - 1})
+
+    # ---------------------------------------------------------------- FP64
     t0 = time.perf_counter()
     plan = P.Plan(subs, panel_width=args.panel_width)
-    log(f"bench: plan created in {time.perf_counter() - t0:.1f}s")
-    t0 = time.perf_counter()
     plan.factor()
     torch.cuda.synchronize()
-    log(f"bench: host factorisation + upload in {time.perf_counter() - t0:.1f}s")
+    log(f"bench: FP64 plan + host factorisation + upload in {time.perf_counter() - t0:.1f}s")
     st = plan.stats()
-
-    for _ in range(args.warmup):
-        plan.assemble()
-    torch.cuda.synchronize()
-    plan.set_timing(True)
-    plan.kernel_times(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plan.assemble()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    kt = plan.kernel_times(reset=True)
-    plan.set_timing(False)
-    ms_per_step = 1e3 * elapsed / args.steps
-    nsub = st["nsub"]
+    ms_per_step, kms = time_assembly(torch, plan, args.steps, args.warmup)
+    log(f"bench: FP64 {ms_per_step:.3f} ms/step, kernels {kms}")
     useful = st["trsm_useful"] + st["syrk_useful"]
-    log(f"bench: {ms_per_step:.3f} ms/step, kernels {kt}")
-
-    flops_per_launch = {"trsm": st["trsm_useful"], "syrk": st["syrk_useful"]}
-    avg_ms = {k: kt[k][0] / max(1, kt[k][1]) for k in ("trsm", "syrk")}
-    dom = max(avg_ms, key=avg_ms.get)
-    achieved = flops_per_launch[dom] / (avg_ms[dom] * 1e-3) / 1e12
-    roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": PEAK_FP64_MATRIX_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_MATRIX_TFLOPS, "traffic": None,
-                "kernel_ms": {k: avg_ms[k] for k in avg_ms},
-                "kernel_tflops": {k: flops_per_launch[k] / (avg_ms[k] * 1e-3) / 1e12 for k in avg_ms}}
-
+    flops = {"trsm": st["trsm_useful"], "syrk": st["syrk_useful"]}
+    dom = max(kms, key=kms.get)
+    achieved = flops[dom] / (kms[dom] * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": PEAK_TFLOPS["fp64"],
+                "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["fp64"],
+                "traffic": measured_traffic(args.workload, "fp64", dom),
+                "kernel_ms": kms,
+                "kernel_tflops": {k: flops[k] / (kms[k] * 1e-3) / 1e12 for k in kms}}
+    errs64 = sampled_error(plan, subs, picks)
+    log(f"bench: FP64 sampled relF {errs64}")
+    _, apply64 = time_apply(torch, plan, "explicit")
+    f_bytes64 = sum(s.m * s.m for s in subs) * 8
+    extra = {"explicit_fp64F_ms": apply64, "explicit_fp64F_GBps": f_bytes64 / (apply64 * 1e-3) / 1e9}
+    pcpg = {}
+    d = None
+    if args.pcpg:
+        d = torch.from_numpy(scgen.splitmix64_uniform(scgen.BASE_SEED + 4, st["dual_total"])).cuda()
+        lam64 = torch.zeros_like(d)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        h64 = plan.pcpg(d, lam64, args.pcpg, history=True)
+        pcpg["iterations"] = args.pcpg
+        pcpg["fp64_s"] = time.perf_counter() - t1
+        pcpg["fp64_w_reduction_worst"] = float(np.max(h64[-1] / np.maximum(h64[0], 1e-300)))
+    if cfg == 5:
+        _, extra["implicit_ms"] = time_apply(torch, plan, "implicit", iters=5)
+        log(f"bench: apply {extra}")
     orig = None
     if args.compare_orig:
         plan_o = P.Plan(subs, staircase=False, panel_width=args.panel_width)
         plan_o.factor()
-        plan_o.assemble()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(max(1, args.steps // 2)):
-            plan_o.assemble()
-        torch.cuda.synchronize()
-        orig = 1e3 * (time.perf_counter() - t1) / max(1, args.steps // 2)
+        orig, _ = time_assembly(torch, plan_o, max(1, args.steps // 2), 1)
         plan_o.destroy()
+    plan.destroy()
 
-    cpu = None
-    errs = []
-    if not args.no_cpu_baseline:
-        cpu, errs = cpu_baseline(subs, plan.get_F, args.cpu_seconds)
+    # ---------------------------------------------------------------- mixed
+    mixed = None
+    if not args.no_mixed:
+        plan_m = P.Plan(subs, precision="mixed", panel_width=args.panel_width)
+        plan_m.factor()
+        ms_m, kms_m = time_assembly(torch, plan_m, args.steps, args.warmup)
+        log(f"bench: mixed {ms_m:.3f} ms/step, kernels {kms_m}")
+        errs_m = sampled_error(plan_m, subs, picks)
+        _, apply32 = time_apply(torch, plan_m, "explicit")
+        mixed = {"ms_per_step": ms_m, "subdomains_per_s": len(subs) / (ms_m * 1e-3),
+                 "useful_gflops": useful / (ms_m * 1e-3) / 1e9, "kernel_ms": kms_m,
+                 "kernel_tflops": {k: flops[k] / (kms_m[k] * 1e-3) / 1e12 for k in kms_m},
+                 "relF_max_sampled": max(errs_m), "relF_samples": len(errs_m)}
+        extra["explicit_fp32F_ms"] = apply32
+        extra["explicit_fp32F_GBps"] = f_bytes64 / 2 / (apply32 * 1e-3) / 1e9
+        if args.pcpg:
+            lam32 = torch.zeros_like(d)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            plan_m.pcpg(d, lam32, args.pcpg, history=False)
+            pcpg["mixed_s"] = time.perf_counter() - t1
+            pcpg["lambda_rel_err_mixed_vs_fp64"] = float(torch.linalg.norm(lam32 - lam64) / torch.linalg.norm(lam64))
+        if cfg == 5:
+            t_impl = extra["implicit_ms"]
+            for name, t_asm, t_expl in (("fp64", ms_per_step, extra["explicit_fp64F_ms"]),
+                                        ("mixed", ms_m, apply32)):
+                gain = t_impl - t_expl
+                extra[f"amortization_iters_{name}"] = (t_asm / gain) if gain > 0 else None
+        plan_m.destroy()
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(subs, args.cpu_seconds)
+    if cpu:
         log(f"bench: cpu baseline {cpu}")
     s0 = subs[0]
     out = {
         "metric": METRIC,
-        "value": nsub / (ms_per_step * 1e-3),
+        "value": len(subs) / (ms_per_step * 1e-3),
         "unit": "subdomains/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -159,19 +278,21 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": scgen.CONFIG_NAMES[cfg], "subdomains": nsub,
-                   "n": s0.n if cfg == 2 else "6..16 elements per axis",
-                   "m": s0.m if cfg == 2 else "surface DOFs", "precision": "fp64", "staircase": True},
+        "config": {"workload": scgen.CONFIG_NAMES[cfg], "subdomains": len(subs),
+                   "n": s0.n if cfg != 3 else "1029..14739", "m": s0.m if cfg != 3 else "654..4614",
+                   "precision": "fp64", "staircase": True},
         "useful_gflops": useful / (ms_per_step * 1e-3) / 1e9,
         "useful_gflop_per_step": useful / 1e9,
-        "relF_max_sampled": max(errs) if errs else None,
-        "relF_samples": len(errs),
+        "relF_max_sampled": max(errs64),
+        "relF_samples": len(errs64),
         "orig_ms_per_step": orig,
+        "mixed": mixed,
+        "pcpg": pcpg or None,
+        "apply": extra,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
-    plan.destroy()
 
 
 if __name__ == "__main__":

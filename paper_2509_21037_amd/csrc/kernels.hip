@@ -671,9 +671,39 @@ __global__ __launch_bounds__(256) void syrk_stair_f32(
 // F_i is symmetric and stored column-major in the original multiplier order,
 // so q[c] = sum_r F[r, c] p[r] is a dot product with one contiguous column.
 // One workgroup per 32 columns of one subdomain; each wavefront reduces 8
-// columns, reading them with 16-byte loads (FP64 F) or 16-byte loads of four
-// values (FP32 F), accumulating in FP64.
+// columns with the widest loads that keep every column start aligned (up to
+// 16 bytes), accumulating in FP64.
 // ---------------------------------------------------------------------------
+template <class T, int V>
+__device__ __forceinline__ void gemv_columns(const T* __restrict__ Fs, const double* __restrict__ ps, int m, int c0,
+                                             int lane, double (&sum)[8]) {
+    for (int r = V * lane; r < m; r += 64 * V) {
+        double pv[V];
+#pragma unroll
+        for (int e = 0; e < V; ++e) pv[e] = ps[r + e];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int cc = c0 + c;
+            if (cc < m) {
+                const T* col = Fs + (int64_t)cc * m + r;
+                if constexpr (V == 1) {
+                    sum[c] += (double)col[0] * pv[0];
+                } else if constexpr (V == 2 && sizeof(T) == 8) {
+                    const double2 f = *reinterpret_cast<const double2*>(col);
+                    sum[c] += f.x * pv[0] + f.y * pv[1];
+                } else if constexpr (V == 2) {
+                    const float2 f = *reinterpret_cast<const float2*>(col);
+                    sum[c] += (double)f.x * pv[0] + (double)f.y * pv[1];
+                } else {
+                    const float4 f = *reinterpret_cast<const float4*>(col);
+                    sum[c] += (double)f.x * pv[0] + (double)f.y * pv[1] + (double)f.z * pv[2] +
+                              (double)f.w * pv[3];
+                }
+            }
+        }
+    }
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void apply_gemv(
     const SubDev* __restrict__ subs, const int2* __restrict__ items, const T* __restrict__ F,
@@ -686,44 +716,14 @@ __global__ __launch_bounds__(256) void apply_gemv(
     const int wv = threadIdx.x >> 6;
     const T* __restrict__ Fs = F + S.F_off;
     const double* __restrict__ ps = p + S.dual_off;
-    constexpr int V = 16 / sizeof(T);            // values per 16-byte load
     const int c0 = it.y + 8 * wv;
     double sum[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) sum[c] = 0.0;
-    // main part: aligned vector loads when the column start allows it
-    const bool vec = (m % V) == 0;
-    if (vec) {
-        for (int r = V * lane; r < m; r += 64 * V) {
-            double pv[V];
-#pragma unroll
-            for (int e = 0; e < V; ++e) pv[e] = ps[r + e];
-#pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                const int cc = c0 + c;
-                if (cc < m) {
-                    const T* col = Fs + (int64_t)cc * m + r;
-                    if constexpr (V == 2) {
-                        const double2 f = *reinterpret_cast<const double2*>(col);
-                        sum[c] += f.x * pv[0] + f.y * pv[1];
-                    } else {
-                        const float4 f = *reinterpret_cast<const float4*>(col);
-                        sum[c] += (double)f.x * pv[0] + (double)f.y * pv[1] + (double)f.z * pv[2] +
-                                  (double)f.w * pv[3];
-                    }
-                }
-            }
-        }
-    } else {
-        for (int r = lane; r < m; r += 64) {
-            const double pr = ps[r];
-#pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                const int cc = c0 + c;
-                if (cc < m) sum[c] += (double)Fs[(int64_t)cc * m + r] * pr;
-            }
-        }
-    }
+    // widest load that keeps every column start aligned (F blocks start 32-byte aligned)
+    if (sizeof(T) == 4 && (m & 3) == 0) gemv_columns<T, 4>(Fs, ps, m, c0, lane, sum);
+    else if ((m & 1) == 0) gemv_columns<T, 2>(Fs, ps, m, c0, lane, sum);
+    else gemv_columns<T, 1>(Fs, ps, m, c0, lane, sum);
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
         double v = sum[c];
