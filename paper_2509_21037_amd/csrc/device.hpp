@@ -10,6 +10,10 @@ constexpr int kTile = 64;
 constexpr int kStripe = 16;
 constexpr int kMaxPanel = 64;      // GPU panel width bound the TRSM kernel is built for
 constexpr int kSyrkTile = 128;     // edge of an F output tile (two X column tiles)
+// Workgroups are dispatched to the accelerator's XCDs round-robin (workgroup
+// k runs on XCD k mod kNumXcd); work lists are interleaved so that all items
+// of one subdomain share an XCD and its L2.
+constexpr int kNumXcd = 8;
 
 struct SubDev {
     int32_t n, m, nblocks, ntiles;

@@ -80,7 +80,7 @@ __global__ __launch_bounds__(256) void trsm_stair_f64(
     const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
     const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows,
     const double* __restrict__ lval, const int32_t* __restrict__ piv,
-    const int8_t* __restrict__ sgn, double* __restrict__ X)
+    const int8_t* __restrict__ sgn, const int32_t* __restrict__ order, double* __restrict__ X)
 {
     __shared__ double sL[64 * kLdsLd];
     __shared__ double sRd[64];
@@ -88,7 +88,9 @@ __global__ __launch_bounds__(256) void trsm_stair_f64(
     const int wv = threadIdx.x >> 6;
     const int g = lane >> 4;
     const int j = lane & 15;
-    const TileDev T = tiles[blockIdx.x];
+    const int ti = order[blockIdx.x];
+    if (ti < 0) return;
+    const TileDev T = tiles[ti];
     const SubDev S = subs[T.sub];
     const int n = S.n;
     const int kstart = T.kstart;
@@ -107,8 +109,8 @@ __global__ __launch_bounds__(256) void trsm_stair_f64(
     const BlockDev* __restrict__ B = blocks + S.blk_off;
     const int32_t* __restrict__ R = rows + S.rows_off;
     const double* __restrict__ L = lval + S.lval_off;
-    const int my_start = tiles[blockIdx.x].start_block[wv];
-    const int first_block = tiles[blockIdx.x].start_block[0];
+    const int my_start = tiles[ti].start_block[wv];
+    const int first_block = tiles[ti].start_block[0];
 
     double pre[16];
     for (int b = first_block; b < S.nblocks; ++b) {
@@ -240,6 +242,7 @@ __global__ __launch_bounds__(256) void syrk_stair_f64(
     __shared__ double sI[2][kSyrkKC * kSyrkLd];
     __shared__ double sJ[2][kSyrkKC * kSyrkLd];
     const SyrkItem it = items[blockIdx.x];
+    if (it.sub < 0) return;
     const SubDev S = subs[it.sub];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -395,7 +398,7 @@ __global__ __launch_bounds__(256) void trsm_stair_mixed(
     const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
     const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows,
     const double* __restrict__ lval, const float* __restrict__ lval32, const int32_t* __restrict__ piv,
-    const int8_t* __restrict__ sgn, float* __restrict__ X)
+    const int8_t* __restrict__ sgn, const int32_t* __restrict__ order, float* __restrict__ X)
 {
     __shared__ double sL[64 * kLdsLd];        // FP64 diagonal block, reused as the FP32 chunk
     __shared__ double sRd[64];
@@ -404,7 +407,9 @@ __global__ __launch_bounds__(256) void trsm_stair_mixed(
     const int wv = threadIdx.x >> 6;
     const int g = lane >> 4;
     const int j = lane & 15;
-    const TileDev T = tiles[blockIdx.x];
+    const int ti = order[blockIdx.x];
+    if (ti < 0) return;
+    const TileDev T = tiles[ti];
     const SubDev S = subs[T.sub];
     const int n = S.n;
     const int kstart = T.kstart;
@@ -423,8 +428,8 @@ __global__ __launch_bounds__(256) void trsm_stair_mixed(
     const int32_t* __restrict__ R = rows + S.rows_off;
     const double* __restrict__ L = lval + S.lval_off;
     const float* __restrict__ L32 = lval32 + S.lval_off;
-    const int my_start = tiles[blockIdx.x].start_block[wv];
-    const int first_block = tiles[blockIdx.x].start_block[0];
+    const int my_start = tiles[ti].start_block[wv];
+    const int first_block = tiles[ti].start_block[0];
 
     double pre[16];
     float pref[16];
@@ -553,6 +558,7 @@ __global__ __launch_bounds__(256) void syrk_stair_f32(
     __shared__ float sI[2][kSyrkKCF * kSyrkLdF];
     __shared__ float sJ[2][kSyrkKCF * kSyrkLdF];
     const SyrkItem it = items[blockIdx.x];
+    if (it.sub < 0) return;
     const SubDev S = subs[it.sub];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -762,7 +768,7 @@ hipError_t launch_assemble_f64(const DevTables& t, hipStream_t stream, hipEvent_
     if (ev && (e = hipEventRecord(ev[0], stream)) != hipSuccess) return e;
     if (t.ntiles > 0)
         hipLaunchKernelGGL(trsm_stair_f64, dim3((unsigned)t.ntiles), dim3(256), 0, stream, t.subs,
-                           t.tiles, t.blocks, t.rows, t.lval, t.piv, t.sgn, t.X);
+                           t.tiles, t.blocks, t.rows, t.lval, t.piv, t.sgn, t.tile_order, t.X);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], stream)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[2], stream)) != hipSuccess) return e;
@@ -1045,7 +1051,7 @@ hipError_t launch_assemble_mixed(const DevTables& t, hipStream_t stream, hipEven
     if (ev && (e = hipEventRecord(ev[0], stream)) != hipSuccess) return e;
     if (t.ntiles > 0)
         hipLaunchKernelGGL(trsm_stair_mixed, dim3((unsigned)t.ntiles), dim3(256), 0, stream, t.subs,
-                           t.tiles, t.blocks, t.rows, t.lval, t.lval32, t.piv, t.sgn, t.X32);
+                           t.tiles, t.blocks, t.rows, t.lval, t.lval32, t.piv, t.sgn, t.tile_order, t.X32);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], stream)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[2], stream)) != hipSuccess) return e;

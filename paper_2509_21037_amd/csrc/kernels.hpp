@@ -17,13 +17,14 @@ struct DevTables {
     const int32_t* pi = nullptr;
     const int8_t* sgn = nullptr;
     const SyrkItem* syrk = nullptr;
+    const int32_t* tile_order = nullptr;   // TRSM workgroup -> tile index (-1 = idle)
     double* X = nullptr;
     float* X32 = nullptr;
     double* F = nullptr;
     float* F32 = nullptr;
     const int2* apply_items = nullptr;     // (subdomain, first column) per GEMV workgroup
-    int64_t ntiles = 0;
-    int64_t nsyrk = 0;
+    int64_t ntiles = 0;          // TRSM workgroups (length of tile_order)
+    int64_t nsyrk = 0;           // SYRK workgroups (items with sub < 0 are idle)
     int64_t napply = 0;
 };
 

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <memory>
 #include <new>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -93,7 +94,8 @@ struct sc_plan_s {
     std::vector<SubDev> h_subs;
     std::vector<TileDev> h_tiles;
     std::vector<BlockDev> h_blocks;
-    std::vector<SyrkItem> h_syrk;
+    std::vector<SyrkItem> h_syrk;               // interleaved over XCDs, idle items sub = -1
+    std::vector<int32_t> h_tile_order;          // TRSM workgroup -> tile (-1 idle)
     std::vector<int2> h_apply;
     int64_t nval_total = 0, nrows_total = 0, ncol_total = 0, X_total = 0, F_total = 0, dual_total = 0;
     double* h_lval = nullptr;                 // pinned
@@ -102,6 +104,7 @@ struct sc_plan_s {
     DevBuf<TileDev> d_tiles;
     DevBuf<BlockDev> d_blocks;
     DevBuf<SyrkItem> d_syrk;
+    DevBuf<int32_t> d_tile_order;
     DevBuf<int2> d_apply;
     DevBuf<int32_t> d_rows, d_piv, d_pi;
     DevBuf<int8_t> d_sgn;
@@ -154,7 +157,7 @@ struct sc_plan_s {
     int64_t device_bytes() const {
         return (int64_t)(d_subs.count * sizeof(SubDev) + d_tiles.count * sizeof(TileDev) +
                          d_blocks.count * sizeof(BlockDev) + d_syrk.count * sizeof(SyrkItem) +
-                         d_apply.count * sizeof(int2) +
+                         d_apply.count * sizeof(int2) + d_tile_order.count * 4 +
                          (d_rows.count + d_piv.count + d_pi.count) * 4 + d_sgn.count +
                          (d_lval.count + d_X.count + d_F.count) * 8 +
                          (d_lval32.count + d_X32.count + d_F32.count) * 4 +
@@ -162,6 +165,7 @@ struct sc_plan_s {
     }
     void release() {
         d_subs.release(); d_tiles.release(); d_blocks.release(); d_syrk.release(); d_apply.release();
+        d_tile_order.release();
         d_rows.release(); d_piv.release(); d_pi.release(); d_sgn.release();
         d_lval.release(); d_X.release(); d_F.release();
         d_lval32.release(); d_X32.release(); d_F32.release();
@@ -180,7 +184,8 @@ struct sc_plan_s {
         t.X = d_X.p; t.F = d_F.p;
         t.lval32 = d_lval32.p; t.X32 = d_X32.p; t.F32 = d_F32.p;
         t.apply_items = d_apply.p;
-        t.ntiles = (int64_t)h_tiles.size();
+        t.tile_order = d_tile_order.p;
+        t.ntiles = (int64_t)h_tile_order.size();
         t.nsyrk = (int64_t)h_syrk.size();
         t.napply = (int64_t)h_apply.size();
         return t;
@@ -280,6 +285,44 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
         P->trsm_d += sp.trsm_dense;
         P->syrk_d += sp.syrk_dense;
     }
+    // ---- XCD-aware work lists: subdomains go to XCDs by longest-processing-
+    // time on their useful flops; XCD x receives workgroups x, x + 8, ...
+    {
+        std::vector<int32_t> byc(nsub);
+        std::iota(byc.begin(), byc.end(), 0);
+        std::stable_sort(byc.begin(), byc.end(), [&](int32_t a, int32_t b) {
+            return P->plans[a].trsm_useful + P->plans[a].syrk_useful >
+                   P->plans[b].trsm_useful + P->plans[b].syrk_useful;
+        });
+        std::vector<double> load(kNumXcd, 0.0);
+        std::vector<std::vector<int32_t>> xsub(kNumXcd);
+        for (int32_t i : byc) {
+            const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            load[x] += P->plans[i].trsm_useful + P->plans[i].syrk_useful + 1.0;
+            xsub[x].push_back(i);
+        }
+        std::vector<std::vector<int32_t>> xt(kNumXcd);
+        std::vector<std::vector<SyrkItem>> xs(kNumXcd);
+        std::vector<std::vector<SyrkItem>> per_sub(nsub);
+        for (const SyrkItem& it : P->h_syrk) per_sub[it.sub].push_back(it);
+        for (int x = 0; x < kNumXcd; ++x)
+            for (int32_t i : xsub[x]) {
+                const SubDev& sd = P->h_subs[i];
+                for (int32_t t = 0; t < sd.ntiles; ++t) xt[x].push_back((int32_t)(sd.tile_off + t));
+                xs[x].insert(xs[x].end(), per_sub[i].begin(), per_sub[i].end());
+            }
+        size_t lt = 0, ls = 0;
+        for (int x = 0; x < kNumXcd; ++x) {
+            lt = std::max(lt, xt[x].size());
+            ls = std::max(ls, xs[x].size());
+        }
+        P->h_tile_order.assign(lt * kNumXcd, -1);
+        P->h_syrk.assign(ls * kNumXcd, SyrkItem{-1, 0, 0, 0});
+        for (int x = 0; x < kNumXcd; ++x) {
+            for (size_t k = 0; k < xt[x].size(); ++k) P->h_tile_order[k * kNumXcd + x] = xt[x][k];
+            for (size_t k = 0; k < xs[x].size(); ++k) P->h_syrk[k * kNumXcd + x] = xs[x][k];
+        }
+    }
     P->nval_total = lv;
     P->nrows_total = rows;
     P->ncol_total = colo;
@@ -303,6 +346,7 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
     ALLOC(p->d_blocks, p->h_blocks.size());
     ALLOC(p->d_syrk, p->h_syrk.size());
     ALLOC(p->d_apply, p->h_apply.size());
+    ALLOC(p->d_tile_order, p->h_tile_order.size());
     ALLOC(p->d_rows, (size_t)rows);
     ALLOC(p->d_piv, (size_t)colo);
     ALLOC(p->d_pi, (size_t)colo);
@@ -343,6 +387,7 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
     if (e == hipSuccess) e = up(p->d_blocks.p, p->h_blocks.data(), p->h_blocks.size() * sizeof(BlockDev));
     if (e == hipSuccess) e = up(p->d_syrk.p, p->h_syrk.data(), p->h_syrk.size() * sizeof(SyrkItem));
     if (e == hipSuccess) e = up(p->d_apply.p, p->h_apply.data(), p->h_apply.size() * sizeof(int2));
+    if (e == hipSuccess) e = up(p->d_tile_order.p, p->h_tile_order.data(), p->h_tile_order.size() * 4);
     if (e == hipSuccess) e = up(p->d_rows.p, h_rows.data(), h_rows.size() * 4);
     if (e == hipSuccess) e = up(p->d_piv.p, h_piv.data(), h_piv.size() * 4);
     if (e == hipSuccess) e = up(p->d_pi.p, h_pi.data(), h_pi.size() * 4);
