@@ -65,18 +65,28 @@ def measured_traffic(workload, precision, kernel):
     return None if k is None else k["fetch_bytes"] + k["write_bytes"]
 
 
-def time_assembly(torch, plan, steps, warmup):
+def time_assembly(torch, plan, steps, warmup, graph=False):
+    """Wall-clock ms per sc_assemble over `steps` synchronised steps, and the
+    mean per-kernel ms from HIP events (an extra eager pass when the plan
+    replays a captured graph)."""
     for _ in range(warmup):
         plan.assemble()
     torch.cuda.synchronize()
-    plan.set_timing(True)
-    plan.kernel_times(reset=True)
+    if not graph:
+        plan.set_timing(True)
+        plan.kernel_times(reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         plan.assemble()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    if graph:
+        plan.set_timing(True)
+        plan.kernel_times(reset=True)
+        for _ in range(max(1, min(steps, 3))):
+            plan.assemble()
+        torch.cuda.synchronize()
     kt = plan.kernel_times(reset=True)
     plan.set_timing(False)
     return 1e3 * elapsed / steps, {k: kt[k][0] / max(1, kt[k][1]) for k in ("trsm", "syrk")}
@@ -158,6 +168,10 @@ def main():
     ap.add_argument("--pcpg", type=int, default=0, help="PCPG iterations on the FP64 and the mixed F")
     ap.add_argument("--compare-orig", action="store_true", help="also time the assembly without the staircase")
     ap.add_argument("--panel-width", type=int, default=0, help="GPU factor block width (0 = library default)")
+    ap.add_argument("--autotune", choices=("auto", "on", "off"), default="auto",
+                    help="pick the factor block width with sc_autotune (auto: on for the elasticity batches)")
+    ap.add_argument("--graph", choices=("auto", "on", "off"), default="auto",
+                    help="replay the assembly as a captured HIP graph (auto: on for the elasticity batches)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain device copy of 2 GiB first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -185,15 +199,23 @@ def main():
     subs = scgen.config_subdomains(cfg)
     log(f"bench: generated {len(subs)} subdomains in {time.perf_counter() - t0:.1f}s")
     picks = sorted({0, len(subs) // 2, len(subs) - 1})
+    use_graph = args.graph == "on" or (args.graph == "auto" and cfg != 2)
+    tune = None
+    if args.autotune == "on" or (args.autotune == "auto" and cfg != 2 and not args.panel_width):
+        t0 = time.perf_counter()
+        best, times = P.autotune(subs, candidates=(32, 48, 64), sample=64 if cfg == 3 else 8, reps=2)
+        tune = {"panel_width": best, "sample_ms": times, "seconds": time.perf_counter() - t0}
+        args.panel_width = best
+        log(f"bench: autotune {tune}")
 
     # ---------------------------------------------------------------- FP64
     t0 = time.perf_counter()
-    plan = P.Plan(subs, panel_width=args.panel_width)
+    plan = P.Plan(subs, panel_width=args.panel_width, use_graph=use_graph)
     plan.factor()
     torch.cuda.synchronize()
     log(f"bench: FP64 plan + host factorisation + upload in {time.perf_counter() - t0:.1f}s")
     st = plan.stats()
-    ms_per_step, kms = time_assembly(torch, plan, args.steps, args.warmup)
+    ms_per_step, kms = time_assembly(torch, plan, args.steps, args.warmup, use_graph)
     log(f"bench: FP64 {ms_per_step:.3f} ms/step, kernels {kms}")
     useful = st["trsm_useful"] + st["syrk_useful"]
     flops = {"trsm": st["trsm_useful"], "syrk": st["syrk_useful"]}
@@ -234,9 +256,9 @@ def main():
     # ---------------------------------------------------------------- mixed
     mixed = None
     if not args.no_mixed:
-        plan_m = P.Plan(subs, precision="mixed", panel_width=args.panel_width)
+        plan_m = P.Plan(subs, precision="mixed", panel_width=args.panel_width, use_graph=use_graph)
         plan_m.factor()
-        ms_m, kms_m = time_assembly(torch, plan_m, args.steps, args.warmup)
+        ms_m, kms_m = time_assembly(torch, plan_m, args.steps, args.warmup, use_graph)
         log(f"bench: mixed {ms_m:.3f} ms/step, kernels {kms_m}")
         errs_m = sampled_error(plan_m, subs, picks)
         _, apply32 = time_apply(torch, plan_m, "explicit")
@@ -280,7 +302,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": scgen.CONFIG_NAMES[cfg], "subdomains": len(subs),
                    "n": s0.n if cfg != 3 else "1029..14739", "m": s0.m if cfg != 3 else "654..4614",
-                   "precision": "fp64", "staircase": True},
+                   "precision": "fp64", "staircase": True, "panel_width": args.panel_width or 64,
+                   "graph": use_graph},
+        "autotune": tune,
         "useful_gflops": useful / (ms_per_step * 1e-3) / 1e9,
         "useful_gflop_per_step": useful / 1e9,
         "relF_max_sampled": max(errs64),

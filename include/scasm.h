@@ -97,6 +97,10 @@ typedef struct {
  *   relax_width      relaxed supernode amalgamation bound (default 64)
  *   leaf_nodes       nested-dissection leaf size in nodes (default 64)
  *   n_threads        host threads for sc_factor (0 = all cores)
+ *   use_graph        1 = sc_assemble captures its kernel launches once into a
+ *                    HIP graph and replays it on every later call (the plan's
+ *                    buffers and tables are fixed, so the graph stays valid);
+ *                    calls made while kernel timing is enabled launch eagerly
  */
 typedef struct {
     int32_t precision;
@@ -105,7 +109,8 @@ typedef struct {
     int32_t relax_width;
     int32_t leaf_nodes;
     int32_t n_threads;
-    int32_t reserved[8];
+    int32_t use_graph;
+    int32_t reserved[7];
 } sc_options_t;
 
 /* Initialisation stage (Sec. 2.2): ordering, symbolic factorisation, staircase
@@ -199,6 +204,23 @@ sc_status_t sc_plan_stats(sc_plan_t plan, int32_t* nsub, int64_t* dual_total,
  * `reset` != 0 clears the sums after reading.  Arrays hold 4 entries. */
 sc_status_t sc_set_timing(sc_plan_t plan, int32_t enable);
 sc_status_t sc_kernel_times(sc_plan_t plan, double* ms, int64_t* counts, int32_t reset);
+
+/* Autotuner for the factor block width (Sec. 4.1: the block size trades the
+ * zeros skipped against the overhead of small blocks; the best value depends
+ * on the hardware and the subdomain size).  Times sc_assemble for every
+ * candidate width on up to `sample` subdomains of the batch, chosen evenly
+ * over the batch sorted by n, on the current device and `stream`:
+ *   sd, nsub, base    the batch and the options to tune (panel_width ignored)
+ *   kreg_vals         [nsub] CSR values, as for sc_factor
+ *   candidates[ncand] widths to try (each in [16, 64])
+ *   reps              timed repetitions per candidate (>= 1)
+ *   best_width        out: the fastest candidate
+ *   times_ms          optional out [ncand]: mean ms per sc_assemble
+ * Allocates and frees temporary plans.  Errors as sc_plan_create/sc_factor. */
+sc_status_t sc_autotune(const sc_subdomain_desc_t* sd, int32_t nsub, const sc_options_t* base,
+                        const double* const* kreg_vals, const int32_t* candidates, int32_t ncand,
+                        int32_t sample, int32_t reps, void* stream, int32_t* best_width,
+                        double* times_ms);
 
 /* Release every device and host buffer of the plan.  NULL is accepted. */
 sc_status_t sc_plan_destroy(sc_plan_t plan);

@@ -114,6 +114,7 @@ struct sc_plan_s {
     DevBuf<int64_t> d_xoff;
     bool mixed = false;
     bool factored = false, assembled = false;
+    hipGraphExec_t graph_exec = nullptr;        // captured assembly (use_graph)
     double trsm_u = 0, syrk_u = 0, trsm_d = 0, syrk_d = 0;
     // kernel timing: event pairs per kernel, pending until read
     bool timing = false;
@@ -172,6 +173,8 @@ struct sc_plan_s {
         d_xwork.release(); d_xoff.release();
         if (h_lval) (void)hipHostFree(h_lval);
         h_lval = nullptr;
+        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+        graph_exec = nullptr;
         for (auto& p : pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
         for (auto& e : event_pool) (void)hipEventDestroy(e);
         pending.clear();
@@ -453,6 +456,32 @@ sc_status_t sc_assemble(sc_plan_t P, void* stream) {
     if (!P) return fail(SC_ERR_INVALID_ARG, "plan is NULL");
     if (!P->factored) return fail(SC_ERR_STATE, "sc_assemble before sc_factor");
     HIP_TRY(hipSetDevice(P->device));
+    if (P->opt.use_graph && !P->timing) {
+        if (!P->graph_exec) {
+            // capture on a private stream (the caller's may be the null stream,
+            // which cannot be captured), replay on the caller's stream
+            hipStream_t cap;
+            HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                const hipError_t el = P->mixed ? launch_assemble_mixed(P->tables(), cap, nullptr)
+                                               : launch_assemble_f64(P->tables(), cap, nullptr);
+                e = hipStreamEndCapture(cap, &g);
+                if (e == hipSuccess) e = el;
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&P->graph_exec, g, nullptr, nullptr, 0);
+            if (g) (void)hipGraphDestroy(g);
+            (void)hipStreamDestroy(cap);
+            if (e != hipSuccess) {
+                P->graph_exec = nullptr;
+                return fail(SC_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+            }
+        }
+        HIP_TRY(hipGraphLaunch(P->graph_exec, (hipStream_t)stream));
+        P->assembled = true;
+        return SC_OK;
+    }
     hipEvent_t ev[4];
     hipEvent_t* evp = nullptr;
     if (P->timing) {
@@ -751,6 +780,68 @@ sc_status_t sc_kernel_times(sc_plan_t P, double* ms, int64_t* counts, int32_t re
         if (reset) { P->ms_sum[k] = 0; P->ms_count[k] = 0; }
     }
     return SC_OK;
+}
+
+sc_status_t sc_autotune(const sc_subdomain_desc_t* sd, int32_t nsub, const sc_options_t* base,
+                        const double* const* kreg_vals, const int32_t* candidates, int32_t ncand,
+                        int32_t sample, int32_t reps, void* stream, int32_t* best_width, double* times_ms) {
+    g_last_error.clear();
+    if (!sd || nsub <= 0 || !kreg_vals || !candidates || ncand <= 0 || !best_width || reps < 1)
+        return fail(SC_ERR_INVALID_ARG, "bad autotune arguments");
+    for (int32_t c = 0; c < ncand; ++c)
+        if (candidates[c] < 16 || candidates[c] > kMaxPanel)
+            return fail(SC_ERR_INVALID_ARG, "candidate width out of [16, 64]");
+    // size-stratified sample
+    std::vector<int32_t> idx(nsub);
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) { return sd[a].n < sd[b].n; });
+    const int32_t ns = std::max(1, std::min(sample > 0 ? sample : nsub, nsub));
+    std::vector<sc_subdomain_desc_t> sub(ns);
+    std::vector<const double*> vals(ns);
+    for (int32_t k = 0; k < ns; ++k) {
+        const int32_t i = idx[(int64_t)k * nsub / ns];
+        sub[k] = sd[i];
+        vals[k] = kreg_vals[i];
+    }
+    sc_options_t o{};
+    if (base) o = *base;
+    o.use_graph = 0;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    double best = 1e300;
+    sc_status_t status = SC_OK;
+    for (int32_t c = 0; c < ncand && status == SC_OK; ++c) {
+        o.panel_width = candidates[c];
+        sc_plan_t P = nullptr;
+        status = sc_plan_create(sub.data(), ns, &o, stream, &P);
+        if (status == SC_OK) status = sc_factor(P, vals.data(), stream, nullptr, nullptr);
+        if (status == SC_OK) status = sc_assemble(P, stream);          // warm-up
+        float ms = 0.f;
+        if (status == SC_OK) {
+            hipError_t e = hipEventRecord(e0, st);
+            for (int32_t r = 0; r < reps && e == hipSuccess; ++r)
+                if (sc_assemble(P, stream) != SC_OK) e = hipErrorUnknown;
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) status = fail(SC_ERR_DEVICE, "autotune timing failed");
+        }
+        const std::string keep = g_last_error;
+        sc_plan_destroy(P);
+        g_last_error = keep;
+        if (status != SC_OK) break;
+        const double t = ms / reps;
+        if (times_ms) times_ms[c] = t;
+        if (t < best) {
+            best = t;
+            *best_width = candidates[c];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return status;
 }
 
 sc_status_t sc_plan_destroy(sc_plan_t P) {

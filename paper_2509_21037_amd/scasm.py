@@ -17,7 +17,7 @@ STATUS_NAMES = {0: "SC_OK", 1: "SC_ERR_INVALID_ARG", 2: "SC_ERR_NOT_SPD", 3: "SC
 
 EXPORTED = ["sc_plan_create", "sc_factor", "sc_assemble", "sc_apply", "sc_apply_implicit",
             "sc_get_F", "sc_query", "sc_plan_stats", "sc_plan_destroy", "sc_host_analyze",
-            "sc_set_timing", "sc_kernel_times", "sc_pcpg", "sc_last_error"]
+            "sc_set_timing", "sc_kernel_times", "sc_pcpg", "sc_autotune", "sc_last_error"]
 
 
 class ScasmError(RuntimeError):
@@ -40,7 +40,7 @@ class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("disable_staircase", ctypes.c_int32),
                 ("panel_width", ctypes.c_int32), ("relax_width", ctypes.c_int32),
                 ("leaf_nodes", ctypes.c_int32), ("n_threads", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 8)]
+                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
 
 
 class HostInfo(ctypes.Structure):
@@ -76,6 +76,9 @@ def load():
         lib.sc_host_analyze.argtypes = [ctypes.POINTER(SubdomainDesc), ctypes.POINTER(Options), vp, vp, vp,
                                          vp, vp, ctypes.POINTER(HostInfo), ctypes.POINTER(i32)]
         lib.sc_pcpg.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(i32), vp, vp, i32, vp, vp]
+        lib.sc_autotune.argtypes = [ctypes.POINTER(SubdomainDesc), i32, ctypes.POINTER(Options),
+                                    ctypes.POINTER(vp), ctypes.POINTER(i32), i32, i32, i32, vp,
+                                    ctypes.POINTER(i32), dp]
         lib.sc_set_timing.argtypes = [vp, i32]
         lib.sc_kernel_times.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), i32]
         lib.sc_last_error.argtypes = []
@@ -132,8 +135,10 @@ def _fill_desc(d, s, keep, use_coords=True):
     d.dofs_per_node = int(getattr(s, "dofs_per_node", 1))
 
 
-def _options(precision="fp64", staircase=True, panel_width=0, relax_width=0, leaf_nodes=0, n_threads=0):
+def _options(precision="fp64", staircase=True, panel_width=0, relax_width=0, leaf_nodes=0, n_threads=0,
+             use_graph=False):
     opt = Options()
+    opt.use_graph = 1 if use_graph else 0
     opt.precision = {"fp64": SC_PREC_FP64, "mixed": SC_PREC_MIXED}.get(precision, precision) \
         if isinstance(precision, str) else int(precision)
     opt.disable_staircase = 0 if staircase else 1
@@ -171,13 +176,33 @@ def host_analyze(s, values=True, want_L=False, use_coords=True, **opts):
     return out
 
 
+def autotune(subdomains, candidates=(32, 48, 64), sample=64, reps=3, use_coords=True, stream=None, **opts):
+    """Fastest factor block width for this batch (sc_autotune): returns
+    (best_width, {width: mean ms per assembly of the sample})."""
+    lib = load()
+    keep = []
+    subs = list(subdomains)
+    descs = (SubdomainDesc * len(subs))()
+    for i, s in enumerate(subs):
+        _fill_desc(descs[i], s, keep, use_coords)
+    arrs = [np.ascontiguousarray(s.val, dtype=np.float64) for s in subs]
+    ptrs = (ctypes.c_void_p * len(arrs))(*[a.ctypes.data for a in arrs])
+    cands = (ctypes.c_int32 * len(candidates))(*candidates)
+    times = (ctypes.c_double * len(candidates))()
+    best = ctypes.c_int32(0)
+    opt = _options(**opts)
+    _check(lib.sc_autotune(descs, len(subs), ctypes.byref(opt), ptrs, cands, len(candidates), int(sample),
+                           int(reps), _stream_handle(stream), ctypes.byref(best), times))
+    return best.value, {c: times[i] for i, c in enumerate(candidates)}
+
+
 class Plan:
     """A batch of subdomains (objects with n, rowptr, col, val, dof, sign and
     optional coords, dim, dofs_per_node, perm attributes)."""
 
     def __init__(self, subdomains: Sequence, precision: str = "fp64", staircase: bool = True,
                  panel_width: int = 0, relax_width: int = 0, leaf_nodes: int = 0, n_threads: int = 0,
-                 use_coords: bool = True, stream=None):
+                 use_coords: bool = True, use_graph: bool = False, stream=None):
         lib = load()
         self._lib = lib
         self._h = ctypes.c_void_p(0)
@@ -187,7 +212,7 @@ class Plan:
         descs = (SubdomainDesc * max(1, len(self.subdomains)))()
         for i, s in enumerate(self.subdomains):
             _fill_desc(descs[i], s, keep, use_coords)
-        opt = _options(precision, staircase, panel_width, relax_width, leaf_nodes, n_threads)
+        opt = _options(precision, staircase, panel_width, relax_width, leaf_nodes, n_threads, use_graph)
         _check(lib.sc_plan_create(descs, len(self.subdomains), ctypes.byref(opt), _stream_handle(stream),
                                   ctypes.byref(self._h)))
         del keep

@@ -317,3 +317,33 @@ def test_implicit_apply_matches_oracle(precision):
             Bt = s.Bt_dense()
             ref = Bt.T @ spla.spsolve(s.Kreg_csr().tocsc(), Bt @ ph[o:o + s.m])
         assert np.linalg.norm(qh[o:o + s.m] - ref) <= 1e-12 * np.linalg.norm(ref), i
+
+
+# ---------------------------------------------------------------- HIP graph
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_graph_replays_match_eager(precision):
+    """The captured assembly, replayed several times with eager work and
+    synchronisations in between, gives the eager result every time."""
+    torch = _torch_init()
+    subs = scgen.config_subdomains(3, count=4) + scgen.config_subdomains(1)
+    eager = _assemble(subs, precision=precision)
+    ref = [eager.get_F(i) for i in range(len(subs))]
+    plan = P.Plan(subs, precision=precision, use_graph=True)
+    plan.factor()
+    for rep in range(3):
+        junk = torch.randn(1 << 20, device="cuda")          # eager work between replays
+        plan.assemble()
+        junk.mul_(2.0)
+        torch.cuda.synchronize()
+        for i in range(len(subs)):
+            assert np.array_equal(plan.get_F(i), ref[i]), (rep, i)
+
+
+def test_autotune_picks_a_candidate():
+    _torch_init()
+    subs = scgen.config_subdomains(3, count=12)
+    best, times = P.autotune(subs, candidates=(32, 64), sample=6, reps=1)
+    assert best in (32, 64)
+    assert all(t > 0 for t in times.values())
+    assert times[best] == min(times.values())
