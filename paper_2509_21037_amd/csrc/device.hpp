@@ -43,8 +43,9 @@ struct SyrkItem {
 
 struct BlockDev {
     int32_t row0, w, nbelow, ld;
-    int64_t lval_off;    // relative to the subdomain's lval_off
+    int64_t lval_off;    // diagonal block (w x w, column-major), relative to the subdomain's lval_off
     int64_t rows_off;    // relative to the subdomain's rows_off
+    int64_t aoff;        // pruned rows as MFMA A tiles, relative to the subdomain's lval_off
 };
 
 }  // namespace scasm

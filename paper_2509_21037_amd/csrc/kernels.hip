@@ -45,38 +45,73 @@ __device__ __forceinline__ void wave_sync() {
 //      the reciprocal of the diagonal, column-wise elimination), each followed
 //      by an MFMA update of the sub-blocks below it inside the diagonal block;
 //   3. the solved rows are stored, then the pruned rows below the block are
-//      updated in chunks of 64, X[R_b] -= L[R_b, b] X[b], with FP64 MFMA:
-//      each chunk of the factor panel is loaded once into LDS for all four
-//      wavefronts (the next chunk is prefetched into registers meanwhile).
+//      updated 64 at a time, X[R_b] -= L[R_b, b] X[b], with FP64 MFMA whose A
+//      operands are read straight from the factor's tile layout (coalesced,
+//      shared by the four wavefronts through the caches).  The first 64 rows
+//      are gathered during step 1: the diagonal solve never writes them.
+// X rows a stripe has not updated yet are not read: the right-hand side (sign
+// at the pivot, zero elsewhere) is used instead, tracked by one bit per row
+// and stripe in LDS.
 // ---------------------------------------------------------------------------
-constexpr int kLdsLd = 64 + 2;            // LDS leading dimension (doubles) of a staged chunk
+constexpr int kLdsLd = 64 + 2;            // LDS leading dimension (doubles) of the diagonal block
+constexpr int kTouchRows = 32768;         // rows covered by the per-stripe "touched" bitmaps
 
-// Loads rows [r0, r0 + 64) x columns [0, w) of a column-major panel (leading
-// dimension ld, nrows valid rows) into 16 registers per thread, negated when
-// `neg` (the update subtracts).
-__device__ __forceinline__ void load_chunk(const double* __restrict__ panel, int ld, int nrows, int w,
-                                           int r0, bool neg, double (&reg)[16]) {
+__device__ __forceinline__ bool touched(const uint32_t* bits, int row) {
+    return (bits[row >> 5] >> (row & 31)) & 1u;
+}
+
+// Stages the w x w diagonal block (column-major, leading dimension w) into
+// LDS [k][kLdsLd], zero padded to 64 x 64; 16 values per thread.
+template <class T>
+__device__ __forceinline__ void stage_diag(const T* __restrict__ Ld, int w, double* __restrict__ sL) {
 #pragma unroll
     for (int it = 0; it < 16; ++it) {
         const int e = threadIdx.x + 256 * it;
         const int row = e & 63;
         const int k = e >> 6;
-        const int gr = r0 + row;
-        double v = 0.0;
-        if (k < w && gr < nrows) v = panel[(int64_t)k * ld + gr];
-        reg[it] = neg ? -v : v;
+        sL[k * kLdsLd + row] = (k < w && row < w) ? (double)Ld[k * w + row] : 0.0;
     }
 }
 
-__device__ __forceinline__ void store_chunk(double* __restrict__ sL, const double (&reg)[16]) {
+// FP64 solve of the stripe's diagonal-block rows in place (xr: MFMA
+// accumulator layout, 4 sub-tiles of 16 rows); sL holds the diagonal block,
+// sRd the reciprocals of its diagonal.
+__device__ __forceinline__ void diag_solve(v4d (&xr)[4], const double* __restrict__ sL,
+                                           const double* __restrict__ sRd, int w, int g, int j) {
 #pragma unroll
-    for (int it = 0; it < 16; ++it) {
-        const int e = threadIdx.x + 256 * it;
-        sL[(e >> 6) * kLdsLd + (e & 63)] = reg[it];
+    for (int t = 0; t < 4; ++t) {
+        if (16 * t < w) {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                if (16 * t + k < w) {
+                    const int gk = k & 3;
+                    const int rk = k >> 2;
+                    const double xk_own = xr[t][rk] * sRd[16 * t + k];
+                    if (g == gk) xr[t][rk] = xk_own;
+                    const double xk = __shfl(xk_own, j + 16 * gk, 64);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int ii = 4 * r + g;
+                        const double lik = sL[(16 * t + k) * kLdsLd + 16 * t + ii];
+                        if (ii > k) xr[t][r] -= lik * xk;
+                    }
+                }
+            }
+#pragma unroll
+            for (int t2 = t + 1; t2 < 4; ++t2) {
+                if (16 * t2 < w) {
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const double a = -sL[(16 * t + 4 * s + g) * kLdsLd + 16 * t2 + j];
+                        xr[t2] = mfma_f64(a, xr[t][s], xr[t2]);
+                    }
+                }
+            }
+        }
     }
 }
 
-__global__ __launch_bounds__(256) void trsm_stair_f64(
+__global__ __launch_bounds__(256, 2) void trsm_stair_f64(
     const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
     const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows,
     const double* __restrict__ lval, const int32_t* __restrict__ piv,
@@ -84,6 +119,7 @@ __global__ __launch_bounds__(256) void trsm_stair_f64(
 {
     __shared__ double sL[64 * kLdsLd];
     __shared__ double sRd[64];
+    __shared__ uint32_t sTouch[4][kTouchRows / 32];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int g = lane >> 4;
@@ -97,126 +133,114 @@ __global__ __launch_bounds__(256) void trsm_stair_f64(
     double* __restrict__ Xs = X + T.x_off;
     const int col = wv * kStripe + j;
     const int64_t cbase = S.col_off + (int64_t)T.tile * kTile;
-
-    // initial right-hand side: zero trapezoid, sign at the pivot row
-    const int nrows = n - kstart;
-    for (int r = g; r < nrows; r += 4) Xs[(int64_t)r * kTile + col] = 0.0;
-    __threadfence_block();
-    if (g == 0 && col < T.ncols)
-        Xs[(int64_t)(piv[cbase + col] - kstart) * kTile + col] = (double)sgn[cbase + col];
-    __syncthreads();
-
     const BlockDev* __restrict__ B = blocks + S.blk_off;
     const int32_t* __restrict__ R = rows + S.rows_off;
     const double* __restrict__ L = lval + S.lval_off;
     const int my_start = tiles[ti].start_block[wv];
     const int first_block = tiles[ti].start_block[0];
 
-    double pre[16];
+    // Right-hand side P B^T: sign at the pivot row, zero elsewhere.  Only the
+    // rows above the stripe's first block, which no block step writes, are
+    // zero-filled; subdomains beyond the bitmap size zero-fill the whole slab.
+    uint32_t* __restrict__ tb = sTouch[wv];
+    const bool lazy = n <= kTouchRows;
+    const int mypiv = col < T.ncols ? piv[cbase + col] : -1;
+    const double mysgn = col < T.ncols ? (double)sgn[cbase + col] : 0.0;
+    const int first_row = lazy ? (my_start < S.nblocks ? B[my_start].row0 : n) : n;
+    for (int r = kstart + g; r < first_row; r += 4) Xs[(int64_t)(r - kstart) * kTile + col] = 0.0;
+    if (lazy) {
+        for (int wd = lane; wd < (n + 31) / 32; wd += 64) tb[wd] = 0u;
+    } else {
+        __threadfence_block();
+        if (g == 0 && col < T.ncols) Xs[(int64_t)(mypiv - kstart) * kTile + col] = mysgn;
+    }
+    __syncthreads();
+    auto xval = [&](int row) -> double {
+        if (!lazy || touched(tb, row)) return Xs[(int64_t)(row - kstart) * kTile + col];
+        return row == mypiv ? mysgn : 0.0;
+    };
+
     for (int b = first_block; b < S.nblocks; ++b) {
         const BlockDev bd = B[b];
         const int w = bd.w;
-        const int ld = bd.ld;
         const int row0 = bd.row0;
         const int nb = bd.nbelow;
-        const double* __restrict__ Lb = L + bd.lval_off;
+        const int nks = (w + 3) / 4;
+        const int nrt = (nb + 15) / 16;
+        const double* __restrict__ At = L + bd.aoff;
+        const int32_t* __restrict__ rw = R + bd.rows_off;
         const bool act = b >= my_start;
 
-        // ---- stage the diagonal block (rows [0, w) of the panel)
-        load_chunk(Lb, ld, w, w, 0, false, pre);
-        __syncthreads();                 // previous users of sL are done
-        store_chunk(sL, pre);
-        __syncthreads();
-        if (threadIdx.x < 64) sRd[threadIdx.x] = threadIdx.x < w ? 1.0 / sL[threadIdx.x * (kLdsLd + 1)] : 0.0;
-        if (nb > 0) load_chunk(Lb, ld, w + nb, w, w, true, pre);     // prefetch first below chunk
-        __syncthreads();
-
-        v4d xr[4];
-        if (act) {
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int i = 16 * t + 4 * r + g;
-                    const int row = row0 + i;
-                    xr[t][r] = (i < w && row >= kstart) ? Xs[(int64_t)(row - kstart) * kTile + col] : 0.0;
-                }
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                if (16 * t < w) {
-#pragma unroll
-                    for (int k = 0; k < 16; ++k) {
-                        if (16 * t + k < w) {
-                            const int gk = k & 3;
-                            const int rk = k >> 2;
-                            const double xk_own = xr[t][rk] * sRd[16 * t + k];
-                            if (g == gk) xr[t][rk] = xk_own;
-                            const double xk = __shfl(xk_own, j + 16 * gk, 64);
-#pragma unroll
-                            for (int r = 0; r < 4; ++r) {
-                                const int ii = 4 * r + g;
-                                const double lik = sL[(16 * t + k) * kLdsLd + 16 * t + ii];
-                                if (ii > k) xr[t][r] -= lik * xk;
-                            }
-                        }
-                    }
-#pragma unroll
-                    for (int t2 = t + 1; t2 < 4; ++t2) {
-                        if (16 * t2 < w) {
-#pragma unroll
-                            for (int s = 0; s < 4; ++s) {
-                                const double a = -sL[(16 * t + 4 * s + g) * kLdsLd + 16 * t2 + j];
-                                xr[t2] = mfma_f64(a, xr[t][s], xr[t2]);
-                            }
-                        }
-                    }
-                }
-            }
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int i = 16 * t + 4 * r + g;
-                    const int row = row0 + i;
-                    if (i < w && row >= kstart) Xs[(int64_t)(row - kstart) * kTile + col] = xr[t][r];
-                }
-        }
-
-        // ---- pruned rows below the block, 64 at a time
-        const int32_t* __restrict__ rw = R + bd.rows_off;
-        for (int q0 = 0; q0 < nb; q0 += 64) {
-            __syncthreads();             // sL free (diagonal block or previous chunk)
-            store_chunk(sL, pre);
-            if (q0 + 64 < nb) load_chunk(Lb, ld, w + nb, w, w + q0 + 64, true, pre);
-            __syncthreads();
-            if (!act) continue;
-            v4d acc[4];
-            int32_t off[4][4];
+        v4d acc[4];
+        auto gather = [&](int q0) {
 #pragma unroll
             for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int q = q0 + 16 * rt + 4 * r + g;
-                    off[rt][r] = q < nb ? (rw[q] - kstart) * kTile + col : -1;
-                    acc[rt][r] = off[rt][r] >= 0 ? Xs[off[rt][r]] : 0.0;
+                    acc[rt][r] = q < nb ? xval(rw[q]) : 0.0;
                 }
+        };
+        __syncthreads();                 // previous block done with sL; its stores ordered
+        if (act && nb > 0) gather(0);    // rows below this block: the diagonal solve never writes them
+        stage_diag(L + bd.lval_off, w, sL);
+        __syncthreads();
+        if (threadIdx.x < 64) sRd[threadIdx.x] = threadIdx.x < w ? 1.0 / sL[threadIdx.x * (kLdsLd + 1)] : 0.0;
+        __syncthreads();
+        if (!act) continue;
+
+        v4d xr[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = 16 * t + 4 * r + g;
+                const int row = row0 + i;
+                xr[t][r] = (i < w && row >= kstart) ? xval(row) : 0.0;
+            }
+        diag_solve(xr, sL, sRd, w, g, j);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = 16 * t + 4 * r + g;
+                const int row = row0 + i;
+                if (i < w && row >= kstart) Xs[(int64_t)(row - kstart) * kTile + col] = xr[t][r];
+            }
+
+        for (int q0 = 0; q0 < nb; q0 += 64) {
+            if (q0 > 0) gather(q0);
+            const int rt0 = q0 >> 4;
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                if (16 * t < w) {
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) {
-                        const double* sk = sL + (16 * t + 4 * s + g) * kLdsLd + j;
+                for (int s = 0; s < 4; ++s) {
+                    const int ks = 4 * t + s;
+                    if (ks < nks) {
 #pragma unroll
-                        for (int rt = 0; rt < 4; ++rt)
-                            acc[rt] = mfma_f64(sk[16 * rt], xr[t][s], acc[rt]);
+                        for (int rt = 0; rt < 4; ++rt) {
+                            const double a = rt0 + rt < nrt ? -At[((int64_t)(rt0 + rt) * nks + ks) * 64 + lane] : 0.0;
+                            acc[rt] = mfma_f64(a, xr[t][s], acc[rt]);
+                        }
                     }
                 }
             }
 #pragma unroll
             for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    if (off[rt][r] >= 0) Xs[off[rt][r]] = acc[rt][r];
+                for (int r = 0; r < 4; ++r) {
+                    const int q = q0 + 16 * rt + 4 * r + g;
+                    if (q < nb) Xs[(int64_t)(rw[q] - kstart) * kTile + col] = acc[rt][r];
+                }
+            if (lazy && j == 0) {
+#pragma unroll
+                for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int q = q0 + 16 * rt + 4 * r + g;
+                        if (q < nb) atomicOr(&tb[rw[q] >> 5], 1u << (rw[q] & 31));
+                    }
+            }
         }
     }
 }
@@ -378,31 +402,15 @@ __global__ __launch_bounds__(256) void convert_f64_f32(const double* __restrict_
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) b[i] = (float)a[i];
 }
 
-constexpr int kLdsLdF = 64 + 4;           // LDS leading dimension (floats) of an FP32 chunk
-
-__device__ __forceinline__ void load_chunk_f32(const float* __restrict__ panel, int ld, int nrows, int w,
-                                               int r0, float (&reg)[16]) {
-#pragma unroll
-    for (int it = 0; it < 16; ++it) {
-        const int e = threadIdx.x + 256 * it;
-        const int row = e & 63;
-        const int k = e >> 6;
-        const int gr = r0 + row;
-        float v = 0.0f;
-        if (k < w && gr < nrows) v = panel[(int64_t)k * ld + gr];
-        reg[it] = -v;
-    }
-}
-
-__global__ __launch_bounds__(256) void trsm_stair_mixed(
+__global__ __launch_bounds__(256, 2) void trsm_stair_mixed(
     const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
     const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows,
     const double* __restrict__ lval, const float* __restrict__ lval32, const int32_t* __restrict__ piv,
     const int8_t* __restrict__ sgn, const int32_t* __restrict__ order, float* __restrict__ X)
 {
-    __shared__ double sL[64 * kLdsLd];        // FP64 diagonal block, reused as the FP32 chunk
+    __shared__ double sL[64 * kLdsLd];
     __shared__ double sRd[64];
-    float* sLf = reinterpret_cast<float*>(sL);
+    __shared__ uint32_t sTouch[4][kTouchRows / 32];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int g = lane >> 4;
@@ -416,14 +424,6 @@ __global__ __launch_bounds__(256) void trsm_stair_mixed(
     float* __restrict__ Xs = X + T.x_off;
     const int col = wv * kStripe + j;
     const int64_t cbase = S.col_off + (int64_t)T.tile * kTile;
-
-    const int nrows = n - kstart;
-    for (int r = g; r < nrows; r += 4) Xs[(int64_t)r * kTile + col] = 0.0f;
-    __threadfence_block();
-    if (g == 0 && col < T.ncols)
-        Xs[(int64_t)(piv[cbase + col] - kstart) * kTile + col] = (float)sgn[cbase + col];
-    __syncthreads();
-
     const BlockDev* __restrict__ B = blocks + S.blk_off;
     const int32_t* __restrict__ R = rows + S.rows_off;
     const double* __restrict__ L = lval + S.lval_off;
@@ -431,116 +431,107 @@ __global__ __launch_bounds__(256) void trsm_stair_mixed(
     const int my_start = tiles[ti].start_block[wv];
     const int first_block = tiles[ti].start_block[0];
 
-    double pre[16];
-    float pref[16];
+    uint32_t* __restrict__ tb = sTouch[wv];
+    const bool lazy = n <= kTouchRows;
+    const int mypiv = col < T.ncols ? piv[cbase + col] : -1;
+    const float mysgn = col < T.ncols ? (float)sgn[cbase + col] : 0.0f;
+    const int first_row = lazy ? (my_start < S.nblocks ? B[my_start].row0 : n) : n;
+    for (int r = kstart + g; r < first_row; r += 4) Xs[(int64_t)(r - kstart) * kTile + col] = 0.0f;
+    if (lazy) {
+        for (int wd = lane; wd < (n + 31) / 32; wd += 64) tb[wd] = 0u;
+    } else {
+        __threadfence_block();
+        if (g == 0 && col < T.ncols) Xs[(int64_t)(mypiv - kstart) * kTile + col] = mysgn;
+    }
+    __syncthreads();
+    auto xval = [&](int row) -> float {
+        if (!lazy || touched(tb, row)) return Xs[(int64_t)(row - kstart) * kTile + col];
+        return row == mypiv ? mysgn : 0.0f;
+    };
+
     for (int b = first_block; b < S.nblocks; ++b) {
         const BlockDev bd = B[b];
         const int w = bd.w;
-        const int ld = bd.ld;
         const int row0 = bd.row0;
         const int nb = bd.nbelow;
-        const double* __restrict__ Lb = L + bd.lval_off;
-        const float* __restrict__ Lb32 = L32 + bd.lval_off;
+        const int nks = (w + 3) / 4;
+        const int nrt = (nb + 15) / 16;
+        const float* __restrict__ At = L32 + bd.aoff;
+        const int32_t* __restrict__ rw = R + bd.rows_off;
         const bool act = b >= my_start;
 
-        load_chunk(Lb, ld, w, w, 0, false, pre);
-        __syncthreads();
-        store_chunk(sL, pre);
-        __syncthreads();
-        if (threadIdx.x < 64) sRd[threadIdx.x] = threadIdx.x < w ? 1.0 / sL[threadIdx.x * (kLdsLd + 1)] : 0.0;
-        if (nb > 0) load_chunk_f32(Lb32, ld, w + nb, w, w, pref);
-        __syncthreads();
-
-        v4d xr[4];
-        float xb[4][4];
-        if (act) {
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int i = 16 * t + 4 * r + g;
-                    const int row = row0 + i;
-                    xr[t][r] = (i < w && row >= kstart) ? (double)Xs[(int64_t)(row - kstart) * kTile + col] : 0.0;
-                }
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                if (16 * t < w) {
-#pragma unroll
-                    for (int k = 0; k < 16; ++k) {
-                        if (16 * t + k < w) {
-                            const int gk = k & 3;
-                            const int rk = k >> 2;
-                            const double xk_own = xr[t][rk] * sRd[16 * t + k];
-                            if (g == gk) xr[t][rk] = xk_own;
-                            const double xk = __shfl(xk_own, j + 16 * gk, 64);
-#pragma unroll
-                            for (int r = 0; r < 4; ++r) {
-                                const int ii = 4 * r + g;
-                                const double lik = sL[(16 * t + k) * kLdsLd + 16 * t + ii];
-                                if (ii > k) xr[t][r] -= lik * xk;
-                            }
-                        }
-                    }
-#pragma unroll
-                    for (int t2 = t + 1; t2 < 4; ++t2) {
-                        if (16 * t2 < w) {
-#pragma unroll
-                            for (int s = 0; s < 4; ++s) {
-                                const double a = -sL[(16 * t + 4 * s + g) * kLdsLd + 16 * t2 + j];
-                                xr[t2] = mfma_f64(a, xr[t][s], xr[t2]);
-                            }
-                        }
-                    }
-                }
-            }
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int i = 16 * t + 4 * r + g;
-                    const int row = row0 + i;
-                    xb[t][r] = (float)xr[t][r];
-                    if (i < w && row >= kstart) Xs[(int64_t)(row - kstart) * kTile + col] = xb[t][r];
-                }
-        }
-
-        const int32_t* __restrict__ rw = R + bd.rows_off;
-        for (int q0 = 0; q0 < nb; q0 += 64) {
-            __syncthreads();
-#pragma unroll
-            for (int it = 0; it < 16; ++it) {
-                const int e = threadIdx.x + 256 * it;
-                sLf[(e >> 6) * kLdsLdF + (e & 63)] = pref[it];
-            }
-            if (q0 + 64 < nb) load_chunk_f32(Lb32, ld, w + nb, w, w + q0 + 64, pref);
-            __syncthreads();
-            if (!act) continue;
-            v4f acc[4];
-            int32_t off[4][4];
+        v4f acc[4];
+        auto gather = [&](int q0) {
 #pragma unroll
             for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int q = q0 + 16 * rt + 4 * g + r;
-                    off[rt][r] = q < nb ? (rw[q] - kstart) * kTile + col : -1;
-                    acc[rt][r] = off[rt][r] >= 0 ? Xs[off[rt][r]] : 0.0f;
+                    acc[rt][r] = q < nb ? xval(rw[q]) : 0.0f;
                 }
+        };
+        __syncthreads();
+        if (act && nb > 0) gather(0);
+        stage_diag(L + bd.lval_off, w, sL);
+        __syncthreads();
+        if (threadIdx.x < 64) sRd[threadIdx.x] = threadIdx.x < w ? 1.0 / sL[threadIdx.x * (kLdsLd + 1)] : 0.0;
+        __syncthreads();
+        if (!act) continue;
+
+        v4d xr[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = 16 * t + 4 * r + g;
+                const int row = row0 + i;
+                xr[t][r] = (i < w && row >= kstart) ? (double)xval(row) : 0.0;
+            }
+        diag_solve(xr, sL, sRd, w, g, j);
+        float xb[4][4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = 16 * t + 4 * r + g;
+                const int row = row0 + i;
+                xb[t][r] = (float)xr[t][r];
+                if (i < w && row >= kstart) Xs[(int64_t)(row - kstart) * kTile + col] = xb[t][r];
+            }
+
+        for (int q0 = 0; q0 < nb; q0 += 64) {
+            if (q0 > 0) gather(q0);
+            const int rt0 = q0 >> 4;
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                if (16 * t < w) {
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) {
-                        const float* sk = sLf + (16 * t + 4 * s + g) * kLdsLdF + j;
+                for (int s = 0; s < 4; ++s) {
+                    const int ks = 4 * t + s;
+                    if (ks < nks) {
 #pragma unroll
-                        for (int rt = 0; rt < 4; ++rt) acc[rt] = mfma_f32(sk[16 * rt], xb[t][s], acc[rt]);
+                        for (int rt = 0; rt < 4; ++rt) {
+                            const float a = rt0 + rt < nrt ? -At[((int64_t)(rt0 + rt) * nks + ks) * 64 + lane] : 0.0f;
+                            acc[rt] = mfma_f32(a, xb[t][s], acc[rt]);
+                        }
                     }
                 }
             }
 #pragma unroll
             for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    if (off[rt][r] >= 0) Xs[off[rt][r]] = acc[rt][r];
+                for (int r = 0; r < 4; ++r) {
+                    const int q = q0 + 16 * rt + 4 * g + r;
+                    if (q < nb) Xs[(int64_t)(rw[q] - kstart) * kTile + col] = acc[rt][r];
+                }
+            if (lazy && j == 0) {
+#pragma unroll
+                for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int q = q0 + 16 * rt + 4 * g + r;
+                        if (q < nb) atomicOr(&tb[rw[q] >> 5], 1u << (rw[q] & 31));
+                    }
+            }
         }
     }
 }
@@ -959,14 +950,19 @@ __global__ __launch_bounds__(256) void implicit_apply(
     }
     __syncthreads();
 
+    // L[q][k] of the pruned rows, tile layout (see BlockDesc)
+    auto lbelow = [&](const double* At, int nks, int q, int k) {
+        return At[((int64_t)(q >> 4) * nks + (k >> 2)) * 64 + (q & 15) + 16 * (k & 3)];
+    };
     // ---- forward
     for (int b = 0; b < S.nblocks; ++b) {
         const BlockDev bd = B[b];
-        const int w = bd.w, ld = bd.ld, nb = bd.nbelow, row0 = bd.row0;
+        const int w = bd.w, nb = bd.nbelow, row0 = bd.row0, nks = (w + 3) / 4;
         const double* __restrict__ Lb = L + bd.lval_off;
+        const double* __restrict__ At = L + bd.aoff;
         for (int e = tid; e < 64 * 64; e += 256) {
             const int r = e & 63, k = e >> 6;
-            sL[k * 65 + r] = (r < w && k < w) ? Lb[(int64_t)k * ld + r] : 0.0;
+            sL[k * 65 + r] = (r < w && k < w) ? Lb[k * w + r] : 0.0;
         }
         __syncthreads();
         if (wv == 0) {
@@ -985,7 +981,7 @@ __global__ __launch_bounds__(256) void implicit_apply(
         const int32_t* __restrict__ rw = R + bd.rows_off;
         for (int qq = tid; qq < nb; qq += 256) {
             double t = 0.0;
-            for (int k = 0; k < w; ++k) t += Lb[(int64_t)k * ld + w + qq] * sv[k];
+            for (int k = 0; k < w; ++k) t += lbelow(At, nks, qq, k) * sv[k];
             x[rw[qq]] -= t;
         }
         __syncthreads();
@@ -993,14 +989,15 @@ __global__ __launch_bounds__(256) void implicit_apply(
     // ---- backward
     for (int b = S.nblocks - 1; b >= 0; --b) {
         const BlockDev bd = B[b];
-        const int w = bd.w, ld = bd.ld, nb = bd.nbelow, row0 = bd.row0;
+        const int w = bd.w, nb = bd.nbelow, row0 = bd.row0, nks = (w + 3) / 4;
         const double* __restrict__ Lb = L + bd.lval_off;
+        const double* __restrict__ At = L + bd.aoff;
         const int32_t* __restrict__ rw = R + bd.rows_off;
         double acc = 0.0;                      // lane k of wavefront 0: sum_q L[q][k] z[R[q]]
         for (int c0 = 0; c0 < nb; c0 += 64) {
             for (int e = tid; e < 64 * 64; e += 256) {
                 const int r = e & 63, k = e >> 6;
-                sL[k * 65 + r] = (c0 + r < nb && k < w) ? Lb[(int64_t)k * ld + w + c0 + r] : 0.0;
+                sL[k * 65 + r] = (c0 + r < nb && k < w) ? lbelow(At, nks, c0 + r, k) : 0.0;
             }
             if (tid < 64) sz[tid] = c0 + tid < nb ? x[rw[c0 + tid]] : 0.0;
             __syncthreads();
@@ -1010,7 +1007,7 @@ __global__ __launch_bounds__(256) void implicit_apply(
         }
         for (int e = tid; e < 64 * 64; e += 256) {
             const int r = e & 63, k = e >> 6;
-            sL[k * 65 + r] = (r < w && k < w) ? Lb[(int64_t)k * ld + r] : 0.0;
+            sL[k * 65 + r] = (r < w && k < w) ? Lb[k * w + r] : 0.0;
         }
         __syncthreads();
         if (wv == 0) {

@@ -505,10 +505,13 @@ std::string build_plan(const SubdomainInput& in, const PlanOptions& opt, SubPlan
             d.row0 = c0;
             d.w = c1 - c0;
             d.nbelow = (int32_t)rows.size();
-            d.ld = d.w + d.nbelow;
+            d.ld = d.w;
             d.lval_off = voff;
             d.rows_off = (int64_t)P.brows.size();
-            voff += (int64_t)d.ld * d.w;
+            voff += (int64_t)d.w * d.w;
+            voff = (voff + 7) / 8 * 8;                  // 64-byte aligned A tiles
+            d.aoff = voff;
+            voff += (int64_t)((d.nbelow + 15) / 16) * ((d.w + 3) / 4) * 64;
             P.brows.insert(P.brows.end(), rows.begin(), rows.end());
             for (int32_t i = c0; i < c1; ++i) P.block_of_row[i] = b;
             P.blocks.push_back(d);
@@ -591,9 +594,11 @@ void repack_blocks(const SubPlan& P, const double* vals, double* bvals) {
     std::vector<int32_t> pos(P.n, -1);
     for (const BlockDesc& b : P.blocks) {
         const int32_t c0 = b.row0, c1 = b.row0 + b.w;
+        const int64_t nks = (b.w + 3) / 4;
         for (int32_t q = 0; q < b.nbelow; ++q) pos[P.brows[b.rows_off + q]] = b.w + q;
         for (int32_t i = c0; i < c1; ++i) pos[i] = i - c0;
-        double* panel = bvals + b.lval_off;
+        double* diag = bvals + b.lval_off;
+        double* at = bvals + b.aoff;
         for (int32_t s = P.col2super[c0]; s < P.nsuper && P.sfirst[s] < c1; ++s) {
             const int32_t f = P.sfirst[s];
             const int64_t ld = P.srow_ptr[s + 1] - P.srow_ptr[s];
@@ -601,9 +606,17 @@ void repack_blocks(const SubPlan& P, const double* vals, double* bvals) {
             const double* A = vals + P.spanel_off[s];
             const int32_t j0 = std::max(c0, f), j1 = std::min(c1, P.sfirst[s + 1]);
             for (int32_t j = j0; j < j1; ++j) {
-                const int32_t cj = j - f;
-                double* dst = panel + (size_t)(j - c0) * b.ld;
-                for (int64_t q = cj; q < ld; ++q) dst[pos[rows[q]]] = A[(size_t)cj * ld + q];
+                const int32_t cj = j - f, k = j - c0;
+                for (int64_t q = cj; q < ld; ++q) {
+                    const int32_t p = pos[rows[q]];
+                    const double v = A[(size_t)cj * ld + q];
+                    if (p < b.w) {
+                        diag[(size_t)k * b.w + p] = v;
+                    } else {
+                        const int32_t r = p - b.w;
+                        at[((r / 16) * nks + k / 4) * 64 + (r % 16) + 16 * (k % 4)] = v;
+                    }
+                }
             }
         }
     }

@@ -40,18 +40,23 @@ struct PlanOptions {
 };
 
 // One GPU factor block (Sec. 3.2, factor splitting with pruning): the column
-// range [row0, row0 + w) of L, uniform width except the last.  Its dense
-// panel of (w + nbelow) x w values (column-major, leading dimension ld =
-// w + nbelow) holds the diagonal triangle in its first w rows and, below,
-// only the `nbelow` non-empty rows of L[row0 + w :, block] (pruning), whose
-// global indices start at rows_off in the block row array.
+// range [row0, row0 + w) of L, uniform width except the last.  Its values:
+//   * the dense diagonal triangle, w x w column-major (leading dimension
+//     ld = w) at lval_off;
+//   * the `nbelow` non-empty rows of L[row0 + w :, block] (pruning), whose
+//     global indices start at rows_off in the block row array, stored at aoff
+//     as MFMA A-operand tiles: rows in tiles of 16, columns in slices of 4;
+//     tile (rt, ks) holds 64 values at aoff + 64 (rt * nks + ks), value
+//     (row 16 rt + i, column 4 ks + k) at position i + 16 k, nks = ceil(w/4),
+//     zero padded.
 struct BlockDesc {
     int32_t row0;
     int32_t w;
     int32_t nbelow;
     int32_t ld;
-    int64_t lval_off;      // offset of the panel in the subdomain's block-value array
-    int64_t rows_off;      // offset of the first pruned row in the block row array
+    int64_t lval_off;
+    int64_t rows_off;
+    int64_t aoff;
 };
 
 struct SubPlan {

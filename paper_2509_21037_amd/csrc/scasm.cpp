@@ -256,7 +256,7 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
         s.F_off = fo;
         s.dual_off = dual;
         for (const BlockDesc& b : sp.blocks)
-            P->h_blocks.push_back(BlockDev{b.row0, b.w, b.nbelow, b.ld, b.lval_off, b.rows_off});
+            P->h_blocks.push_back(BlockDev{b.row0, b.w, b.nbelow, b.ld, b.lval_off, b.rows_off, b.aoff});
         for (int32_t t = 0; t < s.ntiles; ++t) {
             TileDev T{};
             T.sub = i;
