@@ -89,7 +89,8 @@ def time_assembly(torch, plan, steps, warmup, graph=False):
         torch.cuda.synchronize()
     kt = plan.kernel_times(reset=True)
     plan.set_timing(False)
-    return 1e3 * elapsed / steps, {k: kt[k][0] / max(1, kt[k][1]) for k in ("trsm", "syrk")}
+    return 1e3 * elapsed / steps, {k: kt[k][0] / kt[k][1] for k in ("trsm", "syrk", "assemble_fused")
+                                   if kt[k][1] > 0}
 
 
 def time_apply(torch, plan, which, iters=20):
@@ -172,6 +173,10 @@ def main():
                     help="pick the factor block width with sc_autotune (auto: on for the elasticity batches)")
     ap.add_argument("--graph", choices=("auto", "on", "off"), default="auto",
                     help="replay the assembly as a captured HIP graph (auto: on for the elasticity batches)")
+    ap.add_argument("--assembly", choices=("fused", "separate"), default="separate",
+                    help="one fused TRSM+SYRK launch, or two launches")
+    ap.add_argument("--compare-fused", action="store_true",
+                    help="also time the FP64 assembly as one fused launch")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain device copy of 2 GiB first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -210,7 +215,7 @@ def main():
 
     # ---------------------------------------------------------------- FP64
     t0 = time.perf_counter()
-    plan = P.Plan(subs, panel_width=args.panel_width, use_graph=use_graph)
+    plan = P.Plan(subs, panel_width=args.panel_width, use_graph=use_graph, assembly=args.assembly)
     plan.factor()
     torch.cuda.synchronize()
     log(f"bench: FP64 plan + host factorisation + upload in {time.perf_counter() - t0:.1f}s")
@@ -218,7 +223,7 @@ def main():
     ms_per_step, kms = time_assembly(torch, plan, args.steps, args.warmup, use_graph)
     log(f"bench: FP64 {ms_per_step:.3f} ms/step, kernels {kms}")
     useful = st["trsm_useful"] + st["syrk_useful"]
-    flops = {"trsm": st["trsm_useful"], "syrk": st["syrk_useful"]}
+    flops = {"trsm": st["trsm_useful"], "syrk": st["syrk_useful"], "assemble_fused": useful}
     dom = max(kms, key=kms.get)
     achieved = flops[dom] / (kms[dom] * 1e-3) / 1e12
     roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": PEAK_TFLOPS["fp64"],
@@ -251,12 +256,23 @@ def main():
         plan_o.factor()
         orig, _ = time_assembly(torch, plan_o, max(1, args.steps // 2), 1)
         plan_o.destroy()
+    other = None
+    if args.compare_fused:
+        alt = "separate" if args.assembly == "fused" else "fused"
+        plan_s = P.Plan(subs, panel_width=args.panel_width, use_graph=use_graph, assembly=alt)
+        plan_s.factor()
+        ms_s, kms_s = time_assembly(torch, plan_s, args.steps, args.warmup, use_graph)
+        other = {"assembly": alt, "ms_per_step": ms_s, "kernel_ms": kms_s,
+                 "kernel_tflops": {k: flops[k] / (kms_s[k] * 1e-3) / 1e12 for k in kms_s}}
+        log(f"bench: FP64 {alt} assembly {ms_s:.3f} ms/step, kernels {kms_s}")
+        plan_s.destroy()
     plan.destroy()
 
     # ---------------------------------------------------------------- mixed
     mixed = None
     if not args.no_mixed:
-        plan_m = P.Plan(subs, precision="mixed", panel_width=args.panel_width, use_graph=use_graph)
+        plan_m = P.Plan(subs, precision="mixed", panel_width=args.panel_width, use_graph=use_graph,
+                        assembly=args.assembly)
         plan_m.factor()
         ms_m, kms_m = time_assembly(torch, plan_m, args.steps, args.warmup, use_graph)
         log(f"bench: mixed {ms_m:.3f} ms/step, kernels {kms_m}")
@@ -303,13 +319,14 @@ def main():
         "config": {"workload": scgen.CONFIG_NAMES[cfg], "subdomains": len(subs),
                    "n": s0.n if cfg != 3 else "1029..14739", "m": s0.m if cfg != 3 else "654..4614",
                    "precision": "fp64", "staircase": True, "panel_width": args.panel_width or 64,
-                   "graph": use_graph},
+                   "graph": use_graph, "assembly": args.assembly},
         "autotune": tune,
         "useful_gflops": useful / (ms_per_step * 1e-3) / 1e9,
         "useful_gflop_per_step": useful / 1e9,
         "relF_max_sampled": max(errs64),
         "relF_samples": len(errs64),
         "orig_ms_per_step": orig,
+        "other_assembly": other,
         "mixed": mixed,
         "pcpg": pcpg or None,
         "apply": extra,

@@ -101,6 +101,11 @@ typedef struct {
  *                    HIP graph and replays it on every later call (the plan's
  *                    buffers and tables are fixed, so the graph stays valid);
  *                    calls made while kernel timing is enabled launch eagerly
+ *   assembly_kernels 0 = library default (two launches), 1 = one fused
+ *                    launch in which the F tiles of a subdomain (SYRK) wait
+ *                    on a device counter for its X tiles (TRSM) and overlap
+ *                    the TRSM of other subdomains, 2 = two launches (all TRSM
+ *                    tiles, then all SYRK tiles)
  */
 typedef struct {
     int32_t precision;
@@ -110,7 +115,8 @@ typedef struct {
     int32_t leaf_nodes;
     int32_t n_threads;
     int32_t use_graph;
-    int32_t reserved[7];
+    int32_t assembly_kernels;
+    int32_t reserved[6];
 } sc_options_t;
 
 /* Initialisation stage (Sec. 2.2): ordering, symbolic factorisation, staircase
@@ -199,9 +205,10 @@ sc_status_t sc_plan_stats(sc_plan_t plan, int32_t* nsub, int64_t* dual_total,
  * elapsed milliseconds of every completed launch since the last reset
  * (synchronising on the recorded events):
  *   ms[0] staircase TRSM, ms[1] staircase SYRK + permute-back,
- *   ms[2] explicit apply (GEMV), ms[3] implicit apply;
+ *   ms[2] explicit apply (GEMV), ms[3] implicit apply,
+ *   ms[4] fused assembly (TRSM and SYRK in one launch);
  *   counts[k] = number of launches of kernel k summed into ms[k].
- * `reset` != 0 clears the sums after reading.  Arrays hold 4 entries. */
+ * `reset` != 0 clears the sums after reading.  Arrays hold 5 entries. */
 sc_status_t sc_set_timing(sc_plan_t plan, int32_t enable);
 sc_status_t sc_kernel_times(sc_plan_t plan, double* ms, int64_t* counts, int32_t reset);
 

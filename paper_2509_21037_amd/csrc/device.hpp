@@ -14,6 +14,10 @@ constexpr int kSyrkTile = 128;     // edge of an F output tile (two X column til
 // k runs on XCD k mod kNumXcd); work lists are interleaved so that all items
 // of one subdomain share an XCD and its L2.
 constexpr int kNumXcd = 8;
+// Fused assembly: TRSM tiles dispatched on an XCD between the last TRSM tile
+// of a subdomain and its first SYRK item (about 1.5 times the workgroups one
+// XCD holds at once: 32 CUs x 2).
+constexpr int kFusedLagTiles = 96;
 
 struct SubDev {
     int32_t n, m, nblocks, ntiles;
@@ -46,6 +50,7 @@ struct BlockDev {
     int64_t lval_off;    // diagonal block (w x w, column-major), relative to the subdomain's lval_off
     int64_t rows_off;    // relative to the subdomain's rows_off
     int64_t aoff;        // pruned rows as MFMA A tiles, relative to the subdomain's lval_off
+    int64_t linv_off;    // inverse of the diagonal block as MFMA A tiles (same base)
 };
 
 }  // namespace scasm

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <climits>
 #include <cstdint>
+#include <type_traits>
 
 #include "device.hpp"
 #include "kernels.hpp"
@@ -31,219 +32,317 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// v_mfma_f32_16x16x4f32 takes A and B in the same lane layout as the FP64
+// instruction, but its accumulator is laid out differently:
+//   C/D (16x16): lane l, register r holds D[4 (l / 16) + r][l % 16].
+__device__ __forceinline__ v4f mfma_f32(float a, float b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
 // ---------------------------------------------------------------------------
 // Staircase TRSM, X = L^{-1} P B^T (Sec. 3.2, factor splitting with pruning).
-// One workgroup = one 64-column tile of one subdomain; wavefront w owns the
-// 16-column stripe w.  The four wavefronts walk the factor blocks together,
-// from the block holding the tile's first pivot (rows above it are zero and
-// stay zero: forward substitution only propagates downwards); a stripe whose
-// first pivot lies further down joins at its own first block.  Per block:
-//   1. the dense diagonal block (<= 64 x 64) is staged in LDS once for the
-//      workgroup; each wavefront loads its stripe's block rows into registers
-//      (MFMA accumulator layout);
-//   2. diagonal solve in FP64: 16-row sub-blocks by substitution (scaling by
-//      the reciprocal of the diagonal, column-wise elimination), each followed
-//      by an MFMA update of the sub-blocks below it inside the diagonal block;
-//   3. the solved rows are stored, then the pruned rows below the block are
-//      updated 64 at a time, X[R_b] -= L[R_b, b] X[b], with FP64 MFMA whose A
-//      operands are read straight from the factor's tile layout (coalesced,
-//      shared by the four wavefronts through the caches).  The first 64 rows
-//      are gathered during step 1: the diagonal solve never writes them.
-// X rows a stripe has not updated yet are not read: the right-hand side (sign
-// at the pivot, zero elsewhere) is used instead, tracked by one bit per row
-// and stripe in LDS.
+// One workgroup = one 64-column tile of one subdomain; wavefront v owns the
+// 16-column stripe v and holds the X rows of the current factor block in
+// registers (FP64 accumulator layout).  The four wavefronts walk the factor
+// blocks together, from the block holding the tile's first pivot (rows above
+// it are zero and stay zero: forward substitution only propagates
+// downwards); a stripe whose first pivot lies further down joins at its own
+// first block.  Per block b:
+//   1. X[b] <- L_bb^{-1} X[b], FP64 MFMA with the inverse of the diagonal
+//      block computed on the host: one pass, or two when the block has more
+//      than 32 rows (rows 32.. first, while rows 0..31 still hold their old
+//      values);
+//   2. the pruned rows below the block, 32 at a time:
+//      X[R_b] -= L[R_b, b] X[b] (MFMA, rows gathered and scattered).
+// The factor flows through the workgroup as a stream of chunks (up to two
+// 16-row tiles x 64 columns): chunk c+1 is loaded into registers while chunk
+// c is used from LDS, then written to the other half of a double buffer;
+// one barrier per chunk, on LDS only (X columns of a stripe are private to
+// its wavefront, so no barrier waits on global memory).  Rows of the next
+// chunk of the same block are gathered before the current chunk's MFMAs
+// (the chunks of one block update disjoint rows); a wavefront reads rows it
+// wrote itself in program order.
+// Mixed precision: the same with FP32 X and FP32 A tiles / MFMA for step 2;
+// step 1 stays FP64 (the block rows are widened, solved, rounded back).
 // ---------------------------------------------------------------------------
-constexpr int kLdsLd = 64 + 2;            // LDS leading dimension (doubles) of the diagonal block
-constexpr int kTouchRows = 32768;         // rows covered by the per-stripe "touched" bitmaps
+constexpr int kChunkBytes = 2 * 16 * 64 * 8;     // two FP64 row tiles of 16 k-slices
+constexpr int kTrsmSmem = 2 * kChunkBytes;
 
-__device__ __forceinline__ bool touched(const uint32_t* bits, int row) {
-    return (bits[row >> 5] >> (row & 31)) & 1u;
+// Barrier that waits for this wavefront's LDS traffic only: global loads in
+// flight (prefetches, gathers) stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-// Stages the w x w diagonal block (column-major, leading dimension w) into
-// LDS [k][kLdsLd], zero padded to 64 x 64; 16 values per thread.
-template <class T>
-__device__ __forceinline__ void stage_diag(const T* __restrict__ Ld, int w, double* __restrict__ sL) {
-#pragma unroll
-    for (int it = 0; it < 16; ++it) {
-        const int e = threadIdx.x + 256 * it;
-        const int row = e & 63;
-        const int k = e >> 6;
-        sL[k * kLdsLd + row] = (k < w && row < w) ? (double)Ld[k * w + row] : 0.0;
+struct ChunkRegs {
+    uint4 v0, v1, v2, v3;
+};
+struct ChunkSrc {
+    const char* p;       // always a valid address (the subdomain's factor when bytes == 0)
+    int bytes;
+};
+
+// Every thread loads its four 16-byte pieces unconditionally (pieces past the
+// chunk re-read its first bytes) so that the prefetch stays in registers.
+__device__ __forceinline__ void chunk_load(ChunkRegs& c, const ChunkSrc& s) {
+    const int e = threadIdx.x * 16;
+    c.v0 = *reinterpret_cast<const uint4*>(s.p + (e < s.bytes ? e : 0));
+    c.v1 = *reinterpret_cast<const uint4*>(s.p + (e + 4096 < s.bytes ? e + 4096 : 0));
+    c.v2 = *reinterpret_cast<const uint4*>(s.p + (e + 8192 < s.bytes ? e + 8192 : 0));
+    c.v3 = *reinterpret_cast<const uint4*>(s.p + (e + 12288 < s.bytes ? e + 12288 : 0));
+}
+
+__device__ __forceinline__ void chunk_store(const ChunkRegs& c, char* __restrict__ dst, int bytes) {
+    const int e = threadIdx.x * 16;
+    if (e < bytes) *reinterpret_cast<uint4*>(dst + e) = c.v0;
+    if (e + 4096 < bytes) *reinterpret_cast<uint4*>(dst + e + 4096) = c.v1;
+    if (e + 8192 < bytes) *reinterpret_cast<uint4*>(dst + e + 8192) = c.v2;
+    if (e + 12288 < bytes) *reinterpret_cast<uint4*>(dst + e + 12288) = c.v3;
+}
+
+// Scalar copy of the block descriptor fields the TRSM uses.
+struct BlockLite {
+    int w, nb;
+    int64_t aoff, linv_off;
+};
+
+__device__ __forceinline__ BlockLite block_lite(const BlockDev* __restrict__ B, int b) {
+    return {B[b].w, B[b].nbelow, B[b].aoff, B[b].linv_off};
+}
+
+// Chunk c of a block: c < nd are the inverse's row-tile groups, the rest
+// groups of two pruned row tiles (TA = precision of the update's A tiles).
+template <class TA>
+__device__ __forceinline__ ChunkSrc chunk_src(const BlockLite& bd, int c, const double* __restrict__ L,
+                                              const TA* __restrict__ LA) {
+    const int nks = (bd.w + 3) >> 2;
+    const int nrt_d = (bd.w + 15) >> 4;
+    const int nd = nrt_d > 2 ? 2 : 1;
+    if (c < nd) {
+        const int slot0 = c == 0 ? 0 : nrt_d - 2;
+        const int nt = nd == 1 ? nrt_d : (c == 0 ? nrt_d - 2 : 2);
+        return {reinterpret_cast<const char*>(L + bd.linv_off + (int64_t)slot0 * nks * 64), nt * nks * 64 * 8};
     }
+    const int p = c - nd;
+    const int nt = min(2, ((bd.nb + 15) >> 4) - 2 * p);
+    return {reinterpret_cast<const char*>(LA + bd.aoff + (int64_t)2 * p * nks * 64),
+            nt * nks * 64 * (int)sizeof(TA)};
 }
 
-// FP64 solve of the stripe's diagonal-block rows in place (xr: MFMA
-// accumulator layout, 4 sub-tiles of 16 rows); sL holds the diagonal block,
-// sRd the reciprocals of its diagonal.
-__device__ __forceinline__ void diag_solve(v4d (&xr)[4], const double* __restrict__ sL,
-                                           const double* __restrict__ sRd, int w, int g, int j) {
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        if (16 * t < w) {
-#pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                if (16 * t + k < w) {
-                    const int gk = k & 3;
-                    const int rk = k >> 2;
-                    const double xk_own = xr[t][rk] * sRd[16 * t + k];
-                    if (g == gk) xr[t][rk] = xk_own;
-                    const double xk = __shfl(xk_own, j + 16 * gk, 64);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int ii = 4 * r + g;
-                        const double lik = sL[(16 * t + k) * kLdsLd + 16 * t + ii];
-                        if (ii > k) xr[t][r] -= lik * xk;
-                    }
-                }
-            }
-#pragma unroll
-            for (int t2 = t + 1; t2 < 4; ++t2) {
-                if (16 * t2 < w) {
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) {
-                        const double a = -sL[(16 * t + 4 * s + g) * kLdsLd + 16 * t2 + j];
-                        xr[t2] = mfma_f64(a, xr[t][s], xr[t2]);
-                    }
-                }
-            }
-        }
-    }
-}
-
-__global__ __launch_bounds__(256, 2) void trsm_stair_f64(
+template <bool MIXED>
+__device__ __forceinline__ void trsm_tile(
     const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
     const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows,
-    const double* __restrict__ lval, const int32_t* __restrict__ piv,
-    const int8_t* __restrict__ sgn, const int32_t* __restrict__ order, double* __restrict__ X)
+    const double* __restrict__ lval, const float* __restrict__ lval32,
+    const int32_t* __restrict__ piv, const int8_t* __restrict__ sgn,
+    typename std::conditional<MIXED, float, double>::type* __restrict__ X, int ti, char* __restrict__ smem)
 {
-    __shared__ double sL[64 * kLdsLd];
-    __shared__ double sRd[64];
-    __shared__ uint32_t sTouch[4][kTouchRows / 32];
+    using TX = typename std::conditional<MIXED, float, double>::type;
+    using VX = typename std::conditional<MIXED, v4f, v4d>::type;
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int g = lane >> 4;
     const int j = lane & 15;
-    const int ti = order[blockIdx.x];
-    if (ti < 0) return;
     const TileDev T = tiles[ti];
     const SubDev S = subs[T.sub];
     const int n = S.n;
     const int kstart = T.kstart;
-    double* __restrict__ Xs = X + T.x_off;
+    TX* __restrict__ Xs = X + T.x_off;
     const int col = wv * kStripe + j;
     const int64_t cbase = S.col_off + (int64_t)T.tile * kTile;
     const BlockDev* __restrict__ B = blocks + S.blk_off;
     const int32_t* __restrict__ R = rows + S.rows_off;
     const double* __restrict__ L = lval + S.lval_off;
+    const TX* __restrict__ LA;
+    if constexpr (MIXED) LA = lval32 + S.lval_off;
+    else LA = lval + S.lval_off;
     const int my_start = tiles[ti].start_block[wv];
     const int first_block = tiles[ti].start_block[0];
 
-    // Right-hand side P B^T: sign at the pivot row, zero elsewhere.  Only the
-    // rows above the stripe's first block, which no block step writes, are
-    // zero-filled; subdomains beyond the bitmap size zero-fill the whole slab.
-    uint32_t* __restrict__ tb = sTouch[wv];
-    const bool lazy = n <= kTouchRows;
-    const int mypiv = col < T.ncols ? piv[cbase + col] : -1;
-    const double mysgn = col < T.ncols ? (double)sgn[cbase + col] : 0.0;
-    const int first_row = lazy ? (my_start < S.nblocks ? B[my_start].row0 : n) : n;
-    for (int r = kstart + g; r < first_row; r += 4) Xs[(int64_t)(r - kstart) * kTile + col] = 0.0;
-    if (lazy) {
-        for (int wd = lane; wd < (n + 31) / 32; wd += 64) tb[wd] = 0u;
-    } else {
-        __threadfence_block();
-        if (g == 0 && col < T.ncols) Xs[(int64_t)(mypiv - kstart) * kTile + col] = mysgn;
+    // right-hand side P B^T: sign at the pivot row, zero elsewhere
+    for (int r = kstart + g; r < n; r += 4) Xs[(int64_t)(r - kstart) * kTile + col] = TX(0);
+    __threadfence_block();
+    if (g == 0 && col < T.ncols) Xs[(int64_t)(piv[cbase + col] - kstart) * kTile + col] = (TX)sgn[cbase + col];
+    if (first_block >= S.nblocks) return;
+
+    ChunkRegs pre;
+    BlockLite bd = block_lite(B, first_block);
+    {
+        const ChunkSrc c0 = chunk_src(bd, 0, L, LA);
+        chunk_load(pre, c0);
+        chunk_store(pre, smem, c0.bytes);
     }
-    __syncthreads();
-    auto xval = [&](int row) -> double {
-        if (!lazy || touched(tb, row)) return Xs[(int64_t)(row - kstart) * kTile + col];
-        return row == mypiv ? mysgn : 0.0;
+    lds_barrier();
+    int buf = 0;
+
+    auto advance = [&](const ChunkSrc& nx) {     // next chunk: registers -> free LDS half
+        if (nx.bytes > 0) {
+            chunk_store(pre, smem + (buf ^ 1) * kChunkBytes, nx.bytes);
+            lds_barrier();
+            buf ^= 1;
+        }
     };
-
     for (int b = first_block; b < S.nblocks; ++b) {
-        const BlockDev bd = B[b];
         const int w = bd.w;
-        const int row0 = bd.row0;
-        const int nb = bd.nbelow;
-        const int nks = (w + 3) / 4;
-        const int nrt = (nb + 15) / 16;
-        const double* __restrict__ At = L + bd.aoff;
-        const int32_t* __restrict__ rw = R + bd.rows_off;
+        const int row0 = B[b].row0;
+        const int nb = bd.nb;
+        const int nks = (w + 3) >> 2;
+        const int nrt_d = (w + 15) >> 4;
+        const int nd = nrt_d > 2 ? 2 : 1;
+        const int nrt = (nb + 15) >> 4;
+        const int np = (nrt + 1) >> 1;
+        const int nch = nd + np;
+        const int32_t* __restrict__ rw = R + B[b].rows_off;
         const bool act = b >= my_start;
+        const BlockLite bn = block_lite(B, b + 1 < S.nblocks ? b + 1 : b);
+        auto next_src = [&](int c) {
+            ChunkSrc nx{reinterpret_cast<const char*>(L), 0};
+            if (c + 1 < nch) nx = chunk_src(bd, c + 1, L, LA);
+            else if (b + 1 < S.nblocks) nx = chunk_src(bn, 0, L, LA);
+            return nx;
+        };
 
-        v4d acc[4];
-        auto gather = [&](int q0) {
+        VX accn[2];                              // rows of the next pruned chunk
+        int offn[2][4];
+        auto gather = [&](int p) {
 #pragma unroll
-            for (int rt = 0; rt < 4; ++rt)
+            for (int u = 0; u < 2; ++u)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int q = q0 + 16 * rt + 4 * r + g;
-                    acc[rt][r] = q < nb ? xval(rw[q]) : 0.0;
+                    const int q = 32 * p + 16 * u + (MIXED ? 4 * g + r : 4 * r + g);
+                    offn[u][r] = q < nb ? (rw[q] - kstart) * kTile + col : -1;
+                    accn[u][r] = offn[u][r] >= 0 ? Xs[offn[u][r]] : TX(0);
                 }
         };
-        __syncthreads();                 // previous block done with sL; its stores ordered
-        if (act && nb > 0) gather(0);    // rows below this block: the diagonal solve never writes them
-        stage_diag(L + bd.lval_off, w, sL);
-        __syncthreads();
-        if (threadIdx.x < 64) sRd[threadIdx.x] = threadIdx.x < w ? 1.0 / sL[threadIdx.x * (kLdsLd + 1)] : 0.0;
-        __syncthreads();
-        if (!act) continue;
 
-        v4d xr[4];
+        // ---- 1. X[b] <- L_bb^{-1} X[b]
+        TX xb[4][4];                             // -X[b]: B operands of step 2
+        {
+            v4d xr[4];
+            if (act) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = 16 * t + 4 * r + g;
-                const int row = row0 + i;
-                xr[t][r] = (i < w && row >= kstart) ? xval(row) : 0.0;
-            }
-        diag_solve(xr, sL, sRd, w, g, j);
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = 16 * t + 4 * r + g;
-                const int row = row0 + i;
-                if (i < w && row >= kstart) Xs[(int64_t)(row - kstart) * kTile + col] = xr[t][r];
-            }
-
-        for (int q0 = 0; q0 < nb; q0 += 64) {
-            if (q0 > 0) gather(q0);
-            const int rt0 = q0 >> 4;
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-#pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    const int ks = 4 * t + s;
-                    if (ks < nks) {
-#pragma unroll
-                        for (int rt = 0; rt < 4; ++rt) {
-                            const double a = rt0 + rt < nrt ? -At[((int64_t)(rt0 + rt) * nks + ks) * 64 + lane] : 0.0;
-                            acc[rt] = mfma_f64(a, xr[t][s], acc[rt]);
-                        }
-                    }
-                }
-            }
-#pragma unroll
-            for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int q = q0 + 16 * rt + 4 * r + g;
-                    if (q < nb) Xs[(int64_t)(rw[q] - kstart) * kTile + col] = acc[rt][r];
-                }
-            if (lazy && j == 0) {
-#pragma unroll
-                for (int rt = 0; rt < 4; ++rt)
+                for (int t = 0; t < 4; ++t)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int q = q0 + 16 * rt + 4 * r + g;
-                        if (q < nb) atomicOr(&tb[rw[q] >> 5], 1u << (rw[q] & 31));
+                        const int i = 16 * t + 4 * r + g;
+                        const int row = row0 + i;
+                        xr[t][r] = (i < w && row >= kstart) ? (double)Xs[(int64_t)(row - kstart) * kTile + col] : 0.0;
+                    }
+                if (np > 0) gather(0);
+            }
+            for (int c = 0; c < nd; ++c) {
+                const ChunkSrc nx = next_src(c);
+                chunk_load(pre, nx);
+                if (act) {
+                    const double* __restrict__ sA = reinterpret_cast<const double*>(smem + buf * kChunkBytes);
+                    const int t0 = (nd == 2 && c == 0) ? 2 : 0;
+                    const int nt = nd == 1 ? nrt_d : (c == 0 ? nrt_d - 2 : 2);
+                    v4d tmp[2];
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        tmp[u] = v4d{0.0, 0.0, 0.0, 0.0};
+                        if (u < nt) {
+#pragma unroll
+                            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                                for (int s = 0; s < 4; ++s) {
+                                    const int ks = 4 * t + s;
+                                    if (ks < nks && t <= t0 + u)
+                                        tmp[u] = mfma_f64(sA[(u * nks + ks) * 64 + lane], xr[t][s], tmp[u]);
+                                }
+                        }
+                    }
+                    if (t0 == 0) {
+                        xr[0] = tmp[0];
+                        if (nt > 1) xr[1] = tmp[1];
+                    } else {
+                        xr[2] = tmp[0];
+                        if (nt > 1) xr[3] = tmp[1];
+                    }
+                }
+                advance(nx);
+            }
+            if (act) {
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int i = 16 * t + 4 * r + g;
+                        const int row = row0 + i;
+                        const TX v = (TX)xr[t][r];
+                        if (i < w && row >= kstart) Xs[(int64_t)(row - kstart) * kTile + col] = v;
+                        xb[t][r] = -v;
                     }
             }
         }
+
+        // ---- 2. X[R_b] -= L[R_b, b] X[b], pruned row tiles 2p, 2p+1
+        for (int p = 0; p < np; ++p) {
+            const ChunkSrc nx = next_src(nd + p);
+            chunk_load(pre, nx);
+            if (act) {
+                VX acc[2] = {accn[0], accn[1]};
+                int off[2][4];
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) off[u][r] = offn[u][r];
+                if (p + 1 < np) gather(p + 1);
+                const TX* __restrict__ sA = reinterpret_cast<const TX*>(smem + buf * kChunkBytes);
+                const int nt = min(2, nrt - 2 * p);
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    if (u < nt) {
+#pragma unroll
+                        for (int t = 0; t < 4; ++t)
+#pragma unroll
+                            for (int s = 0; s < 4; ++s) {
+                                const int ks = 4 * t + s;
+                                if (ks < nks) {
+                                    if constexpr (MIXED) acc[u] = mfma_f32(sA[(u * nks + ks) * 64 + lane], xb[t][s], acc[u]);
+                                    else acc[u] = mfma_f64(sA[(u * nks + ks) * 64 + lane], xb[t][s], acc[u]);
+                                }
+                            }
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (off[u][r] >= 0) Xs[off[u][r]] = acc[u][r];
+            }
+            advance(nx);
+        }
+        bd = bn;
     }
 }
+
+__global__ __launch_bounds__(256, 3) void trsm_stair_f64(
+    const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
+    const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows,
+    const double* __restrict__ lval, const int32_t* __restrict__ piv,
+    const int8_t* __restrict__ sgn, const int32_t* __restrict__ order, double* __restrict__ X)
+{
+    __shared__ __align__(16) char smem[kTrsmSmem];
+    const int ti = order[blockIdx.x];
+    if (ti < 0) return;
+    trsm_tile<false>(subs, tiles, blocks, rows, lval, nullptr, piv, sgn, X, ti, smem);
+}
+
+__global__ __launch_bounds__(256, 3) void trsm_stair_mixed(
+    const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
+    const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows,
+    const double* __restrict__ lval, const float* __restrict__ lval32, const int32_t* __restrict__ piv,
+    const int8_t* __restrict__ sgn, const int32_t* __restrict__ order, float* __restrict__ X)
+{
+    __shared__ __align__(16) char smem[kTrsmSmem];
+    const int ti = order[blockIdx.x];
+    if (ti < 0) return;
+    trsm_tile<true>(subs, tiles, blocks, rows, lval, lval32, piv, sgn, X, ti, smem);
+}
+
 
 // ---------------------------------------------------------------------------
 // Staircase SYRK, F = X^T X (Sec. 3.3, output splitting): one workgroup per
@@ -258,15 +357,15 @@ __global__ __launch_bounds__(256, 2) void trsm_stair_f64(
 constexpr int kSyrkKC = 16;
 constexpr int kSyrkLd = kSyrkTile + 4;
 
-__global__ __launch_bounds__(256) void syrk_stair_f64(
-    const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
-    const SyrkItem* __restrict__ items, const double* __restrict__ X,
-    const int32_t* __restrict__ pi, double* __restrict__ F)
+constexpr int kSyrkSmem = 4 * kSyrkKC * kSyrkLd * 8;
+
+__device__ __forceinline__ void syrk_item_f64(
+    const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles, const SyrkItem it,
+    const double* __restrict__ X, const int32_t* __restrict__ pi, double* __restrict__ F,
+    char* __restrict__ smem)
 {
-    __shared__ double sI[2][kSyrkKC * kSyrkLd];
-    __shared__ double sJ[2][kSyrkKC * kSyrkLd];
-    const SyrkItem it = items[blockIdx.x];
-    if (it.sub < 0) return;
+    double (*sI)[kSyrkKC * kSyrkLd] = reinterpret_cast<double (*)[kSyrkKC * kSyrkLd]>(smem);
+    double (*sJ)[kSyrkKC * kSyrkLd] = sI + 2;
     const SubDev S = subs[it.sub];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -381,19 +480,21 @@ __global__ __launch_bounds__(256) void syrk_stair_f64(
             }
 }
 
+__global__ __launch_bounds__(256) void syrk_stair_f64(
+    const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
+    const SyrkItem* __restrict__ items, const double* __restrict__ X,
+    const int32_t* __restrict__ pi, double* __restrict__ F)
+{
+    __shared__ __align__(16) char smem[kSyrkSmem];
+    const SyrkItem it = items[blockIdx.x];
+    if (it.sub < 0) return;
+    syrk_item_f64(subs, tiles, it, X, pi, F, smem);
+}
+
 // ---------------------------------------------------------------------------
 // Mixed precision (FP64 diagonal solves; FP32 X, off-diagonal updates and
 // SYRK with FP32 MFMA and FP32 accumulation).
-//
-// v_mfma_f32_16x16x4f32 takes A and B in the same lane layout as the FP64
-// instruction, but its accumulator is laid out differently:
-//   C/D (16x16): lane l, register r holds D[4 (l / 16) + r][l % 16].
 // ---------------------------------------------------------------------------
-typedef float v4f __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ v4f mfma_f32(float a, float b, v4f c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
 
 // FP64 factor values -> FP32 copy (round to nearest even).
 __global__ __launch_bounds__(256) void convert_f64_f32(const double* __restrict__ a, float* __restrict__ b,
@@ -401,155 +502,20 @@ __global__ __launch_bounds__(256) void convert_f64_f32(const double* __restrict_
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) b[i] = (float)a[i];
 }
-
-__global__ __launch_bounds__(256, 2) void trsm_stair_mixed(
-    const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
-    const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows,
-    const double* __restrict__ lval, const float* __restrict__ lval32, const int32_t* __restrict__ piv,
-    const int8_t* __restrict__ sgn, const int32_t* __restrict__ order, float* __restrict__ X)
-{
-    __shared__ double sL[64 * kLdsLd];
-    __shared__ double sRd[64];
-    __shared__ uint32_t sTouch[4][kTouchRows / 32];
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    const int g = lane >> 4;
-    const int j = lane & 15;
-    const int ti = order[blockIdx.x];
-    if (ti < 0) return;
-    const TileDev T = tiles[ti];
-    const SubDev S = subs[T.sub];
-    const int n = S.n;
-    const int kstart = T.kstart;
-    float* __restrict__ Xs = X + T.x_off;
-    const int col = wv * kStripe + j;
-    const int64_t cbase = S.col_off + (int64_t)T.tile * kTile;
-    const BlockDev* __restrict__ B = blocks + S.blk_off;
-    const int32_t* __restrict__ R = rows + S.rows_off;
-    const double* __restrict__ L = lval + S.lval_off;
-    const float* __restrict__ L32 = lval32 + S.lval_off;
-    const int my_start = tiles[ti].start_block[wv];
-    const int first_block = tiles[ti].start_block[0];
-
-    uint32_t* __restrict__ tb = sTouch[wv];
-    const bool lazy = n <= kTouchRows;
-    const int mypiv = col < T.ncols ? piv[cbase + col] : -1;
-    const float mysgn = col < T.ncols ? (float)sgn[cbase + col] : 0.0f;
-    const int first_row = lazy ? (my_start < S.nblocks ? B[my_start].row0 : n) : n;
-    for (int r = kstart + g; r < first_row; r += 4) Xs[(int64_t)(r - kstart) * kTile + col] = 0.0f;
-    if (lazy) {
-        for (int wd = lane; wd < (n + 31) / 32; wd += 64) tb[wd] = 0u;
-    } else {
-        __threadfence_block();
-        if (g == 0 && col < T.ncols) Xs[(int64_t)(mypiv - kstart) * kTile + col] = mysgn;
-    }
-    __syncthreads();
-    auto xval = [&](int row) -> float {
-        if (!lazy || touched(tb, row)) return Xs[(int64_t)(row - kstart) * kTile + col];
-        return row == mypiv ? mysgn : 0.0f;
-    };
-
-    for (int b = first_block; b < S.nblocks; ++b) {
-        const BlockDev bd = B[b];
-        const int w = bd.w;
-        const int row0 = bd.row0;
-        const int nb = bd.nbelow;
-        const int nks = (w + 3) / 4;
-        const int nrt = (nb + 15) / 16;
-        const float* __restrict__ At = L32 + bd.aoff;
-        const int32_t* __restrict__ rw = R + bd.rows_off;
-        const bool act = b >= my_start;
-
-        v4f acc[4];
-        auto gather = [&](int q0) {
-#pragma unroll
-            for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int q = q0 + 16 * rt + 4 * g + r;
-                    acc[rt][r] = q < nb ? xval(rw[q]) : 0.0f;
-                }
-        };
-        __syncthreads();
-        if (act && nb > 0) gather(0);
-        stage_diag(L + bd.lval_off, w, sL);
-        __syncthreads();
-        if (threadIdx.x < 64) sRd[threadIdx.x] = threadIdx.x < w ? 1.0 / sL[threadIdx.x * (kLdsLd + 1)] : 0.0;
-        __syncthreads();
-        if (!act) continue;
-
-        v4d xr[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = 16 * t + 4 * r + g;
-                const int row = row0 + i;
-                xr[t][r] = (i < w && row >= kstart) ? (double)xval(row) : 0.0;
-            }
-        diag_solve(xr, sL, sRd, w, g, j);
-        float xb[4][4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = 16 * t + 4 * r + g;
-                const int row = row0 + i;
-                xb[t][r] = (float)xr[t][r];
-                if (i < w && row >= kstart) Xs[(int64_t)(row - kstart) * kTile + col] = xb[t][r];
-            }
-
-        for (int q0 = 0; q0 < nb; q0 += 64) {
-            if (q0 > 0) gather(q0);
-            const int rt0 = q0 >> 4;
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-#pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    const int ks = 4 * t + s;
-                    if (ks < nks) {
-#pragma unroll
-                        for (int rt = 0; rt < 4; ++rt) {
-                            const float a = rt0 + rt < nrt ? -At[((int64_t)(rt0 + rt) * nks + ks) * 64 + lane] : 0.0f;
-                            acc[rt] = mfma_f32(a, xb[t][s], acc[rt]);
-                        }
-                    }
-                }
-            }
-#pragma unroll
-            for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int q = q0 + 16 * rt + 4 * g + r;
-                    if (q < nb) Xs[(int64_t)(rw[q] - kstart) * kTile + col] = acc[rt][r];
-                }
-            if (lazy && j == 0) {
-#pragma unroll
-                for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int q = q0 + 16 * rt + 4 * g + r;
-                        if (q < nb) atomicOr(&tb[rw[q] >> 5], 1u << (rw[q] & 31));
-                    }
-            }
-        }
-    }
-}
-
 // FP32 staircase SYRK: as syrk_stair_f64 with FP32 X, FP32 MFMA and FP32
 // accumulation, 32 rows per LDS step; F stored FP32.
 constexpr int kSyrkKCF = 32;
 constexpr int kSyrkLdF = kSyrkTile + 4;
 
-__global__ __launch_bounds__(256) void syrk_stair_f32(
-    const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
-    const SyrkItem* __restrict__ items, const float* __restrict__ X,
-    const int32_t* __restrict__ pi, float* __restrict__ F)
+constexpr int kSyrkSmemF = 4 * kSyrkKCF * kSyrkLdF * 4;
+
+__device__ __forceinline__ void syrk_item_f32(
+    const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles, const SyrkItem it,
+    const float* __restrict__ X, const int32_t* __restrict__ pi, float* __restrict__ F,
+    char* __restrict__ smem)
 {
-    __shared__ float sI[2][kSyrkKCF * kSyrkLdF];
-    __shared__ float sJ[2][kSyrkKCF * kSyrkLdF];
-    const SyrkItem it = items[blockIdx.x];
-    if (it.sub < 0) return;
+    float (*sI)[kSyrkKCF * kSyrkLdF] = reinterpret_cast<float (*)[kSyrkKCF * kSyrkLdF]>(smem);
+    float (*sJ)[kSyrkKCF * kSyrkLdF] = sI + 2;
     const SubDev S = subs[it.sub];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -661,6 +627,17 @@ __global__ __launch_bounds__(256) void syrk_stair_f32(
                     Fs[pb + pa * m] = v;
                 }
             }
+}
+
+__global__ __launch_bounds__(256) void syrk_stair_f32(
+    const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
+    const SyrkItem* __restrict__ items, const float* __restrict__ X,
+    const int32_t* __restrict__ pi, float* __restrict__ F)
+{
+    __shared__ __align__(16) char smem[kSyrkSmemF];
+    const SyrkItem it = items[blockIdx.x];
+    if (it.sub < 0) return;
+    syrk_item_f32(subs, tiles, it, X, pi, F, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -1031,6 +1008,106 @@ hipError_t launch_apply_implicit(const DevTables& t, const int64_t* xoff, double
     if (nsub > 0)
         hipLaunchKernelGGL(implicit_apply, dim3((unsigned)nsub), dim3(256), 0, stream, t.subs, t.blocks, t.rows,
                            t.lval, t.piv, t.pi, t.sgn, xoff, p, q, xwork);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[1], stream)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// Fused assembly: one launch over an item list that holds every TRSM tile
+// and every SYRK tile.  A SYRK item of subdomain i waits until all TRSM tiles
+// of i have signalled completion; in the list (per XCD, interleaved modulo
+// the XCD count) those tiles always come first, so they were dispatched
+// before it and never wait themselves.  The wait is bounded: on expiry the
+// item raises the error flag and returns (results are then invalid, nothing
+// hangs).  TRSM tiles of one subdomain overlap SYRK tiles of another, mixing
+// latency-bound and MFMA-bound work on each CU.
+// ---------------------------------------------------------------------------
+constexpr int kFusedSmem = kTrsmSmem > kSyrkSmem ? kTrsmSmem : kSyrkSmem;
+constexpr int kFusedSmemMixed = kTrsmSmem > kSyrkSmemF ? kTrsmSmem : kSyrkSmemF;
+constexpr long long kWaitLimit = 1ll << 24;     // s_sleep rounds (~seconds)
+
+__global__ __launch_bounds__(256) void fill_i32(int32_t* __restrict__ p, int32_t n, int32_t v) {
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) p[i] = v;
+}
+
+__device__ __forceinline__ void signal_done(int32_t* done) {
+    __threadfence();                             // each wavefront releases its own X stores
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(done, 1);
+}
+
+__device__ __forceinline__ bool wait_done(const int32_t* done, int32_t need, int32_t* err) {
+    __shared__ int ok;
+    if (threadIdx.x == 0) {
+        long long spins = 0;
+        while (__hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+            __builtin_amdgcn_s_sleep(8);
+            if (++spins > kWaitLimit) break;
+        }
+        ok = spins <= kWaitLimit;
+        if (!ok) atomicOr(err, 1);
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // the counter's release covers every X store
+    return ok != 0;
+}
+
+__global__ __launch_bounds__(256, 2) void assemble_fused_f64(
+    const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
+    const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows,
+    const double* __restrict__ lval, const int32_t* __restrict__ piv, const int8_t* __restrict__ sgn,
+    const int2* __restrict__ items, const SyrkItem* __restrict__ syrk, double* __restrict__ X,
+    const int32_t* __restrict__ pi, double* __restrict__ F, int32_t* __restrict__ done,
+    int32_t* __restrict__ err)
+{
+    __shared__ __align__(16) char smem[kFusedSmem];
+    const int2 it = items[blockIdx.x];
+    if (it.x == 1) {
+        trsm_tile<false>(subs, tiles, blocks, rows, lval, nullptr, piv, sgn, X, it.y, smem);
+        signal_done(done + tiles[it.y].sub);
+    } else if (it.x == 2) {
+        const SyrkItem si = syrk[it.y];
+        if (wait_done(done + si.sub, subs[si.sub].ntiles, err)) syrk_item_f64(subs, tiles, si, X, pi, F, smem);
+    }
+}
+
+__global__ __launch_bounds__(256, 2) void assemble_fused_mixed(
+    const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
+    const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows,
+    const double* __restrict__ lval, const float* __restrict__ lval32, const int32_t* __restrict__ piv,
+    const int8_t* __restrict__ sgn, const int2* __restrict__ items, const SyrkItem* __restrict__ syrk,
+    float* __restrict__ X, const int32_t* __restrict__ pi, float* __restrict__ F, int32_t* __restrict__ done,
+    int32_t* __restrict__ err)
+{
+    __shared__ __align__(16) char smem[kFusedSmemMixed];
+    const int2 it = items[blockIdx.x];
+    if (it.x == 1) {
+        trsm_tile<true>(subs, tiles, blocks, rows, lval, lval32, piv, sgn, X, it.y, smem);
+        signal_done(done + tiles[it.y].sub);
+    } else if (it.x == 2) {
+        const SyrkItem si = syrk[it.y];
+        if (wait_done(done + si.sub, subs[si.sub].ntiles, err)) syrk_item_f32(subs, tiles, si, X, pi, F, smem);
+    }
+}
+
+hipError_t launch_assemble_fused(const DevTables& t, hipStream_t stream, hipEvent_t* ev) {
+    hipError_t e = hipSuccess;
+    if (ev && (e = hipEventRecord(ev[0], stream)) != hipSuccess) return e;
+    if (t.nsub > 0)
+        hipLaunchKernelGGL(fill_i32, dim3((unsigned)std::min<int64_t>((t.nsub + 255) / 256, 1024)), dim3(256), 0,
+                           stream, t.done, t.nsub, 0);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (t.nfused > 0) {
+        if (t.X32)
+            hipLaunchKernelGGL(assemble_fused_mixed, dim3((unsigned)t.nfused), dim3(256), 0, stream, t.subs,
+                               t.tiles, t.blocks, t.rows, t.lval, t.lval32, t.piv, t.sgn, t.fused, t.syrk_items,
+                               t.X32, t.pi, t.F32, t.done, t.err);
+        else
+            hipLaunchKernelGGL(assemble_fused_f64, dim3((unsigned)t.nfused), dim3(256), 0, stream, t.subs,
+                               t.tiles, t.blocks, t.rows, t.lval, t.piv, t.sgn, t.fused, t.syrk_items, t.X, t.pi,
+                               t.F, t.done, t.err);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], stream)) != hipSuccess) return e;
     return hipSuccess;

@@ -6,6 +6,8 @@
 
 namespace scasm {
 
+constexpr int kNumTimed = 5;   // timed kernels: TRSM, SYRK, apply, implicit apply, fused assembly
+
 struct DevTables {
     const SubDev* subs = nullptr;
     const TileDev* tiles = nullptr;
@@ -23,14 +25,24 @@ struct DevTables {
     double* F = nullptr;
     float* F32 = nullptr;
     const int2* apply_items = nullptr;     // (subdomain, first column) per GEMV workgroup
+    const int2* fused = nullptr;           // fused assembly: (kind 0 idle / 1 TRSM / 2 SYRK, index)
+    const SyrkItem* syrk_items = nullptr;  // SYRK items in subdomain order (indexed by fused items)
+    int32_t* done = nullptr;               // [nsub] TRSM tiles finished (fused assembly)
+    int32_t* err = nullptr;                // device error flag
     int64_t ntiles = 0;          // TRSM workgroups (length of tile_order)
     int64_t nsyrk = 0;           // SYRK workgroups (items with sub < 0 are idle)
     int64_t napply = 0;
+    int64_t nfused = 0;
+    int32_t nsub = 0;
 };
 
 // Optional per-kernel events: ev[2k] before and ev[2k+1] after kernel k
 // (0 = TRSM, 1 = SYRK); null = no timing.
 hipError_t launch_assemble_f64(const DevTables& t, hipStream_t stream, hipEvent_t* ev);
+
+// Single-launch assembly over the fused item list (FP64 or, with X32 set,
+// mixed); optional events ev[0] before, ev[1] after.
+hipError_t launch_assemble_fused(const DevTables& t, hipStream_t stream, hipEvent_t* ev);
 
 // Mixed precision: FP64 factor -> FP32 copy, and the assembly with FP64
 // diagonal solves, FP32 X / updates / SYRK and FP32 F.

@@ -509,7 +509,9 @@ std::string build_plan(const SubdomainInput& in, const PlanOptions& opt, SubPlan
             d.lval_off = voff;
             d.rows_off = (int64_t)P.brows.size();
             voff += (int64_t)d.w * d.w;
-            voff = (voff + 7) / 8 * 8;                  // 64-byte aligned A tiles
+            voff = (voff + 7) / 8 * 8;                  // 64-byte aligned tiles
+            d.linv_off = voff;
+            voff += (int64_t)((d.w + 15) / 16) * ((d.w + 3) / 4) * 64;
             d.aoff = voff;
             voff += (int64_t)((d.nbelow + 15) / 16) * ((d.w + 3) / 4) * 64;
             P.brows.insert(P.brows.end(), rows.begin(), rows.end());
@@ -617,6 +619,22 @@ void repack_blocks(const SubPlan& P, const double* vals, double* bvals) {
                         at[((r / 16) * nks + k / 4) * 64 + (r % 16) + 16 * (k % 4)] = v;
                     }
                 }
+            }
+        }
+        // inverse of the diagonal triangle, column by column (forward
+        // substitution on the unit vectors, accumulated in long double)
+        const int32_t w = b.w;
+        const int32_t nrt_d = (w + 15) / 16;
+        double* li = bvals + b.linv_off;
+        std::vector<long double> z(w);
+        for (int32_t c = 0; c < w; ++c) {
+            for (int32_t i = c; i < w; ++i) {
+                long double acc = (i == c) ? 1.0L : 0.0L;
+                for (int32_t k = c; k < i; ++k) acc -= (long double)diag[(size_t)k * w + i] * z[k];
+                z[i] = acc / (long double)diag[(size_t)i * w + i];
+                const int32_t rt = i / 16;
+                const int32_t slot = nrt_d > 2 ? (rt >= 2 ? rt - 2 : rt + nrt_d - 2) : rt;
+                li[((int64_t)slot * nks + c / 4) * 64 + (i % 16) + 16 * (c % 4)] = (double)z[i];
             }
         }
     }

@@ -48,7 +48,12 @@ struct PlanOptions {
 //     as MFMA A-operand tiles: rows in tiles of 16, columns in slices of 4;
 //     tile (rt, ks) holds 64 values at aoff + 64 (rt * nks + ks), value
 //     (row 16 rt + i, column 4 ks + k) at position i + 16 k, nks = ceil(w/4),
-//     zero padded.
+//     zero padded;
+//   * the inverse of the diagonal triangle (lower triangular) at linv_off, in
+//     the same tile format with nrt_d = ceil(w/16) row tiles, stored in the
+//     order the TRSM consumes them: when nrt_d > 2 the row tiles [2, nrt_d)
+//     first, then [0, 2) (so that X rows 32.. are replaced before the rows
+//     0..31 they depend on); otherwise row tiles [0, nrt_d).
 struct BlockDesc {
     int32_t row0;
     int32_t w;
@@ -57,6 +62,7 @@ struct BlockDesc {
     int64_t lval_off;
     int64_t rows_off;
     int64_t aoff;
+    int64_t linv_off;
 };
 
 struct SubPlan {

@@ -49,6 +49,7 @@ std::string to_plan_options(const sc_options_t& o, PlanOptions& po) {
     if (o.precision != SC_PREC_FP64 && o.precision != SC_PREC_MIXED) return "unknown precision";
     if (o.panel_width < 0 || o.relax_width < 0 || o.leaf_nodes < 0 || o.n_threads < 0)
         return "negative option";
+    if (o.assembly_kernels < 0 || o.assembly_kernels > 2) return "assembly_kernels must be 0, 1 or 2";
     if (o.panel_width) po.panel_width = o.panel_width;
     if (po.panel_width > kMaxPanel || po.panel_width < 16) return "panel_width must be in [16, 64]";
     if (o.relax_width) po.relax_width = o.relax_width;
@@ -96,6 +97,8 @@ struct sc_plan_s {
     std::vector<BlockDev> h_blocks;
     std::vector<SyrkItem> h_syrk;               // interleaved over XCDs, idle items sub = -1
     std::vector<int32_t> h_tile_order;          // TRSM workgroup -> tile (-1 idle)
+    std::vector<SyrkItem> h_syrk_items;         // SYRK items in subdomain order
+    std::vector<int2> h_fused;                  // fused assembly items
     std::vector<int2> h_apply;
     int64_t nval_total = 0, nrows_total = 0, ncol_total = 0, X_total = 0, F_total = 0, dual_total = 0;
     double* h_lval = nullptr;                 // pinned
@@ -105,6 +108,9 @@ struct sc_plan_s {
     DevBuf<BlockDev> d_blocks;
     DevBuf<SyrkItem> d_syrk;
     DevBuf<int32_t> d_tile_order;
+    DevBuf<SyrkItem> d_syrk_items;
+    DevBuf<int2> d_fused;
+    DevBuf<int32_t> d_done, d_err;
     DevBuf<int2> d_apply;
     DevBuf<int32_t> d_rows, d_piv, d_pi;
     DevBuf<int8_t> d_sgn;
@@ -121,9 +127,14 @@ struct sc_plan_s {
     struct PendingTiming { int kernel; hipEvent_t a, b; };
     std::vector<PendingTiming> pending;
     std::vector<hipEvent_t> event_pool;
-    double ms_sum[4] = {0, 0, 0, 0};
-    int64_t ms_count[4] = {0, 0, 0, 0};
+    double ms_sum[kNumTimed] = {};
+    int64_t ms_count[kNumTimed] = {};
 
+    bool fused() const { return opt.assembly_kernels == 1; }
+    hipError_t launch_assembly(hipStream_t st, hipEvent_t* ev) {
+        if (fused()) return launch_assemble_fused(tables(), st, ev);
+        return mixed ? launch_assemble_mixed(tables(), st, ev) : launch_assemble_f64(tables(), st, ev);
+    }
     hipError_t take_events(int k, hipEvent_t* out) {
         for (int i = 0; i < k; ++i) {
             if (event_pool.empty()) {
@@ -159,6 +170,8 @@ struct sc_plan_s {
         return (int64_t)(d_subs.count * sizeof(SubDev) + d_tiles.count * sizeof(TileDev) +
                          d_blocks.count * sizeof(BlockDev) + d_syrk.count * sizeof(SyrkItem) +
                          d_apply.count * sizeof(int2) + d_tile_order.count * 4 +
+                         d_syrk_items.count * sizeof(SyrkItem) + d_fused.count * sizeof(int2) +
+                         (d_done.count + d_err.count) * 4 +
                          (d_rows.count + d_piv.count + d_pi.count) * 4 + d_sgn.count +
                          (d_lval.count + d_X.count + d_F.count) * 8 +
                          (d_lval32.count + d_X32.count + d_F32.count) * 4 +
@@ -166,7 +179,7 @@ struct sc_plan_s {
     }
     void release() {
         d_subs.release(); d_tiles.release(); d_blocks.release(); d_syrk.release(); d_apply.release();
-        d_tile_order.release();
+        d_tile_order.release(); d_syrk_items.release(); d_fused.release(); d_done.release(); d_err.release();
         d_rows.release(); d_piv.release(); d_pi.release(); d_sgn.release();
         d_lval.release(); d_X.release(); d_F.release();
         d_lval32.release(); d_X32.release(); d_F32.release();
@@ -188,6 +201,12 @@ struct sc_plan_s {
         t.lval32 = d_lval32.p; t.X32 = d_X32.p; t.F32 = d_F32.p;
         t.apply_items = d_apply.p;
         t.tile_order = d_tile_order.p;
+        t.fused = d_fused.p;
+        t.syrk_items = d_syrk_items.p;
+        t.done = d_done.p;
+        t.err = d_err.p;
+        t.nfused = (int64_t)h_fused.size();
+        t.nsub = nsub;
         t.ntiles = (int64_t)h_tile_order.size();
         t.nsyrk = (int64_t)h_syrk.size();
         t.napply = (int64_t)h_apply.size();
@@ -256,7 +275,7 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
         s.F_off = fo;
         s.dual_off = dual;
         for (const BlockDesc& b : sp.blocks)
-            P->h_blocks.push_back(BlockDev{b.row0, b.w, b.nbelow, b.ld, b.lval_off, b.rows_off, b.aoff});
+            P->h_blocks.push_back(BlockDev{b.row0, b.w, b.nbelow, b.ld, b.lval_off, b.rows_off, b.aoff, b.linv_off});
         for (int32_t t = 0; t < s.ntiles; ++t) {
             TileDev T{};
             T.sub = i;
@@ -307,7 +326,37 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
         std::vector<std::vector<int32_t>> xt(kNumXcd);
         std::vector<std::vector<SyrkItem>> xs(kNumXcd);
         std::vector<std::vector<SyrkItem>> per_sub(nsub);
+        std::vector<int64_t> syrk_first(nsub + 1, 0);
         for (const SyrkItem& it : P->h_syrk) per_sub[it.sub].push_back(it);
+        P->h_syrk_items = P->h_syrk;                       // subdomain order
+        for (int32_t i = 0; i < nsub; ++i) syrk_first[i + 1] = syrk_first[i] + (int64_t)per_sub[i].size();
+        // fused list per XCD: the SYRK items of a subdomain follow its TRSM
+        // tiles at a distance of kFusedLagTiles further TRSM tiles, so that
+        // by the time they are dispatched their X is normally complete and
+        // they rarely hold a slot while waiting
+        std::vector<std::vector<int2>> xf(kNumXcd);
+        for (int x = 0; x < kNumXcd; ++x) {
+            const auto& L = xsub[x];
+            std::vector<std::pair<int32_t, int64_t>> pend;    // (subdomain, TRSM tiles emitted when it ended)
+            size_t head = 0;
+            int64_t emitted = 0;
+            auto flush_syrk = [&](int32_t i) {
+                for (int64_t q = syrk_first[i]; q < syrk_first[i + 1]; ++q) xf[x].push_back(make_int2(2, (int)q));
+            };
+            for (int32_t i : L) {
+                const SubDev& sd = P->h_subs[i];
+                for (int32_t t = 0; t < sd.ntiles; ++t) xf[x].push_back(make_int2(1, (int)(sd.tile_off + t)));
+                emitted += sd.ntiles;
+                pend.emplace_back(i, emitted);
+                while (head < pend.size() && emitted - pend[head].second >= kFusedLagTiles) flush_syrk(pend[head++].first);
+            }
+            while (head < pend.size()) flush_syrk(pend[head++].first);
+        }
+        size_t lf = 0;
+        for (int x = 0; x < kNumXcd; ++x) lf = std::max(lf, xf[x].size());
+        P->h_fused.assign(lf * kNumXcd, make_int2(0, 0));
+        for (int x = 0; x < kNumXcd; ++x)
+            for (size_t k = 0; k < xf[x].size(); ++k) P->h_fused[k * kNumXcd + x] = xf[x][k];
         for (int x = 0; x < kNumXcd; ++x)
             for (int32_t i : xsub[x]) {
                 const SubDev& sd = P->h_subs[i];
@@ -350,6 +399,10 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
     ALLOC(p->d_syrk, p->h_syrk.size());
     ALLOC(p->d_apply, p->h_apply.size());
     ALLOC(p->d_tile_order, p->h_tile_order.size());
+    ALLOC(p->d_syrk_items, p->h_syrk_items.size());
+    ALLOC(p->d_fused, p->h_fused.size());
+    ALLOC(p->d_done, (size_t)std::max(1, nsub));
+    ALLOC(p->d_err, 1);
     ALLOC(p->d_rows, (size_t)rows);
     ALLOC(p->d_piv, (size_t)colo);
     ALLOC(p->d_pi, (size_t)colo);
@@ -391,6 +444,12 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
     if (e == hipSuccess) e = up(p->d_syrk.p, p->h_syrk.data(), p->h_syrk.size() * sizeof(SyrkItem));
     if (e == hipSuccess) e = up(p->d_apply.p, p->h_apply.data(), p->h_apply.size() * sizeof(int2));
     if (e == hipSuccess) e = up(p->d_tile_order.p, p->h_tile_order.data(), p->h_tile_order.size() * 4);
+    if (e == hipSuccess) e = up(p->d_syrk_items.p, p->h_syrk_items.data(), p->h_syrk_items.size() * sizeof(SyrkItem));
+    if (e == hipSuccess) e = up(p->d_fused.p, p->h_fused.data(), p->h_fused.size() * sizeof(int2));
+    {
+        const int32_t zero = 0;
+        if (e == hipSuccess) e = up(p->d_err.p, &zero, 4);
+    }
     if (e == hipSuccess) e = up(p->d_rows.p, h_rows.data(), h_rows.size() * 4);
     if (e == hipSuccess) e = up(p->d_piv.p, h_piv.data(), h_piv.size() * 4);
     if (e == hipSuccess) e = up(p->d_pi.p, h_pi.data(), h_pi.size() * 4);
@@ -465,8 +524,7 @@ sc_status_t sc_assemble(sc_plan_t P, void* stream) {
             hipGraph_t g = nullptr;
             hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
-                const hipError_t el = P->mixed ? launch_assemble_mixed(P->tables(), cap, nullptr)
-                                               : launch_assemble_f64(P->tables(), cap, nullptr);
+                const hipError_t el = P->launch_assembly(cap, nullptr);
                 e = hipStreamEndCapture(cap, &g);
                 if (e == hipSuccess) e = el;
             }
@@ -488,9 +546,12 @@ sc_status_t sc_assemble(sc_plan_t P, void* stream) {
         HIP_TRY(P->take_events(4, ev));
         evp = ev;
     }
-    if (P->mixed) HIP_TRY(launch_assemble_mixed(P->tables(), (hipStream_t)stream, evp));
-    else HIP_TRY(launch_assemble_f64(P->tables(), (hipStream_t)stream, evp));
-    if (evp) {
+    HIP_TRY(P->launch_assembly((hipStream_t)stream, evp));
+    if (evp && P->fused()) {
+        P->pending.push_back({4, ev[0], ev[1]});
+        P->event_pool.push_back(ev[2]);
+        P->event_pool.push_back(ev[3]);
+    } else if (evp) {
         P->pending.push_back({0, ev[0], ev[1]});
         P->pending.push_back({1, ev[2], ev[3]});
     }
@@ -645,6 +706,12 @@ sc_status_t sc_get_F(sc_plan_t P, int32_t sub, double* out, int32_t ld, int32_t 
     if (!out || ld < s.m) return fail(SC_ERR_INVALID_ARG, "bad output buffer or ld");
     HIP_TRY(hipSetDevice(P->device));
     hipStream_t st = (hipStream_t)stream;
+    {
+        int32_t err = 0;
+        HIP_TRY(hipMemcpyAsync(&err, P->d_err.p, 4, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (err) return fail(SC_ERR_DEVICE, "fused assembly: a SYRK tile gave up waiting for its X tiles");
+    }
     if (!P->mixed) {
         const double* src = P->d_F.p + s.F_off;
         HIP_TRY(hipMemcpy2DAsync(out, (size_t)ld * sizeof(double), src, (size_t)s.m * sizeof(double),
@@ -774,7 +841,7 @@ sc_status_t sc_kernel_times(sc_plan_t P, double* ms, int64_t* counts, int32_t re
     if (!P) return fail(SC_ERR_INVALID_ARG, "plan is NULL");
     HIP_TRY(hipSetDevice(P->device));
     HIP_TRY(P->drain_timing(true));
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < kNumTimed; ++k) {
         if (ms) ms[k] = P->ms_sum[k];
         if (counts) counts[k] = P->ms_count[k];
         if (reset) { P->ms_sum[k] = 0; P->ms_count[k] = 0; }

@@ -40,7 +40,8 @@ class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("disable_staircase", ctypes.c_int32),
                 ("panel_width", ctypes.c_int32), ("relax_width", ctypes.c_int32),
                 ("leaf_nodes", ctypes.c_int32), ("n_threads", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("use_graph", ctypes.c_int32), ("assembly_kernels", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 class HostInfo(ctypes.Structure):
@@ -135,10 +136,14 @@ def _fill_desc(d, s, keep, use_coords=True):
     d.dofs_per_node = int(getattr(s, "dofs_per_node", 1))
 
 
+ASSEMBLY_KERNELS = {"default": 0, "fused": 1, "separate": 2}
+
+
 def _options(precision="fp64", staircase=True, panel_width=0, relax_width=0, leaf_nodes=0, n_threads=0,
-             use_graph=False):
+             use_graph=False, assembly="default"):
     opt = Options()
     opt.use_graph = 1 if use_graph else 0
+    opt.assembly_kernels = ASSEMBLY_KERNELS[assembly] if isinstance(assembly, str) else int(assembly)
     opt.precision = {"fp64": SC_PREC_FP64, "mixed": SC_PREC_MIXED}.get(precision, precision) \
         if isinstance(precision, str) else int(precision)
     opt.disable_staircase = 0 if staircase else 1
@@ -202,7 +207,7 @@ class Plan:
 
     def __init__(self, subdomains: Sequence, precision: str = "fp64", staircase: bool = True,
                  panel_width: int = 0, relax_width: int = 0, leaf_nodes: int = 0, n_threads: int = 0,
-                 use_coords: bool = True, use_graph: bool = False, stream=None):
+                 use_coords: bool = True, use_graph: bool = False, assembly: str = "default", stream=None):
         lib = load()
         self._lib = lib
         self._h = ctypes.c_void_p(0)
@@ -212,7 +217,7 @@ class Plan:
         descs = (SubdomainDesc * max(1, len(self.subdomains)))()
         for i, s in enumerate(self.subdomains):
             _fill_desc(descs[i], s, keep, use_coords)
-        opt = _options(precision, staircase, panel_width, relax_width, leaf_nodes, n_threads, use_graph)
+        opt = _options(precision, staircase, panel_width, relax_width, leaf_nodes, n_threads, use_graph, assembly)
         _check(lib.sc_plan_create(descs, len(self.subdomains), ctypes.byref(opt), _stream_handle(stream),
                                   ctypes.byref(self._h)))
         del keep
@@ -288,12 +293,12 @@ class Plan:
     def set_timing(self, enable: bool = True):
         _check(self._lib.sc_set_timing(self._h, 1 if enable else 0))
 
-    KERNELS = ("trsm", "syrk", "apply", "apply_implicit")
+    KERNELS = ("trsm", "syrk", "apply", "apply_implicit", "assemble_fused")
 
     def kernel_times(self, reset: bool = True) -> dict:
         """Accumulated kernel milliseconds and launch counts (HIP events)."""
-        ms = (ctypes.c_double * 4)()
-        cnt = (ctypes.c_int64 * 4)()
+        ms = (ctypes.c_double * len(self.KERNELS))()
+        cnt = (ctypes.c_int64 * len(self.KERNELS))()
         _check(self._lib.sc_kernel_times(self._h, ms, cnt, 1 if reset else 0))
         return {k: (ms[i], cnt[i]) for i, k in enumerate(self.KERNELS)}
 

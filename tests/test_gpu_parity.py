@@ -121,7 +121,8 @@ def test_run_to_run_deterministic():
         assert np.array_equal(x, y)
 
 
-def test_edge_cases_in_one_batch():
+@pytest.mark.parametrize("assembly", ["fused", "separate"])
+def test_edge_cases_in_one_batch(assembly):
     base = scgen.box_subdomain("heat", (4, 4, 3), 0.25, seed=13)
     tiny = scgen.box_subdomain("heat", (1, 1), 1.0, seed=14)            # n = 4, m = 4
     empty = base.with_columns(np.zeros(0, np.int32), np.zeros(0, np.int8))
@@ -132,7 +133,7 @@ def test_edge_cases_in_one_batch():
     interior = base.with_columns(np.arange(0, base.n, 7, dtype=np.int32),
                                  scgen.rng.signs_from_seed(4, len(range(0, base.n, 7))))
     subs = [base, tiny, empty, one, ragged, same_pivot, interior]
-    plan = _assemble(subs)
+    plan = _assemble(subs, assembly=assembly)
     _check_against_oracle(plan, subs)
 
 
@@ -338,6 +339,46 @@ def test_graph_replays_match_eager(precision):
         torch.cuda.synchronize()
         for i in range(len(subs)):
             assert np.array_equal(plan.get_F(i), ref[i]), (rep, i)
+
+
+# ---------------------------------------------------------- fused assembly
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fused_assembly_matches_two_launches(precision):
+    """One fused launch (SYRK tiles wait on their subdomain's TRSM counter)
+    gives bit for bit the F of the two-launch assembly, on a batch with
+    uneven subdomains, an empty interface and more subdomains than XCDs;
+    repeated calls (counters cleared each time) and graph replays agree."""
+    torch = _torch_init()
+    subs = (scgen.config_subdomains(2, count=12) + scgen.config_subdomains(3, count=6) +
+            scgen.config_subdomains(1))
+    subs.append(subs[1].with_columns(np.zeros(0, np.int32), np.zeros(0, np.int8)))
+    two = _assemble(subs, precision=precision, assembly="separate")
+    ref = [two.get_F(i) for i in range(len(subs))]
+    for use_graph in (False, True):
+        plan = P.Plan(subs, precision=precision, assembly="fused", use_graph=use_graph)
+        plan.factor()
+        for rep in range(3):
+            junk = torch.randn(1 << 20, device="cuda")
+            plan.assemble()
+            junk.mul_(2.0)
+            torch.cuda.synchronize()
+            for i in range(len(subs)):
+                assert np.array_equal(plan.get_F(i), ref[i]), (use_graph, rep, i)
+        plan.destroy()
+
+
+def test_fused_assembly_is_timed_in_its_own_slot():
+    _torch_init()
+    subs = scgen.config_subdomains(3, count=4)
+    plan = P.Plan(subs, assembly="fused")
+    plan.factor()
+    plan.set_timing(True)
+    plan.assemble()
+    plan.assemble()
+    t = plan.kernel_times()
+    assert t["assemble_fused"][1] == 2 and t["assemble_fused"][0] > 0
+    assert t["trsm"][1] == 0 and t["syrk"][1] == 0
 
 
 def test_autotune_picks_a_candidate():
