@@ -68,7 +68,9 @@ __device__ __forceinline__ v4f mfma_f32(float a, float b, v4f c) {
 // step 1 stays FP64 (the block rows are widened, solved, rounded back).
 // ---------------------------------------------------------------------------
 constexpr int kChunkBytes = 2 * 16 * 64 * 8;     // two FP64 row tiles of 16 k-slices
-constexpr int kTrsmSmem = 2 * kChunkBytes;
+constexpr int kIdxBytes = 32 * 4;                // row indices carried by a chunk
+constexpr int kBufBytes = kChunkBytes + kIdxBytes;
+constexpr int kTrsmSmem = 2 * kBufBytes;
 
 // Barrier that waits for this wavefront's LDS traffic only: global loads in
 // flight (prefetches, gathers) stay in flight across it.
@@ -78,10 +80,14 @@ __device__ __forceinline__ void lds_barrier() {
 
 struct ChunkRegs {
     uint4 v0, v1, v2, v3;
+    uint4 vi;            // threads 0..7: the 32 row indices the chunk carries
 };
 struct ChunkSrc {
     const char* p;       // always a valid address (the subdomain's factor when bytes == 0)
     int bytes;
+    bool has_idx;        // the chunk carries the row indices at ip
+    const int32_t* ip;   // 32 row indices of the pruned chunk gathered next; always a
+                         // valid address (the row array is padded by 32 entries)
 };
 
 // Every thread loads its four 16-byte pieces unconditionally (pieces past the
@@ -92,43 +98,49 @@ __device__ __forceinline__ void chunk_load(ChunkRegs& c, const ChunkSrc& s) {
     c.v1 = *reinterpret_cast<const uint4*>(s.p + (e + 4096 < s.bytes ? e + 4096 : 0));
     c.v2 = *reinterpret_cast<const uint4*>(s.p + (e + 8192 < s.bytes ? e + 8192 : 0));
     c.v3 = *reinterpret_cast<const uint4*>(s.p + (e + 12288 < s.bytes ? e + 12288 : 0));
+    c.vi = *reinterpret_cast<const uint4*>(s.ip + 4 * (threadIdx.x & 7));
 }
 
-__device__ __forceinline__ void chunk_store(const ChunkRegs& c, char* __restrict__ dst, int bytes) {
+__device__ __forceinline__ void chunk_store(const ChunkRegs& c, char* __restrict__ dst, const ChunkSrc& s) {
     const int e = threadIdx.x * 16;
-    if (e < bytes) *reinterpret_cast<uint4*>(dst + e) = c.v0;
-    if (e + 4096 < bytes) *reinterpret_cast<uint4*>(dst + e + 4096) = c.v1;
-    if (e + 8192 < bytes) *reinterpret_cast<uint4*>(dst + e + 8192) = c.v2;
-    if (e + 12288 < bytes) *reinterpret_cast<uint4*>(dst + e + 12288) = c.v3;
+    if (e < s.bytes) *reinterpret_cast<uint4*>(dst + e) = c.v0;
+    if (e + 4096 < s.bytes) *reinterpret_cast<uint4*>(dst + e + 4096) = c.v1;
+    if (e + 8192 < s.bytes) *reinterpret_cast<uint4*>(dst + e + 8192) = c.v2;
+    if (e + 12288 < s.bytes) *reinterpret_cast<uint4*>(dst + e + 12288) = c.v3;
+    if (s.has_idx && threadIdx.x < 8) *reinterpret_cast<uint4*>(dst + kChunkBytes + 16 * threadIdx.x) = c.vi;
 }
 
 // Scalar copy of the block descriptor fields the TRSM uses.
 struct BlockLite {
     int w, nb;
-    int64_t aoff, linv_off;
+    int64_t aoff, linv_off, rows_off;
 };
 
 __device__ __forceinline__ BlockLite block_lite(const BlockDev* __restrict__ B, int b) {
-    return {B[b].w, B[b].nbelow, B[b].aoff, B[b].linv_off};
+    return {B[b].w, B[b].nbelow, B[b].aoff, B[b].linv_off, B[b].rows_off};
 }
 
 // Chunk c of a block: c < nd are the inverse's row-tile groups, the rest
 // groups of two pruned row tiles (TA = precision of the update's A tiles).
+// The first chunk carries the row indices of pruned chunk 0, pruned chunk p
+// those of pruned chunk p + 1: they are gathered while the chunk is in use.
 template <class TA>
 __device__ __forceinline__ ChunkSrc chunk_src(const BlockLite& bd, int c, const double* __restrict__ L,
-                                              const TA* __restrict__ LA) {
+                                              const TA* __restrict__ LA, const int32_t* __restrict__ R) {
     const int nks = (bd.w + 3) >> 2;
     const int nrt_d = (bd.w + 15) >> 4;
     const int nd = nrt_d > 2 ? 2 : 1;
+    const int np = (((bd.nb + 15) >> 4) + 1) >> 1;
     if (c < nd) {
         const int slot0 = c == 0 ? 0 : nrt_d - 2;
         const int nt = nd == 1 ? nrt_d : (c == 0 ? nrt_d - 2 : 2);
-        return {reinterpret_cast<const char*>(L + bd.linv_off + (int64_t)slot0 * nks * 64), nt * nks * 64 * 8};
+        return {reinterpret_cast<const char*>(L + bd.linv_off + (int64_t)slot0 * nks * 64), nt * nks * 64 * 8,
+                c == 0 && np > 0, R + bd.rows_off};
     }
     const int p = c - nd;
     const int nt = min(2, ((bd.nb + 15) >> 4) - 2 * p);
     return {reinterpret_cast<const char*>(LA + bd.aoff + (int64_t)2 * p * nks * 64),
-            nt * nks * 64 * (int)sizeof(TA)};
+            nt * nks * 64 * (int)sizeof(TA), p + 1 < np, R + bd.rows_off + 32 * min(p + 1, np - 1)};
 }
 
 template <bool MIXED>
@@ -170,16 +182,16 @@ __device__ __forceinline__ void trsm_tile(
     ChunkRegs pre;
     BlockLite bd = block_lite(B, first_block);
     {
-        const ChunkSrc c0 = chunk_src(bd, 0, L, LA);
+        const ChunkSrc c0 = chunk_src(bd, 0, L, LA, R);
         chunk_load(pre, c0);
-        chunk_store(pre, smem, c0.bytes);
+        chunk_store(pre, smem, c0);
     }
     lds_barrier();
     int buf = 0;
 
     auto advance = [&](const ChunkSrc& nx) {     // next chunk: registers -> free LDS half
         if (nx.bytes > 0) {
-            chunk_store(pre, smem + (buf ^ 1) * kChunkBytes, nx.bytes);
+            chunk_store(pre, smem + (buf ^ 1) * kBufBytes, nx);
             lds_barrier();
             buf ^= 1;
         }
@@ -194,25 +206,25 @@ __device__ __forceinline__ void trsm_tile(
         const int nrt = (nb + 15) >> 4;
         const int np = (nrt + 1) >> 1;
         const int nch = nd + np;
-        const int32_t* __restrict__ rw = R + B[b].rows_off;
         const bool act = b >= my_start;
         const BlockLite bn = block_lite(B, b + 1 < S.nblocks ? b + 1 : b);
         auto next_src = [&](int c) {
-            ChunkSrc nx{reinterpret_cast<const char*>(L), 0};
-            if (c + 1 < nch) nx = chunk_src(bd, c + 1, L, LA);
-            else if (b + 1 < S.nblocks) nx = chunk_src(bn, 0, L, LA);
+            ChunkSrc nx{reinterpret_cast<const char*>(L), 0, false, R};
+            if (c + 1 < nch) nx = chunk_src(bd, c + 1, L, LA, R);
+            else if (b + 1 < S.nblocks) nx = chunk_src(bn, 0, L, LA, R);
             return nx;
         };
 
         VX accn[2];                              // rows of the next pruned chunk
         int offn[2][4];
-        auto gather = [&](int p) {
+        auto gather = [&](int p) {               // row indices from the chunk in LDS
+            const int32_t* __restrict__ sidx = reinterpret_cast<const int32_t*>(smem + buf * kBufBytes + kChunkBytes);
 #pragma unroll
             for (int u = 0; u < 2; ++u)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int q = 32 * p + 16 * u + (MIXED ? 4 * g + r : 4 * r + g);
-                    offn[u][r] = q < nb ? (rw[q] - kstart) * kTile + col : -1;
+                    const int k = 16 * u + (MIXED ? 4 * g + r : 4 * r + g);
+                    offn[u][r] = 32 * p + k < nb ? (sidx[k] - kstart) * kTile + col : -1;
                     accn[u][r] = offn[u][r] >= 0 ? Xs[offn[u][r]] : TX(0);
                 }
         };
@@ -236,7 +248,7 @@ __device__ __forceinline__ void trsm_tile(
                 const ChunkSrc nx = next_src(c);
                 chunk_load(pre, nx);
                 if (act) {
-                    const double* __restrict__ sA = reinterpret_cast<const double*>(smem + buf * kChunkBytes);
+                    const double* __restrict__ sA = reinterpret_cast<const double*>(smem + buf * kBufBytes);
                     const int t0 = (nd == 2 && c == 0) ? 2 : 0;
                     const int nt = nd == 1 ? nrt_d : (c == 0 ? nrt_d - 2 : 2);
                     v4d tmp[2];
@@ -290,7 +302,7 @@ __device__ __forceinline__ void trsm_tile(
 #pragma unroll
                     for (int r = 0; r < 4; ++r) off[u][r] = offn[u][r];
                 if (p + 1 < np) gather(p + 1);
-                const TX* __restrict__ sA = reinterpret_cast<const TX*>(smem + buf * kChunkBytes);
+                const TX* __restrict__ sA = reinterpret_cast<const TX*>(smem + buf * kBufBytes);
                 const int nt = min(2, nrt - 2 * p);
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {

@@ -507,6 +507,7 @@ std::string build_plan(const SubdomainInput& in, const PlanOptions& opt, SubPlan
             d.nbelow = (int32_t)rows.size();
             d.ld = d.w;
             d.lval_off = voff;
+            while (P.brows.size() % 4) P.brows.push_back(-1);   // 16-byte aligned row lists
             d.rows_off = (int64_t)P.brows.size();
             voff += (int64_t)d.w * d.w;
             voff = (voff + 7) / 8 * 8;                  // 64-byte aligned tiles

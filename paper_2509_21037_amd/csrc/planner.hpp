@@ -89,7 +89,7 @@ struct SubPlan {
     // GPU blocks
     int32_t block_width = 64;
     std::vector<BlockDesc> blocks;
-    std::vector<int32_t> brows;                // pruned rows of every block
+    std::vector<int32_t> brows;                // pruned rows of every block (lists start 16-byte aligned)
     int64_t bval = 0;                          // values in all block panels
     std::vector<int32_t> block_of_row;         // row -> block index
     // statistics

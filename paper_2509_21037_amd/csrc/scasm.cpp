@@ -296,7 +296,7 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
         for (int32_t I = 0; I < nst; ++I)
             for (int32_t J = 0; J <= I; ++J) P->h_syrk.push_back(SyrkItem{i, I, J, 0});
         blk += s.nblocks;
-        rows += (int64_t)sp.brows.size();
+        rows += ((int64_t)sp.brows.size() + 3) / 4 * 4;
         lv += sp.bval;
         colo += sp.m;
         fo += ((int64_t)sp.m * sp.m + 3) / 4 * 4;      // 32-byte aligned F blocks
@@ -376,6 +376,7 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
         }
     }
     P->nval_total = lv;
+    rows += 32;                            // the TRSM reads whole 32-entry groups of a row list
     P->nrows_total = rows;
     P->ncol_total = colo;
     P->X_total = xo;
@@ -423,7 +424,7 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
         if (e != hipSuccess) return cleanup_fail(SC_ERR_OOM, "pinned host allocation failed");
     }
     // flatten per-subdomain arrays
-    std::vector<int32_t> h_rows((size_t)rows), h_piv((size_t)colo), h_pi((size_t)colo);
+    std::vector<int32_t> h_rows((size_t)rows, -1), h_piv((size_t)colo), h_pi((size_t)colo);
     std::vector<int8_t> h_sgn((size_t)colo);
     for (int32_t i = 0; i < nsub; ++i) {
         const SubPlan& sp = P->plans[i];
