@@ -89,7 +89,7 @@ def time_assembly(torch, plan, steps, warmup, graph=False):
         torch.cuda.synchronize()
     kt = plan.kernel_times(reset=True)
     plan.set_timing(False)
-    return 1e3 * elapsed / steps, {k: kt[k][0] / kt[k][1] for k in ("trsm", "syrk", "assemble_fused")
+    return 1e3 * elapsed / steps, {k: kt[k][0] / kt[k][1] for k in ("trsm", "syrk", "assemble_overlap")
                                    if kt[k][1] > 0}
 
 
@@ -173,10 +173,10 @@ def main():
                     help="pick the factor block width with sc_autotune (auto: on for the elasticity batches)")
     ap.add_argument("--graph", choices=("auto", "on", "off"), default="auto",
                     help="replay the assembly as a captured HIP graph (auto: on for the elasticity batches)")
-    ap.add_argument("--assembly", choices=("fused", "separate"), default="separate",
-                    help="one fused TRSM+SYRK launch, or two launches")
-    ap.add_argument("--compare-fused", action="store_true",
-                    help="also time the FP64 assembly as one fused launch")
+    ap.add_argument("--assembly", choices=("overlap", "separate"), default="separate",
+                    help="TRSM and SYRK of successive subdomain groups overlapped on two streams, or two launches")
+    ap.add_argument("--compare-assembly", action="store_true",
+                    help="also time the FP64 assembly in the other mode (overlap / separate)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain device copy of 2 GiB first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -223,7 +223,7 @@ def main():
     ms_per_step, kms = time_assembly(torch, plan, args.steps, args.warmup, use_graph)
     log(f"bench: FP64 {ms_per_step:.3f} ms/step, kernels {kms}")
     useful = st["trsm_useful"] + st["syrk_useful"]
-    flops = {"trsm": st["trsm_useful"], "syrk": st["syrk_useful"], "assemble_fused": useful}
+    flops = {"trsm": st["trsm_useful"], "syrk": st["syrk_useful"], "assemble_overlap": useful}
     dom = max(kms, key=kms.get)
     achieved = flops[dom] / (kms[dom] * 1e-3) / 1e12
     roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": PEAK_TFLOPS["fp64"],
@@ -257,8 +257,8 @@ def main():
         orig, _ = time_assembly(torch, plan_o, max(1, args.steps // 2), 1)
         plan_o.destroy()
     other = None
-    if args.compare_fused:
-        alt = "separate" if args.assembly == "fused" else "fused"
+    if args.compare_assembly:
+        alt = "separate" if args.assembly == "overlap" else "overlap"
         plan_s = P.Plan(subs, panel_width=args.panel_width, use_graph=use_graph, assembly=alt)
         plan_s.factor()
         ms_s, kms_s = time_assembly(torch, plan_s, args.steps, args.warmup, use_graph)

@@ -101,10 +101,12 @@ typedef struct {
  *                    HIP graph and replays it on every later call (the plan's
  *                    buffers and tables are fixed, so the graph stays valid);
  *                    calls made while kernel timing is enabled launch eagerly
- *   assembly_kernels 0 = library default (two launches), 1 = one fused
- *                    launch in which the F tiles of a subdomain (SYRK) wait
- *                    on a device counter for its X tiles (TRSM) and overlap
- *                    the TRSM of other subdomains, 2 = two launches (all TRSM
+ *   assembly_kernels 0 = library default (two launches), 1 = overlapped:
+ *                    the batch is cut into groups of subdomains and the SYRK
+ *                    of group g runs on a second, library-owned stream while
+ *                    the TRSM of group g+1 runs on the caller's stream (event
+ *                    dependencies; the call returns with the caller's stream
+ *                    waiting for the last SYRK), 2 = two launches (all TRSM
  *                    tiles, then all SYRK tiles)
  */
 typedef struct {
@@ -206,7 +208,7 @@ sc_status_t sc_plan_stats(sc_plan_t plan, int32_t* nsub, int64_t* dual_total,
  * (synchronising on the recorded events):
  *   ms[0] staircase TRSM, ms[1] staircase SYRK + permute-back,
  *   ms[2] explicit apply (GEMV), ms[3] implicit apply,
- *   ms[4] fused assembly (TRSM and SYRK in one launch);
+ *   ms[4] overlapped assembly (first TRSM to last SYRK, assembly_kernels 1);
  *   counts[k] = number of launches of kernel k summed into ms[k].
  * `reset` != 0 clears the sums after reading.  Arrays hold 5 entries. */
 sc_status_t sc_set_timing(sc_plan_t plan, int32_t enable);

@@ -14,10 +14,10 @@ constexpr int kSyrkTile = 128;     // edge of an F output tile (two X column til
 // k runs on XCD k mod kNumXcd); work lists are interleaved so that all items
 // of one subdomain share an XCD and its L2.
 constexpr int kNumXcd = 8;
-// Fused assembly: TRSM tiles dispatched on an XCD between the last TRSM tile
-// of a subdomain and its first SYRK item (about 1.5 times the workgroups one
-// XCD holds at once: 32 CUs x 2).
-constexpr int kFusedLagTiles = 96;
+// Overlapped assembly: the batch is cut into this many groups of subdomains
+// (each XCD's list into consecutive parts); the SYRK of a group runs on a
+// second stream while the TRSM of the next group runs.
+constexpr int kOverlapGroups = 8;
 
 struct SubDev {
     int32_t n, m, nblocks, ntiles;

@@ -743,19 +743,35 @@ hipError_t launch_apply(const DevTables& t, const double* p, double* q, hipStrea
 }
 
 // ---------------------------------------------------------------------------
-hipError_t launch_assemble_f64(const DevTables& t, hipStream_t stream, hipEvent_t* ev) {
+hipError_t launch_trsm(const DevTables& t, const int32_t* order, int64_t count, hipStream_t stream) {
+    if (count <= 0) return hipSuccess;
+    if (t.X32)
+        hipLaunchKernelGGL(trsm_stair_mixed, dim3((unsigned)count), dim3(256), 0, stream, t.subs, t.tiles,
+                           t.blocks, t.rows, t.lval, t.lval32, t.piv, t.sgn, order, t.X32);
+    else
+        hipLaunchKernelGGL(trsm_stair_f64, dim3((unsigned)count), dim3(256), 0, stream, t.subs, t.tiles,
+                           t.blocks, t.rows, t.lval, t.piv, t.sgn, order, t.X);
+    return hipGetLastError();
+}
+
+hipError_t launch_syrk(const DevTables& t, const SyrkItem* items, int64_t count, hipStream_t stream) {
+    if (count <= 0) return hipSuccess;
+    if (t.X32)
+        hipLaunchKernelGGL(syrk_stair_f32, dim3((unsigned)count), dim3(256), 0, stream, t.subs, t.tiles, items,
+                           t.X32, t.pi, t.F32);
+    else
+        hipLaunchKernelGGL(syrk_stair_f64, dim3((unsigned)count), dim3(256), 0, stream, t.subs, t.tiles, items,
+                           t.X, t.pi, t.F);
+    return hipGetLastError();
+}
+
+hipError_t launch_assemble(const DevTables& t, hipStream_t stream, hipEvent_t* ev) {
     hipError_t e = hipSuccess;
     if (ev && (e = hipEventRecord(ev[0], stream)) != hipSuccess) return e;
-    if (t.ntiles > 0)
-        hipLaunchKernelGGL(trsm_stair_f64, dim3((unsigned)t.ntiles), dim3(256), 0, stream, t.subs,
-                           t.tiles, t.blocks, t.rows, t.lval, t.piv, t.sgn, t.tile_order, t.X);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_trsm(t, t.tile_order, t.ntiles, stream)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], stream)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[2], stream)) != hipSuccess) return e;
-    if (t.nsyrk > 0)
-        hipLaunchKernelGGL(syrk_stair_f64, dim3((unsigned)t.nsyrk), dim3(256), 0, stream, t.subs,
-                           t.tiles, t.syrk, t.X, t.pi, t.F);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_syrk(t, t.syrk, t.nsyrk, stream)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[3], stream)) != hipSuccess) return e;
     return hipSuccess;
 }
@@ -1025,128 +1041,11 @@ hipError_t launch_apply_implicit(const DevTables& t, const int64_t* xoff, double
     return hipSuccess;
 }
 
-// ---------------------------------------------------------------------------
-// Fused assembly: one launch over an item list that holds every TRSM tile
-// and every SYRK tile.  A SYRK item of subdomain i waits until all TRSM tiles
-// of i have signalled completion; in the list (per XCD, interleaved modulo
-// the XCD count) those tiles always come first, so they were dispatched
-// before it and never wait themselves.  The wait is bounded: on expiry the
-// item raises the error flag and returns (results are then invalid, nothing
-// hangs).  TRSM tiles of one subdomain overlap SYRK tiles of another, mixing
-// latency-bound and MFMA-bound work on each CU.
-// ---------------------------------------------------------------------------
-constexpr int kFusedSmem = kTrsmSmem > kSyrkSmem ? kTrsmSmem : kSyrkSmem;
-constexpr int kFusedSmemMixed = kTrsmSmem > kSyrkSmemF ? kTrsmSmem : kSyrkSmemF;
-constexpr long long kWaitLimit = 1ll << 24;     // s_sleep rounds (~seconds)
-
-__global__ __launch_bounds__(256) void fill_i32(int32_t* __restrict__ p, int32_t n, int32_t v) {
-    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) p[i] = v;
-}
-
-__device__ __forceinline__ void signal_done(int32_t* done) {
-    __threadfence();                             // each wavefront releases its own X stores
-    __syncthreads();
-    if (threadIdx.x == 0) atomicAdd(done, 1);
-}
-
-__device__ __forceinline__ bool wait_done(const int32_t* done, int32_t need, int32_t* err) {
-    __shared__ int ok;
-    if (threadIdx.x == 0) {
-        long long spins = 0;
-        while (__hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
-            __builtin_amdgcn_s_sleep(8);
-            if (++spins > kWaitLimit) break;
-        }
-        ok = spins <= kWaitLimit;
-        if (!ok) atomicOr(err, 1);
-    }
-    __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // the counter's release covers every X store
-    return ok != 0;
-}
-
-__global__ __launch_bounds__(256, 2) void assemble_fused_f64(
-    const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
-    const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows,
-    const double* __restrict__ lval, const int32_t* __restrict__ piv, const int8_t* __restrict__ sgn,
-    const int2* __restrict__ items, const SyrkItem* __restrict__ syrk, double* __restrict__ X,
-    const int32_t* __restrict__ pi, double* __restrict__ F, int32_t* __restrict__ done,
-    int32_t* __restrict__ err)
-{
-    __shared__ __align__(16) char smem[kFusedSmem];
-    const int2 it = items[blockIdx.x];
-    if (it.x == 1) {
-        trsm_tile<false>(subs, tiles, blocks, rows, lval, nullptr, piv, sgn, X, it.y, smem);
-        signal_done(done + tiles[it.y].sub);
-    } else if (it.x == 2) {
-        const SyrkItem si = syrk[it.y];
-        if (wait_done(done + si.sub, subs[si.sub].ntiles, err)) syrk_item_f64(subs, tiles, si, X, pi, F, smem);
-    }
-}
-
-__global__ __launch_bounds__(256, 2) void assemble_fused_mixed(
-    const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
-    const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows,
-    const double* __restrict__ lval, const float* __restrict__ lval32, const int32_t* __restrict__ piv,
-    const int8_t* __restrict__ sgn, const int2* __restrict__ items, const SyrkItem* __restrict__ syrk,
-    float* __restrict__ X, const int32_t* __restrict__ pi, float* __restrict__ F, int32_t* __restrict__ done,
-    int32_t* __restrict__ err)
-{
-    __shared__ __align__(16) char smem[kFusedSmemMixed];
-    const int2 it = items[blockIdx.x];
-    if (it.x == 1) {
-        trsm_tile<true>(subs, tiles, blocks, rows, lval, lval32, piv, sgn, X, it.y, smem);
-        signal_done(done + tiles[it.y].sub);
-    } else if (it.x == 2) {
-        const SyrkItem si = syrk[it.y];
-        if (wait_done(done + si.sub, subs[si.sub].ntiles, err)) syrk_item_f32(subs, tiles, si, X, pi, F, smem);
-    }
-}
-
-hipError_t launch_assemble_fused(const DevTables& t, hipStream_t stream, hipEvent_t* ev) {
-    hipError_t e = hipSuccess;
-    if (ev && (e = hipEventRecord(ev[0], stream)) != hipSuccess) return e;
-    if (t.nsub > 0)
-        hipLaunchKernelGGL(fill_i32, dim3((unsigned)std::min<int64_t>((t.nsub + 255) / 256, 1024)), dim3(256), 0,
-                           stream, t.done, t.nsub, 0);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (t.nfused > 0) {
-        if (t.X32)
-            hipLaunchKernelGGL(assemble_fused_mixed, dim3((unsigned)t.nfused), dim3(256), 0, stream, t.subs,
-                               t.tiles, t.blocks, t.rows, t.lval, t.lval32, t.piv, t.sgn, t.fused, t.syrk_items,
-                               t.X32, t.pi, t.F32, t.done, t.err);
-        else
-            hipLaunchKernelGGL(assemble_fused_f64, dim3((unsigned)t.nfused), dim3(256), 0, stream, t.subs,
-                               t.tiles, t.blocks, t.rows, t.lval, t.piv, t.sgn, t.fused, t.syrk_items, t.X, t.pi,
-                               t.F, t.done, t.err);
-    }
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (ev && (e = hipEventRecord(ev[1], stream)) != hipSuccess) return e;
-    return hipSuccess;
-}
-
 hipError_t launch_convert_f32(const double* a, float* b, int64_t n, hipStream_t stream) {
     if (n <= 0) return hipSuccess;
     const int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
     hipLaunchKernelGGL(convert_f64_f32, dim3((unsigned)blocks), dim3(256), 0, stream, a, b, n);
     return hipGetLastError();
-}
-
-hipError_t launch_assemble_mixed(const DevTables& t, hipStream_t stream, hipEvent_t* ev) {
-    hipError_t e = hipSuccess;
-    if (ev && (e = hipEventRecord(ev[0], stream)) != hipSuccess) return e;
-    if (t.ntiles > 0)
-        hipLaunchKernelGGL(trsm_stair_mixed, dim3((unsigned)t.ntiles), dim3(256), 0, stream, t.subs,
-                           t.tiles, t.blocks, t.rows, t.lval, t.lval32, t.piv, t.sgn, t.tile_order, t.X32);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (ev && (e = hipEventRecord(ev[1], stream)) != hipSuccess) return e;
-    if (ev && (e = hipEventRecord(ev[2], stream)) != hipSuccess) return e;
-    if (t.nsyrk > 0)
-        hipLaunchKernelGGL(syrk_stair_f32, dim3((unsigned)t.nsyrk), dim3(256), 0, stream, t.subs,
-                           t.tiles, t.syrk, t.X32, t.pi, t.F32);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (ev && (e = hipEventRecord(ev[3], stream)) != hipSuccess) return e;
-    return hipSuccess;
 }
 
 }  // namespace scasm

@@ -6,7 +6,7 @@
 
 namespace scasm {
 
-constexpr int kNumTimed = 5;   // timed kernels: TRSM, SYRK, apply, implicit apply, fused assembly
+constexpr int kNumTimed = 5;   // timed kernels: TRSM, SYRK, apply, implicit apply, overlapped assembly
 
 struct DevTables {
     const SubDev* subs = nullptr;
@@ -25,29 +25,23 @@ struct DevTables {
     double* F = nullptr;
     float* F32 = nullptr;
     const int2* apply_items = nullptr;     // (subdomain, first column) per GEMV workgroup
-    const int2* fused = nullptr;           // fused assembly: (kind 0 idle / 1 TRSM / 2 SYRK, index)
-    const SyrkItem* syrk_items = nullptr;  // SYRK items in subdomain order (indexed by fused items)
-    int32_t* done = nullptr;               // [nsub] TRSM tiles finished (fused assembly)
-    int32_t* err = nullptr;                // device error flag
     int64_t ntiles = 0;          // TRSM workgroups (length of tile_order)
     int64_t nsyrk = 0;           // SYRK workgroups (items with sub < 0 are idle)
     int64_t napply = 0;
-    int64_t nfused = 0;
-    int32_t nsub = 0;
 };
 
-// Optional per-kernel events: ev[2k] before and ev[2k+1] after kernel k
-// (0 = TRSM, 1 = SYRK); null = no timing.
-hipError_t launch_assemble_f64(const DevTables& t, hipStream_t stream, hipEvent_t* ev);
+// Assembly kernels; FP64, or mixed precision when t.X32 is set (FP64
+// diagonal solves, FP32 X / updates / SYRK and FP32 F).
+//   launch_trsm: TRSM workgroups over `order[0, count)` (tile indices, -1 idle)
+//   launch_syrk: SYRK workgroups over `items[0, count)` (sub < 0 idle)
+//   launch_assemble: all tiles, then all SYRK items, on one stream; optional
+//     events ev[2k] before and ev[2k+1] after kernel k (0 = TRSM, 1 = SYRK).
+hipError_t launch_trsm(const DevTables& t, const int32_t* order, int64_t count, hipStream_t stream);
+hipError_t launch_syrk(const DevTables& t, const SyrkItem* items, int64_t count, hipStream_t stream);
+hipError_t launch_assemble(const DevTables& t, hipStream_t stream, hipEvent_t* ev);
 
-// Single-launch assembly over the fused item list (FP64 or, with X32 set,
-// mixed); optional events ev[0] before, ev[1] after.
-hipError_t launch_assemble_fused(const DevTables& t, hipStream_t stream, hipEvent_t* ev);
-
-// Mixed precision: FP64 factor -> FP32 copy, and the assembly with FP64
-// diagonal solves, FP32 X / updates / SYRK and FP32 F.
+// FP64 factor -> FP32 copy (mixed precision).
 hipError_t launch_convert_f32(const double* a, float* b, int64_t n, hipStream_t stream);
-hipError_t launch_assemble_mixed(const DevTables& t, hipStream_t stream, hipEvent_t* ev);
 
 struct PcpgArgs {
     const double* G;        // concatenated m_i x k_i column-major blocks

@@ -97,8 +97,11 @@ struct sc_plan_s {
     std::vector<BlockDev> h_blocks;
     std::vector<SyrkItem> h_syrk;               // interleaved over XCDs, idle items sub = -1
     std::vector<int32_t> h_tile_order;          // TRSM workgroup -> tile (-1 idle)
-    std::vector<SyrkItem> h_syrk_items;         // SYRK items in subdomain order
-    std::vector<int2> h_fused;                  // fused assembly items
+    // overlapped assembly: groups of subdomains (every XCD's list cut into
+    // kOverlapGroups consecutive parts), per group a TRSM order and SYRK list
+    std::vector<int32_t> h_tile_order_g;
+    std::vector<SyrkItem> h_syrk_g;
+    std::vector<int64_t> g_toff, g_tcnt, g_soff, g_scnt;
     std::vector<int2> h_apply;
     int64_t nval_total = 0, nrows_total = 0, ncol_total = 0, X_total = 0, F_total = 0, dual_total = 0;
     double* h_lval = nullptr;                 // pinned
@@ -108,9 +111,10 @@ struct sc_plan_s {
     DevBuf<BlockDev> d_blocks;
     DevBuf<SyrkItem> d_syrk;
     DevBuf<int32_t> d_tile_order;
-    DevBuf<SyrkItem> d_syrk_items;
-    DevBuf<int2> d_fused;
-    DevBuf<int32_t> d_done, d_err;
+    DevBuf<int32_t> d_tile_order_g;
+    DevBuf<SyrkItem> d_syrk_g;
+    hipStream_t aux = nullptr;                  // second stream of the overlapped assembly
+    std::vector<hipEvent_t> ov_events;          // one per group + join
     DevBuf<int2> d_apply;
     DevBuf<int32_t> d_rows, d_piv, d_pi;
     DevBuf<int8_t> d_sgn;
@@ -130,10 +134,42 @@ struct sc_plan_s {
     double ms_sum[kNumTimed] = {};
     int64_t ms_count[kNumTimed] = {};
 
-    bool fused() const { return opt.assembly_kernels == 1; }
+    bool overlapped() const { return opt.assembly_kernels == 1; }
+    // Overlapped assembly: TRSM of group g+1 on `st` runs while SYRK of group g
+    // runs on the second stream (which waits for TRSM g through an event);
+    // `st` finally waits for the last SYRK.  The two kernels keep their own
+    // register and LDS budgets, so a CU can hold workgroups of both.
+    hipError_t prepare_overlap() {           // at plan creation (not inside a graph capture)
+        hipError_t e = hipSuccess;
+        if (!aux && (e = hipStreamCreateWithFlags(&aux, hipStreamNonBlocking)) != hipSuccess) return e;
+        while (ov_events.size() < g_tcnt.size() + 1) {
+            hipEvent_t ev;
+            if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return e;
+            ov_events.push_back(ev);
+        }
+        return hipSuccess;
+    }
+    hipError_t launch_overlapped(hipStream_t st) {
+        hipError_t e = hipSuccess;
+        const size_t ng = g_tcnt.size();
+        if (!aux || ov_events.size() < ng + 1) return hipErrorNotReady;
+        const DevTables t = tables();
+        for (size_t g = 0; g < ng; ++g) {
+            if ((e = launch_trsm(t, d_tile_order_g.p + g_toff[g], g_tcnt[g], st)) != hipSuccess) return e;
+            if ((e = hipEventRecord(ov_events[g], st)) != hipSuccess) return e;
+            if ((e = hipStreamWaitEvent(aux, ov_events[g], 0)) != hipSuccess) return e;
+            if ((e = launch_syrk(t, d_syrk_g.p + g_soff[g], g_scnt[g], aux)) != hipSuccess) return e;
+        }
+        if ((e = hipEventRecord(ov_events[ng], aux)) != hipSuccess) return e;
+        return hipStreamWaitEvent(st, ov_events[ng], 0);
+    }
     hipError_t launch_assembly(hipStream_t st, hipEvent_t* ev) {
-        if (fused()) return launch_assemble_fused(tables(), st, ev);
-        return mixed ? launch_assemble_mixed(tables(), st, ev) : launch_assemble_f64(tables(), st, ev);
+        if (!overlapped()) return launch_assemble(tables(), st, ev);
+        hipError_t e = hipSuccess;
+        if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
+        if ((e = launch_overlapped(st)) != hipSuccess) return e;
+        if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
+        return hipSuccess;
     }
     hipError_t take_events(int k, hipEvent_t* out) {
         for (int i = 0; i < k; ++i) {
@@ -170,8 +206,7 @@ struct sc_plan_s {
         return (int64_t)(d_subs.count * sizeof(SubDev) + d_tiles.count * sizeof(TileDev) +
                          d_blocks.count * sizeof(BlockDev) + d_syrk.count * sizeof(SyrkItem) +
                          d_apply.count * sizeof(int2) + d_tile_order.count * 4 +
-                         d_syrk_items.count * sizeof(SyrkItem) + d_fused.count * sizeof(int2) +
-                         (d_done.count + d_err.count) * 4 +
+                         d_tile_order_g.count * 4 + d_syrk_g.count * sizeof(SyrkItem) +
                          (d_rows.count + d_piv.count + d_pi.count) * 4 + d_sgn.count +
                          (d_lval.count + d_X.count + d_F.count) * 8 +
                          (d_lval32.count + d_X32.count + d_F32.count) * 4 +
@@ -179,7 +214,7 @@ struct sc_plan_s {
     }
     void release() {
         d_subs.release(); d_tiles.release(); d_blocks.release(); d_syrk.release(); d_apply.release();
-        d_tile_order.release(); d_syrk_items.release(); d_fused.release(); d_done.release(); d_err.release();
+        d_tile_order.release(); d_tile_order_g.release(); d_syrk_g.release();
         d_rows.release(); d_piv.release(); d_pi.release(); d_sgn.release();
         d_lval.release(); d_X.release(); d_F.release();
         d_lval32.release(); d_X32.release(); d_F32.release();
@@ -192,6 +227,10 @@ struct sc_plan_s {
         for (auto& e : event_pool) (void)hipEventDestroy(e);
         pending.clear();
         event_pool.clear();
+        for (auto& e : ov_events) (void)hipEventDestroy(e);
+        ov_events.clear();
+        if (aux) (void)hipStreamDestroy(aux);
+        aux = nullptr;
     }
     DevTables tables() const {
         DevTables t;
@@ -201,12 +240,6 @@ struct sc_plan_s {
         t.lval32 = d_lval32.p; t.X32 = d_X32.p; t.F32 = d_F32.p;
         t.apply_items = d_apply.p;
         t.tile_order = d_tile_order.p;
-        t.fused = d_fused.p;
-        t.syrk_items = d_syrk_items.p;
-        t.done = d_done.p;
-        t.err = d_err.p;
-        t.nfused = (int64_t)h_fused.size();
-        t.nsub = nsub;
         t.ntiles = (int64_t)h_tile_order.size();
         t.nsyrk = (int64_t)h_syrk.size();
         t.napply = (int64_t)h_apply.size();
@@ -326,37 +359,41 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
         std::vector<std::vector<int32_t>> xt(kNumXcd);
         std::vector<std::vector<SyrkItem>> xs(kNumXcd);
         std::vector<std::vector<SyrkItem>> per_sub(nsub);
-        std::vector<int64_t> syrk_first(nsub + 1, 0);
         for (const SyrkItem& it : P->h_syrk) per_sub[it.sub].push_back(it);
-        P->h_syrk_items = P->h_syrk;                       // subdomain order
-        for (int32_t i = 0; i < nsub; ++i) syrk_first[i + 1] = syrk_first[i] + (int64_t)per_sub[i].size();
-        // fused list per XCD: the SYRK items of a subdomain follow its TRSM
-        // tiles at a distance of kFusedLagTiles further TRSM tiles, so that
-        // by the time they are dispatched their X is normally complete and
-        // they rarely hold a slot while waiting
-        std::vector<std::vector<int2>> xf(kNumXcd);
-        for (int x = 0; x < kNumXcd; ++x) {
-            const auto& L = xsub[x];
-            std::vector<std::pair<int32_t, int64_t>> pend;    // (subdomain, TRSM tiles emitted when it ended)
-            size_t head = 0;
-            int64_t emitted = 0;
-            auto flush_syrk = [&](int32_t i) {
-                for (int64_t q = syrk_first[i]; q < syrk_first[i + 1]; ++q) xf[x].push_back(make_int2(2, (int)q));
-            };
-            for (int32_t i : L) {
-                const SubDev& sd = P->h_subs[i];
-                for (int32_t t = 0; t < sd.ntiles; ++t) xf[x].push_back(make_int2(1, (int)(sd.tile_off + t)));
-                emitted += sd.ntiles;
-                pend.emplace_back(i, emitted);
-                while (head < pend.size() && emitted - pend[head].second >= kFusedLagTiles) flush_syrk(pend[head++].first);
+        // groups for the overlapped assembly
+        {
+            size_t lmax = 0;
+            for (int x = 0; x < kNumXcd; ++x) lmax = std::max(lmax, xsub[x].size());
+            const int ng = (int)std::max<size_t>(1, std::min<size_t>(kOverlapGroups, lmax));
+            for (int gi = 0; gi < ng; ++gi) {
+                std::vector<std::vector<int32_t>> gt(kNumXcd);
+                std::vector<std::vector<SyrkItem>> gs(kNumXcd);
+                size_t lt = 0, ls = 0;
+                for (int x = 0; x < kNumXcd; ++x) {
+                    const size_t L = xsub[x].size();
+                    for (size_t k = L * gi / ng; k < L * (gi + 1) / ng; ++k) {
+                        const int32_t i = xsub[x][k];
+                        const SubDev& sd = P->h_subs[i];
+                        for (int32_t t = 0; t < sd.ntiles; ++t) gt[x].push_back((int32_t)(sd.tile_off + t));
+                        gs[x].insert(gs[x].end(), per_sub[i].begin(), per_sub[i].end());
+                    }
+                    lt = std::max(lt, gt[x].size());
+                    ls = std::max(ls, gs[x].size());
+                }
+                P->g_toff.push_back((int64_t)P->h_tile_order_g.size());
+                P->g_tcnt.push_back((int64_t)(lt * kNumXcd));
+                P->g_soff.push_back((int64_t)P->h_syrk_g.size());
+                P->g_scnt.push_back((int64_t)(ls * kNumXcd));
+                P->h_tile_order_g.resize(P->h_tile_order_g.size() + lt * kNumXcd, -1);
+                P->h_syrk_g.resize(P->h_syrk_g.size() + ls * kNumXcd, SyrkItem{-1, 0, 0, 0});
+                for (int x = 0; x < kNumXcd; ++x) {
+                    for (size_t k = 0; k < gt[x].size(); ++k)
+                        P->h_tile_order_g[P->g_toff.back() + (int64_t)(k * kNumXcd + x)] = gt[x][k];
+                    for (size_t k = 0; k < gs[x].size(); ++k)
+                        P->h_syrk_g[P->g_soff.back() + (int64_t)(k * kNumXcd + x)] = gs[x][k];
+                }
             }
-            while (head < pend.size()) flush_syrk(pend[head++].first);
         }
-        size_t lf = 0;
-        for (int x = 0; x < kNumXcd; ++x) lf = std::max(lf, xf[x].size());
-        P->h_fused.assign(lf * kNumXcd, make_int2(0, 0));
-        for (int x = 0; x < kNumXcd; ++x)
-            for (size_t k = 0; k < xf[x].size(); ++k) P->h_fused[k * kNumXcd + x] = xf[x][k];
         for (int x = 0; x < kNumXcd; ++x)
             for (int32_t i : xsub[x]) {
                 const SubDev& sd = P->h_subs[i];
@@ -400,10 +437,8 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
     ALLOC(p->d_syrk, p->h_syrk.size());
     ALLOC(p->d_apply, p->h_apply.size());
     ALLOC(p->d_tile_order, p->h_tile_order.size());
-    ALLOC(p->d_syrk_items, p->h_syrk_items.size());
-    ALLOC(p->d_fused, p->h_fused.size());
-    ALLOC(p->d_done, (size_t)std::max(1, nsub));
-    ALLOC(p->d_err, 1);
+    ALLOC(p->d_tile_order_g, p->h_tile_order_g.size());
+    ALLOC(p->d_syrk_g, p->h_syrk_g.size());
     ALLOC(p->d_rows, (size_t)rows);
     ALLOC(p->d_piv, (size_t)colo);
     ALLOC(p->d_pi, (size_t)colo);
@@ -445,12 +480,9 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
     if (e == hipSuccess) e = up(p->d_syrk.p, p->h_syrk.data(), p->h_syrk.size() * sizeof(SyrkItem));
     if (e == hipSuccess) e = up(p->d_apply.p, p->h_apply.data(), p->h_apply.size() * sizeof(int2));
     if (e == hipSuccess) e = up(p->d_tile_order.p, p->h_tile_order.data(), p->h_tile_order.size() * 4);
-    if (e == hipSuccess) e = up(p->d_syrk_items.p, p->h_syrk_items.data(), p->h_syrk_items.size() * sizeof(SyrkItem));
-    if (e == hipSuccess) e = up(p->d_fused.p, p->h_fused.data(), p->h_fused.size() * sizeof(int2));
-    {
-        const int32_t zero = 0;
-        if (e == hipSuccess) e = up(p->d_err.p, &zero, 4);
-    }
+    if (e == hipSuccess) e = up(p->d_tile_order_g.p, p->h_tile_order_g.data(), p->h_tile_order_g.size() * 4);
+    if (e == hipSuccess) e = up(p->d_syrk_g.p, p->h_syrk_g.data(), p->h_syrk_g.size() * sizeof(SyrkItem));
+    if (e == hipSuccess && p->overlapped()) e = p->prepare_overlap();
     if (e == hipSuccess) e = up(p->d_rows.p, h_rows.data(), h_rows.size() * 4);
     if (e == hipSuccess) e = up(p->d_piv.p, h_piv.data(), h_piv.size() * 4);
     if (e == hipSuccess) e = up(p->d_pi.p, h_pi.data(), h_pi.size() * 4);
@@ -548,7 +580,7 @@ sc_status_t sc_assemble(sc_plan_t P, void* stream) {
         evp = ev;
     }
     HIP_TRY(P->launch_assembly((hipStream_t)stream, evp));
-    if (evp && P->fused()) {
+    if (evp && P->overlapped()) {
         P->pending.push_back({4, ev[0], ev[1]});
         P->event_pool.push_back(ev[2]);
         P->event_pool.push_back(ev[3]);
@@ -707,12 +739,6 @@ sc_status_t sc_get_F(sc_plan_t P, int32_t sub, double* out, int32_t ld, int32_t 
     if (!out || ld < s.m) return fail(SC_ERR_INVALID_ARG, "bad output buffer or ld");
     HIP_TRY(hipSetDevice(P->device));
     hipStream_t st = (hipStream_t)stream;
-    {
-        int32_t err = 0;
-        HIP_TRY(hipMemcpyAsync(&err, P->d_err.p, 4, hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        if (err) return fail(SC_ERR_DEVICE, "fused assembly: a SYRK tile gave up waiting for its X tiles");
-    }
     if (!P->mixed) {
         const double* src = P->d_F.p + s.F_off;
         HIP_TRY(hipMemcpy2DAsync(out, (size_t)ld * sizeof(double), src, (size_t)s.m * sizeof(double),

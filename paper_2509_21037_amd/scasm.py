@@ -136,7 +136,7 @@ def _fill_desc(d, s, keep, use_coords=True):
     d.dofs_per_node = int(getattr(s, "dofs_per_node", 1))
 
 
-ASSEMBLY_KERNELS = {"default": 0, "fused": 1, "separate": 2}
+ASSEMBLY_KERNELS = {"default": 0, "overlap": 1, "separate": 2}
 
 
 def _options(precision="fp64", staircase=True, panel_width=0, relax_width=0, leaf_nodes=0, n_threads=0,
@@ -293,7 +293,7 @@ class Plan:
     def set_timing(self, enable: bool = True):
         _check(self._lib.sc_set_timing(self._h, 1 if enable else 0))
 
-    KERNELS = ("trsm", "syrk", "apply", "apply_implicit", "assemble_fused")
+    KERNELS = ("trsm", "syrk", "apply", "apply_implicit", "assemble_overlap")
 
     def kernel_times(self, reset: bool = True) -> dict:
         """Accumulated kernel milliseconds and launch counts (HIP events)."""

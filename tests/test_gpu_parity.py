@@ -121,7 +121,7 @@ def test_run_to_run_deterministic():
         assert np.array_equal(x, y)
 
 
-@pytest.mark.parametrize("assembly", ["fused", "separate"])
+@pytest.mark.parametrize("assembly", ["overlap", "separate"])
 def test_edge_cases_in_one_batch(assembly):
     base = scgen.box_subdomain("heat", (4, 4, 3), 0.25, seed=13)
     tiny = scgen.box_subdomain("heat", (1, 1), 1.0, seed=14)            # n = 4, m = 4
@@ -341,22 +341,23 @@ def test_graph_replays_match_eager(precision):
             assert np.array_equal(plan.get_F(i), ref[i]), (rep, i)
 
 
-# ---------------------------------------------------------- fused assembly
+# ------------------------------------------------------ overlapped assembly
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_fused_assembly_matches_two_launches(precision):
-    """One fused launch (SYRK tiles wait on their subdomain's TRSM counter)
-    gives bit for bit the F of the two-launch assembly, on a batch with
-    uneven subdomains, an empty interface and more subdomains than XCDs;
-    repeated calls (counters cleared each time) and graph replays agree."""
+def test_overlapped_assembly_matches_two_launches(precision):
+    """The SYRK of one subdomain group on a second stream while the TRSM of
+    the next runs gives bit for bit the F of the two-launch assembly, on a
+    batch with uneven subdomains, an empty interface and more subdomains
+    than XCDs and groups; repeated calls and graph replays (with eager work
+    between them) agree."""
     torch = _torch_init()
-    subs = (scgen.config_subdomains(2, count=12) + scgen.config_subdomains(3, count=6) +
+    subs = (scgen.config_subdomains(2, count=40) + scgen.config_subdomains(3, count=12) +
             scgen.config_subdomains(1))
     subs.append(subs[1].with_columns(np.zeros(0, np.int32), np.zeros(0, np.int8)))
     two = _assemble(subs, precision=precision, assembly="separate")
     ref = [two.get_F(i) for i in range(len(subs))]
     for use_graph in (False, True):
-        plan = P.Plan(subs, precision=precision, assembly="fused", use_graph=use_graph)
+        plan = P.Plan(subs, precision=precision, assembly="overlap", use_graph=use_graph)
         plan.factor()
         for rep in range(3):
             junk = torch.randn(1 << 20, device="cuda")
@@ -368,16 +369,38 @@ def test_fused_assembly_matches_two_launches(precision):
         plan.destroy()
 
 
-def test_fused_assembly_is_timed_in_its_own_slot():
+def test_overlapped_assembly_on_a_side_stream():
+    """Work queued on the caller's stream after sc_assemble sees the whole F
+    (the caller's stream waits for the second stream's last SYRK)."""
+    torch = _torch_init()
+    subs = scgen.config_subdomains(2, count=24)
+    ref = _assemble(subs, assembly="separate")
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        plan = P.Plan(subs, assembly="overlap", stream=side)
+        plan.factor(stream=side)
+        plan.assemble(stream=side)
+        st = plan.stats()
+        p = torch.rand(st["dual_total"], dtype=torch.float64, device="cuda")
+        q = torch.zeros_like(p)
+        q_ref = torch.zeros_like(p)
+        plan.apply(p, q, stream=side)
+    side.synchronize()
+    ref.apply(p, q_ref)
+    torch.cuda.synchronize()
+    assert torch.equal(q, q_ref)
+
+
+def test_overlapped_assembly_is_timed_in_its_own_slot():
     _torch_init()
     subs = scgen.config_subdomains(3, count=4)
-    plan = P.Plan(subs, assembly="fused")
+    plan = P.Plan(subs, assembly="overlap")
     plan.factor()
     plan.set_timing(True)
     plan.assemble()
     plan.assemble()
     t = plan.kernel_times()
-    assert t["assemble_fused"][1] == 2 and t["assemble_fused"][0] > 0
+    assert t["assemble_overlap"][1] == 2 and t["assemble_overlap"][0] > 0
     assert t["trsm"][1] == 0 and t["syrk"][1] == 0
 
 
