@@ -57,10 +57,12 @@ __device__ __forceinline__ v4f mfma_f32(float a, float b, v4f c) {
 //   2. the pruned rows below the block, 32 at a time:
 //      X[R_b] -= L[R_b, b] X[b] (MFMA, rows gathered and scattered).
 // The factor flows through the workgroup as a stream of chunks (up to two
-// 16-row tiles x 64 columns): chunk c+1 is loaded into registers while chunk
-// c is used from LDS, then written to the other half of a double buffer;
-// one barrier per chunk, on LDS only (X columns of a stripe are private to
-// its wavefront, so no barrier waits on global memory).  Rows of the next
+// 16-row tiles x 64 columns): while chunk c is used from LDS, chunks c+1 and
+// c+2 are in registers (loaded two steps ahead: one step of latency hiding
+// was measured 23% slower); c+1 is written to the other half of a double
+// buffer at the end of the step; one barrier per chunk, on LDS only (X
+// columns of a stripe are private to its wavefront, so no barrier waits on
+// global memory).  Rows of the next
 // chunk of the same block are gathered before the current chunk's MFMAs
 // (the chunks of one block update disjoint rows); a wavefront reads rows it
 // wrote itself in program order.
@@ -78,10 +80,6 @@ __device__ __forceinline__ void lds_barrier() {
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-struct ChunkRegs {
-    uint4 v0, v1, v2, v3;
-    uint4 vi;            // threads 0..7: the 32 row indices the chunk carries
-};
 struct ChunkSrc {
     const char* p;       // always a valid address (the subdomain's factor when bytes == 0)
     int bytes;
@@ -90,24 +88,28 @@ struct ChunkSrc {
                          // valid address (the row array is padded by 32 entries)
 };
 
-// Every thread loads its four 16-byte pieces unconditionally (pieces past the
-// chunk re-read its first bytes) so that the prefetch stays in registers.
-__device__ __forceinline__ void chunk_load(ChunkRegs& c, const ChunkSrc& s) {
+// Register prefetch of one chunk: four 16-byte pieces per thread, loaded
+// unconditionally (pieces past the chunk re-read its first bytes), plus the
+// 32 row indices (threads 0..7 keep them).  Separate registers, not a struct:
+// the prefetch must stay out of scratch memory.
+__device__ __forceinline__ void chunk_load(uint4& v0, uint4& v1, uint4& v2, uint4& v3, uint4& vi,
+                                           const ChunkSrc& s) {
     const int e = threadIdx.x * 16;
-    c.v0 = *reinterpret_cast<const uint4*>(s.p + (e < s.bytes ? e : 0));
-    c.v1 = *reinterpret_cast<const uint4*>(s.p + (e + 4096 < s.bytes ? e + 4096 : 0));
-    c.v2 = *reinterpret_cast<const uint4*>(s.p + (e + 8192 < s.bytes ? e + 8192 : 0));
-    c.v3 = *reinterpret_cast<const uint4*>(s.p + (e + 12288 < s.bytes ? e + 12288 : 0));
-    c.vi = *reinterpret_cast<const uint4*>(s.ip + 4 * (threadIdx.x & 7));
+    v0 = *reinterpret_cast<const uint4*>(s.p + (e < s.bytes ? e : 0));
+    v1 = *reinterpret_cast<const uint4*>(s.p + (e + 4096 < s.bytes ? e + 4096 : 0));
+    v2 = *reinterpret_cast<const uint4*>(s.p + (e + 8192 < s.bytes ? e + 8192 : 0));
+    v3 = *reinterpret_cast<const uint4*>(s.p + (e + 12288 < s.bytes ? e + 12288 : 0));
+    vi = *reinterpret_cast<const uint4*>(s.ip + 4 * (threadIdx.x & 7));
 }
 
-__device__ __forceinline__ void chunk_store(const ChunkRegs& c, char* __restrict__ dst, const ChunkSrc& s) {
+__device__ __forceinline__ void chunk_store(const uint4& v0, const uint4& v1, const uint4& v2, const uint4& v3,
+                                            const uint4& vi, char* __restrict__ dst, const ChunkSrc& s) {
     const int e = threadIdx.x * 16;
-    if (e < s.bytes) *reinterpret_cast<uint4*>(dst + e) = c.v0;
-    if (e + 4096 < s.bytes) *reinterpret_cast<uint4*>(dst + e + 4096) = c.v1;
-    if (e + 8192 < s.bytes) *reinterpret_cast<uint4*>(dst + e + 8192) = c.v2;
-    if (e + 12288 < s.bytes) *reinterpret_cast<uint4*>(dst + e + 12288) = c.v3;
-    if (s.has_idx && threadIdx.x < 8) *reinterpret_cast<uint4*>(dst + kChunkBytes + 16 * threadIdx.x) = c.vi;
+    if (e < s.bytes) *reinterpret_cast<uint4*>(dst + e) = v0;
+    if (e + 4096 < s.bytes) *reinterpret_cast<uint4*>(dst + e + 4096) = v1;
+    if (e + 8192 < s.bytes) *reinterpret_cast<uint4*>(dst + e + 8192) = v2;
+    if (e + 12288 < s.bytes) *reinterpret_cast<uint4*>(dst + e + 12288) = v3;
+    if (s.has_idx && threadIdx.x < 8) *reinterpret_cast<uint4*>(dst + kChunkBytes + 16 * threadIdx.x) = vi;
 }
 
 // Scalar copy of the block descriptor fields the TRSM uses.
@@ -179,22 +181,63 @@ __device__ __forceinline__ void trsm_tile(
     if (g == 0 && col < T.ncols) Xs[(int64_t)(piv[cbase + col] - kstart) * kTile + col] = (TX)sgn[cbase + col];
     if (first_block >= S.nblocks) return;
 
-    ChunkRegs pre;
     BlockLite bd = block_lite(B, first_block);
+    // prefetch cursor over the flattened chunk stream: chunk s+2 is loaded
+    // into registers at the start of step s, chunk s+1 goes to LDS at its end
+    int pb = first_block, pc = 0;
+    BlockLite pbd = bd;
+    auto nchunks = [](const BlockLite& x) {
+        const int nrt_d = (x.w + 15) >> 4;
+        return (nrt_d > 2 ? 2 : 1) + ((((x.nb + 15) >> 4) + 1) >> 1);
+    };
+    int pnch = nchunks(pbd);
+    auto take = [&]() {
+        ChunkSrc c{reinterpret_cast<const char*>(L), 0, false, R};
+        if (pb < S.nblocks) {
+            c = chunk_src(pbd, pc, L, LA, R);
+            if (++pc >= pnch) {
+                ++pb;
+                pc = 0;
+                if (pb < S.nblocks) {
+                    pbd = block_lite(B, pb);
+                    pnch = nchunks(pbd);
+                }
+            }
+        }
+        return c;
+    };
+    // a*: chunk s+1 (stored to LDS at the end of step s), b*: chunk s+2;
+    // sa_* / sb_* describe them
+    uint4 a0, a1, a2, a3, ai, b0, b1, b2, b3, bi;
     {
-        const ChunkSrc c0 = chunk_src(bd, 0, L, LA, R);
-        chunk_load(pre, c0);
-        chunk_store(pre, smem, c0);
+        const ChunkSrc c0 = take();
+        chunk_load(a0, a1, a2, a3, ai, c0);
+        chunk_store(a0, a1, a2, a3, ai, smem, c0);
+    }
+    const char* sa_p; int sa_bytes; bool sa_idx; const int32_t* sa_ip;
+    const char* sb_p = reinterpret_cast<const char*>(L); int sb_bytes = 0; bool sb_idx = false; const int32_t* sb_ip = R;
+    {
+        const ChunkSrc c1 = take();
+        chunk_load(a0, a1, a2, a3, ai, c1);
+        sa_p = c1.p; sa_bytes = c1.bytes; sa_idx = c1.has_idx; sa_ip = c1.ip;
     }
     lds_barrier();
     int buf = 0;
 
-    auto advance = [&](const ChunkSrc& nx) {     // next chunk: registers -> free LDS half
-        if (nx.bytes > 0) {
-            chunk_store(pre, smem + (buf ^ 1) * kBufBytes, nx);
+    auto step_begin = [&]() {
+        const ChunkSrc cb = take();
+        chunk_load(b0, b1, b2, b3, bi, cb);
+        sb_p = cb.p; sb_bytes = cb.bytes; sb_idx = cb.has_idx; sb_ip = cb.ip;
+    };
+    auto step_end = [&]() {
+        if (sa_bytes > 0) {
+            const ChunkSrc ca{sa_p, sa_bytes, sa_idx, sa_ip};
+            chunk_store(a0, a1, a2, a3, ai, smem + (buf ^ 1) * kBufBytes, ca);
             lds_barrier();
             buf ^= 1;
         }
+        a0 = b0; a1 = b1; a2 = b2; a3 = b3; ai = bi;
+        sa_p = sb_p; sa_bytes = sb_bytes; sa_idx = sb_idx; sa_ip = sb_ip;
     };
     for (int b = first_block; b < S.nblocks; ++b) {
         const int w = bd.w;
@@ -205,15 +248,8 @@ __device__ __forceinline__ void trsm_tile(
         const int nd = nrt_d > 2 ? 2 : 1;
         const int nrt = (nb + 15) >> 4;
         const int np = (nrt + 1) >> 1;
-        const int nch = nd + np;
         const bool act = b >= my_start;
         const BlockLite bn = block_lite(B, b + 1 < S.nblocks ? b + 1 : b);
-        auto next_src = [&](int c) {
-            ChunkSrc nx{reinterpret_cast<const char*>(L), 0, false, R};
-            if (c + 1 < nch) nx = chunk_src(bd, c + 1, L, LA, R);
-            else if (b + 1 < S.nblocks) nx = chunk_src(bn, 0, L, LA, R);
-            return nx;
-        };
 
         VX accn[2];                              // rows of the next pruned chunk
         int offn[2][4];
@@ -245,8 +281,7 @@ __device__ __forceinline__ void trsm_tile(
                 if (np > 0) gather(0);
             }
             for (int c = 0; c < nd; ++c) {
-                const ChunkSrc nx = next_src(c);
-                chunk_load(pre, nx);
+                step_begin();
                 if (act) {
                     const double* __restrict__ sA = reinterpret_cast<const double*>(smem + buf * kBufBytes);
                     const int t0 = (nd == 2 && c == 0) ? 2 : 0;
@@ -274,7 +309,7 @@ __device__ __forceinline__ void trsm_tile(
                         if (nt > 1) xr[3] = tmp[1];
                     }
                 }
-                advance(nx);
+                step_end();
             }
             if (act) {
 #pragma unroll
@@ -292,8 +327,7 @@ __device__ __forceinline__ void trsm_tile(
 
         // ---- 2. X[R_b] -= L[R_b, b] X[b], pruned row tiles 2p, 2p+1
         for (int p = 0; p < np; ++p) {
-            const ChunkSrc nx = next_src(nd + p);
-            chunk_load(pre, nx);
+            step_begin();
             if (act) {
                 VX acc[2] = {accn[0], accn[1]};
                 int off[2][4];
@@ -325,13 +359,13 @@ __device__ __forceinline__ void trsm_tile(
                     for (int r = 0; r < 4; ++r)
                         if (off[u][r] >= 0) Xs[off[u][r]] = acc[u][r];
             }
-            advance(nx);
+            step_end();
         }
         bd = bn;
     }
 }
 
-__global__ __launch_bounds__(256, 3) void trsm_stair_f64(
+__global__ __launch_bounds__(256, 2) void trsm_stair_f64(
     const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
     const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows,
     const double* __restrict__ lval, const int32_t* __restrict__ piv,
@@ -343,7 +377,7 @@ __global__ __launch_bounds__(256, 3) void trsm_stair_f64(
     trsm_tile<false>(subs, tiles, blocks, rows, lval, nullptr, piv, sgn, X, ti, smem);
 }
 
-__global__ __launch_bounds__(256, 3) void trsm_stair_mixed(
+__global__ __launch_bounds__(256, 2) void trsm_stair_mixed(
     const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
     const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows,
     const double* __restrict__ lval, const float* __restrict__ lval32, const int32_t* __restrict__ piv,
