@@ -234,7 +234,8 @@ def main():
     errs64 = sampled_error(plan, subs, picks)
     log(f"bench: FP64 sampled relF {errs64}")
     _, apply64 = time_apply(torch, plan, "explicit")
-    f_bytes64 = sum(s.m * s.m for s in subs) * 8
+    # the apply reads the stored F: lower 128 x 128 tiles in sorted column order
+    f_bytes64 = sum((t := (s.m + 127) // 128) * (t + 1) // 2 * 128 * 128 for s in subs) * 8
     extra = {"explicit_fp64F_ms": apply64, "explicit_fp64F_GBps": f_bytes64 / (apply64 * 1e-3) / 1e9}
     pcpg = {}
     d = None

@@ -142,16 +142,20 @@ sc_status_t sc_factor(sc_plan_t plan, const double* const* kreg_vals, void* stre
 
 /* Preprocessing, part 2 (the hot path, Sec. 3): on `stream`, for every
  * subdomain, X = L^{-1} P B^T with the staircase TRSM (factor splitting with
- * pruned row lists, Sec. 3.2) and F = X^T X with the staircase SYRK (Sec. 3.3),
- * written back in the original multiplier order (Sec. 3, permutation back).
- * Asynchronous; F stays on the device.  SC_ERR_STATE before sc_factor. */
+ * pruned row lists, Sec. 3.2) and F = X^T X with the staircase SYRK (Sec. 3.3).
+ * F stays on the device in the sorted column order, as the lower triangle of
+ * 128 x 128 tiles (F is symmetric); the permutation back to the multiplier
+ * order (Sec. 3) is applied to the vectors by sc_apply / sc_pcpg and to the
+ * matrix by sc_get_F.  Asynchronous.  SC_ERR_STATE before sc_factor. */
 sc_status_t sc_assemble(sc_plan_t plan, void* stream);
 
 /* Solution stage, explicit apply (eq. (12)): q_i = F_i p_i for every
  * subdomain, on `stream`.  p_dev, q_dev: device FP64 vectors of length
  * sc_query(...)->dual total, concatenated per subdomain in the original
- * multiplier order (offsets from sc_query).  FP32-stored F (mixed) is read
- * as FP32 and accumulated in FP64.  SC_ERR_STATE before sc_assemble. */
+ * multiplier order (offsets from sc_query).  Every stored tile of F is read
+ * once and applied with its transpose as well; sums in a fixed order (the
+ * result is reproducible bit for bit).  FP32-stored F (mixed) is read as FP32
+ * and accumulated in FP64.  SC_ERR_STATE before sc_assemble. */
 sc_status_t sc_apply(sc_plan_t plan, const double* p_dev, double* q_dev, void* stream);
 
 /* Solution stage, implicit apply (eq. (11)): q_i = B_i P^T L^{-T} L^{-1} P B_i^T
@@ -182,8 +186,9 @@ sc_status_t sc_pcpg(sc_plan_t plan, const double* const* R_host, const int32_t* 
                     void* stream);
 
 /* Copy F_i (m_i x m_i, column-major, leading dimension ld >= m_i, original
- * multiplier order) to `out` (host memory when on_device == 0, else device
- * memory), converted to FP64.  Synchronises `stream`. */
+ * multiplier order: the stored tiles expanded and permuted back on the host)
+ * to `out` (host memory when on_device == 0, else device memory), converted
+ * to FP64.  Synchronises `stream`. */
 sc_status_t sc_get_F(sc_plan_t plan, int32_t sub, double* out, int32_t ld, int32_t on_device,
                      void* stream);
 

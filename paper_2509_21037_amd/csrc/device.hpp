@@ -10,6 +10,7 @@ constexpr int kTile = 64;
 constexpr int kStripe = 16;
 constexpr int kMaxPanel = 64;      // GPU panel width bound the TRSM kernel is built for
 constexpr int kSyrkTile = 128;     // edge of an F output tile (two X column tiles)
+constexpr int kFTileElems = kSyrkTile * kSyrkTile;
 // Workgroups are dispatched to the accelerator's XCDs round-robin (workgroup
 // k runs on XCD k mod kNumXcd); work lists are interleaved so that all items
 // of one subdomain share an XCD and its L2.
@@ -26,7 +27,8 @@ struct SubDev {
     int64_t lval_off;    // first factor value
     int64_t col_off;     // first entry of piv / pi / sign (sorted order)
     int64_t tile_off;    // first tile in the global tile table
-    int64_t F_off;       // first element of F (m*m, column-major, original order)
+    int64_t F_off;       // first element of F: packed lower tiles in sorted column order
+    int64_t ftile_off;   // first stored F tile of this subdomain (apply partial sums)
     int64_t dual_off;    // offset of the subdomain's multipliers in dual vectors
 };
 

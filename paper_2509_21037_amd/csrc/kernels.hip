@@ -397,8 +397,11 @@ __global__ __launch_bounds__(256, 2) void trsm_stair_mixed(
 // of tile I, which bounds the nonzero rows of both operands (rows of a slab
 // above its own first pivot are zero and are not stored).  X rows are staged
 // through double-buffered LDS, 16 rows per step, the next step prefetched into
-// registers.  The result goes straight to the original multiplier order:
-// F[pi(a), pi(b)] = F[pi(b), pi(a)] = sum_k X[k, a] X[k, b].
+// registers.  F stays in the sorted column order (the permutation back to the
+// multiplier order is applied to the vectors of the apply and by sc_get_F):
+// the lower triangle of 128 x 128 tiles, tile (I, J) at I(I+1)/2 + J, each
+// row-major; diagonal tiles in full (all four wavefronts compute).  Columns
+// past m are zero in X, so the padding of the last tiles holds zeros.
 // ---------------------------------------------------------------------------
 constexpr int kSyrkKC = 16;
 constexpr int kSyrkLd = kSyrkTile + 4;
@@ -407,7 +410,7 @@ constexpr int kSyrkSmem = 4 * kSyrkKC * kSyrkLd * 8;
 
 __device__ __forceinline__ void syrk_item_f64(
     const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles, const SyrkItem it,
-    const double* __restrict__ X, const int32_t* __restrict__ pi, double* __restrict__ F,
+    const double* __restrict__ X, double* __restrict__ F,
     char* __restrict__ smem)
 {
     double (*sI)[kSyrkKC * kSyrkLd] = reinterpret_cast<double (*)[kSyrkKC * kSyrkLd]>(smem);
@@ -419,8 +422,6 @@ __device__ __forceinline__ void syrk_item_f64(
     const int j = lane & 15;
     const int wi = wv >> 1;
     const int wj = wv & 1;
-    const bool diag = it.I == it.J;
-    const bool active = !(diag && wi < wj);
     const int n = S.n;
 
     // the two 64-column slabs of each 128-column tile (the second may not exist)
@@ -484,7 +485,7 @@ __device__ __forceinline__ void syrk_item_f64(
     for (int st = 0; st < nsteps; ++st) {
         const int buf = st & 1;
         if (st + 1 < nsteps) load_step(kbeg + (st + 1) * kSyrkKC);
-        if (active) {
+        {
 #pragma unroll
             for (int s = 0; s < kSyrkKC / 4; ++s) {
                 const double* ai = &sI[buf][(4 * s + g) * kSyrkLd + 64 * wi + j];
@@ -504,37 +505,24 @@ __device__ __forceinline__ void syrk_item_f64(
         if (st + 1 < nsteps) store_step(buf ^ 1);
         __syncthreads();
     }
-    if (!active) return;
-    const int m = S.m;
-    const int32_t* __restrict__ pis = pi + S.col_off;
-    double* __restrict__ Fs = F + S.F_off;
+    double* __restrict__ Ft = F + S.F_off + (int64_t)(it.I * (it.I + 1) / 2 + it.J) * kFTileElems;
 #pragma unroll
     for (int ti = 0; ti < 4; ++ti)
 #pragma unroll
         for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int a = it.I * kSyrkTile + 64 * wi + 16 * ti + 4 * r + g;
-                const int b = it.J * kSyrkTile + 64 * wj + 16 * tj + j;
-                if (a < m && b < m && (!diag || a >= b)) {
-                    const int64_t pa = pis[a];
-                    const int64_t pb = pis[b];
-                    const double v = acc[ti][tj][r];
-                    Fs[pa + pb * m] = v;
-                    Fs[pb + pa * m] = v;
-                }
-            }
+            for (int r = 0; r < 4; ++r)
+                Ft[(64 * wi + 16 * ti + 4 * r + g) * kSyrkTile + 64 * wj + 16 * tj + j] = acc[ti][tj][r];
 }
 
 __global__ __launch_bounds__(256) void syrk_stair_f64(
     const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
-    const SyrkItem* __restrict__ items, const double* __restrict__ X,
-    const int32_t* __restrict__ pi, double* __restrict__ F)
+    const SyrkItem* __restrict__ items, const double* __restrict__ X, double* __restrict__ F)
 {
     __shared__ __align__(16) char smem[kSyrkSmem];
     const SyrkItem it = items[blockIdx.x];
     if (it.sub < 0) return;
-    syrk_item_f64(subs, tiles, it, X, pi, F, smem);
+    syrk_item_f64(subs, tiles, it, X, F, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -549,15 +537,16 @@ __global__ __launch_bounds__(256) void convert_f64_f32(const double* __restrict_
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) b[i] = (float)a[i];
 }
 // FP32 staircase SYRK: as syrk_stair_f64 with FP32 X, FP32 MFMA and FP32
-// accumulation, 32 rows per LDS step; F stored FP32.
-constexpr int kSyrkKCF = 32;
+// accumulation, 16 rows per LDS step (33 KB of LDS: 3 workgroups per CU); F
+// stored FP32.
+constexpr int kSyrkKCF = 16;
 constexpr int kSyrkLdF = kSyrkTile + 4;
 
 constexpr int kSyrkSmemF = 4 * kSyrkKCF * kSyrkLdF * 4;
 
 __device__ __forceinline__ void syrk_item_f32(
     const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles, const SyrkItem it,
-    const float* __restrict__ X, const int32_t* __restrict__ pi, float* __restrict__ F,
+    const float* __restrict__ X, float* __restrict__ F,
     char* __restrict__ smem)
 {
     float (*sI)[kSyrkKCF * kSyrkLdF] = reinterpret_cast<float (*)[kSyrkKCF * kSyrkLdF]>(smem);
@@ -569,8 +558,6 @@ __device__ __forceinline__ void syrk_item_f32(
     const int j = lane & 15;
     const int wi = wv >> 1;
     const int wj = wv & 1;
-    const bool diag = it.I == it.J;
-    const bool active = !(diag && wi < wj);
     const int n = S.n;
 
     const float* xs[4];
@@ -595,11 +582,11 @@ __device__ __forceinline__ void syrk_item_f32(
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
 
-    // thread -> (row, 4 columns) of a 32 x 128 step, 4 per operand
-    float4 rI[4], rJ[4];
+    // thread -> (row, 4 columns) of a 16 x 128 step, 2 per operand
+    float4 rI[kSyrkKCF / 8], rJ[kSyrkKCF / 8];
     auto load_step = [&](int kb) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < kSyrkKCF / 8; ++e) {
             const int idx = threadIdx.x + 256 * e;
             const int rr = idx >> 5;
             const int cc = 4 * (idx & 31);
@@ -615,7 +602,7 @@ __device__ __forceinline__ void syrk_item_f32(
     };
     auto store_step = [&](int buf) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < kSyrkKCF / 8; ++e) {
             const int idx = threadIdx.x + 256 * e;
             const int rr = idx >> 5;
             const int cc = 4 * (idx & 31);
@@ -633,7 +620,7 @@ __device__ __forceinline__ void syrk_item_f32(
     for (int st = 0; st < nsteps; ++st) {
         const int buf = st & 1;
         if (st + 1 < nsteps) load_step(kbeg + (st + 1) * kSyrkKCF);
-        if (active) {
+        {
 #pragma unroll
             for (int s = 0; s < kSyrkKCF / 4; ++s) {
                 const float* ai = &sI[buf][(4 * s + g) * kSyrkLdF + 64 * wi + j];
@@ -653,123 +640,145 @@ __device__ __forceinline__ void syrk_item_f32(
         if (st + 1 < nsteps) store_step(buf ^ 1);
         __syncthreads();
     }
-    if (!active) return;
-    const int m = S.m;
-    const int32_t* __restrict__ pis = pi + S.col_off;
-    float* __restrict__ Fs = F + S.F_off;
+    float* __restrict__ Ft = F + S.F_off + (int64_t)(it.I * (it.I + 1) / 2 + it.J) * kFTileElems;
 #pragma unroll
     for (int ti = 0; ti < 4; ++ti)
 #pragma unroll
         for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int a = it.I * kSyrkTile + 64 * wi + 16 * ti + 4 * g + r;
-                const int b = it.J * kSyrkTile + 64 * wj + 16 * tj + j;
-                if (a < m && b < m && (!diag || a >= b)) {
-                    const int64_t pa = pis[a];
-                    const int64_t pb = pis[b];
-                    const float v = acc[ti][tj][r];
-                    Fs[pa + pb * m] = v;
-                    Fs[pb + pa * m] = v;
-                }
-            }
+            for (int r = 0; r < 4; ++r)
+                Ft[(64 * wi + 16 * ti + 4 * g + r) * kSyrkTile + 64 * wj + 16 * tj + j] = acc[ti][tj][r];
 }
 
 __global__ __launch_bounds__(256) void syrk_stair_f32(
     const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
-    const SyrkItem* __restrict__ items, const float* __restrict__ X,
-    const int32_t* __restrict__ pi, float* __restrict__ F)
+    const SyrkItem* __restrict__ items, const float* __restrict__ X, float* __restrict__ F)
 {
     __shared__ __align__(16) char smem[kSyrkSmemF];
     const SyrkItem it = items[blockIdx.x];
     if (it.sub < 0) return;
-    syrk_item_f32(subs, tiles, it, X, pi, F, smem);
+    syrk_item_f32(subs, tiles, it, X, F, smem);
 }
 
 // ---------------------------------------------------------------------------
-// Explicit apply, q_i = F_i p_i (Sec. 2.2, eq. (12)), all subdomains at once.
-// F_i is symmetric and stored column-major in the original multiplier order,
-// so q[c] = sum_r F[r, c] p[r] is a dot product with one contiguous column.
-// One workgroup per 32 columns of one subdomain; each wavefront reduces 8
-// columns with the widest loads that keep every column start aligned (up to
-// 16 bytes), accumulating in FP64.
+// Explicit apply q = F p (Sec. 2.2, eq. (12)) on the packed sorted F, FP64
+// accumulation (FP32 or FP64 F).  Each stored lower tile T = F_s[I, J] is
+// read once and used twice: pass 1, one workgroup per tile, writes
+// u = T p_s[J] and v = T^T p_s[I] (p_s: p in sorted column order, gathered
+// through pi; diagonal tiles are stored whole, v unused); pass 2, one
+// workgroup per 128-row block K of a subdomain, sums u of (K, J <= K) and v
+// of (I > K, K) in a fixed order and scatters the result to q in multiplier
+// order.  Deterministic; reads F once, about half of the dense m x m.
 // ---------------------------------------------------------------------------
-template <class T, int V>
-__device__ __forceinline__ void gemv_columns(const T* __restrict__ Fs, const double* __restrict__ ps, int m, int c0,
-                                             int lane, double (&sum)[8]) {
-    for (int r = V * lane; r < m; r += 64 * V) {
-        double pv[V];
+template <class T>
+__device__ __forceinline__ void load8(const T* __restrict__ src, double (&t)[8]) {
+    if constexpr (sizeof(T) == 8) {
 #pragma unroll
-        for (int e = 0; e < V; ++e) pv[e] = ps[r + e];
+        for (int e = 0; e < 4; ++e) {
+            const double2 d = reinterpret_cast<const double2*>(src)[e];
+            t[2 * e] = d.x;
+            t[2 * e + 1] = d.y;
+        }
+    } else {
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const int cc = c0 + c;
-            if (cc < m) {
-                const T* col = Fs + (int64_t)cc * m + r;
-                if constexpr (V == 1) {
-                    sum[c] += (double)col[0] * pv[0];
-                } else if constexpr (V == 2 && sizeof(T) == 8) {
-                    const double2 f = *reinterpret_cast<const double2*>(col);
-                    sum[c] += f.x * pv[0] + f.y * pv[1];
-                } else if constexpr (V == 2) {
-                    const float2 f = *reinterpret_cast<const float2*>(col);
-                    sum[c] += (double)f.x * pv[0] + (double)f.y * pv[1];
-                } else {
-                    const float4 f = *reinterpret_cast<const float4*>(col);
-                    sum[c] += (double)f.x * pv[0] + (double)f.y * pv[1] + (double)f.z * pv[2] +
-                              (double)f.w * pv[3];
-                }
-            }
+        for (int e = 0; e < 2; ++e) {
+            const float4 f = reinterpret_cast<const float4*>(src)[e];
+            t[4 * e] = f.x;
+            t[4 * e + 1] = f.y;
+            t[4 * e + 2] = f.z;
+            t[4 * e + 3] = f.w;
         }
     }
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void apply_gemv(
-    const SubDev* __restrict__ subs, const int2* __restrict__ items, const T* __restrict__ F,
-    const double* __restrict__ p, double* __restrict__ q)
+__global__ __launch_bounds__(256) void symv_tiles(
+    const SubDev* __restrict__ subs, const SyrkItem* __restrict__ ftiles, const T* __restrict__ F,
+    const int32_t* __restrict__ pi, const double* __restrict__ p, double* __restrict__ part)
 {
-    const int2 it = items[blockIdx.x];          // (subdomain, first column)
-    const SubDev S = subs[it.x];
-    const int m = S.m;
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    const T* __restrict__ Fs = F + S.F_off;
-    const double* __restrict__ ps = p + S.dual_off;
-    const int c0 = it.y + 8 * wv;
-    double sum[8];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) sum[c] = 0.0;
-    // widest load that keeps every column start aligned (F blocks start 32-byte aligned)
-    if (sizeof(T) == 4 && (m & 3) == 0) gemv_columns<T, 4>(Fs, ps, m, c0, lane, sum);
-    else if ((m & 1) == 0) gemv_columns<T, 2>(Fs, ps, m, c0, lane, sum);
-    else gemv_columns<T, 1>(Fs, ps, m, c0, lane, sum);
+    __shared__ double sp[2][kSyrkTile];                 // p_s of the tile's columns (J) and rows (I)
+    __shared__ double su[kSyrkTile][17];                // row sums per group of 8 columns
+    __shared__ double sv[kSyrkTile][17];                // column sums per group of 8 rows
+    const SyrkItem it = ftiles[blockIdx.x];
+    const SubDev S = subs[it.sub];
+    const int tid = threadIdx.x;
+    {
+        const int half = tid >> 7;
+        const int a = (half ? it.I : it.J) * kSyrkTile + (tid & 127);
+        sp[half][tid & 127] = a < S.m ? p[S.dual_off + pi[S.col_off + a]] : 0.0;
+    }
+    __syncthreads();
+    const int64_t tile = (int64_t)it.I * (it.I + 1) / 2 + it.J;
+    const T* __restrict__ Ft = F + S.F_off + tile * kFTileElems;
+    const int tr = tid >> 4;                            // rows 8 tr .. 8 tr + 7
+    const int tc = tid & 15;                            // columns 8 tc .. 8 tc + 7
+    double pj[8], u[8], v[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-        double v = sum[c];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        sum[c] = v;
+        pj[c] = sp[0][8 * tc + c];
+        u[c] = 0.0;
+        v[c] = 0.0;
     }
-    if (lane < 8 && c0 + lane < m) {
-        double v = 0.0;
 #pragma unroll
-        for (int c = 0; c < 8; ++c)
-            if (c == lane) v = sum[c];
-        q[S.dual_off + c0 + lane] = v;
+    for (int i = 0; i < 8; ++i) {
+        const int row = 8 * tr + i;
+        const double pr = sp[1][row];
+        double t[8];
+        load8(Ft + row * kSyrkTile + 8 * tc, t);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            u[i] += t[c] * pj[c];
+            v[c] += t[c] * pr;
+        }
     }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        su[8 * tr + i][tc] = u[i];
+        sv[8 * tc + i][tr] = v[i];
+    }
+    __syncthreads();
+    const int k = tid & 127;
+    double acc = 0.0;
+    if (tid < 128) {
+#pragma unroll
+        for (int g = 0; g < 16; ++g) acc += su[k][g];
+    } else {
+#pragma unroll
+        for (int g = 0; g < 16; ++g) acc += sv[k][g];
+    }
+    part[((S.ftile_off + tile) << 8) + tid] = acc;
+}
+
+__global__ __launch_bounds__(128) void symv_rows(
+    const SubDev* __restrict__ subs, const int2* __restrict__ frows, const int32_t* __restrict__ pi,
+    const double* __restrict__ part, double* __restrict__ q)
+{
+    const int2 it = frows[blockIdx.x];                  // (subdomain, row block K)
+    const SubDev S = subs[it.x];
+    const int K = it.y;
+    const int r = threadIdx.x;
+    const int nt = (S.m + kSyrkTile - 1) / kSyrkTile;
+    const double* __restrict__ P = part + (S.ftile_off << 8);
+    double y = 0.0;
+    for (int J = 0; J <= K; ++J) y += P[(((int64_t)K * (K + 1) / 2 + J) << 8) + r];
+    for (int I = K + 1; I < nt; ++I) y += P[(((int64_t)I * (I + 1) / 2 + K) << 8) + 128 + r];
+    const int a = K * kSyrkTile + r;
+    if (a < S.m) q[S.dual_off + pi[S.col_off + a]] = y;
 }
 
 hipError_t launch_apply(const DevTables& t, const double* p, double* q, hipStream_t stream, hipEvent_t* ev) {
     hipError_t e = hipSuccess;
     if (ev && (e = hipEventRecord(ev[0], stream)) != hipSuccess) return e;
-    if (t.napply > 0) {
+    if (t.nftiles > 0) {
         if (t.F32)
-            hipLaunchKernelGGL(apply_gemv<float>, dim3((unsigned)t.napply), dim3(256), 0, stream, t.subs,
-                               t.apply_items, (const float*)t.F32, p, q);
+            hipLaunchKernelGGL(symv_tiles<float>, dim3((unsigned)t.nftiles), dim3(256), 0, stream, t.subs,
+                               t.ftiles, (const float*)t.F32, t.pi, p, t.part);
         else
-            hipLaunchKernelGGL(apply_gemv<double>, dim3((unsigned)t.napply), dim3(256), 0, stream, t.subs,
-                               t.apply_items, (const double*)t.F, p, q);
+            hipLaunchKernelGGL(symv_tiles<double>, dim3((unsigned)t.nftiles), dim3(256), 0, stream, t.subs,
+                               t.ftiles, (const double*)t.F, t.pi, p, t.part);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(symv_rows, dim3((unsigned)t.nfrows), dim3(128), 0, stream, t.subs, t.frows, t.pi,
+                           (const double*)t.part, q);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], stream)) != hipSuccess) return e;
@@ -792,10 +801,10 @@ hipError_t launch_syrk(const DevTables& t, const SyrkItem* items, int64_t count,
     if (count <= 0) return hipSuccess;
     if (t.X32)
         hipLaunchKernelGGL(syrk_stair_f32, dim3((unsigned)count), dim3(256), 0, stream, t.subs, t.tiles, items,
-                           t.X32, t.pi, t.F32);
+                           t.X32, t.F32);
     else
         hipLaunchKernelGGL(syrk_stair_f64, dim3((unsigned)count), dim3(256), 0, stream, t.subs, t.tiles, items,
-                           t.X, t.pi, t.F);
+                           t.X, t.F);
     return hipGetLastError();
 }
 

@@ -24,10 +24,13 @@ struct DevTables {
     float* X32 = nullptr;
     double* F = nullptr;
     float* F32 = nullptr;
-    const int2* apply_items = nullptr;     // (subdomain, first column) per GEMV workgroup
+    const SyrkItem* ftiles = nullptr;      // stored F tiles (subdomain order): symmetric apply pass 1
+    const int2* frows = nullptr;           // (subdomain, 128-row block): symmetric apply pass 2
+    double* part = nullptr;                // 256 partial sums per stored F tile
     int64_t ntiles = 0;          // TRSM workgroups (length of tile_order)
     int64_t nsyrk = 0;           // SYRK workgroups (items with sub < 0 are idle)
-    int64_t napply = 0;
+    int64_t nftiles = 0;
+    int64_t nfrows = 0;
 };
 
 // Assembly kernels; FP64, or mixed precision when t.X32 is set (FP64
@@ -65,8 +68,8 @@ hipError_t launch_pcpg(const DevTables& t, const PcpgArgs& a, hipStream_t stream
 hipError_t launch_apply_implicit(const DevTables& t, const int64_t* xoff, double* xwork, const double* p,
                                  double* q, int32_t nsub, hipStream_t stream, hipEvent_t* ev);
 
-// q = F p for every subdomain (FP32 F when t.F32 is set, else FP64 F);
-// optional events ev[0] before, ev[1] after.
+// q = F p for every subdomain (FP32 F when t.F32 is set, else FP64 F), two
+// passes over the packed sorted F; optional events ev[0] before, ev[1] after.
 hipError_t launch_apply(const DevTables& t, const double* p, double* q, hipStream_t stream, hipEvent_t* ev);
 
 }  // namespace scasm

@@ -102,7 +102,8 @@ struct sc_plan_s {
     std::vector<int32_t> h_tile_order_g;
     std::vector<SyrkItem> h_syrk_g;
     std::vector<int64_t> g_toff, g_tcnt, g_soff, g_scnt;
-    std::vector<int2> h_apply;
+    std::vector<SyrkItem> h_ftiles;             // stored F tiles, subdomain order (apply pass 1)
+    std::vector<int2> h_frows;                  // (subdomain, 128-row block) (apply pass 2)
     int64_t nval_total = 0, nrows_total = 0, ncol_total = 0, X_total = 0, F_total = 0, dual_total = 0;
     double* h_lval = nullptr;                 // pinned
     // device
@@ -115,7 +116,9 @@ struct sc_plan_s {
     DevBuf<SyrkItem> d_syrk_g;
     hipStream_t aux = nullptr;                  // second stream of the overlapped assembly
     std::vector<hipEvent_t> ov_events;          // one per group + join
-    DevBuf<int2> d_apply;
+    DevBuf<SyrkItem> d_ftiles;
+    DevBuf<int2> d_frows;
+    DevBuf<double> d_part;                      // apply partial sums, 256 per stored F tile
     DevBuf<int32_t> d_rows, d_piv, d_pi;
     DevBuf<int8_t> d_sgn;
     DevBuf<double> d_lval, d_X, d_F;
@@ -205,7 +208,8 @@ struct sc_plan_s {
     int64_t device_bytes() const {
         return (int64_t)(d_subs.count * sizeof(SubDev) + d_tiles.count * sizeof(TileDev) +
                          d_blocks.count * sizeof(BlockDev) + d_syrk.count * sizeof(SyrkItem) +
-                         d_apply.count * sizeof(int2) + d_tile_order.count * 4 +
+                         d_ftiles.count * sizeof(SyrkItem) + d_frows.count * sizeof(int2) +
+                         d_part.count * 8 + d_tile_order.count * 4 +
                          d_tile_order_g.count * 4 + d_syrk_g.count * sizeof(SyrkItem) +
                          (d_rows.count + d_piv.count + d_pi.count) * 4 + d_sgn.count +
                          (d_lval.count + d_X.count + d_F.count) * 8 +
@@ -213,7 +217,8 @@ struct sc_plan_s {
                          (d_xwork.count + d_xoff.count) * 8);
     }
     void release() {
-        d_subs.release(); d_tiles.release(); d_blocks.release(); d_syrk.release(); d_apply.release();
+        d_subs.release(); d_tiles.release(); d_blocks.release(); d_syrk.release();
+        d_ftiles.release(); d_frows.release(); d_part.release();
         d_tile_order.release(); d_tile_order_g.release(); d_syrk_g.release();
         d_rows.release(); d_piv.release(); d_pi.release(); d_sgn.release();
         d_lval.release(); d_X.release(); d_F.release();
@@ -238,11 +243,14 @@ struct sc_plan_s {
         t.lval = d_lval.p; t.piv = d_piv.p; t.pi = d_pi.p; t.sgn = d_sgn.p; t.syrk = d_syrk.p;
         t.X = d_X.p; t.F = d_F.p;
         t.lval32 = d_lval32.p; t.X32 = d_X32.p; t.F32 = d_F32.p;
-        t.apply_items = d_apply.p;
+        t.ftiles = d_ftiles.p;
+        t.frows = d_frows.p;
+        t.part = d_part.p;
         t.tile_order = d_tile_order.p;
         t.ntiles = (int64_t)h_tile_order.size();
         t.nsyrk = (int64_t)h_syrk.size();
-        t.napply = (int64_t)h_apply.size();
+        t.nftiles = (int64_t)h_ftiles.size();
+        t.nfrows = (int64_t)h_frows.size();
         return t;
     }
 };
@@ -324,15 +332,18 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
             }
             P->h_tiles.push_back(T);
         }
-        for (int32_t c = 0; c < sp.m; c += 32) P->h_apply.push_back(make_int2(i, c));
         const int32_t nst = (sp.m + kSyrkTile - 1) / kSyrkTile;
-        for (int32_t I = 0; I < nst; ++I)
+        s.ftile_off = (int64_t)P->h_ftiles.size();
+        for (int32_t I = 0; I < nst; ++I) {
+            P->h_frows.push_back(make_int2(i, I));
             for (int32_t J = 0; J <= I; ++J) P->h_syrk.push_back(SyrkItem{i, I, J, 0});
+        }
+        P->h_ftiles.insert(P->h_ftiles.end(), P->h_syrk.end() - (int64_t)nst * (nst + 1) / 2, P->h_syrk.end());
         blk += s.nblocks;
         rows += ((int64_t)sp.brows.size() + 3) / 4 * 4;
         lv += sp.bval;
         colo += sp.m;
-        fo += ((int64_t)sp.m * sp.m + 3) / 4 * 4;      // 32-byte aligned F blocks
+        fo += (int64_t)nst * (nst + 1) / 2 * kFTileElems;   // packed lower tiles
         dual += sp.m;
         P->h_subs.push_back(s);
         P->trsm_u += sp.trsm_useful;
@@ -435,7 +446,9 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
     ALLOC(p->d_tiles, p->h_tiles.size());
     ALLOC(p->d_blocks, p->h_blocks.size());
     ALLOC(p->d_syrk, p->h_syrk.size());
-    ALLOC(p->d_apply, p->h_apply.size());
+    ALLOC(p->d_ftiles, p->h_ftiles.size());
+    ALLOC(p->d_frows, p->h_frows.size());
+    ALLOC(p->d_part, p->h_ftiles.size() * 256);
     ALLOC(p->d_tile_order, p->h_tile_order.size());
     ALLOC(p->d_tile_order_g, p->h_tile_order_g.size());
     ALLOC(p->d_syrk_g, p->h_syrk_g.size());
@@ -478,7 +491,8 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
     if (e == hipSuccess) e = up(p->d_tiles.p, p->h_tiles.data(), p->h_tiles.size() * sizeof(TileDev));
     if (e == hipSuccess) e = up(p->d_blocks.p, p->h_blocks.data(), p->h_blocks.size() * sizeof(BlockDev));
     if (e == hipSuccess) e = up(p->d_syrk.p, p->h_syrk.data(), p->h_syrk.size() * sizeof(SyrkItem));
-    if (e == hipSuccess) e = up(p->d_apply.p, p->h_apply.data(), p->h_apply.size() * sizeof(int2));
+    if (e == hipSuccess) e = up(p->d_ftiles.p, p->h_ftiles.data(), p->h_ftiles.size() * sizeof(SyrkItem));
+    if (e == hipSuccess) e = up(p->d_frows.p, p->h_frows.data(), p->h_frows.size() * sizeof(int2));
     if (e == hipSuccess) e = up(p->d_tile_order.p, p->h_tile_order.data(), p->h_tile_order.size() * 4);
     if (e == hipSuccess) e = up(p->d_tile_order_g.p, p->h_tile_order_g.data(), p->h_tile_order_g.size() * 4);
     if (e == hipSuccess) e = up(p->d_syrk_g.p, p->h_syrk_g.data(), p->h_syrk_g.size() * sizeof(SyrkItem));
@@ -739,27 +753,36 @@ sc_status_t sc_get_F(sc_plan_t P, int32_t sub, double* out, int32_t ld, int32_t 
     if (!out || ld < s.m) return fail(SC_ERR_INVALID_ARG, "bad output buffer or ld");
     HIP_TRY(hipSetDevice(P->device));
     hipStream_t st = (hipStream_t)stream;
+    // packed lower tiles in sorted column order -> dense, original order
+    const int64_t m = s.m;
+    const int64_t nt = (m + kSyrkTile - 1) / kSyrkTile;
+    const size_t cnt = (size_t)(nt * (nt + 1) / 2) * kFTileElems;
+    std::vector<double> tiles(cnt);
     if (!P->mixed) {
-        const double* src = P->d_F.p + s.F_off;
-        HIP_TRY(hipMemcpy2DAsync(out, (size_t)ld * sizeof(double), src, (size_t)s.m * sizeof(double),
-                                 (size_t)s.m * sizeof(double), (size_t)s.m,
-                                 on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        return SC_OK;
-    }
-    // FP32-stored F: copy to the host, widen, and place with the caller's ld
-    std::vector<float> tmp((size_t)s.m * s.m);
-    HIP_TRY(hipMemcpyAsync(tmp.data(), P->d_F32.p + s.F_off, tmp.size() * sizeof(float), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    std::vector<double> wide((size_t)ld * s.m, 0.0);
-    for (int64_t c = 0; c < s.m; ++c)
-        for (int64_t r = 0; r < s.m; ++r) wide[(size_t)c * ld + r] = (double)tmp[(size_t)c * s.m + r];
-    if (on_device) {
-        HIP_TRY(hipMemcpyAsync(out, wide.data(), wide.size() * sizeof(double), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(tiles.data(), P->d_F.p + s.F_off, cnt * sizeof(double), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
     } else {
-        for (int64_t c = 0; c < s.m; ++c)
-            std::copy(wide.begin() + c * ld, wide.begin() + c * ld + s.m, out + c * ld);
+        std::vector<float> t32(cnt);
+        HIP_TRY(hipMemcpyAsync(t32.data(), P->d_F32.p + s.F_off, cnt * sizeof(float), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        for (size_t k = 0; k < cnt; ++k) tiles[k] = (double)t32[k];
+    }
+    const std::vector<int32_t>& pi = P->plans[sub].pi;
+    std::vector<double> dense((size_t)m * m);
+    for (int64_t b = 0; b < m; ++b)
+        for (int64_t a = 0; a < m; ++a) {
+            int64_t hi = a, lo = b;                 // (hi, lo) lies in a stored tile
+            if (a / kSyrkTile < b / kSyrkTile) std::swap(hi, lo);
+            const int64_t I = hi / kSyrkTile, J = lo / kSyrkTile;
+            dense[(size_t)pi[b] * m + pi[a]] =
+                tiles[(size_t)(I * (I + 1) / 2 + J) * kFTileElems + (hi % kSyrkTile) * kSyrkTile + lo % kSyrkTile];
+        }
+    if (on_device) {
+        HIP_TRY(hipMemcpy2DAsync(out, (size_t)ld * sizeof(double), dense.data(), (size_t)m * sizeof(double),
+                                 (size_t)m * sizeof(double), (size_t)m, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    } else {
+        for (int64_t c = 0; c < m; ++c) std::copy(dense.begin() + c * m, dense.begin() + (c + 1) * m, out + c * ld);
     }
     return SC_OK;
 }

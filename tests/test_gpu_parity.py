@@ -211,6 +211,26 @@ def test_explicit_apply_matches_dense_product(cfg, count):
         assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref), i
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_apply_is_deterministic_and_symmetric_storage_complete(precision):
+    """The two-pass apply over the stored lower tiles gives the same bits on
+    every call, and equals get_F(i) @ p (get_F expands the same tiles)."""
+    subs = scgen.config_subdomains(3, count=5)            # m 654 .. 4614: several 128-tiles, ragged
+    plan = _assemble(subs, precision=precision)
+    p, q = _dual_vectors(plan, subs, seed=11)
+    plan.apply(p, q)
+    q1 = q.clone()
+    for _ in range(3):
+        q.zero_()
+        plan.apply(p, q)
+        assert bool((q == q1).all())
+    qh, ph = q.cpu().numpy(), p.cpu().numpy()
+    for i, s in enumerate(subs):
+        o = plan.query(i)["dual_offset"]
+        ref = plan.get_F(i) @ ph[o:o + s.m]
+        assert np.linalg.norm(qh[o:o + s.m] - ref) <= 1e-13 * np.linalg.norm(ref), i
+
+
 def test_apply_state_and_alias_errors():
     torch = _torch_init()
     s = scgen.config_subdomains(1)[0]
