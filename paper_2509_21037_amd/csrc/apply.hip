@@ -1,0 +1,404 @@
+// HIP kernels for gfx950 (CDNA4, wave64): the solution stage on the
+// assembled F (explicit apply, Sec. 2.2 eq. (12); PCPG, Sec. 2.1 eq. (7))
+// and the implicit apply with the factor (Sec. 2.2 eq. (11)).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace scasm {
+
+// ---------------------------------------------------------------------------
+// Explicit apply q = F p (Sec. 2.2, eq. (12)) on the packed sorted F, FP64
+// accumulation (FP32 or FP64 F).  Each stored lower tile T = F_s[I, J] is
+// read once and used twice: pass 1, one workgroup per tile, writes
+// u = T p_s[J] and v = T^T p_s[I] (p_s: p in sorted column order, gathered
+// through pi; diagonal tiles are stored whole, v unused); pass 2, one
+// workgroup per 128-row block K of a subdomain, sums u of (K, J <= K) and v
+// of (I > K, K) in a fixed order and scatters the result to q in multiplier
+// order.  Deterministic; reads F once, about half of the dense m x m.
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ void load8(const T* __restrict__ src, double (&t)[8]) {
+    if constexpr (sizeof(T) == 8) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const double2 d = reinterpret_cast<const double2*>(src)[e];
+            t[2 * e] = d.x;
+            t[2 * e + 1] = d.y;
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const float4 f = reinterpret_cast<const float4*>(src)[e];
+            t[4 * e] = f.x;
+            t[4 * e + 1] = f.y;
+            t[4 * e + 2] = f.z;
+            t[4 * e + 3] = f.w;
+        }
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void symv_tiles(
+    const SubDev* __restrict__ subs, const SyrkItem* __restrict__ ftiles, const T* __restrict__ F,
+    const int32_t* __restrict__ pi, const double* __restrict__ p, double* __restrict__ part)
+{
+    __shared__ double sp[2][kSyrkTile];                 // p_s of the tile's columns (J) and rows (I)
+    __shared__ double su[kSyrkTile][17];                // row sums per group of 8 columns
+    __shared__ double sv[kSyrkTile][17];                // column sums per group of 8 rows
+    const SyrkItem it = ftiles[blockIdx.x];
+    const SubDev S = subs[it.sub];
+    const int tid = threadIdx.x;
+    {
+        const int half = tid >> 7;
+        const int a = (half ? it.I : it.J) * kSyrkTile + (tid & 127);
+        sp[half][tid & 127] = a < S.m ? p[S.dual_off + pi[S.col_off + a]] : 0.0;
+    }
+    __syncthreads();
+    const int64_t tile = (int64_t)it.I * (it.I + 1) / 2 + it.J;
+    const T* __restrict__ Ft = F + S.F_off + tile * kFTileElems;
+    const int tr = tid >> 4;                            // rows 8 tr .. 8 tr + 7
+    const int tc = tid & 15;                            // columns 8 tc .. 8 tc + 7
+    double pj[8], u[8], v[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        pj[c] = sp[0][8 * tc + c];
+        u[c] = 0.0;
+        v[c] = 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int row = 8 * tr + i;
+        const double pr = sp[1][row];
+        double t[8];
+        load8(Ft + row * kSyrkTile + 8 * tc, t);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            u[i] += t[c] * pj[c];
+            v[c] += t[c] * pr;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        su[8 * tr + i][tc] = u[i];
+        sv[8 * tc + i][tr] = v[i];
+    }
+    __syncthreads();
+    const int k = tid & 127;
+    double acc = 0.0;
+    if (tid < 128) {
+#pragma unroll
+        for (int g = 0; g < 16; ++g) acc += su[k][g];
+    } else {
+#pragma unroll
+        for (int g = 0; g < 16; ++g) acc += sv[k][g];
+    }
+    part[((S.ftile_off + tile) << 8) + tid] = acc;
+}
+
+__global__ __launch_bounds__(128) void symv_rows(
+    const SubDev* __restrict__ subs, const int2* __restrict__ frows, const int32_t* __restrict__ pi,
+    const double* __restrict__ part, double* __restrict__ q)
+{
+    const int2 it = frows[blockIdx.x];                  // (subdomain, row block K)
+    const SubDev S = subs[it.x];
+    const int K = it.y;
+    const int r = threadIdx.x;
+    const int nt = (S.m + kSyrkTile - 1) / kSyrkTile;
+    const double* __restrict__ P = part + (S.ftile_off << 8);
+    double y = 0.0;
+    for (int J = 0; J <= K; ++J) y += P[(((int64_t)K * (K + 1) / 2 + J) << 8) + r];
+    for (int I = K + 1; I < nt; ++I) y += P[(((int64_t)I * (I + 1) / 2 + K) << 8) + 128 + r];
+    const int a = K * kSyrkTile + r;
+    if (a < S.m) q[S.dual_off + pi[S.col_off + a]] = y;
+}
+
+hipError_t launch_apply(const DevTables& t, const double* p, double* q, hipStream_t stream, hipEvent_t* ev) {
+    hipError_t e = hipSuccess;
+    if (ev && (e = hipEventRecord(ev[0], stream)) != hipSuccess) return e;
+    if (t.nftiles > 0) {
+        if (t.F32)
+            hipLaunchKernelGGL(symv_tiles<float>, dim3((unsigned)t.nftiles), dim3(256), 0, stream, t.subs,
+                               t.ftiles, (const float*)t.F32, t.pi, p, t.part);
+        else
+            hipLaunchKernelGGL(symv_tiles<double>, dim3((unsigned)t.nftiles), dim3(256), 0, stream, t.subs,
+                               t.ftiles, (const double*)t.F, t.pi, p, t.part);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(symv_rows, dim3((unsigned)t.nfrows), dim3(128), 0, stream, t.subs, t.frows, t.pi,
+                           (const double*)t.part, q);
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[1], stream)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// Projected conjugate gradients on each subdomain's dual problem (Sec. 2.1,
+// eq. (7), with e = 0 and the identity preconditioner), FP64 vectors; the
+// per-subdomain scalars stay on the device.  One workgroup per subdomain.
+//   lambda_0 = 0, r_0 = d, w_0 = P r_0, p_0 = w_0,  P = I - G (G^T G)^{-1} G^T
+//   q = F p;  alpha = (w.w)/(p.q);  lambda += alpha p;  r -= alpha q
+//   w' = P r;  beta = (w'.w')/(w.w);  p = w' + beta p
+// ---------------------------------------------------------------------------
+constexpr int kMaxKer = 8;
+
+struct PcpgDev {
+    const double* G;        // per subdomain m x k, column-major, at g_off
+    const int64_t* g_off;
+    const int32_t* kdim;
+    const double* GtGinv;   // per subdomain k x k at 64 * sub
+    double* r;
+    double* w;
+    double* pvec;
+    double* q;
+    double* ww;             // per subdomain w.w
+    double* hist;           // (iters + 1) x nsub or null
+    int32_t nsub;
+};
+
+__device__ double block_sum(double v, double* red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) t += red[i];
+    return t;
+}
+
+// w = r - G (G^T G)^{-1} G^T r over one subdomain; returns w.w
+__device__ double project(const SubDev& S, const PcpgDev& D, int sub, const double* r, double* w, double* red,
+                          double* su) {
+    const int m = S.m;
+    const int k = D.kdim[sub];
+    const double* G = D.G + D.g_off[sub];
+    for (int c = 0; c < k; ++c) {
+        double t = 0.0;
+        for (int i = threadIdx.x; i < m; i += 256) t += G[(int64_t)c * m + i] * r[i];
+        t = block_sum(t, red);
+        if (threadIdx.x == 0) su[c] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < k) {
+        double u = 0.0;
+        for (int c = 0; c < k; ++c) u += D.GtGinv[64 * sub + threadIdx.x * k + c] * su[c];
+        su[kMaxKer + threadIdx.x] = u;
+    }
+    __syncthreads();
+    double ww = 0.0;
+    for (int i = threadIdx.x; i < m; i += 256) {
+        double v = r[i];
+        for (int c = 0; c < k; ++c) v -= G[(int64_t)c * m + i] * su[kMaxKer + c];
+        w[i] = v;
+        ww += v * v;
+    }
+    return block_sum(ww, red);
+}
+
+__global__ __launch_bounds__(256) void pcpg_init(const SubDev* __restrict__ subs, PcpgDev D,
+                                                 const double* __restrict__ d, double* __restrict__ lambda) {
+    __shared__ double red[4];
+    __shared__ double su[2 * kMaxKer];
+    const int sub = blockIdx.x;
+    const SubDev S = subs[sub];
+    const int64_t o = S.dual_off;
+    for (int i = threadIdx.x; i < S.m; i += 256) {
+        lambda[o + i] = 0.0;
+        D.r[o + i] = d[o + i];
+    }
+    __syncthreads();
+    const double ww = project(S, D, sub, D.r + o, D.w + o, red, su);
+    for (int i = threadIdx.x; i < S.m; i += 256) D.pvec[o + i] = D.w[o + i];
+    if (threadIdx.x == 0) {
+        D.ww[sub] = ww;
+        if (D.hist) D.hist[sub] = sqrt(ww);
+    }
+}
+
+__global__ __launch_bounds__(256) void pcpg_step(const SubDev* __restrict__ subs, PcpgDev D,
+                                                 double* __restrict__ lambda, int iter) {
+    __shared__ double red[4];
+    __shared__ double su[2 * kMaxKer];
+    const int sub = blockIdx.x;
+    const SubDev S = subs[sub];
+    const int64_t o = S.dual_off;
+    const int m = S.m;
+    double* r = D.r + o;
+    double* w = D.w + o;
+    double* pv = D.pvec + o;
+    const double* q = D.q + o;
+    const double ww = D.ww[sub];
+    double pq = 0.0;
+    for (int i = threadIdx.x; i < m; i += 256) pq += pv[i] * q[i];
+    pq = block_sum(pq, red);
+    const bool go = pq > 0.0 && ww > 0.0;       // converged (or breakdown): keep the iterate
+    const double alpha = go ? ww / pq : 0.0;
+    for (int i = threadIdx.x; i < m; i += 256) {
+        lambda[o + i] += alpha * pv[i];
+        r[i] -= alpha * q[i];
+    }
+    __syncthreads();
+    const double ww2 = go ? project(S, D, sub, r, w, red, su) : ww;
+    const double beta = go ? ww2 / ww : 0.0;
+    if (go)
+        for (int i = threadIdx.x; i < m; i += 256) pv[i] = w[i] + beta * pv[i];
+    if (threadIdx.x == 0) {
+        D.ww[sub] = ww2;
+        if (D.hist) D.hist[(int64_t)(iter + 1) * D.nsub + sub] = sqrt(ww2);
+    }
+}
+
+hipError_t launch_pcpg(const DevTables& t, const PcpgArgs& a, hipStream_t stream) {
+    PcpgDev D;
+    D.G = a.G; D.g_off = a.g_off; D.kdim = a.kdim; D.GtGinv = a.GtGinv;
+    D.r = a.r; D.w = a.w; D.pvec = a.p; D.q = a.q; D.ww = a.ww; D.hist = a.hist; D.nsub = a.nsub;
+    if (a.nsub <= 0) return hipSuccess;
+    hipLaunchKernelGGL(pcpg_init, dim3((unsigned)a.nsub), dim3(256), 0, stream, t.subs, D, a.d, a.lambda);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    for (int it = 0; it < a.iters; ++it) {
+        if ((e = launch_apply(t, a.p, a.q, stream, nullptr)) != hipSuccess) return e;
+        hipLaunchKernelGGL(pcpg_step, dim3((unsigned)a.nsub), dim3(256), 0, stream, t.subs, D, a.lambda, it);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// Implicit apply (Sec. 2.2, eq. (11)): q = B P^T L^{-T} L^{-1} P B^T p, one
+// workgroup per subdomain sweeping the factor blocks (forward, then backward),
+// FP64.  x (n doubles per subdomain, global workspace) carries P B^T p, then
+// y = L^{-1} x, then z = L^{-T} y in place.
+//   forward, block b:  y_b = L_bb^{-1} x_b;  x[R_b] -= L[R_b, b] y_b
+//   backward, block b: z_b = L_bb^{-T} (y_b - L[R_b, b]^T z[R_b])
+// Repeated DOFs (several multipliers on one DOF) are summed by one thread per
+// run of equal pivots (sorted), so the result does not depend on scheduling.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void implicit_apply(
+    const SubDev* __restrict__ subs, const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows,
+    const double* __restrict__ lval, const int32_t* __restrict__ piv, const int32_t* __restrict__ pi,
+    const int8_t* __restrict__ sgn, const int64_t* __restrict__ xoff, const double* __restrict__ p,
+    double* __restrict__ q, double* __restrict__ xwork)
+{
+    __shared__ double sL[64 * 65];
+    __shared__ double sv[64];
+    __shared__ double sz[64];
+    const int sub = blockIdx.x;
+    const SubDev S = subs[sub];
+    const int n = S.n;
+    const int m = S.m;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wv = tid >> 6;
+    double* __restrict__ x = xwork + xoff[sub];
+    const int32_t* __restrict__ pv = piv + S.col_off;
+    const int32_t* __restrict__ pis = pi + S.col_off;
+    const int8_t* __restrict__ sg = sgn + S.col_off;
+    const double* __restrict__ ps = p + S.dual_off;
+    const BlockDev* __restrict__ B = blocks + S.blk_off;
+    const int32_t* __restrict__ R = rows + S.rows_off;
+    const double* __restrict__ L = lval + S.lval_off;
+
+    for (int i = tid; i < n; i += 256) x[i] = 0.0;
+    __syncthreads();
+    for (int a = tid; a < m; a += 256) {
+        if (a > 0 && pv[a - 1] == pv[a]) continue;
+        double v = 0.0;
+        for (int b = a; b < m && pv[b] == pv[a]; ++b) v += (double)sg[b] * ps[pis[b]];
+        x[pv[a]] = v;
+    }
+    __syncthreads();
+
+    // L[q][k] of the pruned rows, tile layout (see BlockDesc)
+    auto lbelow = [&](const double* At, int nks, int q, int k) {
+        return At[((int64_t)(q >> 4) * nks + (k >> 2)) * 64 + (q & 15) + 16 * (k & 3)];
+    };
+    // ---- forward
+    for (int b = 0; b < S.nblocks; ++b) {
+        const BlockDev bd = B[b];
+        const int w = bd.w, nb = bd.nbelow, row0 = bd.row0, nks = (w + 3) / 4;
+        const double* __restrict__ Lb = L + bd.lval_off;
+        const double* __restrict__ At = L + bd.aoff;
+        for (int e = tid; e < 64 * 64; e += 256) {
+            const int r = e & 63, k = e >> 6;
+            sL[k * 65 + r] = (r < w && k < w) ? Lb[k * w + r] : 0.0;
+        }
+        __syncthreads();
+        if (wv == 0) {
+            double xi = lane < w ? x[row0 + lane] : 0.0;
+            for (int k = 0; k < w; ++k) {
+                const double xk = __shfl(xi, k, 64) / sL[k * 65 + k];
+                if (lane == k) xi = xk;
+                if (lane > k) xi -= sL[k * 65 + lane] * xk;
+            }
+            if (lane < w) {
+                x[row0 + lane] = xi;
+                sv[lane] = xi;
+            }
+        }
+        __syncthreads();
+        const int32_t* __restrict__ rw = R + bd.rows_off;
+        for (int qq = tid; qq < nb; qq += 256) {
+            double t = 0.0;
+            for (int k = 0; k < w; ++k) t += lbelow(At, nks, qq, k) * sv[k];
+            x[rw[qq]] -= t;
+        }
+        __syncthreads();
+    }
+    // ---- backward
+    for (int b = S.nblocks - 1; b >= 0; --b) {
+        const BlockDev bd = B[b];
+        const int w = bd.w, nb = bd.nbelow, row0 = bd.row0, nks = (w + 3) / 4;
+        const double* __restrict__ Lb = L + bd.lval_off;
+        const double* __restrict__ At = L + bd.aoff;
+        const int32_t* __restrict__ rw = R + bd.rows_off;
+        double acc = 0.0;                      // lane k of wavefront 0: sum_q L[q][k] z[R[q]]
+        for (int c0 = 0; c0 < nb; c0 += 64) {
+            for (int e = tid; e < 64 * 64; e += 256) {
+                const int r = e & 63, k = e >> 6;
+                sL[k * 65 + r] = (c0 + r < nb && k < w) ? lbelow(At, nks, c0 + r, k) : 0.0;
+            }
+            if (tid < 64) sz[tid] = c0 + tid < nb ? x[rw[c0 + tid]] : 0.0;
+            __syncthreads();
+            if (wv == 0 && lane < w)
+                for (int r = 0; r < 64; ++r) acc += sL[lane * 65 + r] * sz[r];
+            __syncthreads();
+        }
+        for (int e = tid; e < 64 * 64; e += 256) {
+            const int r = e & 63, k = e >> 6;
+            sL[k * 65 + r] = (r < w && k < w) ? Lb[k * w + r] : 0.0;
+        }
+        __syncthreads();
+        if (wv == 0) {
+            double vk = lane < w ? x[row0 + lane] - acc : 0.0;
+            for (int i = w - 1; i >= 0; --i) {
+                const double zi = __shfl(vk, i, 64) / sL[i * 65 + i];
+                if (lane == i) vk = zi;
+                if (lane < i) vk -= sL[lane * 65 + i] * zi;
+            }
+            if (lane < w) x[row0 + lane] = vk;
+        }
+        __syncthreads();
+    }
+    for (int a = tid; a < m; a += 256) q[S.dual_off + pis[a]] = (double)sg[a] * x[pv[a]];
+}
+
+hipError_t launch_apply_implicit(const DevTables& t, const int64_t* xoff, double* xwork, const double* p,
+                                 double* q, int32_t nsub, hipStream_t stream, hipEvent_t* ev) {
+    hipError_t e = hipSuccess;
+    if (ev && (e = hipEventRecord(ev[0], stream)) != hipSuccess) return e;
+    if (nsub > 0)
+        hipLaunchKernelGGL(implicit_apply, dim3((unsigned)nsub), dim3(256), 0, stream, t.subs, t.blocks, t.rows,
+                           t.lval, t.piv, t.pi, t.sgn, xoff, p, q, xwork);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[1], stream)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+}  // namespace scasm
