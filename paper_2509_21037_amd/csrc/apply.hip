@@ -271,131 +271,193 @@ hipError_t launch_pcpg(const DevTables& t, const PcpgArgs& a, hipStream_t stream
 }
 
 // ---------------------------------------------------------------------------
-// Implicit apply (Sec. 2.2, eq. (11)): q = B P^T L^{-T} L^{-1} P B^T p, one
-// workgroup per subdomain sweeping the factor blocks (forward, then backward),
-// FP64.  x (n doubles per subdomain, global workspace) carries P B^T p, then
-// y = L^{-1} x, then z = L^{-T} y in place.
-//   forward, block b:  y_b = L_bb^{-1} x_b;  x[R_b] -= L[R_b, b] y_b
-//   backward, block b: z_b = L_bb^{-T} (y_b - L[R_b, b]^T z[R_b])
-// Repeated DOFs (several multipliers on one DOF) are summed by one thread per
-// run of equal pivots (sorted), so the result does not depend on scheduling.
+// Implicit apply (Sec. 2.2, eq. (11)): q = B P^T L^{-T} L^{-1} P B^T p with the
+// factor blocks, FP64.  x (n doubles per subdomain, workspace) holds P B^T p,
+// then y = L^{-1} x, then z = L^{-T} y, in place.  The blocked triangular
+// solves run level by level (planner: a block's forward level is one more
+// than that of every block whose pruned rows reach it; its backward level one
+// more than that of every block its own pruned rows lie in), one launch per
+// level, one wavefront per block of all subdomains at that level:
+//   forward, block b:   y_b = L_bb^{-1} (x_b - sum of the update entries of
+//                       its rows), then u_b = L[R_b, b] y_b into the update
+//                       buffer (parallel to the pruned-row lists); a row's
+//                       entries are summed by its own thread in a fixed order
+//                       (planner lists), no atomics
+//   backward, block b:  z_b = L_bb^{-T} (y_b - L[R_b, b]^T z[R_b])
+// The diagonal inverses are the ones the TRSM uses.  Repeated DOFs (several
+// multipliers on one DOF) are summed by one thread per run of equal pivots.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void implicit_apply(
-    const SubDev* __restrict__ subs, const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows,
-    const double* __restrict__ lval, const int32_t* __restrict__ piv, const int32_t* __restrict__ pi,
+__device__ __forceinline__ double tile_at(const double* __restrict__ At, int nks, int q, int k) {
+    return At[((int64_t)(q >> 4) * nks + (k >> 2)) * 64 + (q & 15) + 16 * (k & 3)];
+}
+
+// Linv[r][k] of a block's inverse diagonal (row tiles stored in TRSM order)
+__device__ __forceinline__ double linv_at(const double* __restrict__ Lv, int nrt_d, int nks, int r, int k) {
+    const int rt = r >> 4;
+    const int slot = nrt_d > 2 ? (rt >= 2 ? rt - 2 : rt + nrt_d - 2) : rt;
+    return Lv[((int64_t)slot * nks + (k >> 2)) * 64 + (r & 15) + 16 * (k & 3)];
+}
+
+__global__ __launch_bounds__(256) void implicit_init(
+    const SubDev* __restrict__ subs, const int32_t* __restrict__ piv, const int32_t* __restrict__ pi,
     const int8_t* __restrict__ sgn, const int64_t* __restrict__ xoff, const double* __restrict__ p,
-    double* __restrict__ q, double* __restrict__ xwork)
+    double* __restrict__ xwork)
 {
-    __shared__ double sL[64 * 65];
-    __shared__ double sv[64];
-    __shared__ double sz[64];
     const int sub = blockIdx.x;
     const SubDev S = subs[sub];
-    const int n = S.n;
-    const int m = S.m;
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wv = tid >> 6;
     double* __restrict__ x = xwork + xoff[sub];
     const int32_t* __restrict__ pv = piv + S.col_off;
     const int32_t* __restrict__ pis = pi + S.col_off;
     const int8_t* __restrict__ sg = sgn + S.col_off;
     const double* __restrict__ ps = p + S.dual_off;
-    const BlockDev* __restrict__ B = blocks + S.blk_off;
-    const int32_t* __restrict__ R = rows + S.rows_off;
-    const double* __restrict__ L = lval + S.lval_off;
-
-    for (int i = tid; i < n; i += 256) x[i] = 0.0;
+    for (int i = threadIdx.x; i < S.n; i += 256) x[i] = 0.0;
     __syncthreads();
-    for (int a = tid; a < m; a += 256) {
+    for (int a = threadIdx.x; a < S.m; a += 256) {
         if (a > 0 && pv[a - 1] == pv[a]) continue;
         double v = 0.0;
-        for (int b = a; b < m && pv[b] == pv[a]; ++b) v += (double)sg[b] * ps[pis[b]];
+        for (int b = a; b < S.m && pv[b] == pv[a]; ++b) v += (double)sg[b] * ps[pis[b]];
         x[pv[a]] = v;
     }
-    __syncthreads();
-
-    // L[q][k] of the pruned rows, tile layout (see BlockDesc)
-    auto lbelow = [&](const double* At, int nks, int q, int k) {
-        return At[((int64_t)(q >> 4) * nks + (k >> 2)) * 64 + (q & 15) + 16 * (k & 3)];
-    };
-    // ---- forward
-    for (int b = 0; b < S.nblocks; ++b) {
-        const BlockDev bd = B[b];
-        const int w = bd.w, nb = bd.nbelow, row0 = bd.row0, nks = (w + 3) / 4;
-        const double* __restrict__ Lb = L + bd.lval_off;
-        const double* __restrict__ At = L + bd.aoff;
-        for (int e = tid; e < 64 * 64; e += 256) {
-            const int r = e & 63, k = e >> 6;
-            sL[k * 65 + r] = (r < w && k < w) ? Lb[k * w + r] : 0.0;
-        }
-        __syncthreads();
-        if (wv == 0) {
-            double xi = lane < w ? x[row0 + lane] : 0.0;
-            for (int k = 0; k < w; ++k) {
-                const double xk = __shfl(xi, k, 64) / sL[k * 65 + k];
-                if (lane == k) xi = xk;
-                if (lane > k) xi -= sL[k * 65 + lane] * xk;
-            }
-            if (lane < w) {
-                x[row0 + lane] = xi;
-                sv[lane] = xi;
-            }
-        }
-        __syncthreads();
-        const int32_t* __restrict__ rw = R + bd.rows_off;
-        for (int qq = tid; qq < nb; qq += 256) {
-            double t = 0.0;
-            for (int k = 0; k < w; ++k) t += lbelow(At, nks, qq, k) * sv[k];
-            x[rw[qq]] -= t;
-        }
-        __syncthreads();
-    }
-    // ---- backward
-    for (int b = S.nblocks - 1; b >= 0; --b) {
-        const BlockDev bd = B[b];
-        const int w = bd.w, nb = bd.nbelow, row0 = bd.row0, nks = (w + 3) / 4;
-        const double* __restrict__ Lb = L + bd.lval_off;
-        const double* __restrict__ At = L + bd.aoff;
-        const int32_t* __restrict__ rw = R + bd.rows_off;
-        double acc = 0.0;                      // lane k of wavefront 0: sum_q L[q][k] z[R[q]]
-        for (int c0 = 0; c0 < nb; c0 += 64) {
-            for (int e = tid; e < 64 * 64; e += 256) {
-                const int r = e & 63, k = e >> 6;
-                sL[k * 65 + r] = (c0 + r < nb && k < w) ? lbelow(At, nks, c0 + r, k) : 0.0;
-            }
-            if (tid < 64) sz[tid] = c0 + tid < nb ? x[rw[c0 + tid]] : 0.0;
-            __syncthreads();
-            if (wv == 0 && lane < w)
-                for (int r = 0; r < 64; ++r) acc += sL[lane * 65 + r] * sz[r];
-            __syncthreads();
-        }
-        for (int e = tid; e < 64 * 64; e += 256) {
-            const int r = e & 63, k = e >> 6;
-            sL[k * 65 + r] = (r < w && k < w) ? Lb[k * w + r] : 0.0;
-        }
-        __syncthreads();
-        if (wv == 0) {
-            double vk = lane < w ? x[row0 + lane] - acc : 0.0;
-            for (int i = w - 1; i >= 0; --i) {
-                const double zi = __shfl(vk, i, 64) / sL[i * 65 + i];
-                if (lane == i) vk = zi;
-                if (lane < i) vk -= sL[lane * 65 + i] * zi;
-            }
-            if (lane < w) x[row0 + lane] = vk;
-        }
-        __syncthreads();
-    }
-    for (int a = tid; a < m; a += 256) q[S.dual_off + pis[a]] = (double)sg[a] * x[pv[a]];
 }
 
-hipError_t launch_apply_implicit(const DevTables& t, const int64_t* xoff, double* xwork, const double* p,
-                                 double* q, int32_t nsub, hipStream_t stream, hipEvent_t* ev) {
+// One block step per workgroup of 256 threads: thread (part, r) = (tid / 64,
+// tid % 64) works on row / column r and a quarter of each sum; partial sums
+// meet in LDS in a fixed order.
+__global__ __launch_bounds__(256) void implicit_fwd(
+    const SubDev* __restrict__ subs, const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows,
+    const double* __restrict__ lval, const int64_t* __restrict__ rptr_off, const int32_t* __restrict__ rptr,
+    const int32_t* __restrict__ rpos, const int2* __restrict__ items, const int64_t* __restrict__ xoff,
+    double* __restrict__ xwork, double* __restrict__ ubuf)
+{
+    __shared__ double sp[4][64];
+    __shared__ double sx[64];
+    const int2 it = items[blockIdx.x];
+    const SubDev S = subs[it.x];
+    const BlockDev bd = blocks[S.blk_off + it.y];
+    const double* __restrict__ L = lval + S.lval_off;
+    double* __restrict__ x = xwork + xoff[it.x];
+    const int32_t* __restrict__ rp = rptr + rptr_off[it.x];
+    const int tid = threadIdx.x;
+    const int r = tid & 63;
+    const int part = tid >> 6;
+    const int w = bd.w;
+    // x_b minus the update entries of its rows
+    double v = 0.0;
+    if (r < w) {
+        const int row = bd.row0 + r;
+        for (int e = rp[row] + part; e < rp[row + 1]; e += 4) v -= ubuf[rpos[e]];
+        if (part == 0) v += x[row];
+    }
+    sp[part][r] = v;
+    __syncthreads();
+    if (tid < 64) sx[tid] = sp[0][tid] + sp[1][tid] + sp[2][tid] + sp[3][tid];
+    __syncthreads();
+    // y_b = L_bb^{-1} x_b: k split in quarters
+    const double* __restrict__ Lv = L + bd.linv_off;
+    const int nrt_d = (w + 15) >> 4, nks = (w + 3) >> 2;
+    double y = 0.0;
+    if (r < w)
+        for (int k = 16 * part; k < min(16 * part + 16, r + 1); ++k) y += linv_at(Lv, nrt_d, nks, r, k) * sx[k];
+    sp[part][r] = y;
+    __syncthreads();
+    if (tid < 64) {
+        const double yb = sp[0][tid] + sp[1][tid] + sp[2][tid] + sp[3][tid];
+        sx[tid] = tid < w ? yb : 0.0;
+        if (tid < w) x[bd.row0 + tid] = yb;
+    }
+    __syncthreads();
+    // u_b = L[R_b, b] y_b, one pruned row per thread
+    const double* __restrict__ At = L + bd.aoff;
+    double* __restrict__ u = ubuf + S.rows_off + bd.rows_off;
+    for (int q = tid; q < bd.nbelow; q += 256) {
+        double t = 0.0;
+        for (int k = 0; k < w; ++k) t += tile_at(At, nks, q, k) * sx[k];
+        u[q] = t;
+    }
+}
+
+__global__ __launch_bounds__(256) void implicit_bwd(
+    const SubDev* __restrict__ subs, const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows,
+    const double* __restrict__ lval, const int2* __restrict__ items, const int64_t* __restrict__ xoff,
+    double* __restrict__ xwork)
+{
+    __shared__ double sp[4][64];
+    __shared__ double sz[256];
+    __shared__ double sv[64];
+    const int2 it = items[blockIdx.x];
+    const SubDev S = subs[it.x];
+    const BlockDev bd = blocks[S.blk_off + it.y];
+    const double* __restrict__ L = lval + S.lval_off;
+    const int32_t* __restrict__ rw = rows + S.rows_off + bd.rows_off;
+    double* __restrict__ x = xwork + xoff[it.x];
+    const int tid = threadIdx.x;
+    const int r = tid & 63;
+    const int part = tid >> 6;
+    const int w = bd.w, nb = bd.nbelow, nks = (w + 3) >> 2;
+    const double* __restrict__ At = L + bd.aoff;
+    // y_b - L[R_b, b]^T z[R_b]: pruned rows in groups of 256, each quarter of
+    // the threads takes every fourth row of a group
+    double v = 0.0;
+    for (int c0 = 0; c0 < nb; c0 += 256) {
+        __syncthreads();
+        sz[tid] = c0 + tid < nb ? x[rw[c0 + tid]] : 0.0;   // z of the pruned rows: final
+        __syncthreads();
+        const int cn = min(256, nb - c0);
+        if (r < w)
+            for (int qq = part; qq < cn; qq += 4) v -= tile_at(At, nks, c0 + qq, r) * sz[qq];
+    }
+    if (part == 0 && r < w) v += x[bd.row0 + r];
+    sp[part][r] = v;
+    __syncthreads();
+    if (tid < 64) sv[tid] = tid < w ? sp[0][tid] + sp[1][tid] + sp[2][tid] + sp[3][tid] : 0.0;
+    __syncthreads();
+    // z_b = L_bb^{-T} v: k split in quarters
+    const double* __restrict__ Lv = L + bd.linv_off;
+    const int nrt_d = (w + 15) >> 4;
+    double z = 0.0;
+    if (r < w)
+        for (int k = max(r, 16 * part); k < min(16 * part + 16, w); ++k) z += linv_at(Lv, nrt_d, nks, k, r) * sv[k];
+    sp[part][r] = z;
+    __syncthreads();
+    if (tid < w) x[bd.row0 + tid] = sp[0][tid] + sp[1][tid] + sp[2][tid] + sp[3][tid];
+}
+
+__global__ __launch_bounds__(256) void implicit_gather(
+    const SubDev* __restrict__ subs, const int32_t* __restrict__ piv, const int32_t* __restrict__ pi,
+    const int8_t* __restrict__ sgn, const int64_t* __restrict__ xoff, const double* __restrict__ xwork,
+    double* __restrict__ q)
+{
+    const int sub = blockIdx.x;
+    const SubDev S = subs[sub];
+    const double* __restrict__ x = xwork + xoff[sub];
+    for (int a = threadIdx.x; a < S.m; a += 256)
+        q[S.dual_off + pi[S.col_off + a]] = (double)sgn[S.col_off + a] * x[piv[S.col_off + a]];
+}
+
+hipError_t launch_apply_implicit(const DevTables& t, const ImplicitLevels& lv, const int64_t* xoff, double* xwork,
+                                 const double* p, double* q, int32_t nsub, hipStream_t stream, hipEvent_t* ev) {
     hipError_t e = hipSuccess;
     if (ev && (e = hipEventRecord(ev[0], stream)) != hipSuccess) return e;
-    if (nsub > 0)
-        hipLaunchKernelGGL(implicit_apply, dim3((unsigned)nsub), dim3(256), 0, stream, t.subs, t.blocks, t.rows,
-                           t.lval, t.piv, t.pi, t.sgn, xoff, p, q, xwork);
+    if (nsub > 0) {
+        hipLaunchKernelGGL(implicit_init, dim3((unsigned)nsub), dim3(256), 0, stream, t.subs, t.piv, t.pi, t.sgn,
+                           xoff, p, xwork);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        for (size_t l = 0; l + 1 < lv.fw_off.size(); ++l) {
+            const int64_t cnt = lv.fw_off[l + 1] - lv.fw_off[l];
+            hipLaunchKernelGGL(implicit_fwd, dim3((unsigned)cnt), dim3(256), 0, stream, t.subs, t.blocks, t.rows,
+                               t.lval, lv.rptr_off, lv.rptr, lv.rpos, lv.fw_items + lv.fw_off[l], xoff, xwork,
+                               lv.ubuf);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        for (size_t l = 0; l + 1 < lv.bw_off.size(); ++l) {
+            const int64_t cnt = lv.bw_off[l + 1] - lv.bw_off[l];
+            hipLaunchKernelGGL(implicit_bwd, dim3((unsigned)cnt), dim3(256), 0, stream, t.subs, t.blocks, t.rows,
+                               t.lval, lv.bw_items + lv.bw_off[l], xoff, xwork);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(implicit_gather, dim3((unsigned)nsub), dim3(256), 0, stream, t.subs, t.piv, t.pi, t.sgn,
+                           xoff, (const double*)xwork, q);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], stream)) != hipSuccess) return e;
     return hipSuccess;

@@ -2,6 +2,9 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
+#include <vector>
+
 #include "device.hpp"
 
 namespace scasm {
@@ -63,10 +66,25 @@ struct PcpgArgs {
 // Projected CG on every subdomain, `iters` iterations (explicit F apply).
 hipError_t launch_pcpg(const DevTables& t, const PcpgArgs& a, hipStream_t stream);
 
+// Level schedule of the blocked triangular solves of the implicit apply:
+// items (subdomain, block) grouped by level (host offsets, levels run in
+// order); per row of a subdomain (rptr at rptr_off[sub], CSR) the positions
+// in the row array where it is a pruned row: its entries in the update
+// buffer ubuf, which runs parallel to the row array.
+struct ImplicitLevels {
+    const int2* fw_items = nullptr;
+    const int2* bw_items = nullptr;
+    const int64_t* rptr_off = nullptr;
+    const int32_t* rptr = nullptr;
+    const int32_t* rpos = nullptr;
+    double* ubuf = nullptr;
+    std::vector<int64_t> fw_off, bw_off;
+};
+
 // Implicit apply q = B P^T L^{-T} L^{-1} P B^T p; xwork holds n_i doubles per
-// subdomain at xoff[i].
-hipError_t launch_apply_implicit(const DevTables& t, const int64_t* xoff, double* xwork, const double* p,
-                                 double* q, int32_t nsub, hipStream_t stream, hipEvent_t* ev);
+// subdomain at xoff[i]; optional events ev[0] before, ev[1] after.
+hipError_t launch_apply_implicit(const DevTables& t, const ImplicitLevels& lv, const int64_t* xoff, double* xwork,
+                                 const double* p, double* q, int32_t nsub, hipStream_t stream, hipEvent_t* ev);
 
 // q = F p for every subdomain (FP32 F when t.F32 is set, else FP64 F), two
 // passes over the packed sorted F; optional events ev[0] before, ev[1] after.

@@ -125,6 +125,12 @@ struct sc_plan_s {
     DevBuf<float> d_lval32, d_X32, d_F32;
     DevBuf<double> d_xwork;                   // implicit apply: n_i doubles per subdomain
     DevBuf<int64_t> d_xoff;
+    // implicit apply level schedule (built with the workspace, on first use)
+    DevBuf<int2> d_ifw, d_ibw;
+    DevBuf<int64_t> d_rptr_off;
+    DevBuf<int32_t> d_rptr, d_rpos;
+    DevBuf<double> d_ubuf;
+    ImplicitLevels ilv;
     bool mixed = false;
     bool factored = false, assembled = false;
     hipGraphExec_t graph_exec = nullptr;        // captured assembly (use_graph)
@@ -214,7 +220,8 @@ struct sc_plan_s {
                          (d_rows.count + d_piv.count + d_pi.count) * 4 + d_sgn.count +
                          (d_lval.count + d_X.count + d_F.count) * 8 +
                          (d_lval32.count + d_X32.count + d_F32.count) * 4 +
-                         (d_xwork.count + d_xoff.count) * 8);
+                         (d_xwork.count + d_xoff.count) * 8 + (d_ifw.count + d_ibw.count) * sizeof(int2) +
+                         (d_rptr.count + d_rpos.count) * 4 + (d_rptr_off.count + d_ubuf.count) * 8);
     }
     void release() {
         d_subs.release(); d_tiles.release(); d_blocks.release(); d_syrk.release();
@@ -224,6 +231,7 @@ struct sc_plan_s {
         d_lval.release(); d_X.release(); d_F.release();
         d_lval32.release(); d_X32.release(); d_F32.release();
         d_xwork.release(); d_xoff.release();
+        d_ifw.release(); d_ibw.release(); d_rptr_off.release(); d_rptr.release(); d_rpos.release(); d_ubuf.release();
         if (h_lval) (void)hipHostFree(h_lval);
         h_lval = nullptr;
         if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
@@ -724,13 +732,81 @@ sc_status_t sc_apply_implicit(sc_plan_t P, const double* p_dev, double* q_dev, v
     if (P->dual_total > 0 && p_dev == q_dev) return fail(SC_ERR_INVALID_ARG, "p and q must not alias");
     HIP_TRY(hipSetDevice(P->device));
     hipStream_t st = (hipStream_t)stream;
-    if (!P->d_xoff.p && P->nsub > 0) {           // workspace, allocated on first use
+    if (!P->d_xoff.p && P->nsub > 0) {           // workspace and level schedule, on first use
         std::vector<int64_t> off(P->nsub + 1, 0);
         for (int32_t i = 0; i < P->nsub; ++i) off[i + 1] = off[i] + P->plans[i].n;
+        // levels: forward = 1 + max over the blocks whose pruned rows reach the
+        // block; backward = 1 + max over the blocks the block's pruned rows lie in
+        std::vector<std::vector<int2>> fw, bw;
+        std::vector<int64_t> rptr_off(P->nsub, 0);
+        std::vector<int32_t> rptr, rpos;
+        for (int32_t i = 0; i < P->nsub; ++i) {
+            const SubPlan& sp = P->plans[i];
+            const SubDev& sd = P->h_subs[i];
+            const int32_t nb = (int32_t)sp.blocks.size();
+            std::vector<int32_t> lf(nb, 0), lb(nb, 0);
+            for (int32_t b = 0; b < nb; ++b) {
+                const BlockDesc& d = sp.blocks[b];
+                for (int32_t q = 0; q < d.nbelow; ++q) {
+                    const int32_t t = sp.block_of_row[sp.brows[d.rows_off + q]];
+                    lf[t] = std::max(lf[t], lf[b] + 1);
+                }
+            }
+            for (int32_t b = nb - 1; b >= 0; --b) {
+                const BlockDesc& d = sp.blocks[b];
+                for (int32_t q = 0; q < d.nbelow; ++q)
+                    lb[b] = std::max(lb[b], lb[sp.block_of_row[sp.brows[d.rows_off + q]]] + 1);
+            }
+            for (int32_t b = 0; b < nb; ++b) {
+                if ((size_t)lf[b] >= fw.size()) fw.resize(lf[b] + 1);
+                if ((size_t)lb[b] >= bw.size()) bw.resize(lb[b] + 1);
+                fw[lf[b]].push_back(make_int2(i, b));
+                bw[lb[b]].push_back(make_int2(i, b));
+            }
+            // per row: positions (in the global row array) where it is a pruned row
+            std::vector<int32_t> cnt(sp.n + 1, 0);
+            for (int32_t b = 0; b < nb; ++b) {
+                const BlockDesc& d = sp.blocks[b];
+                for (int32_t q = 0; q < d.nbelow; ++q) ++cnt[sp.brows[d.rows_off + q] + 1];
+            }
+            for (int32_t r = 0; r < sp.n; ++r) cnt[r + 1] += cnt[r];
+            rptr_off[i] = (int64_t)rptr.size();
+            const int32_t base = (int32_t)rpos.size();
+            for (int32_t r = 0; r <= sp.n; ++r) rptr.push_back(base + cnt[r]);
+            rpos.resize(rpos.size() + cnt[sp.n]);
+            std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+            for (int32_t b = 0; b < nb; ++b) {             // increasing source block: fixed order
+                const BlockDesc& d = sp.blocks[b];
+                for (int32_t q = 0; q < d.nbelow; ++q)
+                    rpos[base + fill[sp.brows[d.rows_off + q]]++] = (int32_t)(sd.rows_off + d.rows_off + q);
+            }
+        }
+        std::vector<int2> fwi, bwi;
+        P->ilv.fw_off.assign(1, 0);
+        P->ilv.bw_off.assign(1, 0);
+        for (auto& l : fw) { fwi.insert(fwi.end(), l.begin(), l.end()); P->ilv.fw_off.push_back((int64_t)fwi.size()); }
+        for (auto& l : bw) { bwi.insert(bwi.end(), l.begin(), l.end()); P->ilv.bw_off.push_back((int64_t)bwi.size()); }
         HIP_TRY(P->d_xwork.alloc((size_t)off[P->nsub]));
         HIP_TRY(P->d_xoff.alloc(off.size()));
+        HIP_TRY(P->d_ifw.alloc(std::max<size_t>(1, fwi.size())));
+        HIP_TRY(P->d_ibw.alloc(std::max<size_t>(1, bwi.size())));
+        HIP_TRY(P->d_rptr_off.alloc(rptr_off.size()));
+        HIP_TRY(P->d_rptr.alloc(rptr.size()));
+        HIP_TRY(P->d_rpos.alloc(std::max<size_t>(1, rpos.size())));
+        HIP_TRY(P->d_ubuf.alloc((size_t)P->nrows_total));
         HIP_TRY(hipMemcpyAsync(P->d_xoff.p, off.data(), off.size() * 8, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(P->d_ifw.p, fwi.data(), fwi.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(P->d_ibw.p, bwi.data(), bwi.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(P->d_rptr_off.p, rptr_off.data(), rptr_off.size() * 8, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(P->d_rptr.p, rptr.data(), rptr.size() * 4, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(P->d_rpos.p, rpos.data(), rpos.size() * 4, hipMemcpyHostToDevice, st));
         HIP_TRY(hipStreamSynchronize(st));
+        P->ilv.fw_items = P->d_ifw.p;
+        P->ilv.bw_items = P->d_ibw.p;
+        P->ilv.rptr_off = P->d_rptr_off.p;
+        P->ilv.rptr = P->d_rptr.p;
+        P->ilv.rpos = P->d_rpos.p;
+        P->ilv.ubuf = P->d_ubuf.p;
     }
     hipEvent_t ev[2];
     hipEvent_t* evp = nullptr;
@@ -738,7 +814,7 @@ sc_status_t sc_apply_implicit(sc_plan_t P, const double* p_dev, double* q_dev, v
         HIP_TRY(P->take_events(2, ev));
         evp = ev;
     }
-    HIP_TRY(launch_apply_implicit(P->tables(), P->d_xoff.p, P->d_xwork.p, p_dev, q_dev, P->nsub, st, evp));
+    HIP_TRY(launch_apply_implicit(P->tables(), P->ilv, P->d_xoff.p, P->d_xwork.p, p_dev, q_dev, P->nsub, st, evp));
     if (evp) P->pending.push_back({3, ev[0], ev[1]});
     return SC_OK;
 }
