@@ -576,6 +576,10 @@ __device__ __forceinline__ void syrk_item_f32(
         }
     }
     const int kbeg = ks[0];
+    // a diagonal tile reads one slab pair (sJ aliases sI); a wavefront skips the
+    // k-steps that lie wholly above the first pivot of both its column halves
+    const bool diag = it.I == it.J;
+    const int kw = max(ks[wi], ks[2 + wj]);
 
     v4f acc[4][4];
 #pragma unroll
@@ -597,8 +601,9 @@ __device__ __forceinline__ void syrk_item_f32(
             const int qi = half, qj = 2 + half;
             rI[e] = (k < n && k >= ks[qi]) ? *reinterpret_cast<const float4*>(xs[qi] + (int64_t)(k - ks[qi]) * kTile + c)
                                            : make_float4(0.f, 0.f, 0.f, 0.f);
-            rJ[e] = (k < n && k >= ks[qj]) ? *reinterpret_cast<const float4*>(xs[qj] + (int64_t)(k - ks[qj]) * kTile + c)
-                                           : make_float4(0.f, 0.f, 0.f, 0.f);
+            rJ[e] = (!diag && k < n && k >= ks[qj])
+                        ? *reinterpret_cast<const float4*>(xs[qj] + (int64_t)(k - ks[qj]) * kTile + c)
+                        : make_float4(0.f, 0.f, 0.f, 0.f);
         }
     };
     auto store_step = [&](int buf) {
@@ -608,7 +613,7 @@ __device__ __forceinline__ void syrk_item_f32(
             const int rr = idx >> 5;
             const int cc = 4 * (idx & 31);
             *reinterpret_cast<float4*>(&sI[buf][rr * kSyrkLdF + cc]) = rI[e];
-            *reinterpret_cast<float4*>(&sJ[buf][rr * kSyrkLdF + cc]) = rJ[e];
+            if (!diag) *reinterpret_cast<float4*>(&sJ[buf][rr * kSyrkLdF + cc]) = rJ[e];
         }
     };
 
@@ -618,14 +623,23 @@ __device__ __forceinline__ void syrk_item_f32(
         store_step(0);
     }
     __syncthreads();
-    for (int st = 0; st < nsteps; ++st) {
+    // leading steps wholly above kw: loads only (same barriers as the rest)
+    const int skip = kw >= n ? nsteps : min(nsteps, (kw - kbeg) / kSyrkKCF);
+    int st = 0;
+    for (; st < skip; ++st) {
+        const int buf = st & 1;
+        if (st + 1 < nsteps) load_step(kbeg + (st + 1) * kSyrkKCF);
+        if (st + 1 < nsteps) store_step(buf ^ 1);
+        __syncthreads();
+    }
+    for (; st < nsteps; ++st) {
         const int buf = st & 1;
         if (st + 1 < nsteps) load_step(kbeg + (st + 1) * kSyrkKCF);
         {
 #pragma unroll
             for (int s = 0; s < kSyrkKCF / 4; ++s) {
                 const float* ai = &sI[buf][(4 * s + g) * kSyrkLdF + 64 * wi + j];
-                const float* bj = &sJ[buf][(4 * s + g) * kSyrkLdF + 64 * wj + j];
+                const float* bj = &(diag ? sI : sJ)[buf][(4 * s + g) * kSyrkLdF + 64 * wj + j];
                 float a[4], b[4];
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
