@@ -71,7 +71,7 @@ __device__ __forceinline__ v4f mfma_f32(float a, float b, v4f c) {
 // step 1 stays FP64 (the block rows are widened, solved, rounded back).
 // ---------------------------------------------------------------------------
 constexpr int kChunkBytes = 2 * 16 * 64 * 8;     // two FP64 row tiles of 16 k-slices
-constexpr int kIdxBytes = 32 * 4;                // row indices carried by a chunk
+constexpr int kIdxBytes = 64 * 4;                // row indices carried by a chunk (up to 64)
 constexpr int kBufBytes = kChunkBytes + kIdxBytes;
 constexpr int kTrsmSmem = 2 * kBufBytes;
 
@@ -85,8 +85,8 @@ struct ChunkSrc {
     const char* p;       // always a valid address (the subdomain's factor when bytes == 0)
     int bytes;
     bool has_idx;        // the chunk carries the row indices at ip
-    const int32_t* ip;   // 32 row indices of the pruned chunk gathered next; always a
-                         // valid address (the row array is padded by 32 entries)
+    const int32_t* ip;   // row indices of the pruned chunk gathered next (64 are read);
+                         // always a valid address (the row array is padded by 64 entries)
 };
 
 // Register prefetch of one chunk: four 16-byte pieces per thread, loaded
@@ -100,7 +100,7 @@ __device__ __forceinline__ void chunk_load(uint4& v0, uint4& v1, uint4& v2, uint
     v1 = *reinterpret_cast<const uint4*>(s.p + (e + 4096 < s.bytes ? e + 4096 : 0));
     v2 = *reinterpret_cast<const uint4*>(s.p + (e + 8192 < s.bytes ? e + 8192 : 0));
     v3 = *reinterpret_cast<const uint4*>(s.p + (e + 12288 < s.bytes ? e + 12288 : 0));
-    vi = *reinterpret_cast<const uint4*>(s.ip + 4 * (threadIdx.x & 7));
+    vi = *reinterpret_cast<const uint4*>(s.ip + 4 * (threadIdx.x & 15));
 }
 
 __device__ __forceinline__ void chunk_store(const uint4& v0, const uint4& v1, const uint4& v2, const uint4& v3,
@@ -110,7 +110,7 @@ __device__ __forceinline__ void chunk_store(const uint4& v0, const uint4& v1, co
     if (e + 4096 < s.bytes) *reinterpret_cast<uint4*>(dst + e + 4096) = v1;
     if (e + 8192 < s.bytes) *reinterpret_cast<uint4*>(dst + e + 8192) = v2;
     if (e + 12288 < s.bytes) *reinterpret_cast<uint4*>(dst + e + 12288) = v3;
-    if (s.has_idx && threadIdx.x < 8) *reinterpret_cast<uint4*>(dst + kChunkBytes + 16 * threadIdx.x) = vi;
+    if (s.has_idx && threadIdx.x < 16) *reinterpret_cast<uint4*>(dst + kChunkBytes + 16 * threadIdx.x) = vi;
 }
 
 // Scalar copy of the block descriptor fields the TRSM uses.
@@ -123,17 +123,24 @@ __device__ __forceinline__ BlockLite block_lite(const BlockDev* __restrict__ B, 
     return {B[b].w, B[b].nbelow, B[b].aoff, B[b].linv_off, B[b].rows_off};
 }
 
+// Pruned row tiles per chunk: 16 KB of A tiles, two FP64 or four FP32 row
+// tiles of 16 k-slices.
+template <class TA>
+constexpr int kPruneTiles = sizeof(TA) == 8 ? 2 : 4;
+
 // Chunk c of a block: c < nd are the inverse's row-tile groups, the rest
-// groups of two pruned row tiles (TA = precision of the update's A tiles).
-// The first chunk carries the row indices of pruned chunk 0, pruned chunk p
-// those of pruned chunk p + 1: they are gathered while the chunk is in use.
+// groups of kPruneTiles pruned row tiles (TA = precision of the update's A
+// tiles).  The first chunk carries the row indices of pruned chunk 0, pruned
+// chunk p those of pruned chunk p + 1: they are gathered while the chunk is
+// in use.
 template <class TA>
 __device__ __forceinline__ ChunkSrc chunk_src(const BlockLite& bd, int c, const double* __restrict__ L,
                                               const TA* __restrict__ LA, const int32_t* __restrict__ R) {
     const int nks = (bd.w + 3) >> 2;
     const int nrt_d = (bd.w + 15) >> 4;
     const int nd = nrt_d > 2 ? 2 : 1;
-    const int np = (((bd.nb + 15) >> 4) + 1) >> 1;
+    constexpr int PT = kPruneTiles<TA>;
+    const int np = (((bd.nb + 15) >> 4) + PT - 1) / PT;
     if (c < nd) {
         const int slot0 = c == 0 ? 0 : nrt_d - 2;
         const int nt = nd == 1 ? nrt_d : (c == 0 ? nrt_d - 2 : 2);
@@ -141,9 +148,9 @@ __device__ __forceinline__ ChunkSrc chunk_src(const BlockLite& bd, int c, const 
                 c == 0 && np > 0, R + bd.rows_off};
     }
     const int p = c - nd;
-    const int nt = min(2, ((bd.nb + 15) >> 4) - 2 * p);
-    return {reinterpret_cast<const char*>(LA + bd.aoff + (int64_t)2 * p * nks * 64),
-            nt * nks * 64 * (int)sizeof(TA), p + 1 < np, R + bd.rows_off + 32 * min(p + 1, np - 1)};
+    const int nt = min(PT, ((bd.nb + 15) >> 4) - PT * p);
+    return {reinterpret_cast<const char*>(LA + bd.aoff + (int64_t)PT * p * nks * 64),
+            nt * nks * 64 * (int)sizeof(TA), p + 1 < np, R + bd.rows_off + 16 * PT * min(p + 1, np - 1)};
 }
 
 template <bool MIXED>
@@ -156,6 +163,7 @@ __device__ __forceinline__ void trsm_tile(
 {
     using TX = typename std::conditional<MIXED, float, double>::type;
     using VX = typename std::conditional<MIXED, v4f, v4d>::type;
+    constexpr int PT = kPruneTiles<TX>;          // pruned row tiles per chunk
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int g = lane >> 4;
@@ -189,7 +197,7 @@ __device__ __forceinline__ void trsm_tile(
     BlockLite pbd = bd;
     auto nchunks = [](const BlockLite& x) {
         const int nrt_d = (x.w + 15) >> 4;
-        return (nrt_d > 2 ? 2 : 1) + ((((x.nb + 15) >> 4) + 1) >> 1);
+        return (nrt_d > 2 ? 2 : 1) + (((x.nb + 15) >> 4) + PT - 1) / PT;
     };
     int pnch = nchunks(pbd);
     auto take = [&]() {
@@ -248,20 +256,20 @@ __device__ __forceinline__ void trsm_tile(
         const int nrt_d = (w + 15) >> 4;
         const int nd = nrt_d > 2 ? 2 : 1;
         const int nrt = (nb + 15) >> 4;
-        const int np = (nrt + 1) >> 1;
+        const int np = (nrt + PT - 1) / PT;
         const bool act = b >= my_start;
         const BlockLite bn = block_lite(B, b + 1 < S.nblocks ? b + 1 : b);
 
-        VX accn[2];                              // rows of the next pruned chunk
-        int offn[2][4];
+        VX accn[PT];                             // rows of the next pruned chunk
+        int offn[PT][4];
         auto gather = [&](int p) {               // row indices from the chunk in LDS
             const int32_t* __restrict__ sidx = reinterpret_cast<const int32_t*>(smem + buf * kBufBytes + kChunkBytes);
 #pragma unroll
-            for (int u = 0; u < 2; ++u)
+            for (int u = 0; u < PT; ++u)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int k = 16 * u + (MIXED ? 4 * g + r : 4 * r + g);
-                    offn[u][r] = 32 * p + k < nb ? (sidx[k] - kstart) * kTile + col : -1;
+                    offn[u][r] = 16 * PT * p + k < nb ? (sidx[k] - kstart) * kTile + col : -1;
                     accn[u][r] = offn[u][r] >= 0 ? Xs[offn[u][r]] : TX(0);
                 }
         };
@@ -326,21 +334,23 @@ __device__ __forceinline__ void trsm_tile(
             }
         }
 
-        // ---- 2. X[R_b] -= L[R_b, b] X[b], pruned row tiles 2p, 2p+1
+        // ---- 2. X[R_b] -= L[R_b, b] X[b], pruned row tiles PT p .. PT p + PT - 1
         for (int p = 0; p < np; ++p) {
             step_begin();
             if (act) {
-                VX acc[2] = {accn[0], accn[1]};
-                int off[2][4];
+                VX acc[PT];
+                int off[PT][4];
 #pragma unroll
-                for (int u = 0; u < 2; ++u)
+                for (int u = 0; u < PT; ++u) {
+                    acc[u] = accn[u];
 #pragma unroll
                     for (int r = 0; r < 4; ++r) off[u][r] = offn[u][r];
+                }
                 if (p + 1 < np) gather(p + 1);
                 const TX* __restrict__ sA = reinterpret_cast<const TX*>(smem + buf * kBufBytes);
-                const int nt = min(2, nrt - 2 * p);
+                const int nt = min(PT, nrt - PT * p);
 #pragma unroll
-                for (int u = 0; u < 2; ++u) {
+                for (int u = 0; u < PT; ++u) {
                     if (u < nt) {
 #pragma unroll
                         for (int t = 0; t < 4; ++t)
@@ -355,7 +365,7 @@ __device__ __forceinline__ void trsm_tile(
                     }
                 }
 #pragma unroll
-                for (int u = 0; u < 2; ++u)
+                for (int u = 0; u < PT; ++u)
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
                         if (off[u][r] >= 0) Xs[off[u][r]] = acc[u][r];

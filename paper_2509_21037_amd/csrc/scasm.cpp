@@ -432,7 +432,7 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
         }
     }
     P->nval_total = lv;
-    rows += 32;                            // the TRSM reads whole 32-entry groups of a row list
+    rows += 64;                            // the TRSM reads whole 64-entry groups of a row list
     P->nrows_total = rows;
     P->ncol_total = colo;
     P->X_total = xo;
