@@ -291,11 +291,11 @@ __device__ __forceinline__ double tile_at(const double* __restrict__ At, int nks
     return At[((int64_t)(q >> 4) * nks + (k >> 2)) * 64 + (q & 15) + 16 * (k & 3)];
 }
 
-// Linv[r][k] of a block's inverse diagonal (row tiles stored in TRSM order)
-__device__ __forceinline__ double linv_at(const double* __restrict__ Lv, int nrt_d, int nks, int r, int k) {
+// Linv[r][k], k <= r (or within r's diagonal 16 x 16 tile), of a block's
+// inverse diagonal: lower tiles only, tile (rt, ks) at 64 (2 rt (rt + 1) + ks)
+__device__ __forceinline__ double linv_at(const double* __restrict__ Lv, int r, int k) {
     const int rt = r >> 4;
-    const int slot = nrt_d > 2 ? (rt >= 2 ? rt - 2 : rt + nrt_d - 2) : rt;
-    return Lv[((int64_t)slot * nks + (k >> 2)) * 64 + (r & 15) + 16 * (k & 3)];
+    return Lv[(2 * rt * (rt + 1) + (k >> 2)) * 64 + (r & 15) + 16 * (k & 3)];
 }
 
 __global__ __launch_bounds__(256) void implicit_init(
@@ -357,7 +357,7 @@ __global__ __launch_bounds__(256) void implicit_fwd(
     const int nrt_d = (w + 15) >> 4, nks = (w + 3) >> 2;
     double y = 0.0;
     if (r < w)
-        for (int k = 16 * part; k < min(16 * part + 16, r + 1); ++k) y += linv_at(Lv, nrt_d, nks, r, k) * sx[k];
+        for (int k = 16 * part; k < min(16 * part + 16, r + 1); ++k) y += linv_at(Lv, r, k) * sx[k];
     sp[part][r] = y;
     __syncthreads();
     if (tid < 64) {
@@ -416,7 +416,7 @@ __global__ __launch_bounds__(256) void implicit_bwd(
     const int nrt_d = (w + 15) >> 4;
     double z = 0.0;
     if (r < w)
-        for (int k = max(r, 16 * part); k < min(16 * part + 16, w); ++k) z += linv_at(Lv, nrt_d, nks, k, r) * sv[k];
+        for (int k = max(r, 16 * part); k < min(16 * part + 16, w); ++k) z += linv_at(Lv, k, r) * sv[k];
     sp[part][r] = z;
     __syncthreads();
     if (tid < w) x[bd.row0 + tid] = sp[0][tid] + sp[1][tid] + sp[2][tid] + sp[3][tid];

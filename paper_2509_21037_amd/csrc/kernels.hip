@@ -52,25 +52,25 @@ __device__ __forceinline__ v4f mfma_f32(float a, float b, v4f c) {
 // downwards); a stripe whose first pivot lies further down joins at its own
 // first block.  Per block b:
 //   1. X[b] <- L_bb^{-1} X[b], FP64 MFMA with the inverse of the diagonal
-//      block computed on the host: one pass, or two when the block has more
-//      than 32 rows (rows 32.. first, while rows 0..31 still hold their old
-//      values);
-//   2. the pruned rows below the block, 32 at a time:
+//      block computed on the host (its lower 16 x 4 tiles, one chunk);
+//   2. the pruned rows below the block, 32 at a time (64 in mixed precision):
 //      X[R_b] -= L[R_b, b] X[b] (MFMA, rows gathered and scattered).
-// The factor flows through the workgroup as a stream of chunks (up to two
-// 16-row tiles x 64 columns): while chunk c is used from LDS, chunks c+1 and
-// c+2 are in registers (loaded two steps ahead: one step of latency hiding
-// was measured 23% slower); c+1 is written to the other half of a double
-// buffer at the end of the step; one barrier per chunk, on LDS only (X
-// columns of a stripe are private to its wavefront, so no barrier waits on
-// global memory).  Rows of the next
-// chunk of the same block are gathered before the current chunk's MFMAs
-// (the chunks of one block update disjoint rows); a wavefront reads rows it
-// wrote itself in program order.
+// The factor flows through the workgroup as a stream of chunks (the inverse
+// of a diagonal block, up to 20 KB, or 16 KB of pruned-row tiles): while
+// chunk c is used from LDS, chunks c+1 and c+2 are in registers (loaded two
+// steps ahead: one step of latency hiding was measured 23% slower); c+1 is
+// written to the other half of a double buffer at the end of the step; one
+// barrier per chunk, on LDS only (X columns of a stripe are private to its
+// wavefront, so no barrier waits on global memory).  Rows of the next chunk
+// of the same block are gathered before the current chunk's MFMAs (the
+// chunks of one block update disjoint rows); a wavefront reads rows it wrote
+// itself in program order.
 // Mixed precision: the same with FP32 X and FP32 A tiles / MFMA for step 2;
 // step 1 stays FP64 (the block rows are widened, solved, rounded back).
 // ---------------------------------------------------------------------------
-constexpr int kChunkBytes = 2 * 16 * 64 * 8;     // two FP64 row tiles of 16 k-slices
+// a chunk: the 40 lower tiles of a 64 x 64 diagonal inverse (20 KB), or 16 KB
+// of pruned-row tiles
+constexpr int kChunkBytes = 40 * 64 * 8;
 constexpr int kIdxBytes = 64 * 4;                // row indices carried by a chunk (up to 64)
 constexpr int kBufBytes = kChunkBytes + kIdxBytes;
 constexpr int kTrsmSmem = 2 * kBufBytes;
@@ -89,27 +89,30 @@ struct ChunkSrc {
                          // always a valid address (the row array is padded by 64 entries)
 };
 
-// Register prefetch of one chunk: four 16-byte pieces per thread, loaded
+// Register prefetch of one chunk: five 16-byte pieces per thread, loaded
 // unconditionally (pieces past the chunk re-read its first bytes), plus the
 // 32 row indices (threads 0..7 keep them).  Separate registers, not a struct:
 // the prefetch must stay out of scratch memory.
-__device__ __forceinline__ void chunk_load(uint4& v0, uint4& v1, uint4& v2, uint4& v3, uint4& vi,
+__device__ __forceinline__ void chunk_load(uint4& v0, uint4& v1, uint4& v2, uint4& v3, uint4& v4, uint4& vi,
                                            const ChunkSrc& s) {
     const int e = threadIdx.x * 16;
     v0 = *reinterpret_cast<const uint4*>(s.p + (e < s.bytes ? e : 0));
     v1 = *reinterpret_cast<const uint4*>(s.p + (e + 4096 < s.bytes ? e + 4096 : 0));
     v2 = *reinterpret_cast<const uint4*>(s.p + (e + 8192 < s.bytes ? e + 8192 : 0));
     v3 = *reinterpret_cast<const uint4*>(s.p + (e + 12288 < s.bytes ? e + 12288 : 0));
+    v4 = *reinterpret_cast<const uint4*>(s.p + (e + 16384 < s.bytes ? e + 16384 : 0));
     vi = *reinterpret_cast<const uint4*>(s.ip + 4 * (threadIdx.x & 15));
 }
 
 __device__ __forceinline__ void chunk_store(const uint4& v0, const uint4& v1, const uint4& v2, const uint4& v3,
-                                            const uint4& vi, char* __restrict__ dst, const ChunkSrc& s) {
+                                            const uint4& v4, const uint4& vi, char* __restrict__ dst,
+                                            const ChunkSrc& s) {
     const int e = threadIdx.x * 16;
     if (e < s.bytes) *reinterpret_cast<uint4*>(dst + e) = v0;
     if (e + 4096 < s.bytes) *reinterpret_cast<uint4*>(dst + e + 4096) = v1;
     if (e + 8192 < s.bytes) *reinterpret_cast<uint4*>(dst + e + 8192) = v2;
     if (e + 12288 < s.bytes) *reinterpret_cast<uint4*>(dst + e + 12288) = v3;
+    if (e + 16384 < s.bytes) *reinterpret_cast<uint4*>(dst + e + 16384) = v4;
     if (s.has_idx && threadIdx.x < 16) *reinterpret_cast<uint4*>(dst + kChunkBytes + 16 * threadIdx.x) = vi;
 }
 
@@ -128,9 +131,9 @@ __device__ __forceinline__ BlockLite block_lite(const BlockDev* __restrict__ B, 
 template <class TA>
 constexpr int kPruneTiles = sizeof(TA) == 8 ? 2 : 4;
 
-// Chunk c of a block: c < nd are the inverse's row-tile groups, the rest
-// groups of kPruneTiles pruned row tiles (TA = precision of the update's A
-// tiles).  The first chunk carries the row indices of pruned chunk 0, pruned
+// Chunk c of a block: c = 0 is the inverse of the diagonal block (its lower
+// tiles), the rest groups of kPruneTiles pruned row tiles (TA = precision of
+// the update's A tiles).  The first chunk carries the row indices of pruned chunk 0, pruned
 // chunk p those of pruned chunk p + 1: they are gathered while the chunk is
 // in use.
 template <class TA>
@@ -138,16 +141,12 @@ __device__ __forceinline__ ChunkSrc chunk_src(const BlockLite& bd, int c, const 
                                               const TA* __restrict__ LA, const int32_t* __restrict__ R) {
     const int nks = (bd.w + 3) >> 2;
     const int nrt_d = (bd.w + 15) >> 4;
-    const int nd = nrt_d > 2 ? 2 : 1;
     constexpr int PT = kPruneTiles<TA>;
     const int np = (((bd.nb + 15) >> 4) + PT - 1) / PT;
-    if (c < nd) {
-        const int slot0 = c == 0 ? 0 : nrt_d - 2;
-        const int nt = nd == 1 ? nrt_d : (c == 0 ? nrt_d - 2 : 2);
-        return {reinterpret_cast<const char*>(L + bd.linv_off + (int64_t)slot0 * nks * 64), nt * nks * 64 * 8,
-                c == 0 && np > 0, R + bd.rows_off};
-    }
-    const int p = c - nd;
+    if (c == 0)
+        return {reinterpret_cast<const char*>(L + bd.linv_off), (2 * (nrt_d - 1) * nrt_d + nks) * 64 * 8, np > 0,
+                R + bd.rows_off};
+    const int p = c - 1;
     const int nt = min(PT, ((bd.nb + 15) >> 4) - PT * p);
     return {reinterpret_cast<const char*>(LA + bd.aoff + (int64_t)PT * p * nks * 64),
             nt * nks * 64 * (int)sizeof(TA), p + 1 < np, R + bd.rows_off + 16 * PT * min(p + 1, np - 1)};
@@ -195,10 +194,7 @@ __device__ __forceinline__ void trsm_tile(
     // into registers at the start of step s, chunk s+1 goes to LDS at its end
     int pb = first_block, pc = 0;
     BlockLite pbd = bd;
-    auto nchunks = [](const BlockLite& x) {
-        const int nrt_d = (x.w + 15) >> 4;
-        return (nrt_d > 2 ? 2 : 1) + (((x.nb + 15) >> 4) + PT - 1) / PT;
-    };
+    auto nchunks = [](const BlockLite& x) { return 1 + (((x.nb + 15) >> 4) + PT - 1) / PT; };
     int pnch = nchunks(pbd);
     auto take = [&]() {
         ChunkSrc c{reinterpret_cast<const char*>(L), 0, false, R};
@@ -217,17 +213,17 @@ __device__ __forceinline__ void trsm_tile(
     };
     // a*: chunk s+1 (stored to LDS at the end of step s), b*: chunk s+2;
     // sa_* / sb_* describe them
-    uint4 a0, a1, a2, a3, ai, b0, b1, b2, b3, bi;
+    uint4 a0, a1, a2, a3, a4, ai, b0, b1, b2, b3, b4, bi;
     {
         const ChunkSrc c0 = take();
-        chunk_load(a0, a1, a2, a3, ai, c0);
-        chunk_store(a0, a1, a2, a3, ai, smem, c0);
+        chunk_load(a0, a1, a2, a3, a4, ai, c0);
+        chunk_store(a0, a1, a2, a3, a4, ai, smem, c0);
     }
     const char* sa_p; int sa_bytes; bool sa_idx; const int32_t* sa_ip;
     const char* sb_p = reinterpret_cast<const char*>(L); int sb_bytes = 0; bool sb_idx = false; const int32_t* sb_ip = R;
     {
         const ChunkSrc c1 = take();
-        chunk_load(a0, a1, a2, a3, ai, c1);
+        chunk_load(a0, a1, a2, a3, a4, ai, c1);
         sa_p = c1.p; sa_bytes = c1.bytes; sa_idx = c1.has_idx; sa_ip = c1.ip;
     }
     lds_barrier();
@@ -235,17 +231,17 @@ __device__ __forceinline__ void trsm_tile(
 
     auto step_begin = [&]() {
         const ChunkSrc cb = take();
-        chunk_load(b0, b1, b2, b3, bi, cb);
+        chunk_load(b0, b1, b2, b3, b4, bi, cb);
         sb_p = cb.p; sb_bytes = cb.bytes; sb_idx = cb.has_idx; sb_ip = cb.ip;
     };
     auto step_end = [&]() {
         if (sa_bytes > 0) {
             const ChunkSrc ca{sa_p, sa_bytes, sa_idx, sa_ip};
-            chunk_store(a0, a1, a2, a3, ai, smem + (buf ^ 1) * kBufBytes, ca);
+            chunk_store(a0, a1, a2, a3, a4, ai, smem + (buf ^ 1) * kBufBytes, ca);
             lds_barrier();
             buf ^= 1;
         }
-        a0 = b0; a1 = b1; a2 = b2; a3 = b3; ai = bi;
+        a0 = b0; a1 = b1; a2 = b2; a3 = b3; a4 = b4; ai = bi;
         sa_p = sb_p; sa_bytes = sb_bytes; sa_idx = sb_idx; sa_ip = sb_ip;
     };
     for (int b = first_block; b < S.nblocks; ++b) {
@@ -254,7 +250,6 @@ __device__ __forceinline__ void trsm_tile(
         const int nb = bd.nb;
         const int nks = (w + 3) >> 2;
         const int nrt_d = (w + 15) >> 4;
-        const int nd = nrt_d > 2 ? 2 : 1;
         const int nrt = (nb + 15) >> 4;
         const int np = (nrt + PT - 1) / PT;
         const bool act = b >= my_start;
@@ -289,37 +284,29 @@ __device__ __forceinline__ void trsm_tile(
                     }
                 if (np > 0) gather(0);
             }
-            for (int c = 0; c < nd; ++c) {
-                step_begin();
-                if (act) {
-                    const double* __restrict__ sA = reinterpret_cast<const double*>(smem + buf * kBufBytes);
-                    const int t0 = (nd == 2 && c == 0) ? 2 : 0;
-                    const int nt = nd == 1 ? nrt_d : (c == 0 ? nrt_d - 2 : 2);
-                    v4d tmp[2];
+            step_begin();
+            if (act) {
+                // lower tiles only: row tile u needs k-slices of row tiles t <= u
+                const double* __restrict__ sA = reinterpret_cast<const double*>(smem + buf * kBufBytes);
+                v4d tmp[4];
 #pragma unroll
-                    for (int u = 0; u < 2; ++u) {
-                        tmp[u] = v4d{0.0, 0.0, 0.0, 0.0};
-                        if (u < nt) {
+                for (int u = 0; u < 4; ++u) {
+                    tmp[u] = v4d{0.0, 0.0, 0.0, 0.0};
+                    if (u < nrt_d) {
 #pragma unroll
-                            for (int t = 0; t < 4; ++t)
+                        for (int t = 0; t <= u; ++t)
 #pragma unroll
-                                for (int s = 0; s < 4; ++s) {
-                                    const int ks = 4 * t + s;
-                                    if (ks < nks && t <= t0 + u)
-                                        tmp[u] = mfma_f64(sA[(u * nks + ks) * 64 + lane], xr[t][s], tmp[u]);
-                                }
-                        }
-                    }
-                    if (t0 == 0) {
-                        xr[0] = tmp[0];
-                        if (nt > 1) xr[1] = tmp[1];
-                    } else {
-                        xr[2] = tmp[0];
-                        if (nt > 1) xr[3] = tmp[1];
+                            for (int s = 0; s < 4; ++s) {
+                                const int ks = 4 * t + s;
+                                if (ks < nks) tmp[u] = mfma_f64(sA[(2 * u * (u + 1) + ks) * 64 + lane], xr[t][s], tmp[u]);
+                            }
                     }
                 }
-                step_end();
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (u < nrt_d) xr[u] = tmp[u];
             }
+            step_end();
             if (act) {
 #pragma unroll
                 for (int t = 0; t < 4; ++t)

@@ -512,7 +512,10 @@ std::string build_plan(const SubdomainInput& in, const PlanOptions& opt, SubPlan
             voff += (int64_t)d.w * d.w;
             voff = (voff + 7) / 8 * 8;                  // 64-byte aligned tiles
             d.linv_off = voff;
-            voff += (int64_t)((d.w + 15) / 16) * ((d.w + 3) / 4) * 64;
+            {
+                const int64_t nrt_d = (d.w + 15) / 16, nks = (d.w + 3) / 4;
+                voff += (2 * (nrt_d - 1) * nrt_d + nks) * 64;   // lower tiles only
+            }
             d.aoff = voff;
             voff += (int64_t)((d.nbelow + 15) / 16) * ((d.w + 3) / 4) * 64;
             P.brows.insert(P.brows.end(), rows.begin(), rows.end());
@@ -625,7 +628,6 @@ void repack_blocks(const SubPlan& P, const double* vals, double* bvals) {
         // inverse of the diagonal triangle, column by column (forward
         // substitution on the unit vectors, accumulated in long double)
         const int32_t w = b.w;
-        const int32_t nrt_d = (w + 15) / 16;
         double* li = bvals + b.linv_off;
         std::vector<long double> z(w);
         for (int32_t c = 0; c < w; ++c) {
@@ -633,9 +635,8 @@ void repack_blocks(const SubPlan& P, const double* vals, double* bvals) {
                 long double acc = (i == c) ? 1.0L : 0.0L;
                 for (int32_t k = c; k < i; ++k) acc -= (long double)diag[(size_t)k * w + i] * z[k];
                 z[i] = acc / (long double)diag[(size_t)i * w + i];
-                const int32_t rt = i / 16;
-                const int32_t slot = nrt_d > 2 ? (rt >= 2 ? rt - 2 : rt + nrt_d - 2) : rt;
-                li[((int64_t)slot * nks + c / 4) * 64 + (i % 16) + 16 * (c % 4)] = (double)z[i];
+                const int64_t rt = i / 16;
+                li[(2 * rt * (rt + 1) + c / 4) * 64 + (i % 16) + 16 * (c % 4)] = (double)z[i];
             }
         }
     }

@@ -50,10 +50,9 @@ struct PlanOptions {
 //     (row 16 rt + i, column 4 ks + k) at position i + 16 k, nks = ceil(w/4),
 //     zero padded;
 //   * the inverse of the diagonal triangle (lower triangular) at linv_off, in
-//     the same tile format with nrt_d = ceil(w/16) row tiles, stored in the
-//     order the TRSM consumes them: when nrt_d > 2 the row tiles [2, nrt_d)
-//     first, then [0, 2) (so that X rows 32.. are replaced before the rows
-//     0..31 they depend on); otherwise row tiles [0, nrt_d).
+//     the same tile format, only the tiles on or below the diagonal: row
+//     tile rt holds k-slices ks < min(nks, 4 (rt + 1)), tile (rt, ks) at
+//     linv_off + 64 (2 rt (rt + 1) + ks).
 struct BlockDesc {
     int32_t row0;
     int32_t w;
