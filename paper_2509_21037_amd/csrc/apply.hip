@@ -320,16 +320,28 @@ __global__ __launch_bounds__(256) void implicit_init(
     }
 }
 
-// One block step per workgroup of 256 threads: thread (part, r) = (tid / 64,
-// tid % 64) works on row / column r and a quarter of each sum; partial sums
-// meet in LDS in a fixed order.
-__global__ __launch_bounds__(256) void implicit_fwd(
+// One block step per workgroup of kImplThreads threads: thread (part, r) =
+// (tid / 64, tid % 64) works on row / column r and a 1/kImplParts share of
+// each sum; partial sums meet in LDS in a fixed order.  The blocks of a level
+// are few (the chain of one subdomain each), so each step spreads its short
+// dependent sums over many threads.
+constexpr int kImplThreads = 1024;
+constexpr int kImplParts = kImplThreads / 64;
+
+__device__ __forceinline__ double sum_parts(const double (*sp)[64], int r) {
+    double v = 0.0;
+#pragma unroll
+    for (int k = 0; k < kImplParts; ++k) v += sp[k][r];
+    return v;
+}
+
+__global__ __launch_bounds__(kImplThreads) void implicit_fwd(
     const SubDev* __restrict__ subs, const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows,
     const double* __restrict__ lval, const int64_t* __restrict__ rptr_off, const int32_t* __restrict__ rptr,
     const int32_t* __restrict__ rpos, const int2* __restrict__ items, const int64_t* __restrict__ xoff,
     double* __restrict__ xwork, double* __restrict__ ubuf)
 {
-    __shared__ double sp[4][64];
+    __shared__ double sp[kImplParts][64];
     __shared__ double sx[64];
     const int2 it = items[blockIdx.x];
     const SubDev S = subs[it.x];
@@ -345,44 +357,49 @@ __global__ __launch_bounds__(256) void implicit_fwd(
     double v = 0.0;
     if (r < w) {
         const int row = bd.row0 + r;
-        for (int e = rp[row] + part; e < rp[row + 1]; e += 4) v -= ubuf[rpos[e]];
+        for (int e = rp[row] + part; e < rp[row + 1]; e += kImplParts) v -= ubuf[rpos[e]];
         if (part == 0) v += x[row];
     }
     sp[part][r] = v;
     __syncthreads();
-    if (tid < 64) sx[tid] = sp[0][tid] + sp[1][tid] + sp[2][tid] + sp[3][tid];
+    if (tid < 64) sx[tid] = sum_parts(sp, tid);
     __syncthreads();
-    // y_b = L_bb^{-1} x_b: k split in quarters
+    // y_b = L_bb^{-1} x_b: k split in kImplParts ranges of 4
     const double* __restrict__ Lv = L + bd.linv_off;
-    const int nrt_d = (w + 15) >> 4, nks = (w + 3) >> 2;
     double y = 0.0;
     if (r < w)
-        for (int k = 16 * part; k < min(16 * part + 16, r + 1); ++k) y += linv_at(Lv, r, k) * sx[k];
+        for (int k = 4 * part; k < min(4 * part + 4, r + 1); ++k) y += linv_at(Lv, r, k) * sx[k];
     sp[part][r] = y;
     __syncthreads();
     if (tid < 64) {
-        const double yb = sp[0][tid] + sp[1][tid] + sp[2][tid] + sp[3][tid];
+        const double yb = sum_parts(sp, tid);
         sx[tid] = tid < w ? yb : 0.0;
         if (tid < w) x[bd.row0 + tid] = yb;
     }
     __syncthreads();
-    // u_b = L[R_b, b] y_b, one pruned row per thread
+    // u_b = L[R_b, b] y_b: four threads per pruned row (16 k each), adjacent lanes
     const double* __restrict__ At = L + bd.aoff;
+    const int nks = (w + 3) >> 2;
     double* __restrict__ u = ubuf + S.rows_off + bd.rows_off;
-    for (int q = tid; q < bd.nbelow; q += 256) {
+    const int kq = tid & 3;
+    for (int q0 = 0; q0 < bd.nbelow; q0 += kImplThreads / 4) {
+        const int q = q0 + (tid >> 2);
         double t = 0.0;
-        for (int k = 0; k < w; ++k) t += tile_at(At, nks, q, k) * sx[k];
-        u[q] = t;
+        if (q < bd.nbelow)
+            for (int k = 16 * kq; k < min(16 * kq + 16, w); ++k) t += tile_at(At, nks, q, k) * sx[k];
+        t += __shfl_xor(t, 1, 64);
+        t += __shfl_xor(t, 2, 64);
+        if (q < bd.nbelow && kq == 0) u[q] = t;
     }
 }
 
-__global__ __launch_bounds__(256) void implicit_bwd(
+__global__ __launch_bounds__(kImplThreads) void implicit_bwd(
     const SubDev* __restrict__ subs, const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows,
     const double* __restrict__ lval, const int2* __restrict__ items, const int64_t* __restrict__ xoff,
     double* __restrict__ xwork)
 {
-    __shared__ double sp[4][64];
-    __shared__ double sz[256];
+    __shared__ double sp[kImplParts][64];
+    __shared__ double sz[kImplThreads];
     __shared__ double sv[64];
     const int2 it = items[blockIdx.x];
     const SubDev S = subs[it.x];
@@ -395,31 +412,30 @@ __global__ __launch_bounds__(256) void implicit_bwd(
     const int part = tid >> 6;
     const int w = bd.w, nb = bd.nbelow, nks = (w + 3) >> 2;
     const double* __restrict__ At = L + bd.aoff;
-    // y_b - L[R_b, b]^T z[R_b]: pruned rows in groups of 256, each quarter of
-    // the threads takes every fourth row of a group
+    // y_b - L[R_b, b]^T z[R_b]: pruned rows in groups of kImplThreads, part p
+    // of the threads takes rows p, p + kImplParts, ... of a group
     double v = 0.0;
-    for (int c0 = 0; c0 < nb; c0 += 256) {
+    for (int c0 = 0; c0 < nb; c0 += kImplThreads) {
         __syncthreads();
         sz[tid] = c0 + tid < nb ? x[rw[c0 + tid]] : 0.0;   // z of the pruned rows: final
         __syncthreads();
-        const int cn = min(256, nb - c0);
+        const int cn = min(kImplThreads, nb - c0);
         if (r < w)
-            for (int qq = part; qq < cn; qq += 4) v -= tile_at(At, nks, c0 + qq, r) * sz[qq];
+            for (int qq = part; qq < cn; qq += kImplParts) v -= tile_at(At, nks, c0 + qq, r) * sz[qq];
     }
     if (part == 0 && r < w) v += x[bd.row0 + r];
     sp[part][r] = v;
     __syncthreads();
-    if (tid < 64) sv[tid] = tid < w ? sp[0][tid] + sp[1][tid] + sp[2][tid] + sp[3][tid] : 0.0;
+    if (tid < 64) sv[tid] = tid < w ? sum_parts(sp, tid) : 0.0;
     __syncthreads();
-    // z_b = L_bb^{-T} v: k split in quarters
+    // z_b = L_bb^{-T} v: k split in kImplParts ranges of 4
     const double* __restrict__ Lv = L + bd.linv_off;
-    const int nrt_d = (w + 15) >> 4;
     double z = 0.0;
     if (r < w)
-        for (int k = max(r, 16 * part); k < min(16 * part + 16, w); ++k) z += linv_at(Lv, k, r) * sv[k];
+        for (int k = max(r, 4 * part); k < min(4 * part + 4, w); ++k) z += linv_at(Lv, k, r) * sv[k];
     sp[part][r] = z;
     __syncthreads();
-    if (tid < w) x[bd.row0 + tid] = sp[0][tid] + sp[1][tid] + sp[2][tid] + sp[3][tid];
+    if (tid < w) x[bd.row0 + tid] = sum_parts(sp, tid);
 }
 
 __global__ __launch_bounds__(256) void implicit_gather(
@@ -444,14 +460,14 @@ hipError_t launch_apply_implicit(const DevTables& t, const ImplicitLevels& lv, c
         if ((e = hipGetLastError()) != hipSuccess) return e;
         for (size_t l = 0; l + 1 < lv.fw_off.size(); ++l) {
             const int64_t cnt = lv.fw_off[l + 1] - lv.fw_off[l];
-            hipLaunchKernelGGL(implicit_fwd, dim3((unsigned)cnt), dim3(256), 0, stream, t.subs, t.blocks, t.rows,
+            hipLaunchKernelGGL(implicit_fwd, dim3((unsigned)cnt), dim3(kImplThreads), 0, stream, t.subs, t.blocks, t.rows,
                                t.lval, lv.rptr_off, lv.rptr, lv.rpos, lv.fw_items + lv.fw_off[l], xoff, xwork,
                                lv.ubuf);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         for (size_t l = 0; l + 1 < lv.bw_off.size(); ++l) {
             const int64_t cnt = lv.bw_off[l + 1] - lv.bw_off[l];
-            hipLaunchKernelGGL(implicit_bwd, dim3((unsigned)cnt), dim3(256), 0, stream, t.subs, t.blocks, t.rows,
+            hipLaunchKernelGGL(implicit_bwd, dim3((unsigned)cnt), dim3(kImplThreads), 0, stream, t.subs, t.blocks, t.rows,
                                t.lval, lv.bw_items + lv.bw_off[l], xoff, xwork);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
