@@ -19,8 +19,10 @@ Prints ONE JSON line on stdout (progress goes to stderr):
   value         subdomains/s of the FP64 assembly over the K timed steps
                 (wall clock, synchronised)
   useful_gflops staircase TRSM + SYRK flop count / time
-  mixed         the same assembly in mixed precision, with its error vs the
-                oracle on sampled subdomains
+  mixed         the same assembly in mixed precision (its difference to the
+                FP64 GPU result on kept subdomains)
+  relF_*        errors against the oracle, computed inside the cpu_baseline
+                leg on the subdomains it runs (GPU F kept from both plans)
   roofline      dominant kernel of the FP64 assembly: useful flops per launch /
                 mean launch duration (HIP events on the launch stream), against
                 the chip's published FP64 matrix peak
@@ -113,48 +115,70 @@ def time_apply(torch, plan, which, iters=20):
     return 1e3 * el / iters, kt[key][0] / max(1, kt[key][1])
 
 
-def sampled_error(plan, subs, picks, nsel=192):
+def sample_ids(subs, k=8):
+    """Subdomains whose GPU F is kept for the error check of the cpu_baseline
+    leg (the leg runs the oracle on subdomains 0, 1, ... in order)."""
+    return list(range(min(k, len(subs))))
+
+
+def sample_cols(s):
+    """Column subset the cpu_baseline leg uses for subdomains with n > 3000."""
     import numpy as np
-    import oracle
-    errs = []
-    for i in picks:
-        s = subs[i]
+    return np.arange(0, s.m, max(1, s.m // 256))[:256]
+
+
+def keep_F(plan, subs, ids):
+    """Host copies of F (or F[S, S] for the large subdomains) for `ids`."""
+    import numpy as np
+    out = {}
+    for i in ids:
         F = plan.get_F(i)
-        if s.n <= 3000:
-            errs.append(oracle.relF(F, oracle.schur(s)))
-        else:
-            sel = np.sort(np.random.default_rng(i).choice(s.m, size=min(nsel, s.m), replace=False))
-            errs.append(oracle.relF(F[np.ix_(sel, sel)], oracle.schur(s, sel=sel)))
-    return errs
+        if subs[i].n > 3000:
+            sel = sample_cols(subs[i])
+            F = F[np.ix_(sel, sel)]
+        out[i] = F
+    return out
 
 
-def cpu_baseline(subs, seconds):
+def rel_diff(a, b):
+    import numpy as np
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def cpu_baseline(subs, seconds, kept=None):
     """The oracle (long double, as it stands) on subdomains 0, 1, ... until
-    `seconds` have elapsed."""
+    `seconds` have elapsed; where a GPU result was kept (`kept`: precision ->
+    {subdomain: F}), its relative Frobenius error against the oracle's F."""
     import numpy as np
     import oracle
+    kept = kept or {}
     nthreads = max(1, min(16, os.cpu_count() or 1))
+    errs = {k: [] for k in kept}
     t0 = time.perf_counter()
     done = 0
     big = subs[0].n > 3000
     while done < len(subs):
         s = subs[done]
-        if big:
-            sel = np.arange(0, s.m, max(1, s.m // 256))[:256]
-            oracle.schur(s, sel=sel, prec="ld", nthreads=nthreads)
+        if s.n > 3000:
+            F = oracle.schur(s, sel=sample_cols(s), prec="ld", nthreads=nthreads)
         else:
-            oracle.schur(s, prec="ld", nthreads=nthreads)
+            F = oracle.schur(s, prec="ld", nthreads=nthreads)
+        for k, fk in kept.items():
+            if done in fk:
+                errs[k].append(oracle.relF(fk[done], F))
         done += 1
         if time.perf_counter() - t0 >= seconds:
             break
     el = time.perf_counter() - t0
     if big:
-        return {"value": None, "unit": "subdomains/s", "cores": nthreads, "kind": "oracle",
-                "sample": f"{done} subdomains, 256-column subsets only, {el:.1f} s "
-                          f"({el / done:.2f} s per 256-column subset)"}
-    return {"value": done / el, "unit": "subdomains/s", "cores": nthreads, "kind": "oracle",
-            "sample": f"first {done} subdomains of the batch, long-double oracle (Cholesky in natural "
-                      f"order, full forward substitution, Y^T Y), {el:.1f} s"}
+        out = {"value": None, "unit": "subdomains/s", "cores": nthreads, "kind": "oracle",
+               "sample": f"{done} subdomains, 256-column subsets for n > 3000, {el:.1f} s "
+                         f"({el / done:.2f} s per subdomain)"}
+    else:
+        out = {"value": done / el, "unit": "subdomains/s", "cores": nthreads, "kind": "oracle",
+               "sample": f"first {done} subdomains of the batch, long-double oracle (Cholesky in natural "
+                         f"order, full forward substitution, Y^T Y; 256-column subsets for n > 3000), {el:.1f} s"}
+    return out, errs
 
 
 def main():
@@ -177,6 +201,8 @@ def main():
                     help="TRSM and SYRK of successive subdomain groups overlapped on two streams, or two launches")
     ap.add_argument("--compare-assembly", action="store_true",
                     help="also time the FP64 assembly in the other mode (overlap / separate)")
+    ap.add_argument("--latency", action="store_true",
+                    help="also time one 16 x 16 Q1 single-subdomain assembly (median of 1000 calls)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain device copy of 2 GiB first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -203,7 +229,7 @@ def main():
     t0 = time.perf_counter()
     subs = scgen.config_subdomains(cfg)
     log(f"bench: generated {len(subs)} subdomains in {time.perf_counter() - t0:.1f}s")
-    picks = sorted({0, len(subs) // 2, len(subs) - 1})
+    ids = sample_ids(subs)
     use_graph = args.graph == "on" or (args.graph == "auto" and cfg != 2)
     tune = None
     if args.autotune == "on" or (args.autotune == "auto" and cfg != 2 and not args.panel_width):
@@ -218,7 +244,8 @@ def main():
     plan = P.Plan(subs, panel_width=args.panel_width, use_graph=use_graph, assembly=args.assembly)
     plan.factor()
     torch.cuda.synchronize()
-    log(f"bench: FP64 plan + host factorisation + upload in {time.perf_counter() - t0:.1f}s")
+    prep_s = time.perf_counter() - t0
+    log(f"bench: FP64 plan + host factorisation + upload in {prep_s:.1f}s (not in the timed region)")
     st = plan.stats()
     ms_per_step, kms = time_assembly(torch, plan, args.steps, args.warmup, use_graph)
     log(f"bench: FP64 {ms_per_step:.3f} ms/step, kernels {kms}")
@@ -231,8 +258,7 @@ def main():
                 "traffic": measured_traffic(args.workload, "fp64", dom),
                 "kernel_ms": kms,
                 "kernel_tflops": {k: flops[k] / (kms[k] * 1e-3) / 1e12 for k in kms}}
-    errs64 = sampled_error(plan, subs, picks)
-    log(f"bench: FP64 sampled relF {errs64}")
+    kept = {"fp64": keep_F(plan, subs, ids)}
     _, apply64 = time_apply(torch, plan, "explicit")
     # the apply reads the stored F: lower 128 x 128 tiles in sorted column order
     f_bytes64 = sum((t := (s.m + 127) // 128) * (t + 1) // 2 * 128 * 128 for s in subs) * 8
@@ -257,6 +283,24 @@ def main():
         plan_o.factor()
         orig, _ = time_assembly(torch, plan_o, max(1, args.steps // 2), 1)
         plan_o.destroy()
+    # latency of one small assembly (16 x 16 Q1 square, m = 64): median of 1000
+    lat1 = None
+    if args.latency:
+        sub1 = scgen.config_subdomains(1)
+        plan1 = P.Plan(sub1)
+        plan1.factor()
+        for _ in range(20):
+            plan1.assemble()
+        torch.cuda.synchronize()
+        lt = []
+        for _ in range(1000):
+            t1 = time.perf_counter()
+            plan1.assemble()
+            torch.cuda.synchronize()
+            lt.append(time.perf_counter() - t1)
+        lat1 = 1e6 * float(np.median(lt))
+        plan1.destroy()
+        log(f"bench: 16x16 Q1 single-subdomain assembly latency {lat1:.1f} us (median of 1000)")
     other = None
     if args.compare_assembly:
         alt = "separate" if args.assembly == "overlap" else "overlap"
@@ -277,12 +321,13 @@ def main():
         plan_m.factor()
         ms_m, kms_m = time_assembly(torch, plan_m, args.steps, args.warmup, use_graph)
         log(f"bench: mixed {ms_m:.3f} ms/step, kernels {kms_m}")
-        errs_m = sampled_error(plan_m, subs, picks)
+        kept["mixed"] = keep_F(plan_m, subs, ids)
         _, apply32 = time_apply(torch, plan_m, "explicit")
         mixed = {"ms_per_step": ms_m, "subdomains_per_s": len(subs) / (ms_m * 1e-3),
                  "useful_gflops": useful / (ms_m * 1e-3) / 1e9, "kernel_ms": kms_m,
                  "kernel_tflops": {k: flops[k] / (kms_m[k] * 1e-3) / 1e12 for k in kms_m},
-                 "relF_max_sampled": max(errs_m), "relF_samples": len(errs_m)}
+                 "frac_of_fp32_mfma_peak": useful / (ms_m * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"],
+                 "relF_vs_fp64_gpu_max": max(rel_diff(kept["mixed"][i], kept["fp64"][i]) for i in ids)}
         extra["explicit_fp32F_ms"] = apply32
         extra["explicit_fp32F_GBps"] = f_bytes64 / 2 / (apply32 * 1e-3) / 1e9
         if args.pcpg:
@@ -300,9 +345,18 @@ def main():
                 extra[f"amortization_iters_{name}"] = (t_asm / gain) if gain > 0 else None
         plan_m.destroy()
 
-    cpu = None if args.no_cpu_baseline else cpu_baseline(subs, args.cpu_seconds)
+    cpu, errs = (None, {}) if args.no_cpu_baseline else cpu_baseline(subs, args.cpu_seconds, kept)
     if cpu:
         log(f"bench: cpu baseline {cpu}")
+    import numpy as np
+
+    def err_stats(e):
+        return {"relF_max_sampled": max(e) if e else None,
+                "relF_median_sampled": float(np.median(e)) if e else None, "relF_samples": len(e)}
+    if mixed is not None:
+        mixed.update(err_stats(errs.get("mixed", [])))
+        log(f"bench: mixed relF vs oracle {errs.get('mixed')}")
+    log(f"bench: FP64 relF vs oracle {errs.get('fp64')}")
     s0 = subs[0]
     out = {
         "metric": METRIC,
@@ -324,8 +378,11 @@ def main():
         "autotune": tune,
         "useful_gflops": useful / (ms_per_step * 1e-3) / 1e9,
         "useful_gflop_per_step": useful / 1e9,
-        "relF_max_sampled": max(errs64),
-        "relF_samples": len(errs64),
+        **err_stats(errs.get("fp64", [])),
+        "relF_source": "cpu_baseline leg: long-double oracle on its sample of subdomains (256-column "
+                       "subsets for n > 3000) against the kept GPU F",
+        "prep_s": prep_s,
+        "latency_config1_us": lat1,
         "orig_ms_per_step": orig,
         "other_assembly": other,
         "mixed": mixed,
