@@ -2,7 +2,7 @@
 """Benchmark of the Schur-complement assembly on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload heat|elast|large]
-                    [--pcpg ITERS] [--no-mixed] [--no-cpu-baseline] [--compare-orig]
+                    [--pcpg ITERS] [--no-mixed] [--no-cpu-baseline] [--compare-orig] [--compare-reach]
 
 A step is one sc_assemble over the whole batch: staircase TRSM X = L^{-1} P B^T
 and staircase SYRK F = X^T X with the permutation back, for every subdomain.
@@ -192,6 +192,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--pcpg", type=int, default=0, help="PCPG iterations on the FP64 and the mixed F")
     ap.add_argument("--compare-orig", action="store_true", help="also time the assembly without the staircase")
+    ap.add_argument("--compare-reach", action="store_true",
+                    help="also time the FP64 assembly with the TRSM sweeping every block after the first pivot")
     ap.add_argument("--panel-width", type=int, default=0, help="GPU factor block width (0 = library default)")
     ap.add_argument("--autotune", choices=("auto", "on", "off"), default="auto",
                     help="pick the factor block width with sc_autotune (auto: on for the elasticity batches)")
@@ -283,6 +285,13 @@ def main():
         plan_o.factor()
         orig, _ = time_assembly(torch, plan_o, max(1, args.steps // 2), 1)
         plan_o.destroy()
+    noreach = None
+    if args.compare_reach:
+        plan_r = P.Plan(subs, reach=False, panel_width=args.panel_width)
+        plan_r.factor()
+        noreach, kms_r = time_assembly(torch, plan_r, max(1, args.steps // 2), 1)
+        plan_r.destroy()
+        log(f"bench: FP64 without the reach {noreach:.3f} ms/step, kernels {kms_r}")
     # latency of one small assembly (16 x 16 Q1 square, m = 64): median of 1000
     lat1 = None
     if args.latency:
@@ -373,7 +382,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": scgen.CONFIG_NAMES[cfg], "subdomains": len(subs),
                    "n": s0.n if cfg != 3 else "1029..14739", "m": s0.m if cfg != 3 else "654..4614",
-                   "precision": "fp64", "staircase": True, "panel_width": args.panel_width or 64,
+                   "precision": "fp64", "staircase": True, "reach": True, "panel_width": args.panel_width or 64,
                    "graph": use_graph, "assembly": args.assembly},
         "autotune": tune,
         "useful_gflops": useful / (ms_per_step * 1e-3) / 1e9,
@@ -384,6 +393,7 @@ def main():
         "prep_s": prep_s,
         "latency_config1_us": lat1,
         "orig_ms_per_step": orig,
+        "no_reach_ms_per_step": noreach,
         "other_assembly": other,
         "mixed": mixed,
         "pcpg": pcpg or None,

@@ -108,6 +108,13 @@ typedef struct {
  *                    dependencies; the call returns with the caller's stream
  *                    waiting for the last SYRK), 2 = two launches (all TRSM
  *                    tiles, then all SYRK tiles)
+ *   disable_reach    0 (default) = a TRSM column tile visits only the factor
+ *                    blocks that hold rows on the elimination-tree paths of
+ *                    its pivots: column j of X = L^{-1} P B^T is nonzero only
+ *                    on the path from its pivot to the root, so every other
+ *                    block works on zero rows (the result is the same up to
+ *                    the sign of zeros); 1 = visit every block from the
+ *                    tile's first pivot on (the staircase of Sec. 3.2 alone)
  */
 typedef struct {
     int32_t precision;
@@ -118,7 +125,8 @@ typedef struct {
     int32_t n_threads;
     int32_t use_graph;
     int32_t assembly_kernels;
-    int32_t reserved[6];
+    int32_t disable_reach;
+    int32_t reserved[5];
 } sc_options_t;
 
 /* Initialisation stage (Sec. 2.2): ordering, symbolic factorisation, staircase

@@ -28,6 +28,8 @@ typedef struct {
     double trsm_useful, syrk_useful;   /* staircase flop counts (Sec. 3.2-3.3) */
     double trsm_dense, syrk_dense;     /* same factor without the staircase    */
     double factor_flops;               /* sum_j c_j^2 (estimate)               */
+    int64_t trsm_visits;   /* (column tile, factor block) pairs the TRSM visits */
+    int64_t stair_visits;  /* the same with the staircase alone (no reach)      */
 } sc_host_info_t;
 
 /*
@@ -45,6 +47,23 @@ sc_status_t sc_host_analyze(const sc_subdomain_desc_t* sd, const sc_options_t* o
                             const double* kreg_vals, int32_t* perm_out, double* L_out,
                             int32_t* piv_out, int32_t* pi_out, sc_host_info_t* info,
                             int32_t* failed_col);
+
+/*
+ * The factor blocks the staircase TRSM visits for each 64-column tile of X
+ * (columns in the sorted order of sc_host_analyze's piv_out), as the device
+ * path receives them.
+ *   sd, opt      as for sc_host_analyze
+ *   counts       [3] out: number of blocks, number of tiles, total visits
+ *   block_row0   optional [blocks + 1] out: first row of each block, then n
+ *   visit_ptr    optional [tiles + 1] out: tile t visits
+ *                visit[visit_ptr[t] .. visit_ptr[t + 1])
+ *   visit        optional [capacity] out: block indices, increasing per tile
+ * Call once with the optional outputs NULL to size them.  Returns SC_OK, or
+ * SC_ERR_INVALID_ARG for a bad descriptor or when capacity < total visits
+ * with visit given (counts are filled in either case).
+ */
+sc_status_t sc_host_tile_visits(const sc_subdomain_desc_t* sd, const sc_options_t* opt, int64_t* counts,
+                                int32_t* block_row0, int64_t* visit_ptr, int32_t* visit, int64_t capacity);
 
 #ifdef __cplusplus
 }

@@ -37,7 +37,9 @@ struct SubDev {
 struct TileDev {
     int32_t sub, tile, kstart, ncols;
     int64_t x_off;
-    int32_t start_block[4];   // first factor block each 16-column stripe visits
+    int32_t start_block[4];   // first factor block each 16-column stripe works on
+    int64_t visit_off;        // blocks the tile visits: visit[visit_off .. + nvisit),
+    int32_t nvisit, pad;      // increasing indices relative to the subdomain's first block
 };
 
 // One lower-triangle F output tile (I >= J, in units of kSyrkTile columns).

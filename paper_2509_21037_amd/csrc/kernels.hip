@@ -156,7 +156,7 @@ template <bool MIXED>
 __device__ __forceinline__ void trsm_tile(
     const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
     const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows,
-    const double* __restrict__ lval, const float* __restrict__ lval32,
+    const int32_t* __restrict__ visit, const double* __restrict__ lval, const float* __restrict__ lval32,
     const int32_t* __restrict__ piv, const int8_t* __restrict__ sgn,
     typename std::conditional<MIXED, float, double>::type* __restrict__ X, int ti, char* __restrict__ smem)
 {
@@ -181,30 +181,33 @@ __device__ __forceinline__ void trsm_tile(
     if constexpr (MIXED) LA = lval32 + S.lval_off;
     else LA = lval + S.lval_off;
     const int my_start = tiles[ti].start_block[wv];
-    const int first_block = tiles[ti].start_block[0];
+    // the blocks this tile visits, increasing: those holding rows on the
+    // elimination-tree paths of its pivots (all other rows of the slab stay 0)
+    const int nv = T.nvisit;
+    const int32_t* __restrict__ V = visit + T.visit_off;
 
     // right-hand side P B^T: sign at the pivot row, zero elsewhere
     for (int r = kstart + g; r < n; r += 4) Xs[(int64_t)(r - kstart) * kTile + col] = TX(0);
     __threadfence_block();
     if (g == 0 && col < T.ncols) Xs[(int64_t)(piv[cbase + col] - kstart) * kTile + col] = (TX)sgn[cbase + col];
-    if (first_block >= S.nblocks) return;
+    if (nv <= 0) return;
 
-    BlockLite bd = block_lite(B, first_block);
+    BlockLite bd = block_lite(B, V[0]);
     // prefetch cursor over the flattened chunk stream: chunk s+2 is loaded
     // into registers at the start of step s, chunk s+1 goes to LDS at its end
-    int pb = first_block, pc = 0;
+    int pk = 0, pc = 0;
     BlockLite pbd = bd;
     auto nchunks = [](const BlockLite& x) { return 1 + (((x.nb + 15) >> 4) + PT - 1) / PT; };
     int pnch = nchunks(pbd);
     auto take = [&]() {
         ChunkSrc c{reinterpret_cast<const char*>(L), 0, false, R};
-        if (pb < S.nblocks) {
+        if (pk < nv) {
             c = chunk_src(pbd, pc, L, LA, R);
             if (++pc >= pnch) {
-                ++pb;
+                ++pk;
                 pc = 0;
-                if (pb < S.nblocks) {
-                    pbd = block_lite(B, pb);
+                if (pk < nv) {
+                    pbd = block_lite(B, V[pk]);
                     pnch = nchunks(pbd);
                 }
             }
@@ -244,7 +247,8 @@ __device__ __forceinline__ void trsm_tile(
         a0 = b0; a1 = b1; a2 = b2; a3 = b3; a4 = b4; ai = bi;
         sa_p = sb_p; sa_bytes = sb_bytes; sa_idx = sb_idx; sa_ip = sb_ip;
     };
-    for (int b = first_block; b < S.nblocks; ++b) {
+    for (int k = 0; k < nv; ++k) {
+        const int b = V[k];
         const int w = bd.w;
         const int row0 = B[b].row0;
         const int nb = bd.nb;
@@ -253,7 +257,7 @@ __device__ __forceinline__ void trsm_tile(
         const int nrt = (nb + 15) >> 4;
         const int np = (nrt + PT - 1) / PT;
         const bool act = b >= my_start;
-        const BlockLite bn = block_lite(B, b + 1 < S.nblocks ? b + 1 : b);
+        const BlockLite bn = block_lite(B, V[k + 1 < nv ? k + 1 : k]);
 
         VX accn[PT];                             // rows of the next pruned chunk
         int offn[PT][4];
@@ -365,26 +369,26 @@ __device__ __forceinline__ void trsm_tile(
 
 __global__ __launch_bounds__(256, 2) void trsm_stair_f64(
     const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
-    const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows,
+    const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows, const int32_t* __restrict__ visit,
     const double* __restrict__ lval, const int32_t* __restrict__ piv,
     const int8_t* __restrict__ sgn, const int32_t* __restrict__ order, double* __restrict__ X)
 {
     __shared__ __align__(16) char smem[kTrsmSmem];
     const int ti = order[blockIdx.x];
     if (ti < 0) return;
-    trsm_tile<false>(subs, tiles, blocks, rows, lval, nullptr, piv, sgn, X, ti, smem);
+    trsm_tile<false>(subs, tiles, blocks, rows, visit, lval, nullptr, piv, sgn, X, ti, smem);
 }
 
 __global__ __launch_bounds__(256, 2) void trsm_stair_mixed(
     const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
-    const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows,
+    const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows, const int32_t* __restrict__ visit,
     const double* __restrict__ lval, const float* __restrict__ lval32, const int32_t* __restrict__ piv,
     const int8_t* __restrict__ sgn, const int32_t* __restrict__ order, float* __restrict__ X)
 {
     __shared__ __align__(16) char smem[kTrsmSmem];
     const int ti = order[blockIdx.x];
     if (ti < 0) return;
-    trsm_tile<true>(subs, tiles, blocks, rows, lval, lval32, piv, sgn, X, ti, smem);
+    trsm_tile<true>(subs, tiles, blocks, rows, visit, lval, lval32, piv, sgn, X, ti, smem);
 }
 
 
@@ -677,10 +681,10 @@ hipError_t launch_trsm(const DevTables& t, const int32_t* order, int64_t count, 
     if (count <= 0) return hipSuccess;
     if (t.X32)
         hipLaunchKernelGGL(trsm_stair_mixed, dim3((unsigned)count), dim3(256), 0, stream, t.subs, t.tiles,
-                           t.blocks, t.rows, t.lval, t.lval32, t.piv, t.sgn, order, t.X32);
+                           t.blocks, t.rows, t.visit, t.lval, t.lval32, t.piv, t.sgn, order, t.X32);
     else
         hipLaunchKernelGGL(trsm_stair_f64, dim3((unsigned)count), dim3(256), 0, stream, t.subs, t.tiles,
-                           t.blocks, t.rows, t.lval, t.piv, t.sgn, order, t.X);
+                           t.blocks, t.rows, t.visit, t.lval, t.piv, t.sgn, order, t.X);
     return hipGetLastError();
 }
 

@@ -16,6 +16,7 @@ struct DevTables {
     const TileDev* tiles = nullptr;
     const BlockDev* blocks = nullptr;
     const int32_t* rows = nullptr;
+    const int32_t* visit = nullptr;        // blocks visited per TRSM tile (TileDev::visit_off)
     const double* lval = nullptr;
     const float* lval32 = nullptr;
     const int32_t* piv = nullptr;

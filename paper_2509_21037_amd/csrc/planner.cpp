@@ -524,6 +524,41 @@ std::string build_plan(const SubdomainInput& in, const PlanOptions& opt, SubPlan
         }
         P.bval = voff;
     }
+
+    // ---- blocks each 64-column tile of X visits.  Column c of X = L^{-1} P B^T
+    // is nonzero only on the elimination-tree path from its pivot to the root
+    // (the reach of one right-hand-side entry); a factor block none of whose
+    // rows lies on the path of any of the tile's columns holds zero rows of
+    // the tile and contributes nothing, so the sweep skips it.  Without the
+    // reach the sweep runs from the first pivot's block to the last block
+    // (the staircase alone), without the staircase over every block.
+    {
+        const int32_t nb = (int32_t)P.blocks.size();
+        const int32_t ntile = (m + 63) / 64;
+        std::vector<int32_t> stamp(n, -1), bstamp(nb, -1);
+        P.visit_ptr.assign(1, 0);
+        P.visit.clear();
+        P.visits_stair = 0;
+        for (int32_t t = 0; t < ntile; ++t) {
+            const int32_t c0 = 64 * t, c1 = std::min(m, c0 + 64);
+            const int32_t first = opt.staircase ? P.block_of_row[P.piv[c0]] : 0;
+            P.visits_stair += nb - first;
+            if (!opt.staircase || !opt.reach) {
+                for (int32_t b = first; b < nb; ++b) P.visit.push_back(b);
+            } else {
+                std::vector<int32_t> bl;
+                for (int32_t c = c0; c < c1; ++c)
+                    for (int32_t r = P.piv[c]; r >= 0 && stamp[r] != t; r = P.parent[r]) {
+                        stamp[r] = t;
+                        const int32_t b = P.block_of_row[r];
+                        if (bstamp[b] != t) { bstamp[b] = t; bl.push_back(b); }
+                    }
+                std::sort(bl.begin(), bl.end());
+                P.visit.insert(P.visit.end(), bl.begin(), bl.end());
+            }
+            P.visit_ptr.push_back((int64_t)P.visit.size());
+        }
+    }
     code = 0;
     return "";
 }

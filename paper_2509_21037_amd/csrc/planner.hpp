@@ -37,6 +37,7 @@ struct PlanOptions {
     double relax_zero_frac = 0.5;     // ... if the merged zero fraction stays below this
     int32_t panel_width = 64;         // GPU factor block width (uniform blocks)
     int32_t staircase = 1;            // 0 = every column treated as pivot 0 ("orig")
+    int32_t reach = 1;                // 0 = a TRSM tile sweeps every block after its first pivot's
 };
 
 // One GPU factor block (Sec. 3.2, factor splitting with pruning): the column
@@ -91,6 +92,11 @@ struct SubPlan {
     std::vector<int32_t> brows;                // pruned rows of every block (lists start 16-byte aligned)
     int64_t bval = 0;                          // values in all block panels
     std::vector<int32_t> block_of_row;         // row -> block index
+    // blocks each 64-column tile of X visits (increasing): tile t holds
+    // visit[visit_ptr[t] .. visit_ptr[t + 1])
+    std::vector<int64_t> visit_ptr;
+    std::vector<int32_t> visit;
+    int64_t visits_stair = 0;                  // the same count for the staircase alone
     // statistics
     int64_t nnzL = 0;                          // exact
     int64_t nnzL_stored = 0;                   // supernodal storage incl. explicit zeros

@@ -55,6 +55,7 @@ std::string to_plan_options(const sc_options_t& o, PlanOptions& po) {
     if (o.relax_width) po.relax_width = o.relax_width;
     if (o.leaf_nodes) po.leaf_nodes = o.leaf_nodes;
     po.staircase = o.disable_staircase ? 0 : 1;
+    po.reach = o.disable_reach ? 0 : 1;
     return "";
 }
 
@@ -95,6 +96,7 @@ struct sc_plan_s {
     std::vector<SubDev> h_subs;
     std::vector<TileDev> h_tiles;
     std::vector<BlockDev> h_blocks;
+    std::vector<int32_t> h_visit;               // TRSM visit lists of all tiles
     std::vector<SyrkItem> h_syrk;               // interleaved over XCDs, idle items sub = -1
     std::vector<int32_t> h_tile_order;          // TRSM workgroup -> tile (-1 idle)
     // overlapped assembly: groups of subdomains (every XCD's list cut into
@@ -119,7 +121,7 @@ struct sc_plan_s {
     DevBuf<SyrkItem> d_ftiles;
     DevBuf<int2> d_frows;
     DevBuf<double> d_part;                      // apply partial sums, 256 per stored F tile
-    DevBuf<int32_t> d_rows, d_piv, d_pi;
+    DevBuf<int32_t> d_rows, d_piv, d_pi, d_visit;
     DevBuf<int8_t> d_sgn;
     DevBuf<double> d_lval, d_X, d_F;
     DevBuf<float> d_lval32, d_X32, d_F32;
@@ -217,7 +219,7 @@ struct sc_plan_s {
                          d_ftiles.count * sizeof(SyrkItem) + d_frows.count * sizeof(int2) +
                          d_part.count * 8 + d_tile_order.count * 4 +
                          d_tile_order_g.count * 4 + d_syrk_g.count * sizeof(SyrkItem) +
-                         (d_rows.count + d_piv.count + d_pi.count) * 4 + d_sgn.count +
+                         (d_rows.count + d_piv.count + d_pi.count + d_visit.count) * 4 + d_sgn.count +
                          (d_lval.count + d_X.count + d_F.count) * 8 +
                          (d_lval32.count + d_X32.count + d_F32.count) * 4 +
                          (d_xwork.count + d_xoff.count) * 8 + (d_ifw.count + d_ibw.count) * sizeof(int2) +
@@ -227,7 +229,7 @@ struct sc_plan_s {
         d_subs.release(); d_tiles.release(); d_blocks.release(); d_syrk.release();
         d_ftiles.release(); d_frows.release(); d_part.release();
         d_tile_order.release(); d_tile_order_g.release(); d_syrk_g.release();
-        d_rows.release(); d_piv.release(); d_pi.release(); d_sgn.release();
+        d_rows.release(); d_piv.release(); d_pi.release(); d_visit.release(); d_sgn.release();
         d_lval.release(); d_X.release(); d_F.release();
         d_lval32.release(); d_X32.release(); d_F32.release();
         d_xwork.release(); d_xoff.release();
@@ -247,7 +249,7 @@ struct sc_plan_s {
     }
     DevTables tables() const {
         DevTables t;
-        t.subs = d_subs.p; t.tiles = d_tiles.p; t.blocks = d_blocks.p; t.rows = d_rows.p;
+        t.subs = d_subs.p; t.tiles = d_tiles.p; t.blocks = d_blocks.p; t.rows = d_rows.p; t.visit = d_visit.p;
         t.lval = d_lval.p; t.piv = d_piv.p; t.pi = d_pi.p; t.sgn = d_sgn.p; t.syrk = d_syrk.p;
         t.X = d_X.p; t.F = d_F.p;
         t.lval32 = d_lval32.p; t.X32 = d_X32.p; t.F32 = d_F32.p;
@@ -338,6 +340,9 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
                 if (w * kStripe >= T.ncols) T.start_block[w] = s.nblocks;
                 else T.start_block[w] = po.staircase ? sp.block_of_row[sp.piv[c]] : 0;
             }
+            T.visit_off = (int64_t)P->h_visit.size();
+            T.nvisit = (int32_t)(sp.visit_ptr[t + 1] - sp.visit_ptr[t]);
+            P->h_visit.insert(P->h_visit.end(), sp.visit.begin() + sp.visit_ptr[t], sp.visit.begin() + sp.visit_ptr[t + 1]);
             P->h_tiles.push_back(T);
         }
         const int32_t nst = (sp.m + kSyrkTile - 1) / kSyrkTile;
@@ -461,6 +466,7 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
     ALLOC(p->d_tile_order_g, p->h_tile_order_g.size());
     ALLOC(p->d_syrk_g, p->h_syrk_g.size());
     ALLOC(p->d_rows, (size_t)rows);
+    ALLOC(p->d_visit, std::max<size_t>(1, p->h_visit.size()));
     ALLOC(p->d_piv, (size_t)colo);
     ALLOC(p->d_pi, (size_t)colo);
     ALLOC(p->d_sgn, (size_t)colo);
@@ -506,6 +512,7 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
     if (e == hipSuccess) e = up(p->d_syrk_g.p, p->h_syrk_g.data(), p->h_syrk_g.size() * sizeof(SyrkItem));
     if (e == hipSuccess && p->overlapped()) e = p->prepare_overlap();
     if (e == hipSuccess) e = up(p->d_rows.p, h_rows.data(), h_rows.size() * 4);
+    if (e == hipSuccess) e = up(p->d_visit.p, p->h_visit.data(), p->h_visit.size() * 4);
     if (e == hipSuccess) e = up(p->d_piv.p, h_piv.data(), h_piv.size() * 4);
     if (e == hipSuccess) e = up(p->d_pi.p, h_pi.data(), h_pi.size() * 4);
     if (e == hipSuccess) e = up(p->d_sgn.p, h_sgn.data(), h_sgn.size());
@@ -930,6 +937,8 @@ sc_status_t sc_host_analyze(const sc_subdomain_desc_t* sd, const sc_options_t* o
         h.trsm_dense = sp.trsm_dense;
         h.syrk_dense = sp.syrk_dense;
         h.factor_flops = sp.factor_flops;
+        h.trsm_visits = (int64_t)sp.visit.size();
+        h.stair_visits = sp.visits_stair;
         *info = h;
     }
     if (kreg_vals) {
@@ -951,6 +960,39 @@ sc_status_t sc_host_analyze(const sc_subdomain_desc_t* sd, const sc_options_t* o
                     for (int64_t q = c; q < ld; ++q) L_out[(int64_t)rows[q] * n + f + c] = A[c * ld + q];
             }
         }
+    }
+    return SC_OK;
+}
+
+sc_status_t sc_host_tile_visits(const sc_subdomain_desc_t* sd, const sc_options_t* opt, int64_t* counts,
+                                int32_t* block_row0, int64_t* visit_ptr, int32_t* visit, int64_t capacity) {
+    g_last_error.clear();
+    if (!sd || !counts) return fail(SC_ERR_INVALID_ARG, "descriptor or counts is NULL");
+    sc_options_t o{};
+    if (opt) o = *opt;
+    PlanOptions po;
+    std::string err = to_plan_options(o, po);
+    if (!err.empty()) return fail(SC_ERR_INVALID_ARG, err);
+    SubPlan sp;
+    int code = 0;
+    try {
+        err = build_plan(to_input(*sd), po, sp, code);
+    } catch (const std::bad_alloc&) {
+        return fail(SC_ERR_OOM, "host allocation failed");
+    }
+    if (!err.empty()) return fail(SC_ERR_INVALID_ARG, err);
+    const int64_t nb = (int64_t)sp.blocks.size(), total = (int64_t)sp.visit.size();
+    counts[0] = nb;
+    counts[1] = (int64_t)sp.visit_ptr.size() - 1;
+    counts[2] = total;
+    if (block_row0) {
+        for (int64_t b = 0; b < nb; ++b) block_row0[b] = sp.blocks[b].row0;
+        block_row0[nb] = sp.n;
+    }
+    if (visit_ptr) std::copy(sp.visit_ptr.begin(), sp.visit_ptr.end(), visit_ptr);
+    if (visit) {
+        if (capacity < total) return fail(SC_ERR_INVALID_ARG, "visit capacity below the total visit count");
+        std::copy(sp.visit.begin(), sp.visit.end(), visit);
     }
     return SC_OK;
 }

@@ -17,7 +17,7 @@ STATUS_NAMES = {0: "SC_OK", 1: "SC_ERR_INVALID_ARG", 2: "SC_ERR_NOT_SPD", 3: "SC
 
 EXPORTED = ["sc_plan_create", "sc_factor", "sc_assemble", "sc_apply", "sc_apply_implicit",
             "sc_get_F", "sc_query", "sc_plan_stats", "sc_plan_destroy", "sc_host_analyze",
-            "sc_set_timing", "sc_kernel_times", "sc_pcpg", "sc_autotune", "sc_last_error"]
+            "sc_host_tile_visits", "sc_set_timing", "sc_kernel_times", "sc_pcpg", "sc_autotune", "sc_last_error"]
 
 
 class ScasmError(RuntimeError):
@@ -41,7 +41,7 @@ class Options(ctypes.Structure):
                 ("panel_width", ctypes.c_int32), ("relax_width", ctypes.c_int32),
                 ("leaf_nodes", ctypes.c_int32), ("n_threads", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("assembly_kernels", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("disable_reach", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class HostInfo(ctypes.Structure):
@@ -50,7 +50,8 @@ class HostInfo(ctypes.Structure):
                 ("max_width", ctypes.c_int64), ("sum_below", ctypes.c_int64),
                 ("trsm_useful", ctypes.c_double), ("syrk_useful", ctypes.c_double),
                 ("trsm_dense", ctypes.c_double), ("syrk_dense", ctypes.c_double),
-                ("factor_flops", ctypes.c_double)]
+                ("factor_flops", ctypes.c_double), ("trsm_visits", ctypes.c_int64),
+                ("stair_visits", ctypes.c_int64)]
 
 
 _lib = None
@@ -76,6 +77,8 @@ def load():
         lib.sc_plan_destroy.argtypes = [vp]
         lib.sc_host_analyze.argtypes = [ctypes.POINTER(SubdomainDesc), ctypes.POINTER(Options), vp, vp, vp,
                                          vp, vp, ctypes.POINTER(HostInfo), ctypes.POINTER(i32)]
+        lib.sc_host_tile_visits.argtypes = [ctypes.POINTER(SubdomainDesc), ctypes.POINTER(Options), vp, vp, vp,
+                                             vp, ctypes.c_int64]
         lib.sc_pcpg.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(i32), vp, vp, i32, vp, vp]
         lib.sc_autotune.argtypes = [ctypes.POINTER(SubdomainDesc), i32, ctypes.POINTER(Options),
                                     ctypes.POINTER(vp), ctypes.POINTER(i32), i32, i32, i32, vp,
@@ -140,8 +143,9 @@ ASSEMBLY_KERNELS = {"default": 0, "overlap": 1, "separate": 2}
 
 
 def _options(precision="fp64", staircase=True, panel_width=0, relax_width=0, leaf_nodes=0, n_threads=0,
-             use_graph=False, assembly="default"):
+             use_graph=False, assembly="default", reach=True):
     opt = Options()
+    opt.disable_reach = 0 if reach else 1
     opt.use_graph = 1 if use_graph else 0
     opt.assembly_kernels = ASSEMBLY_KERNELS[assembly] if isinstance(assembly, str) else int(assembly)
     opt.precision = {"fp64": SC_PREC_FP64, "mixed": SC_PREC_MIXED}.get(precision, precision) \
@@ -181,6 +185,25 @@ def host_analyze(s, values=True, want_L=False, use_coords=True, **opts):
     return out
 
 
+def host_tile_visits(s, use_coords=True, **opts):
+    """Factor blocks the TRSM visits per 64-column X tile (sc_host_tile_visits):
+    returns (block_row0 [nblocks + 1], visit_ptr [ntiles + 1], visit)."""
+    lib = load()
+    keep = []
+    d = SubdomainDesc()
+    _fill_desc(d, s, keep, use_coords)
+    opt = _options(**opts)
+    counts = np.zeros(3, dtype=np.int64)
+    _check(lib.sc_host_tile_visits(ctypes.byref(d), ctypes.byref(opt), counts.ctypes.data, None, None, None, 0))
+    nb, nt, tot = (int(c) for c in counts)
+    row0 = np.zeros(nb + 1, dtype=np.int32)
+    ptr = np.zeros(nt + 1, dtype=np.int64)
+    visit = np.zeros(max(1, tot), dtype=np.int32)
+    _check(lib.sc_host_tile_visits(ctypes.byref(d), ctypes.byref(opt), counts.ctypes.data, row0.ctypes.data,
+                                   ptr.ctypes.data, visit.ctypes.data, tot))
+    return row0, ptr, visit[:tot]
+
+
 def autotune(subdomains, candidates=(32, 48, 64), sample=64, reps=3, use_coords=True, stream=None, **opts):
     """Fastest factor block width for this batch (sc_autotune): returns
     (best_width, {width: mean ms per assembly of the sample})."""
@@ -207,7 +230,8 @@ class Plan:
 
     def __init__(self, subdomains: Sequence, precision: str = "fp64", staircase: bool = True,
                  panel_width: int = 0, relax_width: int = 0, leaf_nodes: int = 0, n_threads: int = 0,
-                 use_coords: bool = True, use_graph: bool = False, assembly: str = "default", stream=None):
+                 use_coords: bool = True, use_graph: bool = False, assembly: str = "default", reach: bool = True,
+                 stream=None):
         lib = load()
         self._lib = lib
         self._h = ctypes.c_void_p(0)
@@ -217,7 +241,8 @@ class Plan:
         descs = (SubdomainDesc * max(1, len(self.subdomains)))()
         for i, s in enumerate(self.subdomains):
             _fill_desc(descs[i], s, keep, use_coords)
-        opt = _options(precision, staircase, panel_width, relax_width, leaf_nodes, n_threads, use_graph, assembly)
+        opt = _options(precision, staircase, panel_width, relax_width, leaf_nodes, n_threads, use_graph, assembly,
+                       reach)
         _check(lib.sc_plan_create(descs, len(self.subdomains), ctypes.byref(opt), _stream_handle(stream),
                                   ctypes.byref(self._h)))
         del keep

@@ -361,6 +361,26 @@ def test_graph_replays_match_eager(precision):
             assert np.array_equal(plan.get_F(i), ref[i]), (rep, i)
 
 
+# ------------------------------------------------------ reach-restricted sweep
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_reach_restricted_sweep_matches_full_staircase_sweep(precision):
+    """Skipping the factor blocks off the elimination-tree paths of a tile's
+    pivots changes nothing: F bit for bit equal to the sweep over every block
+    after the first pivot, on uneven heat and elasticity subdomains, one with
+    an empty interface."""
+    _torch_init()
+    subs = scgen.config_subdomains(2, count=10) + scgen.config_subdomains(3, count=10) + \
+        scgen.config_subdomains(1)
+    subs.append(subs[1].with_columns(np.zeros(0, np.int32), np.zeros(0, np.int8)))
+    full = _assemble(subs, precision=precision, reach=False)
+    part = _assemble(subs, precision=precision)
+    for i in range(len(subs)):
+        assert np.array_equal(part.get_F(i), full.get_F(i)), i
+    full.destroy()
+    part.destroy()
+
+
 # ------------------------------------------------------ overlapped assembly
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])

@@ -129,6 +129,50 @@ def test_useful_flop_model_matches_definition():
     assert abs(r["syrk_dense"] - sd) < 1e-9 * sd
 
 
+VISIT_CASES = [
+    ("heat3d", lambda: scgen.box_subdomain("heat", (8, 8, 7), 0.2, seed=11)),
+    ("elast", lambda: scgen.box_subdomain("elasticity", (5, 4, 4), 0.25, seed=12)),
+    ("heat12", lambda: scgen.config_subdomains(2, count=1)[0]),
+]
+
+
+@pytest.mark.parametrize("name,make", VISIT_CASES)
+def test_trsm_visits_exactly_the_blocks_with_nonzero_rows_of_x(name, make):
+    # X = L^{-1} P B^T solved densely: a tile must visit every block holding a
+    # nonzero row of its columns (else the sweep would drop work), and with
+    # random values nothing else (the reach has no cancellation)
+    import scipy.linalg as sl
+    s = make()
+    r = P.host_analyze(s, want_L=True)
+    row0, ptr, visit = P.host_tile_visits(s)
+    L, piv, n, m = r["L"], r["piv"], s.n, s.m
+    E = np.zeros((n, m))
+    E[piv, np.arange(m)] = 1.0
+    X = sl.solve_triangular(L, E, lower=True)
+    assert row0[0] == 0 and row0[-1] == n and np.all(np.diff(row0) > 0)
+    blk = np.searchsorted(row0, np.arange(n), side="right") - 1
+    nt = (m + 63) // 64
+    assert len(ptr) == nt + 1 and ptr[-1] == len(visit)
+    stair = 0
+    for t in range(nt):
+        got = visit[ptr[t]:ptr[t + 1]]
+        assert np.all(np.diff(got) > 0)
+        rows = np.nonzero(np.abs(X[:, 64 * t:64 * t + 64]).max(axis=1) > 0)[0]
+        assert np.array_equal(got, np.unique(blk[rows])), t
+        stair += len(row0) - 1 - blk[piv[64 * t]]
+    assert r["trsm_visits"] == len(visit)
+    assert r["stair_visits"] == stair
+    if name == "heat12":
+        assert r["trsm_visits"] < 0.6 * r["stair_visits"]
+    # without the reach every block from the first pivot's on; without the
+    # staircase every block
+    _, ptr2, visit2 = P.host_tile_visits(s, reach=False)
+    _, ptr3, visit3 = P.host_tile_visits(s, staircase=False)
+    for t in range(nt):
+        assert np.array_equal(visit2[ptr2[t]:ptr2[t + 1]], np.arange(blk[piv[64 * t]], len(row0) - 1))
+        assert np.array_equal(visit3[ptr3[t]:ptr3[t + 1]], np.arange(len(row0) - 1))
+
+
 def test_triangular_rhs_gives_threefold_saving():
     # Sec. 4.3: pivot of column j at row j*n/m with a dense factor -> 1/3 of the work
     golden = {}
