@@ -210,10 +210,14 @@ sc_status_t sc_query(sc_plan_t plan, int32_t sub, int64_t* n, int64_t* m, int64_
 
 /* Plan-wide totals: number of subdomains, total dual length, useful TRSM and
  * SYRK flops (as in sc_query), the same counts without the staircase
- * ("orig"), and the device bytes held by the plan. */
+ * ("orig"), the structural counts (the same sums with a(i) replaced by r(i),
+ * the number of columns of X whose row i is structurally nonzero: pivots in
+ * the elimination subtree of i; the flops the result needs at all), and the
+ * device bytes held by the plan. */
 sc_status_t sc_plan_stats(sc_plan_t plan, int32_t* nsub, int64_t* dual_total,
                           double* trsm_useful, double* syrk_useful, double* trsm_dense,
-                          double* syrk_dense, int64_t* device_bytes);
+                          double* syrk_dense, double* trsm_reach, double* syrk_reach,
+                          int64_t* device_bytes);
 
 /* Kernel timing.  While enabled, sc_assemble and sc_apply record HIP events
  * on their stream around each kernel they launch; sc_kernel_times adds up the

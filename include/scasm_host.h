@@ -30,6 +30,8 @@ typedef struct {
     double factor_flops;               /* sum_j c_j^2 (estimate)               */
     int64_t trsm_visits;   /* (column tile, factor block) pairs the TRSM visits */
     int64_t stair_visits;  /* the same with the staircase alone (no reach)      */
+    double trsm_reach, syrk_reach;     /* structural counts: a(i) replaced by
+                                          r(i) = columns of X nonzero in row i */
 } sc_host_info_t;
 
 /*

@@ -43,10 +43,15 @@ struct TileDev {
 };
 
 // One lower-triangle F output tile (I >= J, in units of kSyrkTile columns).
+// Its k-range is a list of 16-row steps: those where some X row of tile I and
+// some X row of tile J can be nonzero (every other step adds zero products).
 struct SyrkItem {
     int32_t sub;
     int32_t I, J;
-    int32_t pad;
+    int32_t nsteps;
+    int64_t step_off;     // first row of step s at ksteps[step_off + s]
+    int32_t skip[4];      // FP32 SYRK: leading steps wholly above the first pivots
+                          // of wavefront w's two column halves
 };
 
 struct BlockDev {

@@ -412,7 +412,7 @@ constexpr int kSyrkSmem = 4 * kSyrkKC * kSyrkLd * 8;
 
 __device__ __forceinline__ void syrk_item_f64(
     const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles, const SyrkItem it,
-    const double* __restrict__ X, double* __restrict__ F,
+    const int32_t* __restrict__ ksteps, const double* __restrict__ X, double* __restrict__ F,
     char* __restrict__ smem)
 {
     double (*sI)[kSyrkKC * kSyrkLd] = reinterpret_cast<double (*)[kSyrkKC * kSyrkLd]>(smem);
@@ -441,7 +441,7 @@ __device__ __forceinline__ void syrk_item_f64(
             ks[q] = INT_MAX;
         }
     }
-    const int kbeg = ks[0];
+    const int32_t* __restrict__ KS = ksteps + it.step_off;
 
     v4d acc[4][4];
 #pragma unroll
@@ -478,15 +478,15 @@ __device__ __forceinline__ void syrk_item_f64(
         }
     };
 
-    const int nsteps = kbeg < n ? (n - kbeg + kSyrkKC - 1) / kSyrkKC : 0;
+    const int nsteps = it.nsteps;
     if (nsteps > 0) {
-        load_step(kbeg);
+        load_step(KS[0]);
         store_step(0);
     }
     __syncthreads();
     for (int st = 0; st < nsteps; ++st) {
         const int buf = st & 1;
-        if (st + 1 < nsteps) load_step(kbeg + (st + 1) * kSyrkKC);
+        if (st + 1 < nsteps) load_step(KS[st + 1]);
         {
 #pragma unroll
             for (int s = 0; s < kSyrkKC / 4; ++s) {
@@ -519,12 +519,13 @@ __device__ __forceinline__ void syrk_item_f64(
 
 __global__ __launch_bounds__(256) void syrk_stair_f64(
     const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
-    const SyrkItem* __restrict__ items, const double* __restrict__ X, double* __restrict__ F)
+    const SyrkItem* __restrict__ items, const int32_t* __restrict__ ksteps, const double* __restrict__ X,
+    double* __restrict__ F)
 {
     __shared__ __align__(16) char smem[kSyrkSmem];
     const SyrkItem it = items[blockIdx.x];
     if (it.sub < 0) return;
-    syrk_item_f64(subs, tiles, it, X, F, smem);
+    syrk_item_f64(subs, tiles, it, ksteps, X, F, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -548,7 +549,7 @@ constexpr int kSyrkSmemF = 4 * kSyrkKCF * kSyrkLdF * 4;
 
 __device__ __forceinline__ void syrk_item_f32(
     const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles, const SyrkItem it,
-    const float* __restrict__ X, float* __restrict__ F,
+    const int32_t* __restrict__ ksteps, const float* __restrict__ X, float* __restrict__ F,
     char* __restrict__ smem)
 {
     float (*sI)[kSyrkKCF * kSyrkLdF] = reinterpret_cast<float (*)[kSyrkKCF * kSyrkLdF]>(smem);
@@ -576,11 +577,10 @@ __device__ __forceinline__ void syrk_item_f32(
             ks[q] = INT_MAX;
         }
     }
-    const int kbeg = ks[0];
+    const int32_t* __restrict__ KS = ksteps + it.step_off;
     // a diagonal tile reads one slab pair (sJ aliases sI); a wavefront skips the
     // k-steps that lie wholly above the first pivot of both its column halves
     const bool diag = it.I == it.J;
-    const int kw = max(ks[wi], ks[2 + wj]);
 
     v4f acc[4][4];
 #pragma unroll
@@ -618,24 +618,25 @@ __device__ __forceinline__ void syrk_item_f32(
         }
     };
 
-    const int nsteps = kbeg < n ? (n - kbeg + kSyrkKCF - 1) / kSyrkKCF : 0;
+    const int nsteps = it.nsteps;
     if (nsteps > 0) {
-        load_step(kbeg);
+        load_step(KS[0]);
         store_step(0);
     }
     __syncthreads();
-    // leading steps wholly above kw: loads only (same barriers as the rest)
-    const int skip = kw >= n ? nsteps : min(nsteps, (kw - kbeg) / kSyrkKCF);
+    // leading steps wholly above this wavefront's pivots: loads only (same
+    // barriers as the rest)
+    const int skip = wv == 0 ? it.skip[0] : wv == 1 ? it.skip[1] : wv == 2 ? it.skip[2] : it.skip[3];
     int st = 0;
     for (; st < skip; ++st) {
         const int buf = st & 1;
-        if (st + 1 < nsteps) load_step(kbeg + (st + 1) * kSyrkKCF);
+        if (st + 1 < nsteps) load_step(KS[st + 1]);
         if (st + 1 < nsteps) store_step(buf ^ 1);
         __syncthreads();
     }
     for (; st < nsteps; ++st) {
         const int buf = st & 1;
-        if (st + 1 < nsteps) load_step(kbeg + (st + 1) * kSyrkKCF);
+        if (st + 1 < nsteps) load_step(KS[st + 1]);
         {
 #pragma unroll
             for (int s = 0; s < kSyrkKCF / 4; ++s) {
@@ -668,12 +669,13 @@ __device__ __forceinline__ void syrk_item_f32(
 
 __global__ __launch_bounds__(256) void syrk_stair_f32(
     const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
-    const SyrkItem* __restrict__ items, const float* __restrict__ X, float* __restrict__ F)
+    const SyrkItem* __restrict__ items, const int32_t* __restrict__ ksteps, const float* __restrict__ X,
+    float* __restrict__ F)
 {
     __shared__ __align__(16) char smem[kSyrkSmemF];
     const SyrkItem it = items[blockIdx.x];
     if (it.sub < 0) return;
-    syrk_item_f32(subs, tiles, it, X, F, smem);
+    syrk_item_f32(subs, tiles, it, ksteps, X, F, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -692,10 +694,10 @@ hipError_t launch_syrk(const DevTables& t, const SyrkItem* items, int64_t count,
     if (count <= 0) return hipSuccess;
     if (t.X32)
         hipLaunchKernelGGL(syrk_stair_f32, dim3((unsigned)count), dim3(256), 0, stream, t.subs, t.tiles, items,
-                           t.X32, t.F32);
+                           t.ksteps, t.X32, t.F32);
     else
         hipLaunchKernelGGL(syrk_stair_f64, dim3((unsigned)count), dim3(256), 0, stream, t.subs, t.tiles, items,
-                           t.X, t.F);
+                           t.ksteps, t.X, t.F);
     return hipGetLastError();
 }
 

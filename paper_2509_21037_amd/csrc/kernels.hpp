@@ -17,6 +17,7 @@ struct DevTables {
     const BlockDev* blocks = nullptr;
     const int32_t* rows = nullptr;
     const int32_t* visit = nullptr;        // blocks visited per TRSM tile (TileDev::visit_off)
+    const int32_t* ksteps = nullptr;       // SYRK k-steps per item (SyrkItem::step_off)
     const double* lval = nullptr;
     const float* lval32 = nullptr;
     const int32_t* piv = nullptr;

@@ -482,6 +482,22 @@ std::string build_plan(const SubdomainInput& in, const PlanOptions& opt, SubPlan
         P.trsm_dense += (double)m * (2 * c - 1);
     }
     P.syrk_dense = (double)n * (double)m * (double)(m + 1);
+    // structural counts: row i of column j of X is nonzero iff i lies on the
+    // elimination-tree path from j's pivot to the root, i.e. iff the pivot is
+    // in the subtree of i; r(i) = pivots in that subtree (children precede
+    // their parent, so one increasing pass sums the subtrees)
+    {
+        std::vector<double> r(n, 0.0);
+        for (int32_t j = 0; j < m; ++j) r[pv[j]] += 1;
+        for (int32_t i = 0; i < n; ++i)
+            if (P.parent[i] >= 0) r[P.parent[i]] += r[i];
+        P.trsm_reach = P.syrk_reach = 0;
+        for (int32_t i = 0; i < n; ++i) {
+            const double c = P.colcount[i];
+            P.trsm_reach += r[i] * (2 * c - 1);
+            P.syrk_reach += r[i] * (r[i] + 1);
+        }
+    }
 
     // ---- GPU blocks: uniform column ranges of width bs; pruned rows = rows
     // >= the block end that hold a nonzero in any of the block's columns
@@ -539,17 +555,23 @@ std::string build_plan(const SubdomainInput& in, const PlanOptions& opt, SubPlan
         P.visit_ptr.assign(1, 0);
         P.visit.clear();
         P.visits_stair = 0;
+        P.mask_words = (n + 16 * 64 - 1) / (16 * 64);
+        P.step_mask.assign((size_t)ntile * P.mask_words, 0);
         for (int32_t t = 0; t < ntile; ++t) {
             const int32_t c0 = 64 * t, c1 = std::min(m, c0 + 64);
             const int32_t first = opt.staircase ? P.block_of_row[P.piv[c0]] : 0;
+            uint64_t* mask = P.step_mask.data() + (size_t)t * P.mask_words;
             P.visits_stair += nb - first;
             if (!opt.staircase || !opt.reach) {
                 for (int32_t b = first; b < nb; ++b) P.visit.push_back(b);
+                for (int32_t q = (opt.staircase ? P.piv[c0] : 0) / 16; q < (n + 15) / 16; ++q)
+                    mask[q >> 6] |= 1ull << (q & 63);
             } else {
                 std::vector<int32_t> bl;
                 for (int32_t c = c0; c < c1; ++c)
                     for (int32_t r = P.piv[c]; r >= 0 && stamp[r] != t; r = P.parent[r]) {
                         stamp[r] = t;
+                        mask[r >> 10] |= 1ull << ((r >> 4) & 63);
                         const int32_t b = P.block_of_row[r];
                         if (bstamp[b] != t) { bstamp[b] = t; bl.push_back(b); }
                     }

@@ -97,11 +97,16 @@ struct SubPlan {
     std::vector<int64_t> visit_ptr;
     std::vector<int32_t> visit;
     int64_t visits_stair = 0;                  // the same count for the staircase alone
+    // 16-row steps holding nonzero rows of each 64-column tile of X (bit q of
+    // word q / 64 = rows [16 q, 16 q + 16)), mask_words words per tile
+    int32_t mask_words = 0;
+    std::vector<uint64_t> step_mask;
     // statistics
     int64_t nnzL = 0;                          // exact
     int64_t nnzL_stored = 0;                   // supernodal storage incl. explicit zeros
     double trsm_useful = 0, syrk_useful = 0;   // element-granular staircase counts
     double trsm_dense = 0, syrk_dense = 0;     // same factor, no staircase ("orig")
+    double trsm_reach = 0, syrk_reach = 0;     // structural counts: only the nonzero rows of X
     double factor_flops = 0;
 };
 

@@ -6,6 +6,8 @@
 #include <omp.h>
 
 #include <algorithm>
+#include <climits>
+#include <cstdint>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -97,6 +99,7 @@ struct sc_plan_s {
     std::vector<TileDev> h_tiles;
     std::vector<BlockDev> h_blocks;
     std::vector<int32_t> h_visit;               // TRSM visit lists of all tiles
+    std::vector<int32_t> h_ksteps;              // SYRK k-step lists of all items
     std::vector<SyrkItem> h_syrk;               // interleaved over XCDs, idle items sub = -1
     std::vector<int32_t> h_tile_order;          // TRSM workgroup -> tile (-1 idle)
     // overlapped assembly: groups of subdomains (every XCD's list cut into
@@ -121,7 +124,7 @@ struct sc_plan_s {
     DevBuf<SyrkItem> d_ftiles;
     DevBuf<int2> d_frows;
     DevBuf<double> d_part;                      // apply partial sums, 256 per stored F tile
-    DevBuf<int32_t> d_rows, d_piv, d_pi, d_visit;
+    DevBuf<int32_t> d_rows, d_piv, d_pi, d_visit, d_ksteps;
     DevBuf<int8_t> d_sgn;
     DevBuf<double> d_lval, d_X, d_F;
     DevBuf<float> d_lval32, d_X32, d_F32;
@@ -136,7 +139,7 @@ struct sc_plan_s {
     bool mixed = false;
     bool factored = false, assembled = false;
     hipGraphExec_t graph_exec = nullptr;        // captured assembly (use_graph)
-    double trsm_u = 0, syrk_u = 0, trsm_d = 0, syrk_d = 0;
+    double trsm_u = 0, syrk_u = 0, trsm_d = 0, syrk_d = 0, trsm_r = 0, syrk_r = 0;
     // kernel timing: event pairs per kernel, pending until read
     bool timing = false;
     struct PendingTiming { int kernel; hipEvent_t a, b; };
@@ -219,7 +222,7 @@ struct sc_plan_s {
                          d_ftiles.count * sizeof(SyrkItem) + d_frows.count * sizeof(int2) +
                          d_part.count * 8 + d_tile_order.count * 4 +
                          d_tile_order_g.count * 4 + d_syrk_g.count * sizeof(SyrkItem) +
-                         (d_rows.count + d_piv.count + d_pi.count + d_visit.count) * 4 + d_sgn.count +
+                         (d_rows.count + d_piv.count + d_pi.count + d_visit.count + d_ksteps.count) * 4 + d_sgn.count +
                          (d_lval.count + d_X.count + d_F.count) * 8 +
                          (d_lval32.count + d_X32.count + d_F32.count) * 4 +
                          (d_xwork.count + d_xoff.count) * 8 + (d_ifw.count + d_ibw.count) * sizeof(int2) +
@@ -229,7 +232,7 @@ struct sc_plan_s {
         d_subs.release(); d_tiles.release(); d_blocks.release(); d_syrk.release();
         d_ftiles.release(); d_frows.release(); d_part.release();
         d_tile_order.release(); d_tile_order_g.release(); d_syrk_g.release();
-        d_rows.release(); d_piv.release(); d_pi.release(); d_visit.release(); d_sgn.release();
+        d_rows.release(); d_piv.release(); d_pi.release(); d_visit.release(); d_ksteps.release(); d_sgn.release();
         d_lval.release(); d_X.release(); d_F.release();
         d_lval32.release(); d_X32.release(); d_F32.release();
         d_xwork.release(); d_xoff.release();
@@ -250,6 +253,7 @@ struct sc_plan_s {
     DevTables tables() const {
         DevTables t;
         t.subs = d_subs.p; t.tiles = d_tiles.p; t.blocks = d_blocks.p; t.rows = d_rows.p; t.visit = d_visit.p;
+        t.ksteps = d_ksteps.p;
         t.lval = d_lval.p; t.piv = d_piv.p; t.pi = d_pi.p; t.sgn = d_sgn.p; t.syrk = d_syrk.p;
         t.X = d_X.p; t.F = d_F.p;
         t.lval32 = d_lval32.p; t.X32 = d_X32.p; t.F32 = d_F32.p;
@@ -347,9 +351,38 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
         }
         const int32_t nst = (sp.m + kSyrkTile - 1) / kSyrkTile;
         s.ftile_off = (int64_t)P->h_ftiles.size();
-        for (int32_t I = 0; I < nst; ++I) {
-            P->h_frows.push_back(make_int2(i, I));
-            for (int32_t J = 0; J <= I; ++J) P->h_syrk.push_back(SyrkItem{i, I, J, 0});
+        {
+            // k-steps of each F tile: 16-row steps where both column tiles can
+            // hold nonzero X rows
+            const int32_t nw = sp.mask_words;
+            std::vector<uint64_t> fm((size_t)nst * nw, 0);
+            for (int32_t t = 0; t < s.ntiles; ++t)
+                for (int32_t q = 0; q < nw; ++q) fm[(size_t)(t / 2) * nw + q] |= sp.step_mask[(size_t)t * nw + q];
+            auto kstart = [&](int32_t t64) {
+                return t64 < s.ntiles ? P->h_tiles[s.tile_off + t64].kstart : INT32_MAX;
+            };
+            for (int32_t I = 0; I < nst; ++I) {
+                P->h_frows.push_back(make_int2(i, I));
+                for (int32_t J = 0; J <= I; ++J) {
+                    SyrkItem it{i, I, J, 0};
+                    it.step_off = (int64_t)P->h_ksteps.size();
+                    for (int32_t q = 0; q < nw; ++q) {
+                        uint64_t b = fm[(size_t)I * nw + q] & fm[(size_t)J * nw + q];
+                        while (b) {
+                            P->h_ksteps.push_back(16 * (64 * q + __builtin_ctzll(b)));
+                            b &= b - 1;
+                        }
+                    }
+                    it.nsteps = (int32_t)(P->h_ksteps.size() - it.step_off);
+                    for (int w = 0; w < 4; ++w) {
+                        const int32_t kw = std::max(kstart(2 * I + (w >> 1)), kstart(2 * J + (w & 1)));
+                        int32_t k = 0;
+                        while (k < it.nsteps && P->h_ksteps[it.step_off + k] + 16 <= kw) ++k;
+                        it.skip[w] = k;
+                    }
+                    P->h_syrk.push_back(it);
+                }
+            }
         }
         P->h_ftiles.insert(P->h_ftiles.end(), P->h_syrk.end() - (int64_t)nst * (nst + 1) / 2, P->h_syrk.end());
         blk += s.nblocks;
@@ -363,6 +396,8 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
         P->syrk_u += sp.syrk_useful;
         P->trsm_d += sp.trsm_dense;
         P->syrk_d += sp.syrk_dense;
+        P->trsm_r += sp.trsm_reach;
+        P->syrk_r += sp.syrk_reach;
     }
     // ---- XCD-aware work lists: subdomains go to XCDs by longest-processing-
     // time on their useful flops; XCD x receives workgroups x, x + 8, ...
@@ -467,6 +502,7 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
     ALLOC(p->d_syrk_g, p->h_syrk_g.size());
     ALLOC(p->d_rows, (size_t)rows);
     ALLOC(p->d_visit, std::max<size_t>(1, p->h_visit.size()));
+    ALLOC(p->d_ksteps, std::max<size_t>(1, p->h_ksteps.size()));
     ALLOC(p->d_piv, (size_t)colo);
     ALLOC(p->d_pi, (size_t)colo);
     ALLOC(p->d_sgn, (size_t)colo);
@@ -513,6 +549,7 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
     if (e == hipSuccess && p->overlapped()) e = p->prepare_overlap();
     if (e == hipSuccess) e = up(p->d_rows.p, h_rows.data(), h_rows.size() * 4);
     if (e == hipSuccess) e = up(p->d_visit.p, p->h_visit.data(), p->h_visit.size() * 4);
+    if (e == hipSuccess) e = up(p->d_ksteps.p, p->h_ksteps.data(), p->h_ksteps.size() * 4);
     if (e == hipSuccess) e = up(p->d_piv.p, h_piv.data(), h_piv.size() * 4);
     if (e == hipSuccess) e = up(p->d_pi.p, h_pi.data(), h_pi.size() * 4);
     if (e == hipSuccess) e = up(p->d_sgn.p, h_sgn.data(), h_sgn.size());
@@ -886,7 +923,7 @@ sc_status_t sc_query(sc_plan_t P, int32_t sub, int64_t* n, int64_t* m, int64_t* 
 
 sc_status_t sc_plan_stats(sc_plan_t P, int32_t* nsub, int64_t* dual_total, double* trsm_useful,
                           double* syrk_useful, double* trsm_dense, double* syrk_dense,
-                          int64_t* device_bytes) {
+                          double* trsm_reach, double* syrk_reach, int64_t* device_bytes) {
     g_last_error.clear();
     if (!P) return fail(SC_ERR_INVALID_ARG, "plan is NULL");
     if (nsub) *nsub = P->nsub;
@@ -895,6 +932,8 @@ sc_status_t sc_plan_stats(sc_plan_t P, int32_t* nsub, int64_t* dual_total, doubl
     if (syrk_useful) *syrk_useful = P->syrk_u;
     if (trsm_dense) *trsm_dense = P->trsm_d;
     if (syrk_dense) *syrk_dense = P->syrk_d;
+    if (trsm_reach) *trsm_reach = P->trsm_r;
+    if (syrk_reach) *syrk_reach = P->syrk_r;
     if (device_bytes) *device_bytes = P->device_bytes();
     return SC_OK;
 }
@@ -937,6 +976,8 @@ sc_status_t sc_host_analyze(const sc_subdomain_desc_t* sd, const sc_options_t* o
         h.trsm_dense = sp.trsm_dense;
         h.syrk_dense = sp.syrk_dense;
         h.factor_flops = sp.factor_flops;
+        h.trsm_reach = sp.trsm_reach;
+        h.syrk_reach = sp.syrk_reach;
         h.trsm_visits = (int64_t)sp.visit.size();
         h.stair_visits = sp.visits_stair;
         *info = h;

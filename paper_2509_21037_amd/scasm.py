@@ -51,7 +51,8 @@ class HostInfo(ctypes.Structure):
                 ("trsm_useful", ctypes.c_double), ("syrk_useful", ctypes.c_double),
                 ("trsm_dense", ctypes.c_double), ("syrk_dense", ctypes.c_double),
                 ("factor_flops", ctypes.c_double), ("trsm_visits", ctypes.c_int64),
-                ("stair_visits", ctypes.c_int64)]
+                ("stair_visits", ctypes.c_int64), ("trsm_reach", ctypes.c_double),
+                ("syrk_reach", ctypes.c_double)]
 
 
 _lib = None
@@ -73,7 +74,7 @@ def load():
         lib.sc_apply_implicit.argtypes = [vp, vp, vp, vp]
         lib.sc_get_F.argtypes = [vp, i32, vp, i32, i32, vp]
         lib.sc_query.argtypes = [vp, i32, i64p, i64p, i64p, i64p, dp]
-        lib.sc_plan_stats.argtypes = [vp, ctypes.POINTER(i32), i64p, dp, dp, dp, dp, i64p]
+        lib.sc_plan_stats.argtypes = [vp, ctypes.POINTER(i32), i64p, dp, dp, dp, dp, dp, dp, i64p]
         lib.sc_plan_destroy.argtypes = [vp]
         lib.sc_host_analyze.argtypes = [ctypes.POINTER(SubdomainDesc), ctypes.POINTER(Options), vp, vp, vp,
                                          vp, vp, ctypes.POINTER(HostInfo), ctypes.POINTER(i32)]
@@ -309,11 +310,13 @@ class Plan:
     def stats(self) -> dict:
         ns = ctypes.c_int32()
         dt, db = ctypes.c_int64(), ctypes.c_int64()
-        tu, su, td, sd = (ctypes.c_double() for _ in range(4))
+        tu, su, td, sd, tr, sr = (ctypes.c_double() for _ in range(6))
         _check(self._lib.sc_plan_stats(self._h, ctypes.byref(ns), ctypes.byref(dt), ctypes.byref(tu),
-                                       ctypes.byref(su), ctypes.byref(td), ctypes.byref(sd), ctypes.byref(db)))
+                                       ctypes.byref(su), ctypes.byref(td), ctypes.byref(sd), ctypes.byref(tr),
+                                       ctypes.byref(sr), ctypes.byref(db)))
         return {"nsub": ns.value, "dual_total": dt.value, "trsm_useful": tu.value, "syrk_useful": su.value,
-                "trsm_dense": td.value, "syrk_dense": sd.value, "device_bytes": db.value}
+                "trsm_dense": td.value, "syrk_dense": sd.value, "trsm_reach": tr.value, "syrk_reach": sr.value,
+                "device_bytes": db.value}
 
     def set_timing(self, enable: bool = True):
         _check(self._lib.sc_set_timing(self._h, 1 if enable else 0))

@@ -162,6 +162,20 @@ def test_trsm_visits_exactly_the_blocks_with_nonzero_rows_of_x(name, make):
         stair += len(row0) - 1 - blk[piv[64 * t]]
     assert r["trsm_visits"] == len(visit)
     assert r["stair_visits"] == stair
+    # structural flop counts: r(i) = columns of X nonzero in row i, c_i from
+    # the symbolic pattern of the permuted matrix
+    perm = r["perm"]
+    pat = np.tril(s.Kreg_csr().toarray()[np.ix_(perm, perm)] != 0)
+    for j in range(n):
+        below = np.nonzero(pat[j + 1:, j])[0] + j + 1
+        if len(below):
+            pat[np.ix_(below, below)] |= np.tril(np.ones((len(below), len(below)), bool))
+    c = pat.sum(axis=0).astype(float)
+    a = (X != 0).sum(axis=1).astype(float)
+    t_reach, s_reach = float((a * (2 * c - 1)).sum()), float((a * (a + 1)).sum())
+    assert abs(r["trsm_reach"] - t_reach) <= 1e-12 * t_reach
+    assert abs(r["syrk_reach"] - s_reach) <= 1e-12 * s_reach
+    assert r["trsm_reach"] <= r["trsm_useful"] and r["syrk_reach"] <= r["syrk_useful"]
     if name == "heat12":
         assert r["trsm_visits"] < 0.6 * r["stair_visits"]
     # without the reach every block from the first pivot's on; without the
