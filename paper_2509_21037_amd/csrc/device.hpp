@@ -45,14 +45,16 @@ struct TileDev {
 // One lower-triangle F output tile (I >= J, in units of kSyrkTile columns).
 // Its k-range is a list of 16-row steps: those where some X row of tile I and
 // some X row of tile J can be nonzero (every other step adds zero products).
+// Entry s = first row of the step | slab bits << kStepSlabShift, bit q set
+// when 64-column slab q (2I, 2I+1, 2J, 2J+1) has a nonzero row in the step.
 struct SyrkItem {
     int32_t sub;
     int32_t I, J;
     int32_t nsteps;
-    int64_t step_off;     // first row of step s at ksteps[step_off + s]
-    int32_t skip[4];      // FP32 SYRK: leading steps wholly above the first pivots
-                          // of wavefront w's two column halves
+    int64_t step_off;     // entries at ksteps[step_off .. step_off + nsteps)
 };
+constexpr int kStepSlabShift = 27;
+constexpr int kStepRowMask = (1 << kStepSlabShift) - 1;   // rows below 2^27 (checked at plan creation)
 
 struct BlockDev {
     int32_t row0, w, nbelow, ld;

@@ -182,12 +182,20 @@ __device__ __forceinline__ void trsm_tile(
     else LA = lval + S.lval_off;
     const int my_start = tiles[ti].start_block[wv];
     // the blocks this tile visits, increasing: those holding rows on the
-    // elimination-tree paths of its pivots (all other rows of the slab stay 0)
+    // elimination-tree paths of its pivots (all other rows of X are zero)
     const int nv = T.nvisit;
     const int32_t* __restrict__ V = visit + T.visit_off;
 
-    // right-hand side P B^T: sign at the pivot row, zero elsewhere
-    for (int r = kstart + g; r < n; r += 4) Xs[(int64_t)(r - kstart) * kTile + col] = TX(0);
+    // right-hand side P B^T: sign at the pivot row, zero elsewhere.  Only the
+    // rows of visited blocks are cleared: the others are off every path, the
+    // sweep writes them at most with exact-zero updates of whatever they held,
+    // and the SYRK never reads them (its step entries mark the slabs with
+    // nonzero rows per step)
+    for (int k = 0; k < nv; ++k) {
+        const int r0 = B[V[k]].row0;
+        const int r1 = r0 + B[V[k]].w;
+        for (int r = max(r0, kstart) + g; r < r1; r += 4) Xs[(int64_t)(r - kstart) * kTile + col] = TX(0);
+    }
     __threadfence_block();
     if (g == 0 && col < T.ncols) Xs[(int64_t)(piv[cbase + col] - kstart) * kTile + col] = (TX)sgn[cbase + col];
     if (nv <= 0) return;
@@ -395,11 +403,13 @@ __global__ __launch_bounds__(256, 2) void trsm_stair_mixed(
 // ---------------------------------------------------------------------------
 // Staircase SYRK, F = X^T X (Sec. 3.3, output splitting): one workgroup per
 // lower 128 x 128 tile (I >= J) of the column-sorted F, each wavefront a
-// 64 x 64 quadrant (4 x 4 MFMA tiles).  The k-range starts at the first pivot
-// of tile I, which bounds the nonzero rows of both operands (rows of a slab
-// above its own first pivot are zero and are not stored).  X rows are staged
-// through double-buffered LDS, 16 rows per step, the next step prefetched into
-// registers.  F stays in the sorted column order (the permutation back to the
+// 64 x 64 quadrant (4 x 4 MFMA tiles).  The k-range is the item's list of
+// 16-row steps: those where both column tiles hold rows on the elimination-
+// tree paths of their pivots (the staircase bound, rows below the first pivot
+// of tile I, is the outer limit of that set); each entry marks which of the
+// four 64-column slabs have nonzero rows in the step, the others read as
+// zero (their rows may never have been written).  X rows are staged through double-buffered LDS, 16 rows per
+// step, the next step prefetched into registers.  F stays in the sorted column order (the permutation back to the
 // multiplier order is applied to the vectors of the apply and by sc_get_F):
 // the lower triangle of 128 x 128 tiles, tile (I, J) at I(I+1)/2 + J, each
 // row-major; diagonal tiles in full (all four wavefronts compute).  Columns
@@ -449,9 +459,12 @@ __device__ __forceinline__ void syrk_item_f64(
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
 
-    // thread -> (row, column pair) of a 16 x 128 step, 4 pairs per operand
+    // thread -> (row, column pair) of a 16 x 128 step, 4 pairs per operand;
+    // a slab whose bit is clear in the step entry holds no nonzero row there
+    // (its rows may never have been written) and reads as zero
     double2 rI[4], rJ[4];
-    auto load_step = [&](int kb) {
+    auto load_step = [&](int ent) {
+        const int kb = ent & kStepRowMask;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int idx = threadIdx.x + 256 * e;
@@ -461,10 +474,12 @@ __device__ __forceinline__ void syrk_item_f64(
             const int c = cc & 63;
             const int k = kb + rr;
             const int qi = half, qj = 2 + half;
-            rI[e] = (k < n && k >= ks[qi]) ? *reinterpret_cast<const double2*>(xs[qi] + (int64_t)(k - ks[qi]) * kTile + c)
-                                           : make_double2(0.0, 0.0);
-            rJ[e] = (k < n && k >= ks[qj]) ? *reinterpret_cast<const double2*>(xs[qj] + (int64_t)(k - ks[qj]) * kTile + c)
-                                           : make_double2(0.0, 0.0);
+            const bool li = ((ent >> (kStepSlabShift + qi)) & 1) && k < n && k >= ks[qi];
+            const bool lj = ((ent >> (kStepSlabShift + qj)) & 1) && k < n && k >= ks[qj];
+            rI[e] = li ? *reinterpret_cast<const double2*>(xs[qi] + (int64_t)(k - ks[qi]) * kTile + c)
+                       : make_double2(0.0, 0.0);
+            rJ[e] = lj ? *reinterpret_cast<const double2*>(xs[qj] + (int64_t)(k - ks[qj]) * kTile + c)
+                       : make_double2(0.0, 0.0);
         }
     };
     auto store_step = [&](int buf) {
@@ -578,8 +593,7 @@ __device__ __forceinline__ void syrk_item_f32(
         }
     }
     const int32_t* __restrict__ KS = ksteps + it.step_off;
-    // a diagonal tile reads one slab pair (sJ aliases sI); a wavefront skips the
-    // k-steps that lie wholly above the first pivot of both its column halves
+    // a diagonal tile reads one slab pair (sJ aliases sI)
     const bool diag = it.I == it.J;
 
     v4f acc[4][4];
@@ -590,7 +604,8 @@ __device__ __forceinline__ void syrk_item_f32(
 
     // thread -> (row, 4 columns) of a 16 x 128 step, 2 per operand
     float4 rI[kSyrkKCF / 8], rJ[kSyrkKCF / 8];
-    auto load_step = [&](int kb) {
+    auto load_step = [&](int ent) {
+        const int kb = ent & kStepRowMask;
 #pragma unroll
         for (int e = 0; e < kSyrkKCF / 8; ++e) {
             const int idx = threadIdx.x + 256 * e;
@@ -600,11 +615,12 @@ __device__ __forceinline__ void syrk_item_f32(
             const int c = cc & 63;
             const int k = kb + rr;
             const int qi = half, qj = 2 + half;
-            rI[e] = (k < n && k >= ks[qi]) ? *reinterpret_cast<const float4*>(xs[qi] + (int64_t)(k - ks[qi]) * kTile + c)
-                                           : make_float4(0.f, 0.f, 0.f, 0.f);
-            rJ[e] = (!diag && k < n && k >= ks[qj])
-                        ? *reinterpret_cast<const float4*>(xs[qj] + (int64_t)(k - ks[qj]) * kTile + c)
-                        : make_float4(0.f, 0.f, 0.f, 0.f);
+            const bool li = ((ent >> (kStepSlabShift + qi)) & 1) && k < n && k >= ks[qi];
+            const bool lj = !diag && ((ent >> (kStepSlabShift + qj)) & 1) && k < n && k >= ks[qj];
+            rI[e] = li ? *reinterpret_cast<const float4*>(xs[qi] + (int64_t)(k - ks[qi]) * kTile + c)
+                       : make_float4(0.f, 0.f, 0.f, 0.f);
+            rJ[e] = lj ? *reinterpret_cast<const float4*>(xs[qj] + (int64_t)(k - ks[qj]) * kTile + c)
+                       : make_float4(0.f, 0.f, 0.f, 0.f);
         }
     };
     auto store_step = [&](int buf) {
@@ -624,17 +640,7 @@ __device__ __forceinline__ void syrk_item_f32(
         store_step(0);
     }
     __syncthreads();
-    // leading steps wholly above this wavefront's pivots: loads only (same
-    // barriers as the rest)
-    const int skip = wv == 0 ? it.skip[0] : wv == 1 ? it.skip[1] : wv == 2 ? it.skip[2] : it.skip[3];
-    int st = 0;
-    for (; st < skip; ++st) {
-        const int buf = st & 1;
-        if (st + 1 < nsteps) load_step(KS[st + 1]);
-        if (st + 1 < nsteps) store_step(buf ^ 1);
-        __syncthreads();
-    }
-    for (; st < nsteps; ++st) {
+    for (int st = 0; st < nsteps; ++st) {
         const int buf = st & 1;
         if (st + 1 < nsteps) load_step(KS[st + 1]);
         {

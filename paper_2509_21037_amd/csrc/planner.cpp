@@ -206,6 +206,7 @@ std::string build_plan(const SubdomainInput& in, const PlanOptions& opt, SubPlan
     code = 1;
     const int32_t n = in.n;
     if (n <= 0) return "n must be positive";
+    if (n >= (1 << 27)) return "n must be below 2^27";
     if (!in.rowptr || !in.col) return "K_reg pattern missing";
     if (in.m < 0) return "m must be non-negative";
     if (in.m > 0 && (!in.dof || !in.sign)) return "B^T columns missing";

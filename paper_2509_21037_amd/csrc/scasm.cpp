@@ -353,33 +353,28 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
         s.ftile_off = (int64_t)P->h_ftiles.size();
         {
             // k-steps of each F tile: 16-row steps where both column tiles can
-            // hold nonzero X rows
+            // hold nonzero X rows, tagged with the slabs that do
             const int32_t nw = sp.mask_words;
-            std::vector<uint64_t> fm((size_t)nst * nw, 0);
-            for (int32_t t = 0; t < s.ntiles; ++t)
-                for (int32_t q = 0; q < nw; ++q) fm[(size_t)(t / 2) * nw + q] |= sp.step_mask[(size_t)t * nw + q];
-            auto kstart = [&](int32_t t64) {
-                return t64 < s.ntiles ? P->h_tiles[s.tile_off + t64].kstart : INT32_MAX;
+            auto mask = [&](int32_t t64, int32_t q) -> uint64_t {
+                return t64 < s.ntiles ? sp.step_mask[(size_t)t64 * nw + q] : 0;
             };
             for (int32_t I = 0; I < nst; ++I) {
                 P->h_frows.push_back(make_int2(i, I));
                 for (int32_t J = 0; J <= I; ++J) {
-                    SyrkItem it{i, I, J, 0};
-                    it.step_off = (int64_t)P->h_ksteps.size();
+                    SyrkItem it{i, I, J, 0, (int64_t)P->h_ksteps.size()};
                     for (int32_t q = 0; q < nw; ++q) {
-                        uint64_t b = fm[(size_t)I * nw + q] & fm[(size_t)J * nw + q];
+                        const uint64_t m0 = mask(2 * I, q), m1 = mask(2 * I + 1, q);
+                        const uint64_t m2 = mask(2 * J, q), m3 = mask(2 * J + 1, q);
+                        uint64_t b = (m0 | m1) & (m2 | m3);
                         while (b) {
-                            P->h_ksteps.push_back(16 * (64 * q + __builtin_ctzll(b)));
+                            const int bit = __builtin_ctzll(b);
+                            const int32_t tag = (int32_t)(((m0 >> bit) & 1) | (((m1 >> bit) & 1) << 1) |
+                                                          (((m2 >> bit) & 1) << 2) | (((m3 >> bit) & 1) << 3));
+                            P->h_ksteps.push_back(16 * (64 * q + bit) | tag << kStepSlabShift);
                             b &= b - 1;
                         }
                     }
                     it.nsteps = (int32_t)(P->h_ksteps.size() - it.step_off);
-                    for (int w = 0; w < 4; ++w) {
-                        const int32_t kw = std::max(kstart(2 * I + (w >> 1)), kstart(2 * J + (w & 1)));
-                        int32_t k = 0;
-                        while (k < it.nsteps && P->h_ksteps[it.step_off + k] + 16 <= kw) ++k;
-                        it.skip[w] = k;
-                    }
                     P->h_syrk.push_back(it);
                 }
             }
