@@ -5,12 +5,15 @@ long-double oracle F = B K_reg^{-1} B^T on the same seeded inputs; the bar is
 a relative Frobenius error <= 1e-12 per subdomain.  At the full workload sizes
 the comparison uses seeded column subsets S (F[S, S]) the oracle computes on
 its own."""
+import os
+
 import numpy as np
 import pytest
 
 import oracle
 import scgen
 from scgen.mesh import Subdomain
+from scgen.rng import signs_from_seed, stream_seed
 
 P = pytest.importorskip("paper_2509_21037_amd")
 pytestmark = pytest.mark.gpu
@@ -183,6 +186,38 @@ def test_full_elasticity_workload_sampled():
         sel = np.sort(np.random.default_rng(i).choice(s.m, size=min(128, s.m), replace=False))
         F = plan.get_F(i)
         assert oracle.relF(F[np.ix_(sel, sel)], oracle.schur(s, sel=sel)) <= TOL_FP64
+
+
+def _large_workload_sample():
+    """The 64 x 20^3 elasticity batch (one mesh, per-subdomain signs) and the
+    stored oracle sample F_0[S, S] of its subdomain 0."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "elast3d_hex8_20cube_F_sample.txt")
+    with open(path) as f:
+        f.readline()
+        sel = np.array([int(v) for v in f.readline().split()], dtype=np.int64)
+    F0 = np.loadtxt(path, comments="#", skiprows=2).reshape(len(sel), len(sel), order="F")
+    s0 = scgen.config_subdomains(5, count=1)[0]
+    base = scgen.BASE_SEED + 5
+    subs = [s0] + [s0.with_signs(signs_from_seed(stream_seed(base, i), s0.m)) for i in range(1, 64)]
+    return subs, sel, F0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_full_large_elasticity_workload_sampled(precision):
+    """All 64 subdomains of the 20^3 elasticity workload (n = 27783, m = 7938)
+    in one assembly, as the benchmark launches it (captured graph); sampled
+    columns of four subdomains against the stored oracle sample.  The
+    subdomains share K and the multiplier DOFs, so F_k[S, S] = D F_0[S, S] D
+    with D = diag(sign_k sign_0)[S] exactly."""
+    subs, sel, F0 = _large_workload_sample()
+    plan = _assemble(subs, precision=precision, use_graph=True)
+    plan.assemble()
+    tol = TOL_FP64 if precision == "fp64" else TOL_MIXED
+    for k in (0, 21, 42, 63):
+        d = (subs[k].sign.astype(np.float64) * subs[0].sign)[sel]
+        F = plan.get_F(k)[np.ix_(sel, sel)]
+        assert oracle.relF(F, d[:, None] * F0 * d[None, :]) <= tol, k
+    plan.destroy()
 
 
 def _dual_vectors(plan, subs, seed=0):

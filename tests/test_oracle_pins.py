@@ -199,6 +199,21 @@ def test_each_planted_mistake_is_caught(mutation):
     assert not _pins_pass(mutation)
 
 
+def test_large_golden_sample_reproduces():
+    """The stored F[S, S] sample of the 20^3 elasticity subdomain (written by
+    tests/golden/make_golden.py) is what the oracle computes, and it is
+    symmetric with a positive diagonal."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "elast3d_hex8_20cube_F_sample.txt")
+    with open(path) as f:
+        f.readline()
+        sel = np.array([int(v) for v in f.readline().split()], dtype=np.int64)
+    F = np.loadtxt(path, comments="#", skiprows=2).reshape(len(sel), len(sel), order="F")
+    assert np.array_equal(F, F.T) and np.all(np.diag(F) > 0)
+    s = scgen.config_subdomains(5, count=1)[0]
+    assert oracle.relF(oracle.schur(s, sel=sel), F) < 1e-16
+
+
 def test_golden_fixture_reproduces():
     import os
     path = os.path.join(os.path.dirname(__file__), "golden", "heat2d_q1_16x16_F.txt")
