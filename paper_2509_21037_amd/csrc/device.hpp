@@ -42,17 +42,25 @@ struct TileDev {
     int32_t nvisit, pad;      // increasing indices relative to the subdomain's first block
 };
 
-// One lower-triangle F output tile (I >= J, in units of kSyrkTile columns).
-// Its k-range is a list of 16-row steps: those where some X row of tile I and
-// some X row of tile J can be nonzero (every other step adds zero products).
-// Entry s = first row of the step | slab bits << kStepSlabShift, bit q set
-// when 64-column slab q (2I, 2I+1, 2J, 2J+1) has a nonzero row in the step.
+// SYRK work item.  Subdomains with n <= kSyrkBlockMaxN (FP64; FP32:
+// kSyrkBlockMaxNMixed): a 64 x 64 block of F
+// (I >= J in units of 64-column X tiles), its k-range a list of 16-row steps
+// (first rows at ksteps[step_off .. step_off + nsteps)) where both X tiles can
+// hold a nonzero row.  Larger subdomains: a 128 x 128 tile of F (I >= J in
+// units of kSyrkTile), each step entry = first row | slab bits <<
+// kStepSlabShift, bit q set when 64-column slab q (2I, 2I+1, 2J, 2J+1) has a
+// nonzero row in the step.  Every other step adds zero products.  Also used,
+// in units of kSyrkTile and without steps, for the stored F tiles of the apply.
 struct SyrkItem {
     int32_t sub;
     int32_t I, J;
     int32_t nsteps;
-    int64_t step_off;     // entries at ksteps[step_off .. step_off + nsteps)
+    int64_t step_off;
 };
+// measured on the elasticity batches: the FP64 blocks beat the tiles up to
+// n = 14739 and lose at 27783; the FP32 tiles win above ~6000
+constexpr int kSyrkBlockMaxN = 16384;
+constexpr int kSyrkBlockMaxNMixed = 6144;
 constexpr int kStepSlabShift = 27;
 constexpr int kStepRowMask = (1 << kStepSlabShift) - 1;   // rows below 2^27 (checked at plan creation)
 

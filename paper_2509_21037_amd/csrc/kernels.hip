@@ -402,31 +402,162 @@ __global__ __launch_bounds__(256, 2) void trsm_stair_mixed(
 
 // ---------------------------------------------------------------------------
 // Staircase SYRK, F = X^T X (Sec. 3.3, output splitting): one workgroup per
-// lower 128 x 128 tile (I >= J) of the column-sorted F, each wavefront a
-// 64 x 64 quadrant (4 x 4 MFMA tiles).  The k-range is the item's list of
-// 16-row steps: those where both column tiles hold rows on the elimination-
-// tree paths of their pivots (the staircase bound, rows below the first pivot
-// of tile I, is the outer limit of that set); each entry marks which of the
-// four 64-column slabs have nonzero rows in the step, the others read as
-// zero (their rows may never have been written).  X rows are staged through double-buffered LDS, 16 rows per
-// step, the next step prefetched into registers.  F stays in the sorted column order (the permutation back to the
-// multiplier order is applied to the vectors of the apply and by sc_get_F):
-// the lower triangle of 128 x 128 tiles, tile (I, J) at I(I+1)/2 + J, each
-// row-major; diagonal tiles in full (all four wavefronts compute).  Columns
-// past m are zero in X, so the padding of the last tiles holds zeros.
+// 64 x 64 block (I >= J, in units of 64-column X tiles) of the lower triangle
+// of the column-sorted F; wavefront w computes its rows 16w .. 16w + 15
+// (1 x 4 MFMA tiles).  The k-range is the block's list of 16-row steps: those
+// where both X tiles hold rows on the elimination-tree paths of their pivots
+// (every other step adds zero products; the staircase bound, rows below the
+// first pivot of tile I, is the outer limit of that set).  Blocks with an
+// empty list are structurally zero and are not launched: the plan clears F
+// once when it is created.  Used for subdomains up to kSyrkBlockMaxN rows
+// (FP32: kSyrkBlockMaxNMixed), whose X slabs largely stay in L2 while their
+// blocks re-read them.  X rows are
+// staged through double-buffered LDS, 16 rows per step, the next step
+// prefetched into registers.  F stays in the
+// sorted column order (the permutation back to the multiplier order is applied
+// to the vectors of the apply and by sc_get_F), stored as the lower triangle
+// of 128 x 128 tiles, tile (I, J) at I(I+1)/2 + J, each row-major, diagonal
+// tiles whole: block (2T+1, 2T) also writes its transpose, the upper quadrant
+// of diagonal tile T.  Columns past m are never written and stay zero.
 // ---------------------------------------------------------------------------
-constexpr int kSyrkKC = 16;
-constexpr int kSyrkLd = kSyrkTile + 4;
+constexpr int kSyrkKC = 16;                  // X rows per step
+constexpr int kSyrkLd = kTile + 4;           // LDS row stride (elements)
 
-constexpr int kSyrkSmem = 4 * kSyrkKC * kSyrkLd * 8;
+template <class TX>
+constexpr int kSyrkSmem = 4 * kSyrkKC * kSyrkLd * (int)sizeof(TX);
 
-__device__ __forceinline__ void syrk_item_f64(
+template <bool MIXED>
+__device__ __forceinline__ void syrk_block(
+    const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles, const SyrkItem it,
+    const int32_t* __restrict__ ksteps, const typename std::conditional<MIXED, float, double>::type* __restrict__ X,
+    typename std::conditional<MIXED, float, double>::type* __restrict__ F, char* __restrict__ smem)
+{
+    using TX = typename std::conditional<MIXED, float, double>::type;
+    using VX = typename std::conditional<MIXED, v4f, v4d>::type;
+    using LV = typename std::conditional<MIXED, float4, double2>::type;
+    constexpr int kVec = sizeof(LV) / sizeof(TX);                // elements per load
+    constexpr int kPer = kSyrkKC * kTile / kVec / 256;           // loads per thread and slab
+    TX (*sA)[kSyrkKC * kSyrkLd] = reinterpret_cast<TX (*)[kSyrkKC * kSyrkLd]>(smem);
+    TX (*sB)[kSyrkKC * kSyrkLd] = sA + 2;
+    const SubDev S = subs[it.sub];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int g = lane >> 4;
+    const int j = lane & 15;
+    const int n = S.n;
+    const bool diag = it.I == it.J;          // one slab: sB aliases sA
+    const TileDev& TI = tiles[S.tile_off + it.I];
+    const TileDev& TJ = tiles[S.tile_off + it.J];
+    const TX* __restrict__ xi = X + TI.x_off;
+    const TX* __restrict__ xj = X + TJ.x_off;
+    const int ki = TI.kstart, kj = TJ.kstart;
+    const int32_t* __restrict__ KS = ksteps + it.step_off;
+    const int nsteps = it.nsteps;
+
+    VX acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[t][r] = TX(0);
+
+    LV rA[kPer], rB[kPer];
+    auto load_step = [&](int kb) {
+#pragma unroll
+        for (int e = 0; e < kPer; ++e) {
+            const int idx = threadIdx.x + 256 * e;
+            const int rr = idx / (kTile / kVec);
+            const int cc = kVec * (idx % (kTile / kVec));
+            const int k = kb + rr;
+            if (k < n && k >= ki) rA[e] = *reinterpret_cast<const LV*>(xi + (int64_t)(k - ki) * kTile + cc);
+            else rA[e] = LV{};
+            if (!diag && k < n && k >= kj) rB[e] = *reinterpret_cast<const LV*>(xj + (int64_t)(k - kj) * kTile + cc);
+            else rB[e] = LV{};
+        }
+    };
+    auto store_step = [&](int buf) {
+#pragma unroll
+        for (int e = 0; e < kPer; ++e) {
+            const int idx = threadIdx.x + 256 * e;
+            const int rr = idx / (kTile / kVec);
+            const int cc = kVec * (idx % (kTile / kVec));
+            *reinterpret_cast<LV*>(&sA[buf][rr * kSyrkLd + cc]) = rA[e];
+            if (!diag) *reinterpret_cast<LV*>(&sB[buf][rr * kSyrkLd + cc]) = rB[e];
+        }
+    };
+
+    if (nsteps > 0) {
+        load_step(KS[0]);
+        store_step(0);
+    }
+    __syncthreads();
+    for (int st = 0; st < nsteps; ++st) {
+        const int buf = st & 1;
+        if (st + 1 < nsteps) load_step(KS[st + 1]);
+        const TX* __restrict__ pa = &sA[buf][g * kSyrkLd + 16 * wv + j];
+        const TX* __restrict__ pb = &(diag ? sA : sB)[buf][g * kSyrkLd + j];
+#pragma unroll
+        for (int s = 0; s < kSyrkKC / 4; ++s) {
+            const TX a = pa[4 * s * kSyrkLd];
+            TX b[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) b[t] = pb[4 * s * kSyrkLd + 16 * t];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if constexpr (MIXED) acc[t] = mfma_f32(a, b[t], acc[t]);
+                else acc[t] = mfma_f64(a, b[t], acc[t]);
+            }
+        }
+        if (st + 1 < nsteps) store_step(buf ^ 1);
+        __syncthreads();
+    }
+    const int I2 = it.I >> 1, J2 = it.J >> 1;
+    TX* __restrict__ Ft = F + S.F_off + (int64_t)(I2 * (I2 + 1) / 2 + J2) * kFTileElems;
+    const bool mirror = I2 == J2 && !diag;
+    const int r0 = 64 * (it.I & 1) + 16 * wv;
+    const int c0 = 64 * (it.J & 1);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = r0 + (MIXED ? 4 * g + r : 4 * r + g);
+            const int col = c0 + 16 * t + j;
+            Ft[row * kSyrkTile + col] = acc[t][r];
+            if (mirror) Ft[col * kSyrkTile + row] = acc[t][r];
+        }
+}
+
+__global__ __launch_bounds__(256) void syrk_block_f64(
+    const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
+    const SyrkItem* __restrict__ items, const int32_t* __restrict__ ksteps, const double* __restrict__ X,
+    double* __restrict__ F)
+{
+    __shared__ __align__(16) char smem[kSyrkSmem<double>];
+    const SyrkItem it = items[blockIdx.x];
+    if (it.sub < 0) return;
+    syrk_block<false>(subs, tiles, it, ksteps, X, F, smem);
+}
+
+// ---------------------------------------------------------------------------
+// The same SYRK over 128 x 128 tiles (I >= J in units of kSyrkTile), each
+// wavefront a 64 x 64 quadrant (4 x 4 MFMA tiles): twice the MFMA work per
+// byte of X of the 64 x 64 blocks, used for the subdomains whose X slabs are
+// too large to be re-read from L2 (n above kSyrkBlockMaxN, FP32 above
+// kSyrkBlockMaxNMixed).  The k-range is the
+// tile's list of 16-row steps where both column halves can hold nonzero rows;
+// each entry marks which of the four 64-column slabs have nonzero rows in
+// the step (bits at kStepSlabShift), the others read as zero (their rows may
+// never have been written).  Diagonal tiles are computed whole.
+// ---------------------------------------------------------------------------
+constexpr int kWideLd = kSyrkTile + 4;
+constexpr int kWideSmem = 4 * kSyrkKC * kWideLd * 8;
+
+__device__ __forceinline__ void syrk_tile_item_f64(
     const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles, const SyrkItem it,
     const int32_t* __restrict__ ksteps, const double* __restrict__ X, double* __restrict__ F,
     char* __restrict__ smem)
 {
-    double (*sI)[kSyrkKC * kSyrkLd] = reinterpret_cast<double (*)[kSyrkKC * kSyrkLd]>(smem);
-    double (*sJ)[kSyrkKC * kSyrkLd] = sI + 2;
+    double (*sI)[kSyrkKC * kWideLd] = reinterpret_cast<double (*)[kSyrkKC * kWideLd]>(smem);
+    double (*sJ)[kSyrkKC * kWideLd] = sI + 2;
     const SubDev S = subs[it.sub];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -488,8 +619,8 @@ __device__ __forceinline__ void syrk_item_f64(
             const int idx = threadIdx.x + 256 * e;
             const int rr = idx >> 6;
             const int cc = 2 * (idx & 63);
-            *reinterpret_cast<double2*>(&sI[buf][rr * kSyrkLd + cc]) = rI[e];
-            *reinterpret_cast<double2*>(&sJ[buf][rr * kSyrkLd + cc]) = rJ[e];
+            *reinterpret_cast<double2*>(&sI[buf][rr * kWideLd + cc]) = rI[e];
+            *reinterpret_cast<double2*>(&sJ[buf][rr * kWideLd + cc]) = rJ[e];
         }
     };
 
@@ -505,8 +636,8 @@ __device__ __forceinline__ void syrk_item_f64(
         {
 #pragma unroll
             for (int s = 0; s < kSyrkKC / 4; ++s) {
-                const double* ai = &sI[buf][(4 * s + g) * kSyrkLd + 64 * wi + j];
-                const double* bj = &sJ[buf][(4 * s + g) * kSyrkLd + 64 * wj + j];
+                const double* ai = &sI[buf][(4 * s + g) * kWideLd + 64 * wi + j];
+                const double* bj = &sJ[buf][(4 * s + g) * kWideLd + 64 * wj + j];
                 double a[4], b[4];
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
@@ -532,15 +663,15 @@ __device__ __forceinline__ void syrk_item_f64(
                 Ft[(64 * wi + 16 * ti + 4 * r + g) * kSyrkTile + 64 * wj + 16 * tj + j] = acc[ti][tj][r];
 }
 
-__global__ __launch_bounds__(256) void syrk_stair_f64(
+__global__ __launch_bounds__(256) void syrk_tile_f64(
     const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
     const SyrkItem* __restrict__ items, const int32_t* __restrict__ ksteps, const double* __restrict__ X,
     double* __restrict__ F)
 {
-    __shared__ __align__(16) char smem[kSyrkSmem];
+    __shared__ __align__(16) char smem[kWideSmem];
     const SyrkItem it = items[blockIdx.x];
     if (it.sub < 0) return;
-    syrk_item_f64(subs, tiles, it, ksteps, X, F, smem);
+    syrk_tile_item_f64(subs, tiles, it, ksteps, X, F, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -554,21 +685,30 @@ __global__ __launch_bounds__(256) void convert_f64_f32(const double* __restrict_
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) b[i] = (float)a[i];
 }
-// FP32 staircase SYRK: as syrk_stair_f64 with FP32 X, FP32 MFMA and FP32
-// accumulation, 16 rows per LDS step (33 KB of LDS: 3 workgroups per CU); F
-// stored FP32.
-constexpr int kSyrkKCF = 16;
-constexpr int kSyrkLdF = kSyrkTile + 4;
+// FP32 SYRK over 64 x 64 blocks: as syrk_block_f64 with FP32 X, FP32 MFMA and
+// FP32 accumulation; F stored FP32.
+__global__ __launch_bounds__(256) void syrk_block_f32(
+    const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
+    const SyrkItem* __restrict__ items, const int32_t* __restrict__ ksteps, const float* __restrict__ X,
+    float* __restrict__ F)
+{
+    __shared__ __align__(16) char smem[kSyrkSmem<float>];
+    const SyrkItem it = items[blockIdx.x];
+    if (it.sub < 0) return;
+    syrk_block<true>(subs, tiles, it, ksteps, X, F, smem);
+}
 
-constexpr int kSyrkSmemF = 4 * kSyrkKCF * kSyrkLdF * 4;
+// FP32 SYRK over 128 x 128 tiles: as syrk_tile_f64 with FP32 X, FP32 MFMA and
+// FP32 accumulation (33 KB of LDS: 4 workgroups per CU); F stored FP32.
+constexpr int kWideSmemF = 4 * kSyrkKC * kWideLd * 4;
 
-__device__ __forceinline__ void syrk_item_f32(
+__device__ __forceinline__ void syrk_tile_item_f32(
     const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles, const SyrkItem it,
     const int32_t* __restrict__ ksteps, const float* __restrict__ X, float* __restrict__ F,
     char* __restrict__ smem)
 {
-    float (*sI)[kSyrkKCF * kSyrkLdF] = reinterpret_cast<float (*)[kSyrkKCF * kSyrkLdF]>(smem);
-    float (*sJ)[kSyrkKCF * kSyrkLdF] = sI + 2;
+    float (*sI)[kSyrkKC * kWideLd] = reinterpret_cast<float (*)[kSyrkKC * kWideLd]>(smem);
+    float (*sJ)[kSyrkKC * kWideLd] = sI + 2;
     const SubDev S = subs[it.sub];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -603,11 +743,11 @@ __device__ __forceinline__ void syrk_item_f32(
         for (int b = 0; b < 4; ++b) acc[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
 
     // thread -> (row, 4 columns) of a 16 x 128 step, 2 per operand
-    float4 rI[kSyrkKCF / 8], rJ[kSyrkKCF / 8];
+    float4 rI[kSyrkKC / 8], rJ[kSyrkKC / 8];
     auto load_step = [&](int ent) {
         const int kb = ent & kStepRowMask;
 #pragma unroll
-        for (int e = 0; e < kSyrkKCF / 8; ++e) {
+        for (int e = 0; e < kSyrkKC / 8; ++e) {
             const int idx = threadIdx.x + 256 * e;
             const int rr = idx >> 5;
             const int cc = 4 * (idx & 31);
@@ -625,12 +765,12 @@ __device__ __forceinline__ void syrk_item_f32(
     };
     auto store_step = [&](int buf) {
 #pragma unroll
-        for (int e = 0; e < kSyrkKCF / 8; ++e) {
+        for (int e = 0; e < kSyrkKC / 8; ++e) {
             const int idx = threadIdx.x + 256 * e;
             const int rr = idx >> 5;
             const int cc = 4 * (idx & 31);
-            *reinterpret_cast<float4*>(&sI[buf][rr * kSyrkLdF + cc]) = rI[e];
-            if (!diag) *reinterpret_cast<float4*>(&sJ[buf][rr * kSyrkLdF + cc]) = rJ[e];
+            *reinterpret_cast<float4*>(&sI[buf][rr * kWideLd + cc]) = rI[e];
+            if (!diag) *reinterpret_cast<float4*>(&sJ[buf][rr * kWideLd + cc]) = rJ[e];
         }
     };
 
@@ -645,9 +785,9 @@ __device__ __forceinline__ void syrk_item_f32(
         if (st + 1 < nsteps) load_step(KS[st + 1]);
         {
 #pragma unroll
-            for (int s = 0; s < kSyrkKCF / 4; ++s) {
-                const float* ai = &sI[buf][(4 * s + g) * kSyrkLdF + 64 * wi + j];
-                const float* bj = &(diag ? sI : sJ)[buf][(4 * s + g) * kSyrkLdF + 64 * wj + j];
+            for (int s = 0; s < kSyrkKC / 4; ++s) {
+                const float* ai = &sI[buf][(4 * s + g) * kWideLd + 64 * wi + j];
+                const float* bj = &(diag ? sI : sJ)[buf][(4 * s + g) * kWideLd + 64 * wj + j];
                 float a[4], b[4];
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
@@ -673,15 +813,15 @@ __device__ __forceinline__ void syrk_item_f32(
                 Ft[(64 * wi + 16 * ti + 4 * g + r) * kSyrkTile + 64 * wj + 16 * tj + j] = acc[ti][tj][r];
 }
 
-__global__ __launch_bounds__(256) void syrk_stair_f32(
+__global__ __launch_bounds__(256) void syrk_tile_f32(
     const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
     const SyrkItem* __restrict__ items, const int32_t* __restrict__ ksteps, const float* __restrict__ X,
     float* __restrict__ F)
 {
-    __shared__ __align__(16) char smem[kSyrkSmemF];
+    __shared__ __align__(16) char smem[kWideSmemF];
     const SyrkItem it = items[blockIdx.x];
     if (it.sub < 0) return;
-    syrk_item_f32(subs, tiles, it, ksteps, X, F, smem);
+    syrk_tile_item_f32(subs, tiles, it, ksteps, X, F, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -696,15 +836,28 @@ hipError_t launch_trsm(const DevTables& t, const int32_t* order, int64_t count, 
     return hipGetLastError();
 }
 
-hipError_t launch_syrk(const DevTables& t, const SyrkItem* items, int64_t count, hipStream_t stream) {
-    if (count <= 0) return hipSuccess;
-    if (t.X32)
-        hipLaunchKernelGGL(syrk_stair_f32, dim3((unsigned)count), dim3(256), 0, stream, t.subs, t.tiles, items,
-                           t.ksteps, t.X32, t.F32);
-    else
-        hipLaunchKernelGGL(syrk_stair_f64, dim3((unsigned)count), dim3(256), 0, stream, t.subs, t.tiles, items,
-                           t.ksteps, t.X, t.F);
-    return hipGetLastError();
+hipError_t launch_syrk(const DevTables& t, const SyrkItem* items, int64_t ntile, int64_t nblock,
+                       hipStream_t stream) {
+    if (ntile > 0) {
+        if (t.X32)
+            hipLaunchKernelGGL(syrk_tile_f32, dim3((unsigned)ntile), dim3(256), 0, stream, t.subs, t.tiles, items,
+                               t.ksteps, t.X32, t.F32);
+        else
+            hipLaunchKernelGGL(syrk_tile_f64, dim3((unsigned)ntile), dim3(256), 0, stream, t.subs, t.tiles, items,
+                               t.ksteps, t.X, t.F);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (nblock > 0) {
+        if (t.X32)
+            hipLaunchKernelGGL(syrk_block_f32, dim3((unsigned)nblock), dim3(256), 0, stream, t.subs, t.tiles,
+                               items + ntile, t.ksteps, t.X32, t.F32);
+        else
+            hipLaunchKernelGGL(syrk_block_f64, dim3((unsigned)nblock), dim3(256), 0, stream, t.subs, t.tiles,
+                               items + ntile, t.ksteps, t.X, t.F);
+        return hipGetLastError();
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_assemble(const DevTables& t, hipStream_t stream, hipEvent_t* ev) {
@@ -713,7 +866,7 @@ hipError_t launch_assemble(const DevTables& t, hipStream_t stream, hipEvent_t* e
     if ((e = launch_trsm(t, t.tile_order, t.ntiles, stream)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], stream)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[2], stream)) != hipSuccess) return e;
-    if ((e = launch_syrk(t, t.syrk, t.nsyrk, stream)) != hipSuccess) return e;
+    if ((e = launch_syrk(t, t.syrk, t.nsyrk_tile, t.nsyrk - t.nsyrk_tile, stream)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[3], stream)) != hipSuccess) return e;
     return hipSuccess;
 }

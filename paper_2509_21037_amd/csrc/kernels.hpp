@@ -34,6 +34,7 @@ struct DevTables {
     double* part = nullptr;                // 256 partial sums per stored F tile
     int64_t ntiles = 0;          // TRSM workgroups (length of tile_order)
     int64_t nsyrk = 0;           // SYRK workgroups (items with sub < 0 are idle)
+    int64_t nsyrk_tile = 0;      // the first nsyrk_tile of them are 128 x 128 tiles, the rest 64 x 64 blocks
     int64_t nftiles = 0;
     int64_t nfrows = 0;
 };
@@ -45,7 +46,10 @@ struct DevTables {
 //   launch_assemble: all tiles, then all SYRK items, on one stream; optional
 //     events ev[2k] before and ev[2k+1] after kernel k (0 = TRSM, 1 = SYRK).
 hipError_t launch_trsm(const DevTables& t, const int32_t* order, int64_t count, hipStream_t stream);
-hipError_t launch_syrk(const DevTables& t, const SyrkItem* items, int64_t count, hipStream_t stream);
+// SYRK over items[0, ntile) (128 x 128 tiles) then items[ntile, ntile + nblock)
+// (64 x 64 blocks).
+hipError_t launch_syrk(const DevTables& t, const SyrkItem* items, int64_t ntile, int64_t nblock,
+                       hipStream_t stream);
 hipError_t launch_assemble(const DevTables& t, hipStream_t stream, hipEvent_t* ev);
 
 // FP64 factor -> FP32 copy (mixed precision).

@@ -106,7 +106,8 @@ struct sc_plan_s {
     // kOverlapGroups consecutive parts), per group a TRSM order and SYRK list
     std::vector<int32_t> h_tile_order_g;
     std::vector<SyrkItem> h_syrk_g;
-    std::vector<int64_t> g_toff, g_tcnt, g_soff, g_scnt;
+    std::vector<int64_t> g_toff, g_tcnt, g_soff, g_stile, g_sblock;
+    int64_t nsyrk_tile = 0;                     // h_syrk: 128 x 128 tiles first, then 64 x 64 blocks
     std::vector<SyrkItem> h_ftiles;             // stored F tiles, subdomain order (apply pass 1)
     std::vector<int2> h_frows;                  // (subdomain, 128-row block) (apply pass 2)
     int64_t nval_total = 0, nrows_total = 0, ncol_total = 0, X_total = 0, F_total = 0, dual_total = 0;
@@ -172,7 +173,7 @@ struct sc_plan_s {
             if ((e = launch_trsm(t, d_tile_order_g.p + g_toff[g], g_tcnt[g], st)) != hipSuccess) return e;
             if ((e = hipEventRecord(ov_events[g], st)) != hipSuccess) return e;
             if ((e = hipStreamWaitEvent(aux, ov_events[g], 0)) != hipSuccess) return e;
-            if ((e = launch_syrk(t, d_syrk_g.p + g_soff[g], g_scnt[g], aux)) != hipSuccess) return e;
+            if ((e = launch_syrk(t, d_syrk_g.p + g_soff[g], g_stile[g], g_sblock[g], aux)) != hipSuccess) return e;
         }
         if ((e = hipEventRecord(ov_events[ng], aux)) != hipSuccess) return e;
         return hipStreamWaitEvent(st, ov_events[ng], 0);
@@ -263,6 +264,7 @@ struct sc_plan_s {
         t.tile_order = d_tile_order.p;
         t.ntiles = (int64_t)h_tile_order.size();
         t.nsyrk = (int64_t)h_syrk.size();
+        t.nsyrk_tile = nsyrk_tile;
         t.nftiles = (int64_t)h_ftiles.size();
         t.nfrows = (int64_t)h_frows.size();
         return t;
@@ -314,6 +316,9 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
                         "subdomain " + std::to_string(i) + ": " + errs[i]);
 
     // ---- tables
+    // SYRK items per subdomain: 128 x 128 tiles (large subdomains) or 64 x 64
+    // blocks
+    std::vector<std::vector<SyrkItem>> sub_tiles(nsub), sub_blocks(nsub);
     int64_t blk = 0, rows = 0, lv = 0, colo = 0, xo = 0, fo = 0, dual = 0;
     for (int32_t i = 0; i < nsub; ++i) {
         const SubPlan& sp = P->plans[i];
@@ -351,35 +356,53 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
         }
         const int32_t nst = (sp.m + kSyrkTile - 1) / kSyrkTile;
         s.ftile_off = (int64_t)P->h_ftiles.size();
+        for (int32_t I = 0; I < nst; ++I) {
+            P->h_frows.push_back(make_int2(i, I));
+            for (int32_t J = 0; J <= I; ++J) P->h_ftiles.push_back(SyrkItem{i, I, J, 0, 0});
+        }
         {
-            // k-steps of each F tile: 16-row steps where both column tiles can
-            // hold nonzero X rows, tagged with the slabs that do
+            // SYRK items with their 16-row steps where both sides can hold
+            // nonzero X rows; items without any are structurally zero and are
+            // left to the one-time clear of F
             const int32_t nw = sp.mask_words;
             auto mask = [&](int32_t t64, int32_t q) -> uint64_t {
                 return t64 < s.ntiles ? sp.step_mask[(size_t)t64 * nw + q] : 0;
             };
-            for (int32_t I = 0; I < nst; ++I) {
-                P->h_frows.push_back(make_int2(i, I));
-                for (int32_t J = 0; J <= I; ++J) {
-                    SyrkItem it{i, I, J, 0, (int64_t)P->h_ksteps.size()};
-                    for (int32_t q = 0; q < nw; ++q) {
-                        const uint64_t m0 = mask(2 * I, q), m1 = mask(2 * I + 1, q);
-                        const uint64_t m2 = mask(2 * J, q), m3 = mask(2 * J + 1, q);
-                        uint64_t b = (m0 | m1) & (m2 | m3);
-                        while (b) {
-                            const int bit = __builtin_ctzll(b);
-                            const int32_t tag = (int32_t)(((m0 >> bit) & 1) | (((m1 >> bit) & 1) << 1) |
-                                                          (((m2 >> bit) & 1) << 2) | (((m3 >> bit) & 1) << 3));
-                            P->h_ksteps.push_back(16 * (64 * q + bit) | tag << kStepSlabShift);
-                            b &= b - 1;
+            if (sp.n <= (P->mixed ? kSyrkBlockMaxNMixed : kSyrkBlockMaxN)) {
+                for (int32_t I = 0; I < s.ntiles; ++I)
+                    for (int32_t J = 0; J <= I; ++J) {
+                        SyrkItem it{i, I, J, 0, (int64_t)P->h_ksteps.size()};
+                        for (int32_t q = 0; q < nw; ++q) {
+                            uint64_t b = mask(I, q) & mask(J, q);
+                            while (b) {
+                                P->h_ksteps.push_back(16 * (64 * q + __builtin_ctzll(b)));
+                                b &= b - 1;
+                            }
                         }
+                        it.nsteps = (int32_t)(P->h_ksteps.size() - it.step_off);
+                        if (it.nsteps > 0) sub_blocks[i].push_back(it);
                     }
-                    it.nsteps = (int32_t)(P->h_ksteps.size() - it.step_off);
-                    P->h_syrk.push_back(it);
-                }
+            } else {
+                for (int32_t I = 0; I < nst; ++I)
+                    for (int32_t J = 0; J <= I; ++J) {
+                        SyrkItem it{i, I, J, 0, (int64_t)P->h_ksteps.size()};
+                        for (int32_t q = 0; q < nw; ++q) {
+                            const uint64_t m0 = mask(2 * I, q), m1 = mask(2 * I + 1, q);
+                            const uint64_t m2 = mask(2 * J, q), m3 = mask(2 * J + 1, q);
+                            uint64_t b = (m0 | m1) & (m2 | m3);
+                            while (b) {
+                                const int bit = __builtin_ctzll(b);
+                                const int32_t tag = (int32_t)(((m0 >> bit) & 1) | (((m1 >> bit) & 1) << 1) |
+                                                              (((m2 >> bit) & 1) << 2) | (((m3 >> bit) & 1) << 3));
+                                P->h_ksteps.push_back(16 * (64 * q + bit) | tag << kStepSlabShift);
+                                b &= b - 1;
+                            }
+                        }
+                        it.nsteps = (int32_t)(P->h_ksteps.size() - it.step_off);
+                        if (it.nsteps > 0) sub_tiles[i].push_back(it);
+                    }
             }
         }
-        P->h_ftiles.insert(P->h_ftiles.end(), P->h_syrk.end() - (int64_t)nst * (nst + 1) / 2, P->h_syrk.end());
         blk += s.nblocks;
         rows += ((int64_t)sp.brows.size() + 3) / 4 * 4;
         lv += sp.bval;
@@ -410,61 +433,70 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
             load[x] += P->plans[i].trsm_useful + P->plans[i].syrk_useful + 1.0;
             xsub[x].push_back(i);
         }
+        // SYRK list of a set of subdomains per XCD: the 128 x 128 tiles, then
+        // the 64 x 64 blocks, each part interleaved over the XCDs
+        auto syrk_list = [&](const std::vector<std::vector<int32_t>>& subs_of_xcd, std::vector<SyrkItem>& out,
+                             int64_t& ntile, int64_t& nblock) {
+            for (int part = 0; part < 2; ++part) {
+                const auto& src = part == 0 ? sub_tiles : sub_blocks;
+                std::vector<std::vector<SyrkItem>> xl(kNumXcd);
+                size_t len = 0;
+                for (int x = 0; x < kNumXcd; ++x) {
+                    for (int32_t i : subs_of_xcd[x]) xl[x].insert(xl[x].end(), src[i].begin(), src[i].end());
+                    len = std::max(len, xl[x].size());
+                }
+                const size_t base = out.size();
+                out.resize(base + len * kNumXcd, SyrkItem{-1, 0, 0, 0, 0});
+                for (int x = 0; x < kNumXcd; ++x)
+                    for (size_t k = 0; k < xl[x].size(); ++k) out[base + k * kNumXcd + x] = xl[x][k];
+                (part == 0 ? ntile : nblock) = (int64_t)(len * kNumXcd);
+            }
+        };
         std::vector<std::vector<int32_t>> xt(kNumXcd);
-        std::vector<std::vector<SyrkItem>> xs(kNumXcd);
-        std::vector<std::vector<SyrkItem>> per_sub(nsub);
-        for (const SyrkItem& it : P->h_syrk) per_sub[it.sub].push_back(it);
         // groups for the overlapped assembly
         {
             size_t lmax = 0;
             for (int x = 0; x < kNumXcd; ++x) lmax = std::max(lmax, xsub[x].size());
             const int ng = (int)std::max<size_t>(1, std::min<size_t>(kOverlapGroups, lmax));
             for (int gi = 0; gi < ng; ++gi) {
-                std::vector<std::vector<int32_t>> gt(kNumXcd);
-                std::vector<std::vector<SyrkItem>> gs(kNumXcd);
-                size_t lt = 0, ls = 0;
+                std::vector<std::vector<int32_t>> gt(kNumXcd), gsub(kNumXcd);
+                size_t lt = 0;
                 for (int x = 0; x < kNumXcd; ++x) {
                     const size_t L = xsub[x].size();
                     for (size_t k = L * gi / ng; k < L * (gi + 1) / ng; ++k) {
                         const int32_t i = xsub[x][k];
                         const SubDev& sd = P->h_subs[i];
                         for (int32_t t = 0; t < sd.ntiles; ++t) gt[x].push_back((int32_t)(sd.tile_off + t));
-                        gs[x].insert(gs[x].end(), per_sub[i].begin(), per_sub[i].end());
+                        gsub[x].push_back(i);
                     }
                     lt = std::max(lt, gt[x].size());
-                    ls = std::max(ls, gs[x].size());
                 }
                 P->g_toff.push_back((int64_t)P->h_tile_order_g.size());
                 P->g_tcnt.push_back((int64_t)(lt * kNumXcd));
                 P->g_soff.push_back((int64_t)P->h_syrk_g.size());
-                P->g_scnt.push_back((int64_t)(ls * kNumXcd));
+                int64_t nt = 0, nb = 0;
+                syrk_list(gsub, P->h_syrk_g, nt, nb);
+                P->g_stile.push_back(nt);
+                P->g_sblock.push_back(nb);
                 P->h_tile_order_g.resize(P->h_tile_order_g.size() + lt * kNumXcd, -1);
-                P->h_syrk_g.resize(P->h_syrk_g.size() + ls * kNumXcd, SyrkItem{-1, 0, 0, 0});
-                for (int x = 0; x < kNumXcd; ++x) {
+                for (int x = 0; x < kNumXcd; ++x)
                     for (size_t k = 0; k < gt[x].size(); ++k)
                         P->h_tile_order_g[P->g_toff.back() + (int64_t)(k * kNumXcd + x)] = gt[x][k];
-                    for (size_t k = 0; k < gs[x].size(); ++k)
-                        P->h_syrk_g[P->g_soff.back() + (int64_t)(k * kNumXcd + x)] = gs[x][k];
-                }
             }
         }
         for (int x = 0; x < kNumXcd; ++x)
             for (int32_t i : xsub[x]) {
                 const SubDev& sd = P->h_subs[i];
                 for (int32_t t = 0; t < sd.ntiles; ++t) xt[x].push_back((int32_t)(sd.tile_off + t));
-                xs[x].insert(xs[x].end(), per_sub[i].begin(), per_sub[i].end());
             }
-        size_t lt = 0, ls = 0;
-        for (int x = 0; x < kNumXcd; ++x) {
-            lt = std::max(lt, xt[x].size());
-            ls = std::max(ls, xs[x].size());
-        }
+        size_t lt = 0;
+        for (int x = 0; x < kNumXcd; ++x) lt = std::max(lt, xt[x].size());
         P->h_tile_order.assign(lt * kNumXcd, -1);
-        P->h_syrk.assign(ls * kNumXcd, SyrkItem{-1, 0, 0, 0});
-        for (int x = 0; x < kNumXcd; ++x) {
+        for (int x = 0; x < kNumXcd; ++x)
             for (size_t k = 0; k < xt[x].size(); ++k) P->h_tile_order[k * kNumXcd + x] = xt[x][k];
-            for (size_t k = 0; k < xs[x].size(); ++k) P->h_syrk[k * kNumXcd + x] = xs[x][k];
-        }
+        P->h_syrk.clear();
+        int64_t nb = 0;
+        syrk_list(xsub, P->h_syrk, P->nsyrk_tile, nb);
     }
     P->nval_total = lv;
     rows += 64;                            // the TRSM reads whole 64-entry groups of a row list
@@ -545,6 +577,11 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
     if (e == hipSuccess) e = up(p->d_rows.p, h_rows.data(), h_rows.size() * 4);
     if (e == hipSuccess) e = up(p->d_visit.p, p->h_visit.data(), p->h_visit.size() * 4);
     if (e == hipSuccess) e = up(p->d_ksteps.p, p->h_ksteps.data(), p->h_ksteps.size() * 4);
+    // F is cleared once: the SYRK never writes its structurally zero blocks
+    // nor the columns past m of the last tiles
+    if (e == hipSuccess && fo > 0)
+        e = p->mixed ? hipMemsetAsync(p->d_F32.p, 0, (size_t)fo * sizeof(float), st)
+                     : hipMemsetAsync(p->d_F.p, 0, (size_t)fo * sizeof(double), st);
     if (e == hipSuccess) e = up(p->d_piv.p, h_piv.data(), h_piv.size() * 4);
     if (e == hipSuccess) e = up(p->d_pi.p, h_pi.data(), h_pi.size() * 4);
     if (e == hipSuccess) e = up(p->d_sgn.p, h_sgn.data(), h_sgn.size());
