@@ -283,12 +283,13 @@ def main():
     if cfg == 5:
         _, extra["implicit_ms"] = time_apply(torch, plan, "implicit", iters=5)
         log(f"bench: apply {extra}")
-    orig = None
+    orig, kms_o = None, None
     if args.compare_orig:
         plan_o = P.Plan(subs, staircase=False, panel_width=args.panel_width)
         plan_o.factor()
-        orig, _ = time_assembly(torch, plan_o, max(1, args.steps // 2), 1)
+        orig, kms_o = time_assembly(torch, plan_o, max(1, args.steps // 2), 1)
         plan_o.destroy()
+        log(f"bench: FP64 without the staircase {orig:.3f} ms/step, kernels {kms_o}")
     noreach = None
     if args.compare_reach:
         plan_r = P.Plan(subs, reach=False, panel_width=args.panel_width)
@@ -398,6 +399,7 @@ def main():
         "prep_s": prep_s,
         "latency_config1_us": lat1,
         "orig_ms_per_step": orig,
+        "orig_kernel_ms": kms_o,
         "no_reach_ms_per_step": noreach,
         "other_assembly": other,
         "mixed": mixed,
