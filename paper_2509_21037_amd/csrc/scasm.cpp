@@ -452,6 +452,21 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
                 (part == 0 ? ntile : nblock) = (int64_t)(len * kNumXcd);
             }
         };
+        // the tiles of one subdomain in order of decreasing visit count, its
+        // SYRK items in order of decreasing step count (long items first)
+        auto push_tiles = [&](std::vector<int32_t>& list, int32_t i) {
+            const SubDev& sd = P->h_subs[i];
+            const size_t b0 = list.size();
+            for (int32_t t = 0; t < sd.ntiles; ++t) list.push_back((int32_t)(sd.tile_off + t));
+            std::stable_sort(list.begin() + b0, list.end(), [&](int32_t a, int32_t b) {
+                return P->h_tiles[a].nvisit > P->h_tiles[b].nvisit;
+            });
+        };
+        auto by_steps = [](const SyrkItem& a, const SyrkItem& b) { return a.nsteps > b.nsteps; };
+        for (int32_t i = 0; i < nsub; ++i) {
+            std::stable_sort(sub_tiles[i].begin(), sub_tiles[i].end(), by_steps);
+            std::stable_sort(sub_blocks[i].begin(), sub_blocks[i].end(), by_steps);
+        }
         std::vector<std::vector<int32_t>> xt(kNumXcd);
         // groups for the overlapped assembly
         {
@@ -465,8 +480,7 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
                     const size_t L = xsub[x].size();
                     for (size_t k = L * gi / ng; k < L * (gi + 1) / ng; ++k) {
                         const int32_t i = xsub[x][k];
-                        const SubDev& sd = P->h_subs[i];
-                        for (int32_t t = 0; t < sd.ntiles; ++t) gt[x].push_back((int32_t)(sd.tile_off + t));
+                        push_tiles(gt[x], i);
                         gsub[x].push_back(i);
                     }
                     lt = std::max(lt, gt[x].size());
@@ -485,10 +499,7 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
             }
         }
         for (int x = 0; x < kNumXcd; ++x)
-            for (int32_t i : xsub[x]) {
-                const SubDev& sd = P->h_subs[i];
-                for (int32_t t = 0; t < sd.ntiles; ++t) xt[x].push_back((int32_t)(sd.tile_off + t));
-            }
+            for (int32_t i : xsub[x]) push_tiles(xt[x], i);
         size_t lt = 0;
         for (int x = 0; x < kNumXcd; ++x) lt = std::max(lt, xt[x].size());
         P->h_tile_order.assign(lt * kNumXcd, -1);
