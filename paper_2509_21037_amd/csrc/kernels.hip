@@ -156,7 +156,8 @@ template <bool MIXED>
 __device__ __forceinline__ void trsm_tile(
     const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
     const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows,
-    const int32_t* __restrict__ visit, const double* __restrict__ lval, const float* __restrict__ lval32,
+    const int32_t* __restrict__ visit, const uint64_t* __restrict__ vrows,
+    const double* __restrict__ lval, const float* __restrict__ lval32,
     const int32_t* __restrict__ piv, const int8_t* __restrict__ sgn,
     typename std::conditional<MIXED, float, double>::type* __restrict__ X, int ti, char* __restrict__ smem)
 {
@@ -185,6 +186,9 @@ __device__ __forceinline__ void trsm_tile(
     // elimination-tree paths of its pivots (all other rows of X are zero)
     const int nv = T.nvisit;
     const int32_t* __restrict__ V = visit + T.visit_off;
+    // per visit, the rows of the block on the paths: the others are zero
+    // before and after its diagonal solve and are neither read nor written
+    const uint64_t* __restrict__ VR = vrows + T.visit_off;
 
     // right-hand side P B^T: sign at the pivot row, zero elsewhere.  Only the
     // rows of visited blocks are cleared: the others are off every path, the
@@ -257,6 +261,7 @@ __device__ __forceinline__ void trsm_tile(
     };
     for (int k = 0; k < nv; ++k) {
         const int b = V[k];
+        const uint64_t on = VR[k] >> g;          // bit 16t + 4r: row 16t + 4r + g of the block
         const int w = bd.w;
         const int row0 = B[b].row0;
         const int nb = bd.nb;
@@ -292,7 +297,8 @@ __device__ __forceinline__ void trsm_tile(
                     for (int r = 0; r < 4; ++r) {
                         const int i = 16 * t + 4 * r + g;
                         const int row = row0 + i;
-                        xr[t][r] = (i < w && row >= kstart) ? (double)Xs[(int64_t)(row - kstart) * kTile + col] : 0.0;
+                        xr[t][r] = (((on >> (16 * t + 4 * r)) & 1) && row >= kstart)
+                                       ? (double)Xs[(int64_t)(row - kstart) * kTile + col] : 0.0;
                     }
                 if (np > 0) gather(0);
             }
@@ -327,7 +333,8 @@ __device__ __forceinline__ void trsm_tile(
                         const int i = 16 * t + 4 * r + g;
                         const int row = row0 + i;
                         const TX v = (TX)xr[t][r];
-                        if (i < w && row >= kstart) Xs[(int64_t)(row - kstart) * kTile + col] = v;
+                        if (((on >> (16 * t + 4 * r)) & 1) && row >= kstart)
+                            Xs[(int64_t)(row - kstart) * kTile + col] = v;
                         xb[t][r] = -v;
                     }
             }
@@ -378,25 +385,26 @@ __device__ __forceinline__ void trsm_tile(
 __global__ __launch_bounds__(256, 2) void trsm_stair_f64(
     const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
     const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows, const int32_t* __restrict__ visit,
-    const double* __restrict__ lval, const int32_t* __restrict__ piv,
+    const uint64_t* __restrict__ vrows, const double* __restrict__ lval, const int32_t* __restrict__ piv,
     const int8_t* __restrict__ sgn, const int32_t* __restrict__ order, double* __restrict__ X)
 {
     __shared__ __align__(16) char smem[kTrsmSmem];
     const int ti = order[blockIdx.x];
     if (ti < 0) return;
-    trsm_tile<false>(subs, tiles, blocks, rows, visit, lval, nullptr, piv, sgn, X, ti, smem);
+    trsm_tile<false>(subs, tiles, blocks, rows, visit, vrows, lval, nullptr, piv, sgn, X, ti, smem);
 }
 
 __global__ __launch_bounds__(256, 2) void trsm_stair_mixed(
     const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
     const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows, const int32_t* __restrict__ visit,
-    const double* __restrict__ lval, const float* __restrict__ lval32, const int32_t* __restrict__ piv,
+    const uint64_t* __restrict__ vrows, const double* __restrict__ lval, const float* __restrict__ lval32,
+    const int32_t* __restrict__ piv,
     const int8_t* __restrict__ sgn, const int32_t* __restrict__ order, float* __restrict__ X)
 {
     __shared__ __align__(16) char smem[kTrsmSmem];
     const int ti = order[blockIdx.x];
     if (ti < 0) return;
-    trsm_tile<true>(subs, tiles, blocks, rows, visit, lval, lval32, piv, sgn, X, ti, smem);
+    trsm_tile<true>(subs, tiles, blocks, rows, visit, vrows, lval, lval32, piv, sgn, X, ti, smem);
 }
 
 
@@ -829,10 +837,10 @@ hipError_t launch_trsm(const DevTables& t, const int32_t* order, int64_t count, 
     if (count <= 0) return hipSuccess;
     if (t.X32)
         hipLaunchKernelGGL(trsm_stair_mixed, dim3((unsigned)count), dim3(256), 0, stream, t.subs, t.tiles,
-                           t.blocks, t.rows, t.visit, t.lval, t.lval32, t.piv, t.sgn, order, t.X32);
+                           t.blocks, t.rows, t.visit, t.vrows, t.lval, t.lval32, t.piv, t.sgn, order, t.X32);
     else
         hipLaunchKernelGGL(trsm_stair_f64, dim3((unsigned)count), dim3(256), 0, stream, t.subs, t.tiles,
-                           t.blocks, t.rows, t.visit, t.lval, t.piv, t.sgn, order, t.X);
+                           t.blocks, t.rows, t.visit, t.vrows, t.lval, t.piv, t.sgn, order, t.X);
     return hipGetLastError();
 }
 

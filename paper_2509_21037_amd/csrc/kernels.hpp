@@ -18,6 +18,7 @@ struct DevTables {
     const int32_t* rows = nullptr;
     const int32_t* visit = nullptr;        // blocks visited per TRSM tile (TileDev::visit_off)
     const int32_t* ksteps = nullptr;       // SYRK k-steps per item (SyrkItem::step_off)
+    const uint64_t* vrows = nullptr;       // per visit: rows of the block on the tile's paths
     const double* lval = nullptr;
     const float* lval32 = nullptr;
     const int32_t* piv = nullptr;

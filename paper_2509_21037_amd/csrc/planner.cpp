@@ -552,9 +552,11 @@ std::string build_plan(const SubdomainInput& in, const PlanOptions& opt, SubPlan
     {
         const int32_t nb = (int32_t)P.blocks.size();
         const int32_t ntile = (m + 63) / 64;
-        std::vector<int32_t> stamp(n, -1), bstamp(nb, -1);
+        std::vector<int32_t> stamp(n, -1), bstamp(nb, -1), bpos(nb, 0);
         P.visit_ptr.assign(1, 0);
         P.visit.clear();
+        P.visit_rows.clear();
+        std::vector<int32_t> rr;
         P.visits_stair = 0;
         P.mask_words = (n + 16 * 64 - 1) / (16 * 64);
         P.step_mask.assign((size_t)ntile * P.mask_words, 0);
@@ -564,20 +566,32 @@ std::string build_plan(const SubdomainInput& in, const PlanOptions& opt, SubPlan
             uint64_t* mask = P.step_mask.data() + (size_t)t * P.mask_words;
             P.visits_stair += nb - first;
             if (!opt.staircase || !opt.reach) {
-                for (int32_t b = first; b < nb; ++b) P.visit.push_back(b);
+                for (int32_t b = first; b < nb; ++b) {
+                    P.visit.push_back(b);
+                    P.visit_rows.push_back(P.blocks[b].w >= 64 ? ~0ull : (1ull << P.blocks[b].w) - 1);
+                }
                 for (int32_t q = (opt.staircase ? P.piv[c0] : 0) / 16; q < (n + 15) / 16; ++q)
                     mask[q >> 6] |= 1ull << (q & 63);
             } else {
                 std::vector<int32_t> bl;
+                rr.clear();
                 for (int32_t c = c0; c < c1; ++c)
                     for (int32_t r = P.piv[c]; r >= 0 && stamp[r] != t; r = P.parent[r]) {
                         stamp[r] = t;
+                        rr.push_back(r);
                         mask[r >> 10] |= 1ull << ((r >> 4) & 63);
                         const int32_t b = P.block_of_row[r];
                         if (bstamp[b] != t) { bstamp[b] = t; bl.push_back(b); }
                     }
                 std::sort(bl.begin(), bl.end());
+                const size_t v0 = P.visit.size();
+                for (size_t q = 0; q < bl.size(); ++q) bpos[bl[q]] = (int32_t)q;
                 P.visit.insert(P.visit.end(), bl.begin(), bl.end());
+                P.visit_rows.resize(P.visit.size(), 0);
+                for (int32_t r : rr) {
+                    const int32_t b = P.block_of_row[r];
+                    P.visit_rows[v0 + bpos[b]] |= 1ull << (r - P.blocks[b].row0);
+                }
             }
             P.visit_ptr.push_back((int64_t)P.visit.size());
         }

@@ -96,6 +96,7 @@ struct SubPlan {
     // visit[visit_ptr[t] .. visit_ptr[t + 1])
     std::vector<int64_t> visit_ptr;
     std::vector<int32_t> visit;
+    std::vector<uint64_t> visit_rows;          // per visit: rows of the block on the paths (bit i = row0 + i)
     int64_t visits_stair = 0;                  // the same count for the staircase alone
     // 16-row steps holding nonzero rows of each 64-column tile of X (bit q of
     // word q / 64 = rows [16 q, 16 q + 16)), mask_words words per tile

@@ -99,6 +99,7 @@ struct sc_plan_s {
     std::vector<TileDev> h_tiles;
     std::vector<BlockDev> h_blocks;
     std::vector<int32_t> h_visit;               // TRSM visit lists of all tiles
+    std::vector<uint64_t> h_vrows;              // per visit: the block's rows on the paths
     std::vector<int32_t> h_ksteps;              // SYRK k-step lists of all items
     std::vector<SyrkItem> h_syrk;               // interleaved over XCDs, idle items sub = -1
     std::vector<int32_t> h_tile_order;          // TRSM workgroup -> tile (-1 idle)
@@ -126,6 +127,7 @@ struct sc_plan_s {
     DevBuf<int2> d_frows;
     DevBuf<double> d_part;                      // apply partial sums, 256 per stored F tile
     DevBuf<int32_t> d_rows, d_piv, d_pi, d_visit, d_ksteps;
+    DevBuf<uint64_t> d_vrows;
     DevBuf<int8_t> d_sgn;
     DevBuf<double> d_lval, d_X, d_F;
     DevBuf<float> d_lval32, d_X32, d_F32;
@@ -223,7 +225,7 @@ struct sc_plan_s {
                          d_ftiles.count * sizeof(SyrkItem) + d_frows.count * sizeof(int2) +
                          d_part.count * 8 + d_tile_order.count * 4 +
                          d_tile_order_g.count * 4 + d_syrk_g.count * sizeof(SyrkItem) +
-                         (d_rows.count + d_piv.count + d_pi.count + d_visit.count + d_ksteps.count) * 4 + d_sgn.count +
+                         (d_rows.count + d_piv.count + d_pi.count + d_visit.count + d_ksteps.count) * 4 + d_vrows.count * 8 + d_sgn.count +
                          (d_lval.count + d_X.count + d_F.count) * 8 +
                          (d_lval32.count + d_X32.count + d_F32.count) * 4 +
                          (d_xwork.count + d_xoff.count) * 8 + (d_ifw.count + d_ibw.count) * sizeof(int2) +
@@ -233,7 +235,7 @@ struct sc_plan_s {
         d_subs.release(); d_tiles.release(); d_blocks.release(); d_syrk.release();
         d_ftiles.release(); d_frows.release(); d_part.release();
         d_tile_order.release(); d_tile_order_g.release(); d_syrk_g.release();
-        d_rows.release(); d_piv.release(); d_pi.release(); d_visit.release(); d_ksteps.release(); d_sgn.release();
+        d_rows.release(); d_piv.release(); d_pi.release(); d_visit.release(); d_ksteps.release(); d_vrows.release(); d_sgn.release();
         d_lval.release(); d_X.release(); d_F.release();
         d_lval32.release(); d_X32.release(); d_F32.release();
         d_xwork.release(); d_xoff.release();
@@ -255,6 +257,7 @@ struct sc_plan_s {
         DevTables t;
         t.subs = d_subs.p; t.tiles = d_tiles.p; t.blocks = d_blocks.p; t.rows = d_rows.p; t.visit = d_visit.p;
         t.ksteps = d_ksteps.p;
+        t.vrows = d_vrows.p;
         t.lval = d_lval.p; t.piv = d_piv.p; t.pi = d_pi.p; t.sgn = d_sgn.p; t.syrk = d_syrk.p;
         t.X = d_X.p; t.F = d_F.p;
         t.lval32 = d_lval32.p; t.X32 = d_X32.p; t.F32 = d_F32.p;
@@ -352,6 +355,8 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
             T.visit_off = (int64_t)P->h_visit.size();
             T.nvisit = (int32_t)(sp.visit_ptr[t + 1] - sp.visit_ptr[t]);
             P->h_visit.insert(P->h_visit.end(), sp.visit.begin() + sp.visit_ptr[t], sp.visit.begin() + sp.visit_ptr[t + 1]);
+            P->h_vrows.insert(P->h_vrows.end(), sp.visit_rows.begin() + sp.visit_ptr[t],
+                              sp.visit_rows.begin() + sp.visit_ptr[t + 1]);
             P->h_tiles.push_back(T);
         }
         const int32_t nst = (sp.m + kSyrkTile - 1) / kSyrkTile;
@@ -541,6 +546,7 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
     ALLOC(p->d_rows, (size_t)rows);
     ALLOC(p->d_visit, std::max<size_t>(1, p->h_visit.size()));
     ALLOC(p->d_ksteps, std::max<size_t>(1, p->h_ksteps.size()));
+    ALLOC(p->d_vrows, std::max<size_t>(1, p->h_vrows.size()));
     ALLOC(p->d_piv, (size_t)colo);
     ALLOC(p->d_pi, (size_t)colo);
     ALLOC(p->d_sgn, (size_t)colo);
@@ -588,6 +594,7 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
     if (e == hipSuccess) e = up(p->d_rows.p, h_rows.data(), h_rows.size() * 4);
     if (e == hipSuccess) e = up(p->d_visit.p, p->h_visit.data(), p->h_visit.size() * 4);
     if (e == hipSuccess) e = up(p->d_ksteps.p, p->h_ksteps.data(), p->h_ksteps.size() * 4);
+    if (e == hipSuccess) e = up(p->d_vrows.p, p->h_vrows.data(), p->h_vrows.size() * 8);
     // F is cleared once: the SYRK never writes its structurally zero blocks
     // nor the columns past m of the last tiles
     if (e == hipSuccess && fo > 0)
