@@ -132,9 +132,10 @@ typedef struct {
 /* Initialisation stage (Sec. 2.2): ordering, symbolic factorisation, staircase
  * plan (Sec. 3, column pivots and stable sort), GPU block and tile lists, and
  * allocation of every persistent device buffer (factor values, X, F, tables)
- * on the current HIP device.  `stream` is used for the table uploads.
- * Errors: SC_ERR_INVALID_ARG (bad descriptor: index out of range, sign not
- * +-1, n <= 0, perm not a permutation), SC_ERR_OOM, SC_ERR_DEVICE. */
+ * on the current HIP device.  `stream` is used for the table uploads and the
+ * one-time clear of F.  Errors: SC_ERR_INVALID_ARG (bad descriptor: index out
+ * of range, sign not +-1, n <= 0 or n >= 2^27, perm not a permutation),
+ * SC_ERR_OOM, SC_ERR_DEVICE. */
 sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub,
                            const sc_options_t* opt, void* stream, sc_plan_t* out);
 
@@ -150,9 +151,12 @@ sc_status_t sc_factor(sc_plan_t plan, const double* const* kreg_vals, void* stre
 
 /* Preprocessing, part 2 (the hot path, Sec. 3): on `stream`, for every
  * subdomain, X = L^{-1} P B^T with the staircase TRSM (factor splitting with
- * pruned row lists, Sec. 3.2) and F = X^T X with the staircase SYRK (Sec. 3.3).
- * F stays on the device in the sorted column order, as the lower triangle of
- * 128 x 128 tiles (F is symmetric); the permutation back to the multiplier
+ * pruned row lists, Sec. 3.2) and F = X^T X with the staircase SYRK (Sec. 3.3),
+ * both restricted to the rows of X on the elimination-tree paths of the
+ * pivots unless disable_reach is set.  F stays on the device in the sorted
+ * column order, as the lower triangle of 128 x 128 tiles (F is symmetric;
+ * its structurally zero 64 x 64 blocks and the padding past m are cleared
+ * once by sc_plan_create and never written again); the permutation back to the multiplier
  * order (Sec. 3) is applied to the vectors by sc_apply / sc_pcpg and to the
  * matrix by sc_get_F.  Asynchronous.  SC_ERR_STATE before sc_factor. */
 sc_status_t sc_assemble(sc_plan_t plan, void* stream);
