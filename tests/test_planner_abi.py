@@ -187,6 +187,26 @@ def test_trsm_visits_exactly_the_blocks_with_nonzero_rows_of_x(name, make):
         assert np.array_equal(visit3[ptr3[t]:ptr3[t + 1]], np.arange(len(row0) - 1))
 
 
+def test_tile_visits_capacity_error():
+    s = scgen.box_subdomain("heat", (6, 5, 4), 0.2, seed=7)
+    lib = P.load()
+    import ctypes
+    from paper_2509_21037_amd.scasm import SubdomainDesc, _fill_desc, _options
+    keep = []
+    d = SubdomainDesc()
+    _fill_desc(d, s, keep)
+    opt = _options()
+    counts = np.zeros(3, dtype=np.int64)
+    assert lib.sc_host_tile_visits(ctypes.byref(d), ctypes.byref(opt), counts.ctypes.data, None, None, None, 0) == 0
+    assert counts[2] > 0
+    small = np.zeros(int(counts[2]) - 1, dtype=np.int32)
+    st = lib.sc_host_tile_visits(ctypes.byref(d), ctypes.byref(opt), counts.ctypes.data, None, None,
+                                 small.ctypes.data, int(counts[2]) - 1)
+    assert st == P.SC_ERR_INVALID_ARG and b"capacity" in lib.sc_last_error()
+    assert lib.sc_host_tile_visits(ctypes.byref(d), ctypes.byref(opt), None, None, None, None, 0) == \
+        P.SC_ERR_INVALID_ARG
+
+
 def test_triangular_rhs_gives_threefold_saving():
     # Sec. 4.3: pivot of column j at row j*n/m with a dense factor -> 1/3 of the work
     golden = {}
@@ -230,6 +250,9 @@ def test_not_spd_reported_with_column():
     (lambda s: setattr(s, "sign", np.concatenate([s.sign[:-1], [0]]).astype(np.int8)), "sign"),
     (lambda s: setattr(s, "perm", np.zeros(s.n, np.int32)), "perm"),
     (lambda s: setattr(s, "col", np.where(np.arange(len(s.col)) == 3, s.n, s.col).astype(np.int32)), "column"),
+    # rejected before the pattern is read (the step entries of the SYRK hold
+    # a row below 2^27)
+    (lambda s: setattr(s, "n", 1 << 27), "2^27"),
 ])
 def test_invalid_arguments(mutate, msg):
     s = scgen.box_subdomain("heat", (3, 3), 0.3, seed=1)
