@@ -191,14 +191,20 @@ __device__ __forceinline__ void trsm_tile(
     const uint64_t* __restrict__ VR = vrows + T.visit_off;
 
     // right-hand side P B^T: sign at the pivot row, zero elsewhere.  Only the
-    // rows of visited blocks are cleared: the others are off every path, the
-    // sweep writes them at most with exact-zero updates of whatever they held,
-    // and the SYRK never reads them (its step entries mark the slabs with
-    // nonzero rows per step)
+    // 16-row steps of visited blocks that hold a row on the paths are cleared:
+    // the other rows are off every path, the sweep writes them at most with
+    // exact-zero updates of whatever they held, the diagonal step neither
+    // reads nor writes them, and the SYRK reads only the steps of a slab that
+    // hold a row on its paths
     for (int k = 0; k < nv; ++k) {
         const int r0 = B[V[k]].row0;
         const int r1 = r0 + B[V[k]].w;
-        for (int r = max(r0, kstart) + g; r < r1; r += 4) Xs[(int64_t)(r - kstart) * kTile + col] = TX(0);
+        const uint64_t on = VR[k];
+        for (int q = 0; q < 4; ++q) {
+            if (((on >> (16 * q)) & 0xFFFFull) == 0) continue;
+            const int qe = min(r0 + 16 * (q + 1), r1);
+            for (int r = max(r0 + 16 * q, kstart) + g; r < qe; r += 4) Xs[(int64_t)(r - kstart) * kTile + col] = TX(0);
+        }
     }
     __threadfence_block();
     if (g == 0 && col < T.ncols) Xs[(int64_t)(piv[cbase + col] - kstart) * kTile + col] = (TX)sgn[cbase + col];
