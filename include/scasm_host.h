@@ -52,20 +52,25 @@ sc_status_t sc_host_analyze(const sc_subdomain_desc_t* sd, const sc_options_t* o
 
 /*
  * The factor blocks the staircase TRSM visits for each 64-column tile of X
- * (columns in the sorted order of sc_host_analyze's piv_out), as the device
- * path receives them.
+ * (columns in the sorted order of sc_host_analyze's piv_out), and the 16-row
+ * steps in which each tile can hold nonzero rows (the SYRK's k-steps are the
+ * steps marked for both of its tiles), as the device path receives them.
  *   sd, opt      as for sc_host_analyze
- *   counts       [3] out: number of blocks, number of tiles, total visits
+ *   counts       [4] out: number of blocks, number of tiles, total visits,
+ *                mask words per tile
  *   block_row0   optional [blocks + 1] out: first row of each block, then n
  *   visit_ptr    optional [tiles + 1] out: tile t visits
  *                visit[visit_ptr[t] .. visit_ptr[t + 1])
  *   visit        optional [capacity] out: block indices, increasing per tile
+ *   step_mask    optional [tiles * words] out: bit q of word q / 64 of tile t
+ *                set when rows [16 q, 16 q + 16) can hold nonzeros of tile t
  * Call once with the optional outputs NULL to size them.  Returns SC_OK, or
  * SC_ERR_INVALID_ARG for a bad descriptor or when capacity < total visits
  * with visit given (counts are filled in either case).
  */
 sc_status_t sc_host_tile_visits(const sc_subdomain_desc_t* sd, const sc_options_t* opt, int64_t* counts,
-                                int32_t* block_row0, int64_t* visit_ptr, int32_t* visit, int64_t capacity);
+                                int32_t* block_row0, int64_t* visit_ptr, int32_t* visit, int64_t capacity,
+                                uint64_t* step_mask);
 
 #ifdef __cplusplus
 }

@@ -1056,7 +1056,8 @@ sc_status_t sc_host_analyze(const sc_subdomain_desc_t* sd, const sc_options_t* o
 }
 
 sc_status_t sc_host_tile_visits(const sc_subdomain_desc_t* sd, const sc_options_t* opt, int64_t* counts,
-                                int32_t* block_row0, int64_t* visit_ptr, int32_t* visit, int64_t capacity) {
+                                int32_t* block_row0, int64_t* visit_ptr, int32_t* visit, int64_t capacity,
+                                uint64_t* step_mask) {
     g_last_error.clear();
     if (!sd || !counts) return fail(SC_ERR_INVALID_ARG, "descriptor or counts is NULL");
     sc_options_t o{};
@@ -1076,6 +1077,8 @@ sc_status_t sc_host_tile_visits(const sc_subdomain_desc_t* sd, const sc_options_
     counts[0] = nb;
     counts[1] = (int64_t)sp.visit_ptr.size() - 1;
     counts[2] = total;
+    counts[3] = sp.mask_words;
+    if (step_mask) std::copy(sp.step_mask.begin(), sp.step_mask.end(), step_mask);
     if (block_row0) {
         for (int64_t b = 0; b < nb; ++b) block_row0[b] = sp.blocks[b].row0;
         block_row0[nb] = sp.n;

@@ -79,7 +79,7 @@ def load():
         lib.sc_host_analyze.argtypes = [ctypes.POINTER(SubdomainDesc), ctypes.POINTER(Options), vp, vp, vp,
                                          vp, vp, ctypes.POINTER(HostInfo), ctypes.POINTER(i32)]
         lib.sc_host_tile_visits.argtypes = [ctypes.POINTER(SubdomainDesc), ctypes.POINTER(Options), vp, vp, vp,
-                                             vp, ctypes.c_int64]
+                                             vp, ctypes.c_int64, vp]
         lib.sc_pcpg.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(i32), vp, vp, i32, vp, vp]
         lib.sc_autotune.argtypes = [ctypes.POINTER(SubdomainDesc), i32, ctypes.POINTER(Options),
                                     ctypes.POINTER(vp), ctypes.POINTER(i32), i32, i32, i32, vp,
@@ -186,22 +186,27 @@ def host_analyze(s, values=True, want_L=False, use_coords=True, **opts):
     return out
 
 
-def host_tile_visits(s, use_coords=True, **opts):
+def host_tile_visits(s, use_coords=True, with_masks=False, **opts):
     """Factor blocks the TRSM visits per 64-column X tile (sc_host_tile_visits):
-    returns (block_row0 [nblocks + 1], visit_ptr [ntiles + 1], visit)."""
+    returns (block_row0 [nblocks + 1], visit_ptr [ntiles + 1], visit), and with
+    with_masks the 16-row step masks [ntiles, words] (uint64) as a fourth item."""
     lib = load()
     keep = []
     d = SubdomainDesc()
     _fill_desc(d, s, keep, use_coords)
     opt = _options(**opts)
-    counts = np.zeros(3, dtype=np.int64)
-    _check(lib.sc_host_tile_visits(ctypes.byref(d), ctypes.byref(opt), counts.ctypes.data, None, None, None, 0))
-    nb, nt, tot = (int(c) for c in counts)
+    counts = np.zeros(4, dtype=np.int64)
+    _check(lib.sc_host_tile_visits(ctypes.byref(d), ctypes.byref(opt), counts.ctypes.data, None, None, None, 0,
+                                   None))
+    nb, nt, tot, nw = (int(c) for c in counts)
     row0 = np.zeros(nb + 1, dtype=np.int32)
     ptr = np.zeros(nt + 1, dtype=np.int64)
     visit = np.zeros(max(1, tot), dtype=np.int32)
+    masks = np.zeros((max(1, nt), max(1, nw)), dtype=np.uint64)
     _check(lib.sc_host_tile_visits(ctypes.byref(d), ctypes.byref(opt), counts.ctypes.data, row0.ctypes.data,
-                                   ptr.ctypes.data, visit.ctypes.data, tot))
+                                   ptr.ctypes.data, visit.ctypes.data, tot, masks.ctypes.data))
+    if with_masks:
+        return row0, ptr, visit[:tot], masks[:nt, :nw]
     return row0, ptr, visit[:tot]
 
 

@@ -144,7 +144,7 @@ def test_trsm_visits_exactly_the_blocks_with_nonzero_rows_of_x(name, make):
     import scipy.linalg as sl
     s = make()
     r = P.host_analyze(s, want_L=True)
-    row0, ptr, visit = P.host_tile_visits(s)
+    row0, ptr, visit, masks = P.host_tile_visits(s, with_masks=True)
     L, piv, n, m = r["L"], r["piv"], s.n, s.m
     E = np.zeros((n, m))
     E[piv, np.arange(m)] = 1.0
@@ -159,6 +159,9 @@ def test_trsm_visits_exactly_the_blocks_with_nonzero_rows_of_x(name, make):
         assert np.all(np.diff(got) > 0)
         rows = np.nonzero(np.abs(X[:, 64 * t:64 * t + 64]).max(axis=1) > 0)[0]
         assert np.array_equal(got, np.unique(blk[rows])), t
+        # the 16-row steps marked for the tile are exactly those with a nonzero row
+        steps = np.nonzero([(int(masks[t, q >> 6]) >> (q & 63)) & 1 for q in range((n + 15) // 16)])[0]
+        assert np.array_equal(steps, np.unique(rows // 16)), t
         stair += len(row0) - 1 - blk[piv[64 * t]]
     assert r["trsm_visits"] == len(visit)
     assert r["stair_visits"] == stair
@@ -196,14 +199,15 @@ def test_tile_visits_capacity_error():
     d = SubdomainDesc()
     _fill_desc(d, s, keep)
     opt = _options()
-    counts = np.zeros(3, dtype=np.int64)
-    assert lib.sc_host_tile_visits(ctypes.byref(d), ctypes.byref(opt), counts.ctypes.data, None, None, None, 0) == 0
-    assert counts[2] > 0
+    counts = np.zeros(4, dtype=np.int64)
+    assert lib.sc_host_tile_visits(ctypes.byref(d), ctypes.byref(opt), counts.ctypes.data, None, None, None, 0,
+                                   None) == 0
+    assert counts[2] > 0 and counts[3] == (s.n + 1023) // 1024
     small = np.zeros(int(counts[2]) - 1, dtype=np.int32)
     st = lib.sc_host_tile_visits(ctypes.byref(d), ctypes.byref(opt), counts.ctypes.data, None, None,
-                                 small.ctypes.data, int(counts[2]) - 1)
+                                 small.ctypes.data, int(counts[2]) - 1, None)
     assert st == P.SC_ERR_INVALID_ARG and b"capacity" in lib.sc_last_error()
-    assert lib.sc_host_tile_visits(ctypes.byref(d), ctypes.byref(opt), None, None, None, None, 0) == \
+    assert lib.sc_host_tile_visits(ctypes.byref(d), ctypes.byref(opt), None, None, None, None, 0, None) == \
         P.SC_ERR_INVALID_ARG
 
 
