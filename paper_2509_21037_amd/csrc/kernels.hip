@@ -425,14 +425,14 @@ __global__ __launch_bounds__(256, 2) void trsm_stair_mixed(
 // empty list are structurally zero and are not launched: the plan clears F
 // once when it is created.  Used for subdomains up to kSyrkBlockMaxN rows
 // (FP32: kSyrkBlockMaxNMixed), whose X slabs largely stay in L2 while their
-// blocks re-read them.  X rows are
-// staged through double-buffered LDS, 16 rows per step, the next step
-// prefetched into registers.  F stays in the
-// sorted column order (the permutation back to the multiplier order is applied
-// to the vectors of the apply and by sc_get_F), stored as the lower triangle
-// of 128 x 128 tiles, tile (I, J) at I(I+1)/2 + J, each row-major, diagonal
-// tiles whole: block (2T+1, 2T) also writes its transpose, the upper quadrant
-// of diagonal tile T.  Columns past m are never written and stay zero.
+// blocks re-read them.  X rows are staged through double-buffered LDS, 16
+// rows per step, the next step prefetched into registers.  F stays in the
+// sorted column order (the permutation back to the multiplier order is
+// applied to the vectors of the apply and by sc_get_F), stored as the lower
+// triangle of 128 x 128 tiles, tile (I, J) at I(I+1)/2 + J, each row-major,
+// diagonal tiles whole: block (2T+1, 2T) also writes its transpose, the upper
+// quadrant of diagonal tile T.  Columns past m are never written and stay
+// zero.
 // ---------------------------------------------------------------------------
 constexpr int kSyrkKC = 16;                  // X rows per step
 constexpr int kSyrkLd = kTile + 4;           // LDS row stride (elements)
