@@ -416,6 +416,28 @@ def test_reach_restricted_sweep_matches_full_staircase_sweep(precision):
     part.destroy()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_scattered_interior_columns(precision):
+    """Multipliers on random interior DOFs (pivots spread over the whole
+    elimination tree, so the visit lists and step lists have gaps everywhere)
+    on a 12^3 heat subdomain and a 12^3 elasticity subdomain (n = 6591: the
+    mixed SYRK takes the 128 x 128 tiles there, the FP64 SYRK the 64 x 64
+    blocks), against the oracle on seeded column samples."""
+    rng = np.random.default_rng(21)
+    subs = []
+    for kind, m in (("heat", 300), ("elasticity", 400)):
+        s = scgen.box_subdomain(kind, (12, 12, 12), 1.0 / 12, seed=22)
+        dof = np.sort(rng.choice(s.n, size=m, replace=False)).astype(np.int32)
+        subs.append(s.with_columns(dof, scgen.rng.signs_from_seed(23, m)))
+    plan = _assemble(subs, precision=precision)
+    tol = TOL_FP64 if precision == "fp64" else TOL_MIXED
+    for i, s in enumerate(subs):
+        sel = np.sort(np.random.default_rng(i).choice(s.m, size=96, replace=False))
+        F = plan.get_F(i)
+        assert oracle.relF(F[np.ix_(sel, sel)], oracle.schur(s, sel=sel)) <= tol, i
+    plan.destroy()
+
+
 # ------------------------------------------------------ overlapped assembly
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
