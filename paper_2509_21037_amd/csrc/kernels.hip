@@ -170,7 +170,6 @@ __device__ __forceinline__ void trsm_tile(
     const int j = lane & 15;
     const TileDev T = tiles[ti];
     const SubDev S = subs[T.sub];
-    const int n = S.n;
     const int kstart = T.kstart;
     TX* __restrict__ Xs = X + T.x_off;
     const int col = wv * kStripe + j;
