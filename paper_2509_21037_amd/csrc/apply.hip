@@ -185,7 +185,7 @@ __device__ double project(const SubDev& S, const PcpgDev& D, int sub, const doub
         if (threadIdx.x == 0) su[c] = t;
     }
     __syncthreads();
-    if (threadIdx.x < k) {
+    if ((int)threadIdx.x < k) {
         double u = 0.0;
         for (int c = 0; c < k; ++c) u += D.GtGinv[64 * sub + threadIdx.x * k + c] * su[c];
         su[kMaxKer + threadIdx.x] = u;
@@ -336,8 +336,7 @@ __device__ __forceinline__ double sum_parts(const double (*sp)[64], int r) {
 }
 
 __global__ __launch_bounds__(kImplThreads) void implicit_fwd(
-    const SubDev* __restrict__ subs, const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows,
-    const double* __restrict__ lval, const int64_t* __restrict__ rptr_off, const int32_t* __restrict__ rptr,
+    const SubDev* __restrict__ subs, const BlockDev* __restrict__ blocks, const double* __restrict__ lval, const int64_t* __restrict__ rptr_off, const int32_t* __restrict__ rptr,
     const int32_t* __restrict__ rpos, const int2* __restrict__ items, const int64_t* __restrict__ xoff,
     double* __restrict__ xwork, double* __restrict__ ubuf)
 {
@@ -460,7 +459,7 @@ hipError_t launch_apply_implicit(const DevTables& t, const ImplicitLevels& lv, c
         if ((e = hipGetLastError()) != hipSuccess) return e;
         for (size_t l = 0; l + 1 < lv.fw_off.size(); ++l) {
             const int64_t cnt = lv.fw_off[l + 1] - lv.fw_off[l];
-            hipLaunchKernelGGL(implicit_fwd, dim3((unsigned)cnt), dim3(kImplThreads), 0, stream, t.subs, t.blocks, t.rows,
+            hipLaunchKernelGGL(implicit_fwd, dim3((unsigned)cnt), dim3(kImplThreads), 0, stream, t.subs, t.blocks,
                                t.lval, lv.rptr_off, lv.rptr, lv.rpos, lv.fw_items + lv.fw_off[l], xoff, xwork,
                                lv.ubuf);
             if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -12,7 +12,6 @@ import pytest
 
 import oracle
 import scgen
-from scgen.mesh import Subdomain
 from scgen.rng import signs_from_seed, stream_seed
 
 P = pytest.importorskip("paper_2509_21037_amd")
