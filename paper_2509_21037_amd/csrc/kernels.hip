@@ -347,10 +347,13 @@ __device__ __forceinline__ void trsm_tile(
 
         // ---- 2. X[R_b] -= L[R_b, b] X[b], pruned row tiles PT p .. PT p + PT - 1
         for (int p = 0; p < np; ++p) {
-            step_begin();
+            // FP64: the next gather is issued before the next chunk's loads, so
+            // that waiting for it a step later does not wait for them as well
+            // (the mixed kernel has no registers left for that order)
+            VX acc[PT];
+            int off[PT][4];
+            if constexpr (MIXED) step_begin();
             if (act) {
-                VX acc[PT];
-                int off[PT][4];
 #pragma unroll
                 for (int u = 0; u < PT; ++u) {
                     acc[u] = accn[u];
@@ -358,6 +361,9 @@ __device__ __forceinline__ void trsm_tile(
                     for (int r = 0; r < 4; ++r) off[u][r] = offn[u][r];
                 }
                 if (p + 1 < np) gather(p + 1);
+            }
+            if constexpr (!MIXED) step_begin();
+            if (act) {
                 const TX* __restrict__ sA = reinterpret_cast<const TX*>(smem + buf * kBufBytes);
                 const int nt = min(PT, nrt - PT * p);
 #pragma unroll
