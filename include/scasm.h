@@ -100,7 +100,9 @@ typedef struct {
  *   use_graph        1 = sc_assemble captures its kernel launches once into a
  *                    HIP graph and replays it on every later call (the plan's
  *                    buffers and tables are fixed, so the graph stays valid);
- *                    calls made while kernel timing is enabled launch eagerly
+ *                    sc_apply_implicit likewise (captured again whenever it
+ *                    is called with other p / q pointers); calls made while
+ *                    kernel timing is enabled launch eagerly
  *   assembly_kernels 0 = library default (two launches), 1 = overlapped:
  *                    the batch is cut into groups of subdomains and the SYRK
  *                    of group g runs on a second, library-owned stream while

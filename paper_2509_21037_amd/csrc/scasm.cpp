@@ -142,6 +142,9 @@ struct sc_plan_s {
     bool mixed = false;
     bool factored = false, assembled = false;
     hipGraphExec_t graph_exec = nullptr;        // captured assembly (use_graph)
+    hipGraphExec_t impl_graph = nullptr;        // captured implicit apply (use_graph), for impl_p / impl_q
+    const double* impl_p = nullptr;
+    double* impl_q = nullptr;
     double trsm_u = 0, syrk_u = 0, trsm_d = 0, syrk_d = 0, trsm_r = 0, syrk_r = 0;
     // kernel timing: event pairs per kernel, pending until read
     bool timing = false;
@@ -244,6 +247,8 @@ struct sc_plan_s {
         h_lval = nullptr;
         if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
         graph_exec = nullptr;
+        if (impl_graph) (void)hipGraphExecDestroy(impl_graph);
+        impl_graph = nullptr;
         for (auto& p : pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
         for (auto& e : event_pool) (void)hipEventDestroy(e);
         pending.clear();
@@ -901,6 +906,35 @@ sc_status_t sc_apply_implicit(sc_plan_t P, const double* p_dev, double* q_dev, v
         P->ilv.rptr = P->d_rptr.p;
         P->ilv.rpos = P->d_rpos.p;
         P->ilv.ubuf = P->d_ubuf.p;
+    }
+    if (P->opt.use_graph && !P->timing) {
+        // one launch per level and sweep: replayed as a captured graph, made
+        // again when the vectors change (their addresses are in the nodes)
+        if (!P->impl_graph || P->impl_p != p_dev || P->impl_q != q_dev) {
+            if (P->impl_graph) (void)hipGraphExecDestroy(P->impl_graph);
+            P->impl_graph = nullptr;
+            hipStream_t cap;
+            HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                const hipError_t el = launch_apply_implicit(P->tables(), P->ilv, P->d_xoff.p, P->d_xwork.p, p_dev,
+                                                            q_dev, P->nsub, cap, nullptr);
+                e = hipStreamEndCapture(cap, &g);
+                if (e == hipSuccess) e = el;
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&P->impl_graph, g, nullptr, nullptr, 0);
+            if (g) (void)hipGraphDestroy(g);
+            (void)hipStreamDestroy(cap);
+            if (e != hipSuccess) {
+                P->impl_graph = nullptr;
+                return fail(SC_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+            }
+            P->impl_p = p_dev;
+            P->impl_q = q_dev;
+        }
+        HIP_TRY(hipGraphLaunch(P->impl_graph, st));
+        return SC_OK;
     }
     hipEvent_t ev[2];
     hipEvent_t* evp = nullptr;
