@@ -335,19 +335,14 @@ __device__ __forceinline__ double sum_parts(const double (*sp)[64], int r) {
     return v;
 }
 
-__global__ __launch_bounds__(kImplThreads) void implicit_fwd(
-    const SubDev* __restrict__ subs, const BlockDev* __restrict__ blocks, const double* __restrict__ lval, const int64_t* __restrict__ rptr_off, const int32_t* __restrict__ rptr,
-    const int32_t* __restrict__ rpos, const int2* __restrict__ items, const int64_t* __restrict__ xoff,
-    double* __restrict__ xwork, double* __restrict__ ubuf)
+// forward step of block bd of subdomain S: x_b <- L_bb^{-1}(x_b - updates),
+// then its updates L[R_b, b] x_b into its entries of ubuf
+__device__ __forceinline__ void implicit_fwd_block(
+    const SubDev& S, const BlockDev& bd, const double* __restrict__ lval, const int32_t* __restrict__ rp,
+    const int32_t* __restrict__ rpos, double* __restrict__ x, double* __restrict__ ubuf,
+    double (*sp)[64], double* sx)
 {
-    __shared__ double sp[kImplParts][64];
-    __shared__ double sx[64];
-    const int2 it = items[blockIdx.x];
-    const SubDev S = subs[it.x];
-    const BlockDev bd = blocks[S.blk_off + it.y];
     const double* __restrict__ L = lval + S.lval_off;
-    double* __restrict__ x = xwork + xoff[it.x];
-    const int32_t* __restrict__ rp = rptr + rptr_off[it.x];
     const int tid = threadIdx.x;
     const int r = tid & 63;
     const int part = tid >> 6;
@@ -392,20 +387,27 @@ __global__ __launch_bounds__(kImplThreads) void implicit_fwd(
     }
 }
 
-__global__ __launch_bounds__(kImplThreads) void implicit_bwd(
-    const SubDev* __restrict__ subs, const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows,
-    const double* __restrict__ lval, const int2* __restrict__ items, const int64_t* __restrict__ xoff,
-    double* __restrict__ xwork)
+__global__ __launch_bounds__(kImplThreads) void implicit_fwd(
+    const SubDev* __restrict__ subs, const BlockDev* __restrict__ blocks, const double* __restrict__ lval,
+    const int64_t* __restrict__ rptr_off, const int32_t* __restrict__ rptr, const int32_t* __restrict__ rpos,
+    const int2* __restrict__ items, const int64_t* __restrict__ xoff, double* __restrict__ xwork,
+    double* __restrict__ ubuf)
 {
     __shared__ double sp[kImplParts][64];
-    __shared__ double sz[kImplThreads];
-    __shared__ double sv[64];
+    __shared__ double sx[64];
     const int2 it = items[blockIdx.x];
     const SubDev S = subs[it.x];
     const BlockDev bd = blocks[S.blk_off + it.y];
+    implicit_fwd_block(S, bd, lval, rptr + rptr_off[it.x], rpos, xwork + xoff[it.x], ubuf, sp, sx);
+}
+
+// backward step of block bd: z_b <- L_bb^{-T}(y_b - L[R_b, b]^T z[R_b])
+__device__ __forceinline__ void implicit_bwd_block(
+    const SubDev& S, const BlockDev& bd, const int32_t* __restrict__ rows, const double* __restrict__ lval,
+    double* __restrict__ x, double (*sp)[64], double* sz, double* sv)
+{
     const double* __restrict__ L = lval + S.lval_off;
     const int32_t* __restrict__ rw = rows + S.rows_off + bd.rows_off;
-    double* __restrict__ x = xwork + xoff[it.x];
     const int tid = threadIdx.x;
     const int r = tid & 63;
     const int part = tid >> 6;
@@ -437,6 +439,49 @@ __global__ __launch_bounds__(kImplThreads) void implicit_bwd(
     if (tid < w) x[bd.row0 + tid] = sum_parts(sp, tid);
 }
 
+__global__ __launch_bounds__(kImplThreads) void implicit_bwd(
+    const SubDev* __restrict__ subs, const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows,
+    const double* __restrict__ lval, const int2* __restrict__ items, const int64_t* __restrict__ xoff,
+    double* __restrict__ xwork)
+{
+    __shared__ double sp[kImplParts][64];
+    __shared__ double sz[kImplThreads];
+    __shared__ double sv[64];
+    const int2 it = items[blockIdx.x];
+    const SubDev S = subs[it.x];
+    const BlockDev bd = blocks[S.blk_off + it.y];
+    implicit_bwd_block(S, bd, rows, lval, xwork + xoff[it.x], sp, sz, sv);
+}
+
+// Both sweeps of one subdomain in one workgroup: its blocks in increasing
+// order (forward) and decreasing order (backward) are dependency orders, and
+// a workgroup barrier (a workgroup-scope release / acquire of the global
+// writes) separates consecutive blocks; no launch per level.
+__global__ __launch_bounds__(kImplThreads) void implicit_sweeps(
+    const SubDev* __restrict__ subs, const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows,
+    const double* __restrict__ lval, const int64_t* __restrict__ rptr_off, const int32_t* __restrict__ rptr,
+    const int32_t* __restrict__ rpos, const int64_t* __restrict__ xoff, double* __restrict__ xwork,
+    double* __restrict__ ubuf)
+{
+    __shared__ double sp[kImplParts][64];
+    __shared__ double sx[64];
+    __shared__ double sz[kImplThreads];
+    const int sub = blockIdx.x;
+    const SubDev S = subs[sub];
+    double* __restrict__ x = xwork + xoff[sub];
+    const int32_t* __restrict__ rp = rptr + rptr_off[sub];
+    for (int b = 0; b < S.nblocks; ++b) {
+        const BlockDev bd = blocks[S.blk_off + b];
+        implicit_fwd_block(S, bd, lval, rp, rpos, x, ubuf, sp, sx);
+        __syncthreads();
+    }
+    for (int b = S.nblocks - 1; b >= 0; --b) {
+        const BlockDev bd = blocks[S.blk_off + b];
+        implicit_bwd_block(S, bd, rows, lval, x, sp, sz, sx);
+        __syncthreads();
+    }
+}
+
 __global__ __launch_bounds__(256) void implicit_gather(
     const SubDev* __restrict__ subs, const int32_t* __restrict__ piv, const int32_t* __restrict__ pi,
     const int8_t* __restrict__ sgn, const int64_t* __restrict__ xoff, const double* __restrict__ xwork,
@@ -457,18 +502,24 @@ hipError_t launch_apply_implicit(const DevTables& t, const ImplicitLevels& lv, c
         hipLaunchKernelGGL(implicit_init, dim3((unsigned)nsub), dim3(256), 0, stream, t.subs, t.piv, t.pi, t.sgn,
                            xoff, p, xwork);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        for (size_t l = 0; l + 1 < lv.fw_off.size(); ++l) {
-            const int64_t cnt = lv.fw_off[l + 1] - lv.fw_off[l];
-            hipLaunchKernelGGL(implicit_fwd, dim3((unsigned)cnt), dim3(kImplThreads), 0, stream, t.subs, t.blocks,
-                               t.lval, lv.rptr_off, lv.rptr, lv.rpos, lv.fw_items + lv.fw_off[l], xoff, xwork,
-                               lv.ubuf);
+        if (lv.per_subdomain) {
+            hipLaunchKernelGGL(implicit_sweeps, dim3((unsigned)nsub), dim3(kImplThreads), 0, stream, t.subs, t.blocks,
+                               t.rows, t.lval, lv.rptr_off, lv.rptr, lv.rpos, xoff, xwork, lv.ubuf);
             if ((e = hipGetLastError()) != hipSuccess) return e;
-        }
-        for (size_t l = 0; l + 1 < lv.bw_off.size(); ++l) {
-            const int64_t cnt = lv.bw_off[l + 1] - lv.bw_off[l];
-            hipLaunchKernelGGL(implicit_bwd, dim3((unsigned)cnt), dim3(kImplThreads), 0, stream, t.subs, t.blocks, t.rows,
-                               t.lval, lv.bw_items + lv.bw_off[l], xoff, xwork);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
+        } else {
+            for (size_t l = 0; l + 1 < lv.fw_off.size(); ++l) {
+                const int64_t cnt = lv.fw_off[l + 1] - lv.fw_off[l];
+                hipLaunchKernelGGL(implicit_fwd, dim3((unsigned)cnt), dim3(kImplThreads), 0, stream, t.subs,
+                                   t.blocks, t.lval, lv.rptr_off, lv.rptr, lv.rpos, lv.fw_items + lv.fw_off[l], xoff,
+                                   xwork, lv.ubuf);
+                if ((e = hipGetLastError()) != hipSuccess) return e;
+            }
+            for (size_t l = 0; l + 1 < lv.bw_off.size(); ++l) {
+                const int64_t cnt = lv.bw_off[l + 1] - lv.bw_off[l];
+                hipLaunchKernelGGL(implicit_bwd, dim3((unsigned)cnt), dim3(kImplThreads), 0, stream, t.subs,
+                                   t.blocks, t.rows, t.lval, lv.bw_items + lv.bw_off[l], xoff, xwork);
+                if ((e = hipGetLastError()) != hipSuccess) return e;
+            }
         }
         hipLaunchKernelGGL(implicit_gather, dim3((unsigned)nsub), dim3(256), 0, stream, t.subs, t.piv, t.pi, t.sgn,
                            xoff, (const double*)xwork, q);

@@ -86,6 +86,9 @@ struct ImplicitLevels {
     const int32_t* rpos = nullptr;
     double* ubuf = nullptr;
     std::vector<int64_t> fw_off, bw_off;
+    // true: one workgroup per subdomain runs both sweeps block by block (the
+    // block DAGs are near chains); false: one launch per level
+    bool per_subdomain = false;
 };
 
 // Implicit apply q = B P^T L^{-T} L^{-1} P B^T p; xwork holds n_i doubles per

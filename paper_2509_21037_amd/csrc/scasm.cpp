@@ -839,6 +839,7 @@ sc_status_t sc_apply_implicit(sc_plan_t P, const double* p_dev, double* q_dev, v
         std::vector<std::vector<int2>> fw, bw;
         std::vector<int64_t> rptr_off(P->nsub, 0);
         std::vector<int32_t> rptr, rpos;
+        int64_t nblocks_all = 0, nlevels_all = 0;
         for (int32_t i = 0; i < P->nsub; ++i) {
             const SubPlan& sp = P->plans[i];
             const SubDev& sd = P->h_subs[i];
@@ -856,6 +857,8 @@ sc_status_t sc_apply_implicit(sc_plan_t P, const double* p_dev, double* q_dev, v
                 for (int32_t q = 0; q < d.nbelow; ++q)
                     lb[b] = std::max(lb[b], lb[sp.block_of_row[sp.brows[d.rows_off + q]]] + 1);
             }
+            nblocks_all += nb;
+            nlevels_all += nb > 0 ? 1 + *std::max_element(lf.begin(), lf.end()) : 0;
             for (int32_t b = 0; b < nb; ++b) {
                 if ((size_t)lf[b] >= fw.size()) fw.resize(lf[b] + 1);
                 if ((size_t)lb[b] >= bw.size()) bw.resize(lb[b] + 1);
@@ -906,6 +909,9 @@ sc_status_t sc_apply_implicit(sc_plan_t P, const double* p_dev, double* q_dev, v
         P->ilv.rptr = P->d_rptr.p;
         P->ilv.rpos = P->d_rpos.p;
         P->ilv.ubuf = P->d_ubuf.p;
+        // near-chain block DAGs (fewer than 1.5 blocks per level): a level
+        // launch would carry one block per subdomain
+        P->ilv.per_subdomain = 2 * nblocks_all < 3 * nlevels_all;
     }
     if (P->opt.use_graph && !P->timing) {
         // one launch per level and sweep: replayed as a captured graph, made
