@@ -13,6 +13,7 @@ imports nothing from it.  Inputs come from `scgen` (seeded generator).
   pinv_F(sd)          F with the Moore-Penrose inverse of K (another valid K^+)
   projector(G)        I - G (G^T G)^{-1} G^T
   pcpg(F, G, d, it)   projected CG on one subdomain's dual problem
+  dual_direct(F,G,d)  the same problem by one dense saddle-point solve (pins pcpg)
 """
 import ctypes
 import os
@@ -163,18 +164,25 @@ def relF(A, B):
 # iteration phase
 # --------------------------------------------------------------------------
 
-def pcpg(F, G, d, iters):
+PCPG_MUTATIONS = ("none", "no_projection", "beta_unprojected", "alpha_inverted", "lambda_minus")
+
+
+def pcpg(F, G, d, iters, mutation="none"):
     """Projected conjugate gradients on one subdomain's dual problem
     [F -G; -G^T 0][lambda; alpha] = [d; -e] with e = 0 (paper eq. (7); the
     paper cites PCPG without listing it), identity preconditioner, FP64:
         lambda_0 = 0, r_0 = d, w_0 = P r_0, p_0 = w_0
         q = F p;  alpha = (w.w)/(p.q);  lambda += alpha p;  r -= alpha q
         w' = P r;  beta = (w'.w')/(w.w);  p = w' + beta p
-    Returns lambda and the history of ||w_k||."""
+    Returns lambda and the history of ||w_k||.  `mutation` plants one
+    deliberate mistake (PCPG_MUTATIONS; tests show that the direct solve of
+    the dual system catches each); "none" = the correct iteration."""
+    assert mutation in PCPG_MUTATIONS, mutation
     P = projector(G)
+    proj = (lambda v: v.copy()) if mutation == "no_projection" else (lambda v: P @ v)
     lam = np.zeros_like(d)
     r = d.copy()
-    w = P @ r
+    w = proj(r)
     p = w.copy()
     ww = float(w @ w)
     hist = [np.sqrt(ww)]
@@ -183,13 +191,28 @@ def pcpg(F, G, d, iters):
         pq = float(p @ q)
         if pq == 0.0 or ww == 0.0:
             break
-        alpha = ww / pq
-        lam += alpha * p
+        alpha = pq / ww if mutation == "alpha_inverted" else ww / pq
+        lam = lam - alpha * p if mutation == "lambda_minus" else lam + alpha * p
         r -= alpha * q
-        w = P @ r
+        w = proj(r)
         ww_new = float(w @ w)
-        beta = ww_new / ww
+        beta = (float(r @ r) if mutation == "beta_unprojected" else ww_new) / ww
         p = w + beta * p
         ww = ww_new
         hist.append(np.sqrt(ww))
     return lam, np.array(hist)
+
+
+def dual_direct(F, G, d):
+    """lambda of the dual problem (paper eq. (7)) with e = 0 by one dense
+    solve of the saddle-point system [F -G; -G^T 0][lambda; alpha] = [d; 0]
+    (numpy LU; F SPD on ker G^T, G of full column rank).  Returns (lambda,
+    alpha)."""
+    m, k = G.shape
+    A = np.zeros((m + k, m + k))
+    A[:m, :m] = F
+    A[:m, m:] = -G
+    A[m:, :m] = -G.T
+    rhs = np.concatenate([d, np.zeros(k)])
+    x = np.linalg.solve(A, rhs)
+    return x[:m], x[m:]
