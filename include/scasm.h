@@ -100,9 +100,11 @@ typedef struct {
  *   use_graph        1 = sc_assemble captures its kernel launches once into a
  *                    HIP graph and replays it on every later call (the plan's
  *                    buffers and tables are fixed, so the graph stays valid);
- *                    sc_apply_implicit likewise (captured again whenever it
- *                    is called with other p / q pointers); calls made while
- *                    kernel timing is enabled launch eagerly
+ *                    sc_apply_implicit captures its triangular sweeps once
+ *                    (they touch plan-owned buffers only) and launches the
+ *                    scatter of p and the gather into q eagerly around each
+ *                    replay, so any p / q pointers reuse the one graph; calls
+ *                    made while kernel timing is enabled launch eagerly
  *   assembly_kernels 0 = library default (two launches), 1 = overlapped:
  *                    the batch is cut into groups of subdomains and the SYRK
  *                    of group g runs on a second, library-owned stream while
@@ -254,7 +256,8 @@ sc_status_t sc_autotune(const sc_subdomain_desc_t* sd, int32_t nsub, const sc_op
                         int32_t sample, int32_t reps, void* stream, int32_t* best_width,
                         double* times_ms);
 
-/* Release every device and host buffer of the plan.  NULL is accepted. */
+/* Release every device and host buffer of the plan, after waiting for the
+ * device (work queued on any stream may still use them).  NULL is accepted. */
 sc_status_t sc_plan_destroy(sc_plan_t plan);
 
 /* Thread-local message describing the last failure ("" if none). */

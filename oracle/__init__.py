@@ -54,6 +54,8 @@ def _load():
                                   ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                   ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.c_int32, ctypes.c_int32]
+        lib.orc_last_phase_seconds.restype = None
+        lib.orc_last_phase_seconds.argtypes = [ctypes.c_void_p]
         lib.orc_cholesky_dense.restype = ctypes.c_int
         lib.orc_cholesky_dense.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_void_p, ctypes.c_void_p]
@@ -99,6 +101,14 @@ def schur(sd, sel=None, prec="ld", nthreads=None, mutation="none", want_Y=False)
     """F[S,S] for a scgen.Subdomain (all columns when sel is None)."""
     return schur_csr(sd.n, sd.rowptr, sd.col, sd.val, sd.dof, sd.sign, sel=sel, prec=prec,
                      nthreads=nthreads, mutation=mutation, want_Y=want_Y)
+
+
+def last_phase_seconds():
+    """(Cholesky, forward substitution, Y^T Y) wall seconds of the last
+    schur() call in this process."""
+    out = np.zeros(3)
+    _load().orc_last_phase_seconds(_ptr(out))
+    return tuple(float(x) for x in out)
 
 
 def cholesky_dense(sd):

@@ -34,6 +34,19 @@
 #include <omp.h>
 #endif
 
+/* wall-clock seconds of the three steps of the last orc_schur call
+ * (factorisation, forward substitution, Y^T Y); timing only */
+static double g_phase[3];
+
+static double wall_seconds(void)
+{
+#ifdef _OPENMP
+    return omp_get_wtime();
+#else
+    return 0.0;
+#endif
+}
+
 enum {
     MUT_NONE = 0,
     MUT_CHOL_SKIP_FIRST_TERM = 1,  /* Cholesky sum misses its first term */
@@ -113,8 +126,10 @@ static int schur_##SUFFIX(int32_t n, const int64_t* rp, const int32_t* ci,      
     T* L = (T*)malloc(sizeof(T) * (size_t)(start[n] > 0 ? start[n] : 1));              \
     T* Y = (T*)calloc((size_t)n * (size_t)(nsel > 0 ? nsel : 1), sizeof(T));           \
     if (!L || !Y) { free(first); free(start); free(L); free(Y); return -2; }           \
+    double t0 = wall_seconds();                                                        \
     int bad = chol_##SUFFIX(n, rp, ci, v, start, first, L, mutation);                  \
     if (bad) { free(first); free(start); free(L); free(Y); return bad; }               \
+    double t1 = wall_seconds();                                                        \
     (void)nthreads;                                                                    \
     _Pragma("omp parallel for schedule(dynamic, 4) num_threads(nthreads)")             \
     for (int32_t s = 0; s < nsel; ++s) {                                               \
@@ -125,6 +140,7 @@ static int schur_##SUFFIX(int32_t n, const int64_t* rp, const int32_t* ci,      
         y[row] = (mutation == MUT_IGNORE_SIGN) ? (T)1 : (T)sign[j];                    \
         fwd_##SUFFIX(n, start, first, L, y, mutation);                                 \
     }                                                                                  \
+    double t2 = wall_seconds();                                                        \
     _Pragma("omp parallel for schedule(dynamic, 4) num_threads(nthreads)")             \
     for (int32_t b = 0; b < nsel; ++b) {                                               \
         const T* yb = Y + (size_t)b * (size_t)n;                                       \
@@ -137,6 +153,9 @@ static int schur_##SUFFIX(int32_t n, const int64_t* rp, const int32_t* ci,      
             F[(size_t)a * nsel + b] = (double)s;                                       \
         }                                                                              \
     }                                                                                  \
+    g_phase[0] = t1 - t0;                                                              \
+    g_phase[1] = t2 - t1;                                                              \
+    g_phase[2] = wall_seconds() - t2;                                                  \
     if (Yout)                                                                          \
         for (size_t t = 0; t < (size_t)n * (size_t)nsel; ++t) Yout[t] = (double)Y[t];  \
     free(first); free(start); free(L); free(Y);                                        \
@@ -174,6 +193,15 @@ int orc_schur(int32_t n, const int64_t* rowptr, const int32_t* col, const double
     if (prec == 1)
         return schur_ld(n, rowptr, col, val, m, dof, sign, nsel, sel, F, Y, nthreads, mutation);
     return schur_d(n, rowptr, col, val, m, dof, sign, nsel, sel, F, Y, nthreads, mutation);
+}
+
+/* Seconds spent by the last orc_schur call in its three steps: out[0]
+ * Cholesky, out[1] forward substitution, out[2] Y^T Y. */
+void orc_last_phase_seconds(double* out)
+{
+    out[0] = g_phase[0];
+    out[1] = g_phase[1];
+    out[2] = g_phase[2];
 }
 
 /* Cholesky factor alone (long double), returned densely (n*n, row-major, upper

@@ -494,37 +494,53 @@ __global__ __launch_bounds__(256) void implicit_gather(
         q[S.dual_off + pi[S.col_off + a]] = (double)sgn[S.col_off + a] * x[piv[S.col_off + a]];
 }
 
+hipError_t launch_implicit_init(const DevTables& t, const int64_t* xoff, double* xwork, const double* p, int32_t nsub,
+                                hipStream_t stream) {
+    if (nsub <= 0) return hipSuccess;
+    hipLaunchKernelGGL(implicit_init, dim3((unsigned)nsub), dim3(256), 0, stream, t.subs, t.piv, t.pi, t.sgn, xoff, p,
+                       xwork);
+    return hipGetLastError();
+}
+
+hipError_t launch_implicit_sweeps(const DevTables& t, const ImplicitLevels& lv, const int64_t* xoff, double* xwork,
+                                  int32_t nsub, hipStream_t stream) {
+    if (nsub <= 0) return hipSuccess;
+    hipError_t e = hipSuccess;
+    if (lv.per_subdomain) {
+        hipLaunchKernelGGL(implicit_sweeps, dim3((unsigned)nsub), dim3(kImplThreads), 0, stream, t.subs, t.blocks,
+                           t.rows, t.lval, lv.rptr_off, lv.rptr, lv.rpos, xoff, xwork, lv.ubuf);
+        return hipGetLastError();
+    }
+    for (size_t l = 0; l + 1 < lv.fw_off.size(); ++l) {
+        const int64_t cnt = lv.fw_off[l + 1] - lv.fw_off[l];
+        hipLaunchKernelGGL(implicit_fwd, dim3((unsigned)cnt), dim3(kImplThreads), 0, stream, t.subs, t.blocks, t.lval,
+                           lv.rptr_off, lv.rptr, lv.rpos, lv.fw_items + lv.fw_off[l], xoff, xwork, lv.ubuf);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    for (size_t l = 0; l + 1 < lv.bw_off.size(); ++l) {
+        const int64_t cnt = lv.bw_off[l + 1] - lv.bw_off[l];
+        hipLaunchKernelGGL(implicit_bwd, dim3((unsigned)cnt), dim3(kImplThreads), 0, stream, t.subs, t.blocks, t.rows,
+                           t.lval, lv.bw_items + lv.bw_off[l], xoff, xwork);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_implicit_gather(const DevTables& t, const int64_t* xoff, const double* xwork, double* q,
+                                  int32_t nsub, hipStream_t stream) {
+    if (nsub <= 0) return hipSuccess;
+    hipLaunchKernelGGL(implicit_gather, dim3((unsigned)nsub), dim3(256), 0, stream, t.subs, t.piv, t.pi, t.sgn, xoff,
+                       xwork, q);
+    return hipGetLastError();
+}
+
 hipError_t launch_apply_implicit(const DevTables& t, const ImplicitLevels& lv, const int64_t* xoff, double* xwork,
                                  const double* p, double* q, int32_t nsub, hipStream_t stream, hipEvent_t* ev) {
     hipError_t e = hipSuccess;
     if (ev && (e = hipEventRecord(ev[0], stream)) != hipSuccess) return e;
-    if (nsub > 0) {
-        hipLaunchKernelGGL(implicit_init, dim3((unsigned)nsub), dim3(256), 0, stream, t.subs, t.piv, t.pi, t.sgn,
-                           xoff, p, xwork);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        if (lv.per_subdomain) {
-            hipLaunchKernelGGL(implicit_sweeps, dim3((unsigned)nsub), dim3(kImplThreads), 0, stream, t.subs, t.blocks,
-                               t.rows, t.lval, lv.rptr_off, lv.rptr, lv.rpos, xoff, xwork, lv.ubuf);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-        } else {
-            for (size_t l = 0; l + 1 < lv.fw_off.size(); ++l) {
-                const int64_t cnt = lv.fw_off[l + 1] - lv.fw_off[l];
-                hipLaunchKernelGGL(implicit_fwd, dim3((unsigned)cnt), dim3(kImplThreads), 0, stream, t.subs,
-                                   t.blocks, t.lval, lv.rptr_off, lv.rptr, lv.rpos, lv.fw_items + lv.fw_off[l], xoff,
-                                   xwork, lv.ubuf);
-                if ((e = hipGetLastError()) != hipSuccess) return e;
-            }
-            for (size_t l = 0; l + 1 < lv.bw_off.size(); ++l) {
-                const int64_t cnt = lv.bw_off[l + 1] - lv.bw_off[l];
-                hipLaunchKernelGGL(implicit_bwd, dim3((unsigned)cnt), dim3(kImplThreads), 0, stream, t.subs,
-                                   t.blocks, t.rows, t.lval, lv.bw_items + lv.bw_off[l], xoff, xwork);
-                if ((e = hipGetLastError()) != hipSuccess) return e;
-            }
-        }
-        hipLaunchKernelGGL(implicit_gather, dim3((unsigned)nsub), dim3(256), 0, stream, t.subs, t.piv, t.pi, t.sgn,
-                           xoff, (const double*)xwork, q);
-    }
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_implicit_init(t, xoff, xwork, p, nsub, stream)) != hipSuccess) return e;
+    if ((e = launch_implicit_sweeps(t, lv, xoff, xwork, nsub, stream)) != hipSuccess) return e;
+    if ((e = launch_implicit_gather(t, xoff, xwork, q, nsub, stream)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], stream)) != hipSuccess) return e;
     return hipSuccess;
 }

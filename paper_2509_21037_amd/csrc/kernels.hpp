@@ -92,7 +92,16 @@ struct ImplicitLevels {
 };
 
 // Implicit apply q = B P^T L^{-T} L^{-1} P B^T p; xwork holds n_i doubles per
-// subdomain at xoff[i]; optional events ev[0] before, ev[1] after.
+// subdomain at xoff[i]; optional events ev[0] before, ev[1] after.  It is the
+// three launches below in order: x = P B^T p (init), the two blocked
+// triangular sweeps on x in place (they read no caller pointer, so a captured
+// graph of them stays valid for any p and q), q = B P^T x (gather).
+hipError_t launch_implicit_init(const DevTables& t, const int64_t* xoff, double* xwork, const double* p, int32_t nsub,
+                                hipStream_t stream);
+hipError_t launch_implicit_sweeps(const DevTables& t, const ImplicitLevels& lv, const int64_t* xoff, double* xwork,
+                                  int32_t nsub, hipStream_t stream);
+hipError_t launch_implicit_gather(const DevTables& t, const int64_t* xoff, const double* xwork, double* q,
+                                  int32_t nsub, hipStream_t stream);
 hipError_t launch_apply_implicit(const DevTables& t, const ImplicitLevels& lv, const int64_t* xoff, double* xwork,
                                  const double* p, double* q, int32_t nsub, hipStream_t stream, hipEvent_t* ev);
 

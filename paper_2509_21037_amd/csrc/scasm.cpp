@@ -142,9 +142,8 @@ struct sc_plan_s {
     bool mixed = false;
     bool factored = false, assembled = false;
     hipGraphExec_t graph_exec = nullptr;        // captured assembly (use_graph)
-    hipGraphExec_t impl_graph = nullptr;        // captured implicit apply (use_graph), for impl_p / impl_q
-    const double* impl_p = nullptr;
-    double* impl_q = nullptr;
+    hipGraphExec_t impl_graph = nullptr;        // captured triangular sweeps of the implicit apply (use_graph)
+    bool impl_ready = false;                    // implicit apply schedule and workspace built
     double trsm_u = 0, syrk_u = 0, trsm_d = 0, syrk_d = 0, trsm_r = 0, syrk_r = 0;
     // kernel timing: event pairs per kernel, pending until read
     bool timing = false;
@@ -823,6 +822,115 @@ sc_status_t sc_pcpg(sc_plan_t P, const double* const* R_host, const int32_t* k_h
     return SC_OK;
 }
 
+// Level schedule and workspace of the implicit apply, built on first use:
+// everything goes into locals and is committed to the plan only when every
+// allocation, copy and the final synchronisation succeeded (a failed attempt
+// leaves the plan as it was and releases what it allocated).
+static sc_status_t build_implicit(sc_plan_s* P, hipStream_t st) {
+    std::vector<int64_t> off(P->nsub + 1, 0);
+    for (int32_t i = 0; i < P->nsub; ++i) off[i + 1] = off[i] + P->plans[i].n;
+    // levels: forward = 1 + max over the blocks whose pruned rows reach the
+    // block; backward = 1 + max over the blocks the block's pruned rows lie in
+    std::vector<std::vector<int2>> fw, bw;
+    std::vector<int64_t> rptr_off(P->nsub, 0);
+    std::vector<int32_t> rptr, rpos;
+    int64_t nblocks_all = 0, nlevels_all = 0;
+    for (int32_t i = 0; i < P->nsub; ++i) {
+        const SubPlan& sp = P->plans[i];
+        const SubDev& sd = P->h_subs[i];
+        const int32_t nb = (int32_t)sp.blocks.size();
+        std::vector<int32_t> lf(nb, 0), lb(nb, 0);
+        for (int32_t b = 0; b < nb; ++b) {
+            const BlockDesc& d = sp.blocks[b];
+            for (int32_t q = 0; q < d.nbelow; ++q) {
+                const int32_t t = sp.block_of_row[sp.brows[d.rows_off + q]];
+                lf[t] = std::max(lf[t], lf[b] + 1);
+            }
+        }
+        for (int32_t b = nb - 1; b >= 0; --b) {
+            const BlockDesc& d = sp.blocks[b];
+            for (int32_t q = 0; q < d.nbelow; ++q)
+                lb[b] = std::max(lb[b], lb[sp.block_of_row[sp.brows[d.rows_off + q]]] + 1);
+        }
+        nblocks_all += nb;
+        nlevels_all += nb > 0 ? 1 + *std::max_element(lf.begin(), lf.end()) : 0;
+        for (int32_t b = 0; b < nb; ++b) {
+            if ((size_t)lf[b] >= fw.size()) fw.resize(lf[b] + 1);
+            if ((size_t)lb[b] >= bw.size()) bw.resize(lb[b] + 1);
+            fw[lf[b]].push_back(make_int2(i, b));
+            bw[lb[b]].push_back(make_int2(i, b));
+        }
+        // per row: positions (in the global row array) where it is a pruned row
+        std::vector<int32_t> cnt(sp.n + 1, 0);
+        for (int32_t b = 0; b < nb; ++b) {
+            const BlockDesc& d = sp.blocks[b];
+            for (int32_t q = 0; q < d.nbelow; ++q) ++cnt[sp.brows[d.rows_off + q] + 1];
+        }
+        for (int32_t r = 0; r < sp.n; ++r) cnt[r + 1] += cnt[r];
+        rptr_off[i] = (int64_t)rptr.size();
+        const int32_t base = (int32_t)rpos.size();
+        for (int32_t r = 0; r <= sp.n; ++r) rptr.push_back(base + cnt[r]);
+        rpos.resize(rpos.size() + cnt[sp.n]);
+        std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+        for (int32_t b = 0; b < nb; ++b) {             // increasing source block: fixed order
+            const BlockDesc& d = sp.blocks[b];
+            for (int32_t q = 0; q < d.nbelow; ++q)
+                rpos[base + fill[sp.brows[d.rows_off + q]]++] = (int32_t)(sd.rows_off + d.rows_off + q);
+        }
+    }
+    std::vector<int2> fwi, bwi;
+    ImplicitLevels lv;
+    lv.fw_off.assign(1, 0);
+    lv.bw_off.assign(1, 0);
+    for (auto& l : fw) { fwi.insert(fwi.end(), l.begin(), l.end()); lv.fw_off.push_back((int64_t)fwi.size()); }
+    for (auto& l : bw) { bwi.insert(bwi.end(), l.begin(), l.end()); lv.bw_off.push_back((int64_t)bwi.size()); }
+    DevBuf<double> xwork, ubuf;
+    DevBuf<int64_t> xoff, rptr_off_d;
+    DevBuf<int2> ifw, ibw;
+    DevBuf<int32_t> rptr_d, rpos_d;
+    auto release_all = [&]() {
+        xwork.release(); ubuf.release(); xoff.release(); rptr_off_d.release();
+        ifw.release(); ibw.release(); rptr_d.release(); rpos_d.release();
+    };
+    hipError_t e = xwork.alloc((size_t)off[P->nsub]);
+    if (e == hipSuccess) e = xoff.alloc(off.size());
+    if (e == hipSuccess) e = ifw.alloc(std::max<size_t>(1, fwi.size()));
+    if (e == hipSuccess) e = ibw.alloc(std::max<size_t>(1, bwi.size()));
+    if (e == hipSuccess) e = rptr_off_d.alloc(rptr_off.size());
+    if (e == hipSuccess) e = rptr_d.alloc(rptr.size());
+    if (e == hipSuccess) e = rpos_d.alloc(std::max<size_t>(1, rpos.size()));
+    if (e == hipSuccess) e = ubuf.alloc((size_t)P->nrows_total);
+    auto up = [&](void* d, const void* h, size_t bytes) -> hipError_t {
+        return bytes ? hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, st) : hipSuccess;
+    };
+    if (e == hipSuccess) e = up(xoff.p, off.data(), off.size() * 8);
+    if (e == hipSuccess) e = up(ifw.p, fwi.data(), fwi.size() * sizeof(int2));
+    if (e == hipSuccess) e = up(ibw.p, bwi.data(), bwi.size() * sizeof(int2));
+    if (e == hipSuccess) e = up(rptr_off_d.p, rptr_off.data(), rptr_off.size() * 8);
+    if (e == hipSuccess) e = up(rptr_d.p, rptr.data(), rptr.size() * 4);
+    if (e == hipSuccess) e = up(rpos_d.p, rpos.data(), rpos.size() * 4);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);    // the host tables go out of scope
+    if (e != hipSuccess) {
+        release_all();
+        return fail(e == hipErrorOutOfMemory ? SC_ERR_OOM : SC_ERR_DEVICE,
+                    std::string("implicit apply setup: ") + hipGetErrorString(e));
+    }
+    lv.fw_items = ifw.p;
+    lv.bw_items = ibw.p;
+    lv.rptr_off = rptr_off_d.p;
+    lv.rptr = rptr_d.p;
+    lv.rpos = rpos_d.p;
+    lv.ubuf = ubuf.p;
+    // near-chain block DAGs (fewer than 1.5 blocks per level): a level
+    // launch would carry one block per subdomain
+    lv.per_subdomain = 2 * nblocks_all < 3 * nlevels_all;
+    P->d_xwork = xwork; P->d_xoff = xoff; P->d_ifw = ifw; P->d_ibw = ibw;
+    P->d_rptr_off = rptr_off_d; P->d_rptr = rptr_d; P->d_rpos = rpos_d; P->d_ubuf = ubuf;
+    P->ilv = lv;
+    P->impl_ready = true;
+    return SC_OK;
+}
+
 sc_status_t sc_apply_implicit(sc_plan_t P, const double* p_dev, double* q_dev, void* stream) {
     g_last_error.clear();
     if (!P) return fail(SC_ERR_INVALID_ARG, "plan is NULL");
@@ -831,115 +939,36 @@ sc_status_t sc_apply_implicit(sc_plan_t P, const double* p_dev, double* q_dev, v
     if (P->dual_total > 0 && p_dev == q_dev) return fail(SC_ERR_INVALID_ARG, "p and q must not alias");
     HIP_TRY(hipSetDevice(P->device));
     hipStream_t st = (hipStream_t)stream;
-    if (!P->d_xoff.p && P->nsub > 0) {           // workspace and level schedule, on first use
-        std::vector<int64_t> off(P->nsub + 1, 0);
-        for (int32_t i = 0; i < P->nsub; ++i) off[i + 1] = off[i] + P->plans[i].n;
-        // levels: forward = 1 + max over the blocks whose pruned rows reach the
-        // block; backward = 1 + max over the blocks the block's pruned rows lie in
-        std::vector<std::vector<int2>> fw, bw;
-        std::vector<int64_t> rptr_off(P->nsub, 0);
-        std::vector<int32_t> rptr, rpos;
-        int64_t nblocks_all = 0, nlevels_all = 0;
-        for (int32_t i = 0; i < P->nsub; ++i) {
-            const SubPlan& sp = P->plans[i];
-            const SubDev& sd = P->h_subs[i];
-            const int32_t nb = (int32_t)sp.blocks.size();
-            std::vector<int32_t> lf(nb, 0), lb(nb, 0);
-            for (int32_t b = 0; b < nb; ++b) {
-                const BlockDesc& d = sp.blocks[b];
-                for (int32_t q = 0; q < d.nbelow; ++q) {
-                    const int32_t t = sp.block_of_row[sp.brows[d.rows_off + q]];
-                    lf[t] = std::max(lf[t], lf[b] + 1);
-                }
-            }
-            for (int32_t b = nb - 1; b >= 0; --b) {
-                const BlockDesc& d = sp.blocks[b];
-                for (int32_t q = 0; q < d.nbelow; ++q)
-                    lb[b] = std::max(lb[b], lb[sp.block_of_row[sp.brows[d.rows_off + q]]] + 1);
-            }
-            nblocks_all += nb;
-            nlevels_all += nb > 0 ? 1 + *std::max_element(lf.begin(), lf.end()) : 0;
-            for (int32_t b = 0; b < nb; ++b) {
-                if ((size_t)lf[b] >= fw.size()) fw.resize(lf[b] + 1);
-                if ((size_t)lb[b] >= bw.size()) bw.resize(lb[b] + 1);
-                fw[lf[b]].push_back(make_int2(i, b));
-                bw[lb[b]].push_back(make_int2(i, b));
-            }
-            // per row: positions (in the global row array) where it is a pruned row
-            std::vector<int32_t> cnt(sp.n + 1, 0);
-            for (int32_t b = 0; b < nb; ++b) {
-                const BlockDesc& d = sp.blocks[b];
-                for (int32_t q = 0; q < d.nbelow; ++q) ++cnt[sp.brows[d.rows_off + q] + 1];
-            }
-            for (int32_t r = 0; r < sp.n; ++r) cnt[r + 1] += cnt[r];
-            rptr_off[i] = (int64_t)rptr.size();
-            const int32_t base = (int32_t)rpos.size();
-            for (int32_t r = 0; r <= sp.n; ++r) rptr.push_back(base + cnt[r]);
-            rpos.resize(rpos.size() + cnt[sp.n]);
-            std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
-            for (int32_t b = 0; b < nb; ++b) {             // increasing source block: fixed order
-                const BlockDesc& d = sp.blocks[b];
-                for (int32_t q = 0; q < d.nbelow; ++q)
-                    rpos[base + fill[sp.brows[d.rows_off + q]]++] = (int32_t)(sd.rows_off + d.rows_off + q);
-            }
-        }
-        std::vector<int2> fwi, bwi;
-        P->ilv.fw_off.assign(1, 0);
-        P->ilv.bw_off.assign(1, 0);
-        for (auto& l : fw) { fwi.insert(fwi.end(), l.begin(), l.end()); P->ilv.fw_off.push_back((int64_t)fwi.size()); }
-        for (auto& l : bw) { bwi.insert(bwi.end(), l.begin(), l.end()); P->ilv.bw_off.push_back((int64_t)bwi.size()); }
-        HIP_TRY(P->d_xwork.alloc((size_t)off[P->nsub]));
-        HIP_TRY(P->d_xoff.alloc(off.size()));
-        HIP_TRY(P->d_ifw.alloc(std::max<size_t>(1, fwi.size())));
-        HIP_TRY(P->d_ibw.alloc(std::max<size_t>(1, bwi.size())));
-        HIP_TRY(P->d_rptr_off.alloc(rptr_off.size()));
-        HIP_TRY(P->d_rptr.alloc(rptr.size()));
-        HIP_TRY(P->d_rpos.alloc(std::max<size_t>(1, rpos.size())));
-        HIP_TRY(P->d_ubuf.alloc((size_t)P->nrows_total));
-        HIP_TRY(hipMemcpyAsync(P->d_xoff.p, off.data(), off.size() * 8, hipMemcpyHostToDevice, st));
-        HIP_TRY(hipMemcpyAsync(P->d_ifw.p, fwi.data(), fwi.size() * sizeof(int2), hipMemcpyHostToDevice, st));
-        HIP_TRY(hipMemcpyAsync(P->d_ibw.p, bwi.data(), bwi.size() * sizeof(int2), hipMemcpyHostToDevice, st));
-        HIP_TRY(hipMemcpyAsync(P->d_rptr_off.p, rptr_off.data(), rptr_off.size() * 8, hipMemcpyHostToDevice, st));
-        HIP_TRY(hipMemcpyAsync(P->d_rptr.p, rptr.data(), rptr.size() * 4, hipMemcpyHostToDevice, st));
-        HIP_TRY(hipMemcpyAsync(P->d_rpos.p, rpos.data(), rpos.size() * 4, hipMemcpyHostToDevice, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        P->ilv.fw_items = P->d_ifw.p;
-        P->ilv.bw_items = P->d_ibw.p;
-        P->ilv.rptr_off = P->d_rptr_off.p;
-        P->ilv.rptr = P->d_rptr.p;
-        P->ilv.rpos = P->d_rpos.p;
-        P->ilv.ubuf = P->d_ubuf.p;
-        // near-chain block DAGs (fewer than 1.5 blocks per level): a level
-        // launch would carry one block per subdomain
-        P->ilv.per_subdomain = 2 * nblocks_all < 3 * nlevels_all;
+    if (P->nsub == 0) return SC_OK;
+    if (!P->impl_ready) {
+        const sc_status_t s = build_implicit(P, st);
+        if (s != SC_OK) return s;
     }
+    const DevTables t = P->tables();
     if (P->opt.use_graph && !P->timing) {
-        // one launch per level and sweep: replayed as a captured graph, made
-        // again when the vectors change (their addresses are in the nodes)
-        if (!P->impl_graph || P->impl_p != p_dev || P->impl_q != q_dev) {
-            if (P->impl_graph) (void)hipGraphExecDestroy(P->impl_graph);
-            P->impl_graph = nullptr;
+        // the triangular sweeps read and write only plan-owned buffers: they
+        // are captured once and replayed for every call; the scatter of p and
+        // the gather into q run eagerly around the replay
+        if (!P->impl_graph) {
             hipStream_t cap;
             HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
             hipGraph_t g = nullptr;
+            hipGraphExec_t ex = nullptr;
             hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
-                const hipError_t el = launch_apply_implicit(P->tables(), P->ilv, P->d_xoff.p, P->d_xwork.p, p_dev,
-                                                            q_dev, P->nsub, cap, nullptr);
+                const hipError_t el = launch_implicit_sweeps(t, P->ilv, P->d_xoff.p, P->d_xwork.p, P->nsub, cap);
                 e = hipStreamEndCapture(cap, &g);
                 if (e == hipSuccess) e = el;
             }
-            if (e == hipSuccess) e = hipGraphInstantiate(&P->impl_graph, g, nullptr, nullptr, 0);
+            if (e == hipSuccess) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
             if (g) (void)hipGraphDestroy(g);
             (void)hipStreamDestroy(cap);
-            if (e != hipSuccess) {
-                P->impl_graph = nullptr;
-                return fail(SC_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
-            }
-            P->impl_p = p_dev;
-            P->impl_q = q_dev;
+            if (e != hipSuccess) return fail(SC_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+            P->impl_graph = ex;
         }
+        HIP_TRY(launch_implicit_init(t, P->d_xoff.p, P->d_xwork.p, p_dev, P->nsub, st));
         HIP_TRY(hipGraphLaunch(P->impl_graph, st));
+        HIP_TRY(launch_implicit_gather(t, P->d_xoff.p, P->d_xwork.p, q_dev, P->nsub, st));
         return SC_OK;
     }
     hipEvent_t ev[2];
@@ -948,7 +977,7 @@ sc_status_t sc_apply_implicit(sc_plan_t P, const double* p_dev, double* q_dev, v
         HIP_TRY(P->take_events(2, ev));
         evp = ev;
     }
-    HIP_TRY(launch_apply_implicit(P->tables(), P->ilv, P->d_xoff.p, P->d_xwork.p, p_dev, q_dev, P->nsub, st, evp));
+    HIP_TRY(launch_apply_implicit(t, P->ilv, P->d_xoff.p, P->d_xwork.p, p_dev, q_dev, P->nsub, st, evp));
     if (evp) P->pending.push_back({3, ev[0], ev[1]});
     return SC_OK;
 }
@@ -1216,6 +1245,8 @@ sc_status_t sc_autotune(const sc_subdomain_desc_t* sd, int32_t nsub, const sc_op
 sc_status_t sc_plan_destroy(sc_plan_t P) {
     if (!P) return SC_OK;
     (void)hipSetDevice(P->device);
+    // queued work may still use the plan's buffers and graphs
+    (void)hipDeviceSynchronize();
     P->release();
     delete P;
     return SC_OK;

@@ -143,6 +143,28 @@ def _fill_desc(d, s, keep, use_coords=True):
 ASSEMBLY_KERNELS = {"default": 0, "overlap": 1, "separate": 2}
 
 
+def check_dual_tensor(t, length: int, device_index: int, name: str):
+    """Raises ScasmError(SC_ERR_INVALID_ARG) unless `t` is a contiguous FP64
+    tensor on HIP device `device_index` with at least `length` elements: the
+    library reads and writes `length` doubles through its data pointer."""
+    import torch
+    bad = None
+    if not isinstance(t, torch.Tensor):
+        bad = f"{name} must be a torch.Tensor, got {type(t).__name__}"
+    elif t.dtype != torch.float64:
+        bad = f"{name} must be float64, got {t.dtype}"
+    elif not t.is_contiguous():
+        bad = f"{name} must be contiguous"
+    elif t.numel() < length:
+        bad = f"{name} has {t.numel()} elements, the plan's dual vectors have {length}"
+    elif not t.is_cuda:
+        bad = f"{name} must be a device tensor, got one on {t.device}"
+    elif t.device.index != device_index:
+        bad = f"{name} is on device {t.device.index}, the plan on device {device_index}"
+    if bad is not None:
+        raise ScasmError(SC_ERR_INVALID_ARG, bad)
+
+
 def _options(precision="fp64", staircase=True, panel_width=0, relax_width=0, leaf_nodes=0, n_threads=0,
              use_graph=False, assembly="default", reach=True):
     opt = Options()
@@ -252,6 +274,13 @@ class Plan:
         _check(lib.sc_plan_create(descs, len(self.subdomains), ctypes.byref(opt), _stream_handle(stream),
                                   ctypes.byref(self._h)))
         del keep
+        import torch
+        self.device_index = torch.cuda.current_device()
+        self.dual_total = self.stats()["dual_total"]
+
+    def _dual(self, t, name):
+        check_dual_tensor(t, self.dual_total, self.device_index, name)
+        return ctypes.c_void_p(t.data_ptr())
 
     # ---------------------------------------------------------------- stages
     def factor(self, kvals: Optional[List[np.ndarray]] = None, stream=None):
@@ -272,13 +301,13 @@ class Plan:
 
     def apply(self, p, q, stream=None):
         """q = F p on device FP64 tensors of length dual_total."""
-        _check(self._lib.sc_apply(self._h, ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(q.data_ptr()),
-                                  _stream_handle(stream)))
+        pp, qp = self._dual(p, "p"), self._dual(q, "q")
+        _check(self._lib.sc_apply(self._h, pp, qp, _stream_handle(stream)))
         return q
 
     def apply_implicit(self, p, q, stream=None):
-        _check(self._lib.sc_apply_implicit(self._h, ctypes.c_void_p(p.data_ptr()),
-                                           ctypes.c_void_p(q.data_ptr()), _stream_handle(stream)))
+        pp, qp = self._dual(p, "p"), self._dual(q, "q")
+        _check(self._lib.sc_apply_implicit(self._h, pp, qp, _stream_handle(stream)))
         return q
 
     def pcpg(self, d, lam, iters: int, R_list=None, history: bool = False, stream=None):
@@ -292,7 +321,13 @@ class Plan:
         ks = (ctypes.c_int32 * max(1, len(Rs)))(*[R.shape[1] for R in Rs])
         ptrs = (ctypes.c_void_p * max(1, len(Rs)))(*[R.ctypes.data for R in Rs])
         hist = np.zeros((iters + 1, len(Rs))) if history else None
-        _check(self._lib.sc_pcpg(self._h, ptrs, ks, ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(lam.data_ptr()),
+        if len(Rs) != len(self.subdomains):
+            raise ScasmError(SC_ERR_INVALID_ARG, f"{len(Rs)} kernel bases for {len(self.subdomains)} subdomains")
+        for i, (R, s) in enumerate(zip(Rs, self.subdomains)):
+            if R.ndim != 2 or R.shape[0] != int(s.n):
+                raise ScasmError(SC_ERR_INVALID_ARG, f"R[{i}] must be n_i x k_i, got {R.shape}")
+        dp, lp = self._dual(d, "d"), self._dual(lam, "lambda")
+        _check(self._lib.sc_pcpg(self._h, ptrs, ks, dp, lp,
                                  int(iters), hist.ctypes.data if hist is not None else None,
                                  _stream_handle(stream)))
         return hist

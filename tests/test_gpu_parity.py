@@ -280,6 +280,32 @@ def test_apply_state_and_alias_errors():
     assert e.value.status == P.SC_ERR_INVALID_ARG
 
 
+def test_wrong_dual_tensors_are_rejected_before_any_launch():
+    """FP32, short, strided and host tensors never reach the kernels of the
+    explicit apply, the implicit apply or PCPG."""
+    torch = _torch_init()
+    s = scgen.config_subdomains(1)[0]
+    plan = P.Plan([s])
+    plan.factor()
+    plan.assemble()
+    good = torch.zeros(s.m, dtype=torch.float64, device="cuda")
+    bad = [torch.zeros(s.m, dtype=torch.float32, device="cuda"),
+           torch.zeros(s.m - 1, dtype=torch.float64, device="cuda"),
+           torch.zeros(2 * s.m, dtype=torch.float64, device="cuda")[::2],
+           torch.zeros(s.m, dtype=torch.float64)]
+    for b in bad:
+        for f in (plan.apply, plan.apply_implicit):
+            for args in ((b, good), (good, b)):
+                with pytest.raises(P.ScasmError) as e:
+                    f(*args)
+                assert e.value.status == P.SC_ERR_INVALID_ARG
+        with pytest.raises(P.ScasmError) as e:
+            plan.pcpg(b, good, 3)
+        assert e.value.status == P.SC_ERR_INVALID_ARG
+    torch.cuda.synchronize()
+    plan.destroy()
+
+
 # ---------------------------------------------------------------- mixed precision
 
 TOL_MIXED = 1e-5
@@ -439,6 +465,14 @@ def test_implicit_apply_graph_replays_match_eager():
             junk.mul_(2.0)
             torch.cuda.synchronize()
             assert np.array_equal(q2.cpu().numpy(), ref), rep
+    # alternating input and output buffers, no synchronisation in between
+    ps = [p.clone(), p.clone()]
+    qs = [torch.full_like(p, 7.0) for _ in range(4)]
+    for k in range(4):
+        plan.apply_implicit(ps[k % 2], qs[k])
+    torch.cuda.synchronize()
+    for k in range(4):
+        assert np.array_equal(qs[k].cpu().numpy(), ref), k
     plan.destroy()
 
 

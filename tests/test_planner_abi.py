@@ -301,3 +301,21 @@ def test_zero_multipliers_and_tiny_subdomain():
     e.sign = np.zeros(0, np.int8)
     r = P.host_analyze(e)
     assert r["m"] == 0 and r["trsm_useful"] == 0 and r["syrk_useful"] == 0
+
+
+def test_dual_vector_checks_reject_bad_tensors_before_any_call():
+    import torch
+    n = 50
+    good = torch.zeros(n, dtype=torch.float64)
+    cases = [
+        (np.zeros(n), "must be a torch.Tensor"),
+        (torch.zeros(n, dtype=torch.float32), "must be float64"),
+        (torch.zeros(2 * n, dtype=torch.float64)[::2], "must be contiguous"),
+        (torch.zeros(n - 1, dtype=torch.float64), "elements, the plan's dual vectors have"),
+        (good, "must be a device tensor"),
+    ]
+    for t, msg in cases:
+        with pytest.raises(P.ScasmError) as e:
+            P.check_dual_tensor(t, n, 0, "p")
+        assert e.value.status == P.SC_ERR_INVALID_ARG
+        assert msg in e.value.message, (msg, e.value.message)
