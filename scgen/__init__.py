@@ -22,12 +22,14 @@ Problem statement (paper, Sec. 2.1, eqs. (1)-(9)):
 """
 from .mesh import (Subdomain, heat_q1_2d, heat_hex8, elasticity_hex8, laplace_1d,
                    box_subdomain)
+from .simplex import simplex_subdomain, p1_stiffness
 from .rng import splitmix64, splitmix64_uniform
 from .configs import (config_subdomains, CONFIG_NAMES, BASE_SEED, config_description,
-                      uneven_sizes)
+                      uneven_sizes, paper_subdomains, paper_batch_size, PAPER_NODES)
 
 __all__ = [
     "Subdomain", "heat_q1_2d", "heat_hex8", "elasticity_hex8", "laplace_1d",
-    "box_subdomain", "splitmix64", "splitmix64_uniform", "config_subdomains",
-    "CONFIG_NAMES", "BASE_SEED", "config_description", "uneven_sizes",
+    "box_subdomain", "simplex_subdomain", "p1_stiffness", "splitmix64", "splitmix64_uniform", "config_subdomains",
+    "CONFIG_NAMES", "BASE_SEED", "config_description", "uneven_sizes", "paper_subdomains",
+    "paper_batch_size", "PAPER_NODES",
 ]

@@ -35,6 +35,35 @@ CONFIG_NAMES = {
 CONFIG_BATCH = {1: 1, 2: 1024, 3: 512, 4: 512, 5: 64}
 
 
+# The paper's own workloads (Sec. 4): heat transfer on P1 triangles (2D) and
+# tetrahedra (3D), subdomain sizes from its figures (nodes per side), batches
+# of about the paper's total problem size (8.4 M unknowns in 2D, 1.1 M in 3D)
+# between 16 and 512 subdomains.  Subdomain i of the (dim, nodes) batch draws
+# its signs from the stream seeded with
+# stream_seed(BASE_SEED + 100 * dim + nodes, i).
+PAPER_NODES = {2: (7, 33, 129, 257, 513, 725), 3: (4, 9, 14, 21, 33, 41)}
+PAPER_TOTAL_DOFS = {2: 8.4e6, 3: 1.1e6}
+
+
+def paper_batch_size(dim: int, nodes: int) -> int:
+    n = nodes ** dim
+    return int(min(512, max(16, round(PAPER_TOTAL_DOFS[dim] / n))))
+
+
+def paper_subdomains(dim: int, nodes: int, count: Optional[int] = None, start: int = 0) -> List[Subdomain]:
+    """P1 heat subdomains (triangles for dim 2, tetrahedra for dim 3) with
+    `nodes` nodes per side on the unit square / cube, multipliers on every
+    boundary node; subdomains start .. start + count - 1 of the batch."""
+    from .simplex import simplex_subdomain
+    if count is None:
+        count = paper_batch_size(dim, nodes) - start
+    base = BASE_SEED + 100 * dim + nodes
+    out = [simplex_subdomain(dim, nodes - 1, stream_seed(base, i)) for i in range(start, start + count)]
+    for s in out:
+        s.meta["paper"] = (dim, nodes)
+    return out
+
+
 def config_description(cfg: int) -> str:
     return CONFIG_NAMES[cfg]
 

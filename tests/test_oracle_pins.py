@@ -18,6 +18,8 @@ def _small_cases():
         scgen.box_subdomain("heat", (4, 5, 3), 0.25, seed=11),
         scgen.box_subdomain("elasticity", (3, 4, 3), 0.25, seed=12),
         scgen.box_subdomain("elasticity", (2, 2, 5), 0.5, seed=13, gluing="unique"),
+        scgen.simplex_subdomain(2, 9, seed=14),
+        scgen.simplex_subdomain(3, 5, seed=15),
     ]
 
 
@@ -45,20 +47,20 @@ def test_1d_laplace_closed_form(N):
 
 # ---------------------------------------------------------------- independent routes
 
-@pytest.mark.parametrize("case", range(4))
+@pytest.mark.parametrize("case", range(6))
 def test_matches_dense_lu(case):
     s = _small_cases()[case]
     assert oracle.relF(oracle.schur(s), oracle.brute_F(s)) < 1e-13
 
 
-@pytest.mark.parametrize("case", range(4))
+@pytest.mark.parametrize("case", range(6))
 def test_matches_saddle_point_route(case):
     # -F is the Schur complement of [[K_reg, B^T], [B, 0]] (paper eq. (13))
     s = _small_cases()[case]
     assert oracle.relF(oracle.schur(s), oracle.saddle_F(s)) < 1e-11
 
 
-@pytest.mark.parametrize("case", range(4))
+@pytest.mark.parametrize("case", range(6))
 def test_projected_invariance_moore_penrose(case):
     # any two generalised inverses give the same P_G F P_G, G = B R
     s = _small_cases()[case]
@@ -104,7 +106,7 @@ def test_projected_invariance_spectral_full_heat_workload():
 
 # ---------------------------------------------------------------- residuals / invariants
 
-@pytest.mark.parametrize("case", range(4))
+@pytest.mark.parametrize("case", range(6))
 def test_factor_and_forward_residuals(case):
     s = _small_cases()[case]
     L = oracle.cholesky_dense(s)
@@ -119,7 +121,7 @@ def test_factor_and_forward_residuals(case):
     assert np.linalg.norm(K @ Z - Bt) / np.linalg.norm(Bt) < 1e-11
 
 
-@pytest.mark.parametrize("case", range(4))
+@pytest.mark.parametrize("case", range(6))
 def test_symmetric_positive_definite(case):
     s = _small_cases()[case]
     F = oracle.schur(s)

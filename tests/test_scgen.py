@@ -103,3 +103,74 @@ def test_signs_per_subdomain_differ_and_are_pm1():
     for s in ss:
         assert set(np.unique(s.sign).tolist()) == {-1, 1}
     assert not np.array_equal(ss[0].sign, ss[1].sign)
+
+
+# ------------------------------------------------ P1 triangles / tetrahedra
+
+def test_p1_triangle_closed_form():
+    # right isosceles triangle, right angle at vertex 0: K = 1/2 [[2,-1,-1],[-1,1,0],[-1,0,1]]
+    # for any leg length (the 2D Laplace stiffness is scale-free)
+    for h in (1.0, 0.125):
+        K = scgen.p1_stiffness(np.array([[0, 0], [h, 0], [0, h]]))
+        assert np.allclose(K, 0.5 * np.array([[2, -1, -1], [-1, 1, 0], [-1, 0, 1]]), rtol=0, atol=1e-15)
+
+
+def test_p1_tetrahedron_closed_form():
+    # corner tetrahedron of the unit cube: K = (1/6) [[3,-1,-1,-1],[-1,1,0,0],[-1,0,1,0],[-1,0,0,1]],
+    # scaling like h in 3D
+    for h in (1.0, 0.25):
+        K = scgen.p1_stiffness(h * np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1.0]]))
+        ref = h / 6 * np.array([[3, -1, -1, -1], [-1, 1, 0, 0], [-1, 0, 1, 0], [-1, 0, 0, 1]])
+        assert np.allclose(K, ref, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("dim,e", [(2, 6), (2, 9), (3, 4), (3, 5)])
+def test_simplex_grids_give_the_finite_difference_stencils(dim, e):
+    # P1 on the diagonal-split square grid is the 5-point Laplacian; on the
+    # Kuhn subdivision of the cube grid it is h times the 7-point Laplacian
+    # (the face- and body-diagonal couplings of the six tetrahedra cancel)
+    s = scgen.simplex_subdomain(dim, e, seed=3)
+    K = s.K_csr()
+    npx = e + 1
+    h = 1.0 / e
+    scale = 1.0 if dim == 2 else h
+    for c in range(s.n):
+        idx = np.unravel_index(c, (npx,) * dim, order="F")
+        if min(idx) == 0 or max(idx) == e:
+            continue
+        row = K.getrow(c)
+        nb = sorted(row.indices.tolist())
+        strides = [1, npx, npx * npx][:dim]
+        expect = sorted([c] + [c + st for st in strides] + [c - st for st in strides])
+        assert nb == expect
+        assert np.isclose(row[0, c], 2 * dim * scale, rtol=1e-14)
+        for st in strides:
+            assert np.isclose(row[0, c + st], -scale, rtol=1e-14)
+    assert np.abs(K @ np.ones(s.n)).max() <= 1e-13
+    assert abs(K - K.T).max() == 0.0
+    assert np.linalg.eigvalsh(K.toarray()).min() > -1e-12
+    assert s.m == npx ** dim - (npx - 2) ** dim
+
+
+def test_kuhn_tetrahedra_fill_the_cube():
+    from scgen.simplex import _local_simplices
+    vols = [abs(np.linalg.det((t[1:] - t[0]).astype(float))) / 6 for t in _local_simplices(3)]
+    assert np.allclose(vols, 1 / 6) and abs(sum(vols) - 1.0) < 1e-15
+
+
+@pytest.mark.parametrize("dim,e", [(2, 5), (3, 3)])
+def test_simplex_regularised_inverse_is_generalised_inverse(dim, e):
+    s = scgen.simplex_subdomain(dim, e, seed=1)
+    K = s.K_csr().toarray()
+    Kr = s.Kreg_csr().toarray()
+    X = np.linalg.solve(Kr, K)
+    assert np.abs(K @ X - K).max() <= 1e-10 * np.abs(K).max()
+
+
+def test_paper_batches_are_seeded_and_distinct():
+    a = scgen.paper_subdomains(3, 9, count=3)
+    b = scgen.paper_subdomains(3, 9, count=2, start=1)
+    assert np.array_equal(a[1].sign, b[0].sign)
+    assert not np.array_equal(a[0].sign, a[1].sign)
+    assert a[0].n == 729 and a[0].m == 729 - 343
+    assert scgen.paper_batch_size(3, 41) == 16 and scgen.paper_batch_size(2, 7) == 512
