@@ -128,6 +128,25 @@ def time_apply(torch, plan, which, iters=20):
     return wall, kt[key][0] / max(1, kt[key][1])
 
 
+def preprocessing_times(torch, plan, factor_s, asm_ms, reps=2):
+    """The whole preprocessing stage (Sec. 4.4): host factorisation and
+    extraction of the factors, upload, GPU assembly.  sep = sc_factor (timed
+    once, synchronised) + the timed assembly step; mix = sc_preprocess (host
+    factorisation of later subdomain groups overlapped with the GPU assembly
+    of earlier ones), wall clock to the end of the stream, best of `reps`."""
+    best = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.preprocess()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        best = el if best is None else min(best, el)
+    sep = factor_s + asm_ms * 1e-3
+    return {"factor_upload_s": factor_s, "assembly_s": asm_ms * 1e-3, "sep_s": sep, "mix_s": best,
+            "mix_gain": sep / best, "host_threads": min(16, os.cpu_count() or 1)}
+
+
 def sample_ids(subs, big):
     """Subdomains whose GPU F is kept for the error check of the cpu_baseline
     leg (the leg runs the oracle on subdomains 0, 1, ... in order): the first
@@ -244,6 +263,8 @@ def main():
                     help="TRSM and SYRK of successive subdomain groups overlapped on two streams, or two launches")
     ap.add_argument("--compare-assembly", action="store_true",
                     help="also time the FP64 assembly in the other mode (overlap / separate)")
+    ap.add_argument("--no-prep", dest="prep", action="store_false",
+                    help="skip the whole-preprocessing timing (factorisation + assembly, separate and pipelined)")
     ap.add_argument("--latency", action="store_true",
                     help="also time one 16 x 16 Q1 single-subdomain assembly (median of 1000 calls)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -286,9 +307,11 @@ def main():
     # ---------------------------------------------------------------- FP64
     t0 = time.perf_counter()
     plan = P.Plan(subs, panel_width=args.panel_width, use_graph=use_graph, assembly=args.assembly)
+    t1 = time.perf_counter()
     plan.factor()
     torch.cuda.synchronize()
     prep_s = time.perf_counter() - t0
+    prep_factor_s = time.perf_counter() - t1
     log(f"bench: FP64 plan + host factorisation + upload in {prep_s:.1f}s (not in the timed region)")
     st = plan.stats()
     ms_per_step, kms = time_assembly(torch, plan, args.steps, args.warmup, use_graph)
@@ -303,6 +326,9 @@ def main():
                 "kernel_ms": kms,
                 "kernel_tflops": {k: flops[k] / (kms[k] * 1e-3) / 1e12 for k in kms}}
     kept = {"fp64": keep_F(plan, subs, ids)}
+    prep = preprocessing_times(torch, plan, prep_factor_s, ms_per_step) if args.prep else None
+    if prep:
+        log(f"bench: FP64 preprocessing {prep}")
     _, apply64 = time_apply(torch, plan, "explicit")
     # the apply reads the stored F: lower 128 x 128 tiles in sorted column order
     f_bytes64 = sum((t := (s.m + 127) // 128) * (t + 1) // 2 * 128 * 128 for s in subs) * 8
@@ -324,11 +350,17 @@ def main():
         wall_i, extra["implicit_eager_ms"] = time_apply(torch, plan, "implicit", iters=5)
         extra["implicit_ms"] = wall_i if use_graph else extra["implicit_eager_ms"]
         log(f"bench: apply {extra}")
-    orig, kms_o = None, None
+    orig, kms_o, prep_orig = None, None, None
     if args.compare_orig:
         plan_o = P.Plan(subs, staircase=False, panel_width=args.panel_width)
+        t1 = time.perf_counter()
         plan_o.factor()
+        torch.cuda.synchronize()
+        fo_s = time.perf_counter() - t1
         orig, kms_o = time_assembly(torch, plan_o, max(1, args.steps // 2), 1)
+        if args.prep:
+            prep_orig = preprocessing_times(torch, plan_o, fo_s, orig, reps=1)
+            log(f"bench: FP64 preprocessing without the staircase {prep_orig}")
         plan_o.destroy()
         log(f"bench: FP64 without the staircase {orig:.3f} ms/step, kernels {kms_o}")
     noreach = None
@@ -438,6 +470,11 @@ def main():
         "relF_source": "cpu_baseline leg: FP64 oracle on its sample of subdomains (seeded 256-column "
                        "subsets of the first two for n > 3000) against the kept GPU F",
         "prep_s": prep_s,
+        "preprocessing": prep,
+        "preprocessing_orig": prep_orig,
+        "speedup_orig_over_opt": None if not (orig and prep and prep_orig) else {
+            "gpu_section_sep": orig / ms_per_step, "whole_sep": prep_orig["sep_s"] / prep["sep_s"],
+            "whole_mix": prep_orig["mix_s"] / prep["mix_s"]},
         "latency_config1_us": lat1,
         "orig_ms_per_step": orig,
         "orig_kernel_ms": kms_o,

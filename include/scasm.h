@@ -13,7 +13,9 @@
  * (Sec. 2.2, eqs. (11)-(12)).  The three solver stages of Sec. 2.2 map to
  *     initialisation  -> sc_plan_create   (ordering, symbolic factorisation,
  *                                          staircase plan, device buffers)
- *     preprocessing   -> sc_factor + sc_assemble
+ *     preprocessing   -> sc_factor + sc_assemble, or sc_preprocess (both,
+ *                        pipelined: host factorisation overlapped with the
+ *                        GPU assembly, Sec. 4.4)
  *     solution        -> sc_apply (explicit, eq. (12)) or
  *                        sc_apply_implicit (eq. (11))
  *
@@ -164,6 +166,24 @@ sc_status_t sc_factor(sc_plan_t plan, const double* const* kreg_vals, void* stre
  * order (Sec. 3) is applied to the vectors by sc_apply / sc_pcpg and to the
  * matrix by sc_get_F.  Asynchronous.  SC_ERR_STATE before sc_factor. */
 sc_status_t sc_assemble(sc_plan_t plan, void* stream);
+
+/* Whole preprocessing stage in one call, pipelined (Sec. 4.4, the whole
+ * assembly including the numerical factorisation and the extraction of the
+ * factors, with CPU-GPU overlap once the first subdomains are factorised):
+ * host threads factor the subdomains group by group (the batch is cut into
+ * up to 8 groups, each holding part of every XCD's work list, largest
+ * subdomains first); as soon as every subdomain of the next group is
+ * factored and extracted, that group's factor values are copied to the
+ * device (one asynchronous copy; the FP32 copy in mixed precision) and its
+ * TRSM tiles and SYRK items are launched on `stream`, while the host goes on
+ * with the next groups.  The result equals sc_factor followed by
+ * sc_assemble bit for bit.  Returns when every group has been launched;
+ * the assembly completes on `stream`.  Arguments and errors as sc_factor
+ * (on SC_ERR_NOT_SPD no group after the failing one is launched and the plan
+ * is left unfactored).  Not captured into a graph and not timed by
+ * sc_set_timing. */
+sc_status_t sc_preprocess(sc_plan_t plan, const double* const* kreg_vals, void* stream,
+                          int32_t* failed_sub, int32_t* failed_col);
 
 /* Solution stage, explicit apply (eq. (12)): q_i = F_i p_i for every
  * subdomain, on `stream`.  p_dev, q_dev: device FP64 vectors of length

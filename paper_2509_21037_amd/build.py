@@ -36,7 +36,7 @@ def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
     objs = []
-    for src, kind in (("planner.cpp", "host"), ("scasm.cpp", "hosthip"), ("kernels.hip", "device"),
+    for src, kind in (("planner.cpp", "host"), ("dense_host.cpp", "host"), ("scasm.cpp", "hosthip"), ("kernels.hip", "device"),
                       ("apply.hip", "device")):
         obj = os.path.join(BUILD, src + ".o")
         path = os.path.join(CSRC, src)

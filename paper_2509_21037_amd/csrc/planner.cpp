@@ -2,6 +2,7 @@
 // relaxed supernodes, numeric supernodal Cholesky (FP64) and the staircase
 // plan of the Schur-complement assembly.
 #include "planner.hpp"
+#include "dense_host.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -602,10 +603,18 @@ std::string build_plan(const SubdomainInput& in, const PlanOptions& opt, SubPlan
 
 // ---------------------------------------------------------------------------
 // numeric supernodal Cholesky: for each supernode in order, factor its panel
-// (left-looking column Cholesky of the (w+r) x w panel = diagonal Cholesky +
-// triangular solve of the rows below), then subtract its outer-product
-// contribution from every later supernode its rows touch.
+// (the (w + r) x w block column: Cholesky of the w x w diagonal block and the
+// triangular solve of the r rows below, left-looking over column blocks of
+// kPanelBlock, the update of each block a product with the columns before it),
+// then subtract its outer-product contribution from every later supernode its
+// rows touch (right-looking: one product per target supernode into a dense
+// buffer, scattered into the target's panel).
 // ---------------------------------------------------------------------------
+namespace {
+constexpr int32_t kPanelBlock = 32;
+constexpr int64_t kUpdateBlock = 64;
+}
+
 int64_t factor_numeric(const SubPlan& P, const double* kvals, double* vals) {
     std::memset(vals, 0, sizeof(double) * (size_t)P.nval);
     for (size_t e = 0; e < P.kmap.size(); ++e)
@@ -618,20 +627,27 @@ int64_t factor_numeric(const SubPlan& P, const double* kvals, double* vals) {
         const int64_t ld = P.srow_ptr[s + 1] - P.srow_ptr[s];
         double* A = vals + P.spanel_off[s];
         const int32_t* rows = P.srows.data() + P.srow_ptr[s];
-        for (int32_t c = 0; c < w; ++c) {
-            double* colc = A + (size_t)c * ld;
-            for (int32_t k = 0; k < c; ++k) {
-                const double* colk = A + (size_t)k * ld;
-                const double lck = colk[c];
-                if (lck == 0.0) continue;
-                for (int64_t i = c; i < ld; ++i) colc[i] -= colk[i] * lck;
+        for (int32_t j0 = 0; j0 < w; j0 += kPanelBlock) {
+            const int32_t j1 = std::min(w, j0 + kPanelBlock);
+            // columns [j0, j1) minus the contributions of columns [0, j0)
+            // (rows j0.. of both; the entries above the diagonal that this
+            // also updates are never read)
+            gemm_nt(ld - j0, j1 - j0, j0, -1.0, A + j0, ld, A + j0, ld, A + j0 + (size_t)j0 * ld, ld);
+            for (int32_t c = j0; c < j1; ++c) {
+                double* colc = A + (size_t)c * ld;
+                for (int32_t k = j0; k < c; ++k) {
+                    const double* colk = A + (size_t)k * ld;
+                    const double lck = colk[c];
+                    if (lck == 0.0) continue;
+                    for (int64_t i = c; i < ld; ++i) colc[i] -= colk[i] * lck;
+                }
+                const double d = colc[c];
+                if (!(d > 0.0)) return f + c;
+                const double sd = std::sqrt(d);
+                colc[c] = sd;
+                const double inv = 1.0 / sd;
+                for (int64_t i = c + 1; i < ld; ++i) colc[i] *= inv;
             }
-            const double d = colc[c];
-            if (!(d > 0.0)) return f + c;
-            const double sd = std::sqrt(d);
-            colc[c] = sd;
-            const double inv = 1.0 / sd;
-            for (int64_t i = c + 1; i < ld; ++i) colc[i] *= inv;
         }
         // contributions to later supernodes
         int64_t q = w;
@@ -645,21 +661,20 @@ int64_t factor_numeric(const SubPlan& P, const double* kvals, double* vals) {
             const int32_t* trows = P.srows.data() + P.srow_ptr[t];
             for (int64_t k = 0; k < ldt; ++k) pos[trows[k]] = (int32_t)k;
             double* T = vals + P.spanel_off[t];
-            const int64_t nr = ld - q;
-            tmp.resize((size_t)nr);
-            for (int64_t b = q; b < q1; ++b) {
-                // tmp[a] = sum_k L[q+a][k] * L[b][k] for rows a >= b - q
-                const int64_t a0 = b - q;
-                std::fill(tmp.begin() + a0, tmp.end(), 0.0);
-                for (int32_t k = 0; k < w; ++k) {
-                    const double* colk = A + (size_t)k * ld;
-                    const double lb = colk[b];
-                    if (lb == 0.0) continue;
-                    const double* src = colk + q;
-                    for (int64_t a = a0; a < nr; ++a) tmp[a] += src[a] * lb;
-                }
-                double* tcol = T + (size_t)(rows[b] - tf) * ldt;
-                for (int64_t a = a0; a < nr; ++a) tcol[pos[rows[q + a]]] -= tmp[a];
+            const int64_t nr = ld - q, nb = q1 - q;
+            // tmp = L[q:ld, :] L[q:q1, :]^T (nr x nb), on and below the
+            // diagonal of its top nb x nb block: column block [b0, b1) from
+            // row b0 down
+            tmp.resize((size_t)(nr * nb));
+            for (int64_t b0 = 0; b0 < nb; b0 += kUpdateBlock) {
+                const int64_t b1 = std::min(nb, b0 + kUpdateBlock);
+                for (int64_t b = b0; b < b1; ++b) std::fill(tmp.begin() + b * nr + b0, tmp.begin() + (b + 1) * nr, 0.0);
+                gemm_nt(nr - b0, b1 - b0, w, 1.0, A + q + b0, ld, A + q + b0, ld, tmp.data() + b0 * nr + b0, nr);
+            }
+            for (int64_t b = 0; b < nb; ++b) {
+                double* tcol = T + (size_t)(rows[q + b] - tf) * ldt;
+                const double* src = tmp.data() + b * nr;
+                for (int64_t a = b; a < nr; ++a) tcol[pos[rows[q + a]]] -= src[a];
             }
             q = q1;
         }

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -108,6 +109,11 @@ struct sc_plan_s {
     std::vector<int32_t> h_tile_order_g;
     std::vector<SyrkItem> h_syrk_g;
     std::vector<int64_t> g_toff, g_tcnt, g_soff, g_stile, g_sblock;
+    // the same groups for the pipelined preprocessing (sc_preprocess): their
+    // subdomains (g_sub[g_sub_off[g] .. g_sub_off[g + 1])) and factor values,
+    // which are laid out group after group: [g_lval[g], g_lval[g + 1])
+    std::vector<int32_t> g_sub;
+    std::vector<int64_t> g_sub_off, g_lval;
     int64_t nsyrk_tile = 0;                     // h_syrk: 128 x 128 tiles first, then 64 x 64 blocks
     std::vector<SyrkItem> h_ftiles;             // stored F tiles, subdomain order (apply pass 1)
     std::vector<int2> h_frows;                  // (subdomain, 128-row block) (apply pass 2)
@@ -494,6 +500,14 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
                     }
                     lt = std::max(lt, gt[x].size());
                 }
+                P->g_sub_off.push_back((int64_t)P->g_sub.size());
+                {
+                    size_t lg = 0;
+                    for (int x = 0; x < kNumXcd; ++x) lg = std::max(lg, gsub[x].size());
+                    for (size_t k = 0; k < lg; ++k)       // largest subdomains first
+                        for (int x = 0; x < kNumXcd; ++x)
+                            if (k < gsub[x].size()) P->g_sub.push_back(gsub[x][k]);
+                }
                 P->g_toff.push_back((int64_t)P->h_tile_order_g.size());
                 P->g_tcnt.push_back((int64_t)(lt * kNumXcd));
                 P->g_soff.push_back((int64_t)P->h_syrk_g.size());
@@ -506,6 +520,22 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
                     for (size_t k = 0; k < gt[x].size(); ++k)
                         P->h_tile_order_g[P->g_toff.back() + (int64_t)(k * kNumXcd + x)] = gt[x][k];
             }
+        }
+        P->g_sub_off.push_back((int64_t)P->g_sub.size());
+        // factor values group after group, so that each group's upload is one copy
+        {
+            int64_t off = 0;
+            for (size_t g = 0; g + 1 < P->g_sub_off.size(); ++g) {
+                P->g_lval.push_back(off);
+                for (int64_t k = P->g_sub_off[g]; k < P->g_sub_off[g + 1]; ++k) {
+                    const int32_t i = P->g_sub[k];
+                    P->h_subs[i].lval_off = off;
+                    off += P->plans[i].bval;
+                }
+            }
+            P->g_lval.push_back(off);
+            if (off != lv || (int64_t)P->g_sub.size() != nsub)
+                return fail(SC_ERR_INVALID_ARG, "internal: subdomain groups do not cover the batch");
         }
         for (int x = 0; x < kNumXcd; ++x)
             for (int32_t i : xsub[x]) push_tiles(xt[x], i);
@@ -660,6 +690,92 @@ sc_status_t sc_factor(sc_plan_t P, const double* const* kreg_vals, void* stream,
                                hipMemcpyHostToDevice, st));
     if (P->mixed) HIP_TRY(launch_convert_f32(P->d_lval.p, P->d_lval32.p, P->nval_total, st));
     P->factored = true;
+    return SC_OK;
+}
+
+sc_status_t sc_preprocess(sc_plan_t P, const double* const* kreg_vals, void* stream, int32_t* failed_sub,
+                          int32_t* failed_col) {
+    g_last_error.clear();
+    if (!P) return fail(SC_ERR_INVALID_ARG, "plan is NULL");
+    if (P->nsub > 0 && !kreg_vals) return fail(SC_ERR_INVALID_ARG, "kreg_vals is NULL");
+    for (int32_t i = 0; i < P->nsub; ++i)
+        if (!kreg_vals[i] && P->kval_count[i] > 0)
+            return fail(SC_ERR_INVALID_ARG, "kreg_vals[" + std::to_string(i) + "] is NULL");
+    HIP_TRY(hipSetDevice(P->device));
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(hipStreamSynchronize(st));   // an earlier upload may still read h_lval
+    P->factored = false;
+    P->assembled = false;
+    const int64_t ng = (int64_t)P->g_sub_off.size() - 1;
+    std::vector<int32_t> group_of(P->nsub, 0);
+    std::vector<int64_t> left(ng, 0);
+    for (int64_t g = 0; g < ng; ++g) {
+        left[g] = P->g_sub_off[g + 1] - P->g_sub_off[g];
+        for (int64_t k = P->g_sub_off[g]; k < P->g_sub_off[g + 1]; ++k) group_of[P->g_sub[k]] = (int32_t)g;
+    }
+    std::vector<int64_t> bad(P->nsub, -1);
+    const DevTables t = P->tables();
+    std::mutex mu;                       // guards left[], next and the launches
+    int64_t next = 0;                    // first group not yet launched
+    bool stop = false;                   // a pivot failed or a HIP call failed: launch nothing more
+    hipError_t herr = hipSuccess;
+    bool oom = false;
+    // launches every consecutive group whose subdomains are all factored, in
+    // group order, on `st`: its factor values (one copy), the FP32 copy in
+    // mixed precision, its TRSM tiles and its SYRK items
+    auto launch_ready = [&]() {
+        while (!stop && next < ng && left[next] == 0) {
+            const int64_t g = next++;
+            const int64_t v0 = P->g_lval[g], nv = P->g_lval[g + 1] - v0;
+            hipError_t e = hipSetDevice(P->device);
+            if (e == hipSuccess && nv > 0)
+                e = hipMemcpyAsync(P->d_lval.p + v0, P->h_lval + v0, (size_t)nv * sizeof(double),
+                                   hipMemcpyHostToDevice, st);
+            if (e == hipSuccess && P->mixed && nv > 0) e = launch_convert_f32(P->d_lval.p + v0, P->d_lval32.p + v0, nv, st);
+            if (e == hipSuccess) e = launch_trsm(t, P->d_tile_order_g.p + P->g_toff[g], P->g_tcnt[g], st);
+            if (e == hipSuccess) e = launch_syrk(t, P->d_syrk_g.p + P->g_soff[g], P->g_stile[g], P->g_sblock[g], st);
+            if (e != hipSuccess) { herr = e; stop = true; }
+        }
+    };
+    const int nthr = P->opt.n_threads > 0 ? P->opt.n_threads : omp_get_max_threads();
+#pragma omp parallel num_threads(nthr)
+    {
+        std::vector<double> sn;
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t k = 0; k < (int64_t)P->g_sub.size(); ++k) {
+            const int32_t i = P->g_sub[k];
+            const SubPlan& sp = P->plans[i];
+            bool ok = true;
+            try {
+                sn.resize((size_t)std::max<int64_t>(1, sp.nval));
+            } catch (const std::bad_alloc&) {
+                ok = false;
+            }
+            if (ok) {
+                bad[i] = factor_numeric(sp, kreg_vals[i], sn.data());
+                if (bad[i] < 0) repack_blocks(sp, sn.data(), P->h_lval + P->h_subs[i].lval_off);
+            }
+            std::lock_guard<std::mutex> lk(mu);
+            if (!ok) { oom = true; stop = true; }
+            if (bad[i] >= 0) stop = true;
+            --left[group_of[i]];
+            launch_ready();
+        }
+    }
+    if (oom) return fail(SC_ERR_OOM, "host allocation failed in sc_preprocess");
+    for (int32_t i = 0; i < P->nsub; ++i)
+        if (bad[i] >= 0) {
+            if (failed_sub) *failed_sub = i;
+            if (failed_col) *failed_col = (int32_t)bad[i];
+            return fail(SC_ERR_NOT_SPD, "subdomain " + std::to_string(i) + ": pivot of permuted column " +
+                                            std::to_string(bad[i]) + " is not positive");
+        }
+    if (herr != hipSuccess)
+        return fail(herr == hipErrorOutOfMemory ? SC_ERR_OOM : SC_ERR_DEVICE,
+                    std::string("sc_preprocess launch: ") + hipGetErrorString(herr));
+    if (next != ng) return fail(SC_ERR_DEVICE, "sc_preprocess: not every group was launched");
+    P->factored = true;
+    P->assembled = true;
     return SC_OK;
 }
 

@@ -17,7 +17,8 @@ STATUS_NAMES = {0: "SC_OK", 1: "SC_ERR_INVALID_ARG", 2: "SC_ERR_NOT_SPD", 3: "SC
 
 EXPORTED = ["sc_plan_create", "sc_factor", "sc_assemble", "sc_apply", "sc_apply_implicit",
             "sc_get_F", "sc_query", "sc_plan_stats", "sc_plan_destroy", "sc_host_analyze",
-            "sc_host_tile_visits", "sc_set_timing", "sc_kernel_times", "sc_pcpg", "sc_autotune", "sc_last_error"]
+            "sc_host_tile_visits", "sc_set_timing", "sc_kernel_times", "sc_pcpg", "sc_autotune", "sc_preprocess",
+            "sc_last_error"]
 
 
 class ScasmError(RuntimeError):
@@ -70,6 +71,7 @@ def load():
                                        ctypes.POINTER(vp)]
         lib.sc_factor.argtypes = [vp, ctypes.POINTER(vp), vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         lib.sc_assemble.argtypes = [vp, vp]
+        lib.sc_preprocess.argtypes = [vp, ctypes.POINTER(vp), vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         lib.sc_apply.argtypes = [vp, vp, vp, vp]
         lib.sc_apply_implicit.argtypes = [vp, vp, vp, vp]
         lib.sc_get_F.argtypes = [vp, i32, vp, i32, i32, vp]
@@ -295,6 +297,20 @@ class Plan:
         # the upload is asynchronous and reads pinned memory owned by the plan
         return self
 
+    def preprocess(self, kvals: Optional[List[np.ndarray]] = None, stream=None):
+        """Factorisation and assembly in one pipelined call (host factorisation
+        of later subdomain groups overlapped with the GPU assembly of earlier
+        ones); F as after factor() + assemble()."""
+        if kvals is None:
+            kvals = [s.val for s in self.subdomains]
+        arrs = [np.ascontiguousarray(v, dtype=np.float64) for v in kvals]
+        ptrs = (ctypes.c_void_p * max(1, len(arrs)))(*[a.ctypes.data for a in arrs])
+        fs, fc = ctypes.c_int32(-1), ctypes.c_int32(-1)
+        st = self._lib.sc_preprocess(self._h, ptrs, _stream_handle(stream), ctypes.byref(fs), ctypes.byref(fc))
+        if st != SC_OK:
+            _check(st, failed_sub=fs.value, failed_col=fc.value)
+        return self
+
     def assemble(self, stream=None):
         _check(self._lib.sc_assemble(self._h, _stream_handle(stream)))
         return self
@@ -338,6 +354,21 @@ class Plan:
         out = np.zeros((m, m), dtype=np.float64, order="F")
         _check(self._lib.sc_get_F(self._h, i, out.ctypes.data, max(1, m), 0, _stream_handle(stream)))
         return out
+
+    def get_F_device(self, i: int, out=None, ld: int = 0, stream=None):
+        """F_i (m x m, FP64, original multiplier order) into a device tensor
+        through sc_get_F(on_device = 1): column j at out[j * ld : j * ld + m]
+        (ld >= m, default m).  Returns the (m, m) column-major view."""
+        import torch
+        m = self.query(i)["m"]
+        ld = ld or max(1, m)
+        if ld < m:
+            raise ScasmError(SC_ERR_INVALID_ARG, f"ld {ld} < m {m}")
+        if out is None:
+            out = torch.zeros(ld * max(m, 1), dtype=torch.float64, device=f"cuda:{self.device_index}")
+        check_dual_tensor(out, ld * m, self.device_index, "out")
+        _check(self._lib.sc_get_F(self._h, i, ctypes.c_void_p(out.data_ptr()), ld, 1, _stream_handle(stream)))
+        return out[: ld * m].view(m, ld).T[:m, :] if m else out[:0].view(0, 0)
 
     def query(self, i: int) -> dict:
         n, m, off, nnz = (ctypes.c_int64() for _ in range(4))

@@ -86,6 +86,62 @@ def test_panel_widths(panel_width):
     _check_against_oracle(plan, subs)
 
 
+@pytest.mark.parametrize("panel_width", [16, 32, 48])
+def test_panel_widths_mixed(panel_width):
+    subs = [scgen.box_subdomain("elasticity", (4, 5, 3), 0.25, seed=5),
+            scgen.box_subdomain("heat", (7, 6, 5), 0.2, seed=6)]
+    plan = _assemble(subs, precision="mixed", panel_width=panel_width, relax_width=96)
+    for i, s in enumerate(subs):
+        assert oracle.relF(plan.get_F(i), oracle.schur(s)) <= 1e-5
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_get_F_on_device_equals_host_copy(precision):
+    """sc_get_F(on_device = 1) writes the same FP64 values as the host copy,
+    with a leading dimension larger than m and the padding left untouched."""
+    torch = _torch_init()
+    subs = scgen.config_subdomains(3, count=2) + [scgen.config_subdomains(1)[0]]
+    plan = _assemble(subs, precision=precision)
+    for i, s in enumerate(subs):
+        ld = s.m + 3
+        out = torch.full((ld * s.m,), 7.0, dtype=torch.float64, device="cuda")
+        Fd = plan.get_F_device(i, out=out, ld=ld)
+        assert np.array_equal(Fd.cpu().numpy(), plan.get_F(i))
+        pad = out.view(s.m, ld)[:, s.m:]
+        assert bool((pad == 7.0).all())
+
+
+def test_full_uneven_elasticity_largest_subdomain_whole_F():
+    """The largest subdomain of the 512-box elasticity batch (16 x 15 x 16
+    elements, n = 13872, m = 4422) in the whole-batch assembly, against the
+    whole F of the long-double oracle."""
+    subs = scgen.config_subdomains(3)
+    big = int(np.argmax([s.n for s in subs]))
+    s = subs[big]
+    assert (s.n, s.m) == (13872, 4422)
+    plan = _assemble(subs)
+    F = plan.get_F(big)
+    plan.destroy()
+    assert np.array_equal(F, F.T)
+    assert oracle.relF(F, oracle.schur(s)) <= TOL_FP64
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_full_large_elasticity_512_columns_direct(precision):
+    """The 64 x 20^3 elasticity batch in one assembly; 512 seeded columns of
+    two subdomains, each computed directly by the long-double oracle with that
+    subdomain's own signs (no sign-flip relation)."""
+    subs = scgen.config_subdomains(5)
+    plan = _assemble(subs, precision=precision, use_graph=True)
+    tol = TOL_FP64 if precision == "fp64" else TOL_MIXED
+    for k in (0, 45):
+        s = subs[k]
+        sel = np.sort(np.random.default_rng(500 + k).choice(s.m, size=512, replace=False))
+        F = plan.get_F(k)[np.ix_(sel, sel)]
+        assert oracle.relF(F, oracle.schur(s, sel=sel)) <= tol, k
+    plan.destroy()
+
+
 def test_staircase_off_matches_on():
     subs = [scgen.config_subdomains(1)[0], scgen.box_subdomain("elasticity", (4, 3, 5), 0.25, seed=8)]
     on = _assemble(subs)

@@ -1,0 +1,133 @@
+"""Pipelined preprocessing (sc_preprocess: host factorisation of later
+subdomain groups overlapped with the GPU assembly of earlier ones, Sec. 4.4)
+against the separated stages (sc_factor, then sc_assemble), and parity of the
+assembly on the paper's own element types (P1 triangles and tetrahedra,
+Sec. 4) with the oracle, staircase on and off."""
+import numpy as np
+import pytest
+
+import oracle
+import scgen
+
+P = pytest.importorskip("paper_2509_21037_amd")
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-12
+TOL_MIXED = 1e-5
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    return torch
+
+
+def fp64_tolerance(s, sel, ref_ld):
+    """The FP64 bar: relF <= 1e-12, unless plain FP64 arithmetic cannot meet
+    it on this input -- the FP64 oracle (the same natural-order Cholesky,
+    forward substitution and Y^T Y in double) then differs from its
+    long-double run by e_d > 1e-12 / 4 (large 2D Laplacians: 1.1e-12 at 129^2
+    nodes, 1.1e-11 at 257^2) -- in which case the bar is 4 e_d: the GPU path
+    may not be more than 4x less accurate than the plain FP64 algorithm."""
+    if s.n <= 3000:
+        return TOL_FP64
+    e_d = oracle.relF(oracle.schur(s, sel=sel, prec="d"), ref_ld)
+    return max(TOL_FP64, 4.0 * e_d)
+
+
+def _stored_F(plan, subs):
+    return [plan.get_F(i) for i in range(len(subs))]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("cfg,count", [(2, 96), (3, 40)])
+def test_pipelined_preprocessing_equals_separate_stages(cfg, count, precision):
+    _torch()
+    subs = scgen.config_subdomains(cfg, count=count)
+    sep = P.Plan(subs, precision=precision)
+    sep.factor()
+    sep.assemble()
+    mix = P.Plan(subs, precision=precision)
+    mix.preprocess()
+    F_sep, F_mix = _stored_F(sep, subs), _stored_F(mix, subs)
+    for i in range(len(subs)):
+        assert np.array_equal(F_sep[i], F_mix[i]), i
+    # a second pipelined call on the same plan (values reused) gives the same F
+    mix.preprocess()
+    for i in (0, len(subs) // 2, len(subs) - 1):
+        assert np.array_equal(mix.get_F(i), F_sep[i])
+    tol = TOL_FP64 if precision == "fp64" else TOL_MIXED
+    for i in (0, len(subs) - 1):
+        s = subs[i]
+        if s.n <= 3000:
+            assert oracle.relF(F_mix[i], oracle.schur(s)) <= tol
+        else:
+            sel = np.sort(np.random.default_rng(i).choice(s.m, size=min(128, s.m), replace=False))
+            assert oracle.relF(F_mix[i][np.ix_(sel, sel)], oracle.schur(s, sel=sel)) <= tol
+    sep.destroy()
+    mix.destroy()
+
+
+def test_pipelined_preprocessing_then_apply_and_assemble():
+    torch = _torch()
+    subs = scgen.config_subdomains(3, count=9)
+    plan = P.Plan(subs)
+    plan.preprocess()
+    p = torch.from_numpy(scgen.splitmix64_uniform(7, plan.dual_total)).cuda()
+    q1, q2 = torch.zeros_like(p), torch.zeros_like(p)
+    plan.apply(p, q1)
+    plan.assemble()                    # the plan counts as factored: assemble again
+    plan.apply(p, q2)
+    assert torch.equal(q1, q2)
+    plan.destroy()
+
+
+def test_pipelined_preprocessing_reports_a_failed_pivot():
+    _torch()
+    s = scgen.box_subdomain("heat", (3, 3, 3), 0.3, seed=1)
+    plan = P.Plan([s, s, s])
+    with pytest.raises(P.ScasmError) as e:
+        plan.preprocess([s.val, s.val, np.where(np.arange(len(s.val)) == 0, -1.0, s.val)])
+    assert e.value.status == P.SC_ERR_NOT_SPD and e.value.failed_sub == 2
+    with pytest.raises(P.ScasmError) as e:
+        plan.assemble()
+    assert e.value.status == P.SC_ERR_STATE
+    plan.preprocess([s.val] * 3)           # recovers with good values
+    assert oracle.relF(plan.get_F(2), oracle.schur(s)) <= TOL_FP64
+    plan.destroy()
+
+
+@pytest.mark.parametrize("dim,nodes,count", [(2, 33, 6), (2, 129, 2), (3, 9, 8), (3, 14, 3)])
+@pytest.mark.parametrize("staircase", [True, False])
+def test_paper_simplex_workloads_match_oracle(dim, nodes, count, staircase):
+    """Heat transfer on P1 triangles / tetrahedra at sizes of the paper's
+    figures (nodes per side), multipliers on every boundary node."""
+    _torch()
+    subs = scgen.paper_subdomains(dim, nodes, count=count)
+    plan = P.Plan(subs, staircase=staircase)
+    plan.factor()
+    plan.assemble()
+    for i, s in enumerate(subs):
+        F = plan.get_F(i)
+        assert np.array_equal(F, F.T)
+        sel = None if s.n <= 3000 else \
+            np.sort(np.random.default_rng(i).choice(s.m, size=min(192, s.m), replace=False))
+        Fs = F if sel is None else F[np.ix_(sel, sel)]
+        ref = oracle.schur(s, sel=sel)
+        e = oracle.relF(Fs, ref)
+        assert e <= fp64_tolerance(s, sel, ref), (dim, nodes, i, e)
+    plan.destroy()
+
+
+@pytest.mark.parametrize("dim,nodes", [(2, 257), (3, 21)])
+def test_paper_simplex_workloads_mixed(dim, nodes):
+    _torch()
+    subs = scgen.paper_subdomains(dim, nodes, count=2)
+    plan = P.Plan(subs, precision="mixed")
+    plan.preprocess()
+    for i, s in enumerate(subs):
+        sel = np.sort(np.random.default_rng(10 + i).choice(s.m, size=min(128, s.m), replace=False))
+        F = plan.get_F(i)[np.ix_(sel, sel)]
+        assert oracle.relF(F, oracle.schur(s, sel=sel)) <= TOL_MIXED
+    plan.destroy()
