@@ -147,6 +147,39 @@ def preprocessing_times(torch, plan, factor_s, asm_ms, reps=2):
             "mix_gain": sep / best, "host_threads": min(16, os.cpu_count() or 1)}
 
 
+def time_selection(torch, subs, iters, panel_width, use_graph):
+    """Per-subdomain explicit / implicit choice for `iters` applications
+    (Sec. 5): the whole cost (assembly + iters applications, FP64) with the
+    plan's choice, all explicit, and all implicit (the implicit apply needs no
+    assembly)."""
+    out = {"iterations": iters}
+    for name, kw in (("hybrid", {"select_iters": iters}), ("explicit", {}),
+                     ("implicit", {"select_iters": iters, "select_model": (1.0, 1.0, 1e9)})):
+        plan = P_mod().Plan(subs, panel_width=panel_width, use_graph=use_graph, block_split="etree", **kw)
+        plan.factor()
+        ms_asm, _ = time_assembly(torch, plan, 3, 1, use_graph)
+        st = plan.stats()
+        p = torch.rand(st["dual_total"], dtype=torch.float64, device="cuda")
+        q = torch.zeros_like(p)
+        plan.apply(p, q)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(iters):
+            plan.apply(p, q)
+        torch.cuda.synchronize()
+        ms_apply = 1e3 * (time.perf_counter() - t0) / iters
+        nimp = sum(plan.selection(i)["implicit"] for i in range(len(subs)))
+        out[name] = {"implicit_subdomains": nimp, "assembly_ms": ms_asm, "apply_ms": ms_apply,
+                     "total_ms": ms_asm + iters * ms_apply}
+        plan.destroy()
+    return out
+
+
+def P_mod():
+    import paper_2509_21037_amd as P
+    return P
+
+
 def sample_ids(subs, big):
     """Subdomains whose GPU F is kept for the error check of the cpu_baseline
     leg (the leg runs the oracle on subdomains 0, 1, ... in order): the first
@@ -241,6 +274,26 @@ def cpu_baseline(subs, seconds, kept=None, big=False):
     return out, errs
 
 
+def ld_errors(subs, kept, big):
+    """relF of the kept GPU F against the long-double oracle (the parity
+    reference: on the 20^3 elasticity subdomains the FP64 oracle itself is
+    ~7e-12 away from it): every kept subdomain when they are small, the first
+    one (its seeded 256-column subset) when they are large."""
+    import oracle
+    nthreads = max(1, min(16, os.cpu_count() or 1))
+    ids = sorted(next(iter(kept.values())).keys()) if kept else []
+    if big:
+        ids = ids[:1]
+    errs = {k: [] for k in kept}
+    for i in ids:
+        s = subs[i]
+        sel = sample_cols(s, i) if big else None
+        ref = oracle.schur(s, sel=sel, prec="ld", nthreads=nthreads)
+        for key, fk in kept.items():
+            errs[key].append(oracle.relF(fk[i], ref))
+    return errs
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -263,6 +316,12 @@ def main():
                     help="TRSM and SYRK of successive subdomain groups overlapped on two streams, or two launches")
     ap.add_argument("--compare-assembly", action="store_true",
                     help="also time the FP64 assembly in the other mode (overlap / separate)")
+    ap.add_argument("--tune-cache", default=None, help="autotune cache file (read, and appended to)")
+    ap.add_argument("--select", type=int, default=0,
+                    help="also time K applications with per-subdomain explicit / implicit selection for K "
+                         "iterations, against all-explicit and all-implicit (FP64)")
+    ap.add_argument("--block-split", choices=("uniform", "etree"), default="uniform",
+                    help="GPU factor blocks: uniform column ranges, or ranges that follow the elimination tree")
     ap.add_argument("--no-prep", dest="prep", action="store_false",
                     help="skip the whole-preprocessing timing (factorisation + assembly, separate and pipelined)")
     ap.add_argument("--latency", action="store_true",
@@ -296,17 +355,23 @@ def main():
     big = subs[0].n > 3000
     ids = sample_ids(subs, big)
     use_graph = args.graph == "on" or (args.graph == "auto" and cfg != 2)
-    tune = None
+    tune, classes64, classes32 = None, None, None
     if args.autotune == "on" or (args.autotune == "auto" and cfg != 2 and not args.panel_width):
+        # per size class: block split, block width, SYRK work items (FP64 and
+        # mixed tuned separately), on samples of each class; not timed
         t0 = time.perf_counter()
-        best, times = P.autotune(subs, candidates=(32, 48, 64), sample=64 if cfg == 3 else 8, reps=2)
-        tune = {"panel_width": best, "sample_ms": times, "seconds": time.perf_counter() - t0}
-        args.panel_width = best
+        smp = 8 if cfg == 3 else 4
+        classes64 = P.autotune_classes(subs, sample=smp, reps=2, cache_path=args.tune_cache)
+        classes32 = None if args.no_mixed else \
+            P.autotune_classes(subs, sample=smp, reps=2, cache_path=args.tune_cache, precision="mixed")
+        tune = {"fp64": classes64, "mixed": classes32, "sample_per_class": smp,
+                "seconds": time.perf_counter() - t0}
         log(f"bench: autotune {tune}")
 
     # ---------------------------------------------------------------- FP64
     t0 = time.perf_counter()
-    plan = P.Plan(subs, panel_width=args.panel_width, use_graph=use_graph, assembly=args.assembly)
+    plan = P.Plan(subs, panel_width=args.panel_width, use_graph=use_graph, assembly=args.assembly,
+                  block_split=args.block_split, tune_classes=classes64)
     t1 = time.perf_counter()
     plan.factor()
     torch.cuda.synchronize()
@@ -314,6 +379,7 @@ def main():
     prep_factor_s = time.perf_counter() - t1
     log(f"bench: FP64 plan + host factorisation + upload in {prep_s:.1f}s (not in the timed region)")
     st = plan.stats()
+    plan_nnzl = [plan.query(i)["nnzL"] for i in range(len(subs))]
     ms_per_step, kms = time_assembly(torch, plan, args.steps, args.warmup, use_graph)
     log(f"bench: FP64 {ms_per_step:.3f} ms/step, kernels {kms}")
     useful = st["trsm_reach"] + st["syrk_reach"]
@@ -345,10 +411,11 @@ def main():
         pcpg["fp64_s"] = time.perf_counter() - t1
         pcpg["fp64_w_reduction_worst"] = float(np.max(h64[-1] / np.maximum(h64[0], 1e-300)))
     if cfg == 5:
-        # graph replays (one launch per elimination level and sweep) where the
-        # plan uses them; the HIP-event time of the eager launches beside it
+        # graph replays (the triangular sweeps) where the plan uses them; the
+        # HIP-event time of the eager launches beside it
         wall_i, extra["implicit_eager_ms"] = time_apply(torch, plan, "implicit", iters=5)
         extra["implicit_ms"] = wall_i if use_graph else extra["implicit_eager_ms"]
+        extra["implicit_split"] = args.block_split
         log(f"bench: apply {extra}")
     orig, kms_o, prep_orig = None, None, None
     if args.compare_orig:
@@ -399,12 +466,37 @@ def main():
         log(f"bench: FP64 {alt} assembly {ms_s:.3f} ms/step, kernels {kms_s}")
         plan_s.destroy()
     plan.destroy()
+    if cfg == 5 and args.block_split != "etree":
+        # the implicit apply on factor blocks that follow the elimination tree
+        # (independent subtrees solved in parallel): a plan of its own, factor
+        # only; the amortisation point uses the faster of the two
+        plan_i = P.Plan(subs, panel_width=args.panel_width, use_graph=use_graph, block_split="etree")
+        plan_i.factor()
+        wall_e, eager_e = time_apply(torch, plan_i, "implicit", iters=5)
+        plan_i.destroy()
+        t_e = wall_e if use_graph else eager_e
+        extra["implicit_etree_ms"] = t_e
+        extra["implicit_etree_eager_ms"] = eager_e
+        if t_e < extra["implicit_ms"]:
+            extra["implicit_uniform_ms"] = extra["implicit_ms"]
+            extra["implicit_ms"], extra["implicit_split"] = t_e, "etree"
+        log(f"bench: implicit apply, etree blocks: {t_e:.3f} ms")
+    if cfg == 5:
+        # HBM floor of the implicit apply: the factor read twice (FP64)
+        nnzl = sum(plan_nnzl)
+        extra["implicit_hbm_floor_ms"] = 2 * 8 * nnzl / (PEAK_HBM_GBS * 1e9) * 1e3
+        extra["implicit_frac_of_floor"] = extra["implicit_hbm_floor_ms"] / extra["implicit_ms"]
+
+    selection = None
+    if args.select:
+        selection = time_selection(torch, subs, args.select, args.panel_width, use_graph)
+        log(f"bench: selection for {args.select} iterations {selection}")
 
     # ---------------------------------------------------------------- mixed
     mixed = None
     if not args.no_mixed:
         plan_m = P.Plan(subs, precision="mixed", panel_width=args.panel_width, use_graph=use_graph,
-                        assembly=args.assembly)
+                        assembly=args.assembly, block_split=args.block_split, tune_classes=classes32)
         plan_m.factor()
         ms_m, kms_m = time_assembly(torch, plan_m, args.steps, args.warmup, use_graph)
         log(f"bench: mixed {ms_m:.3f} ms/step, kernels {kms_m}")
@@ -432,9 +524,11 @@ def main():
                 extra[f"amortization_iters_{name}"] = (t_asm / gain) if gain > 0 else None
         plan_m.destroy()
 
-    cpu, errs = (None, {}) if args.no_cpu_baseline else cpu_baseline(subs, args.cpu_seconds, kept, big)
+    cpu, errs64 = (None, {}) if args.no_cpu_baseline else cpu_baseline(subs, args.cpu_seconds, kept, big)
     if cpu:
         log(f"bench: cpu baseline {cpu}")
+        log(f"bench: relF against the FP64 oracle {errs64}")
+    errs = {} if args.no_cpu_baseline else ld_errors(subs, kept, big)
     import numpy as np
 
     def err_stats(e):
@@ -460,15 +554,17 @@ def main():
         "data": "synthetic",
         "config": {"workload": scgen.CONFIG_NAMES[cfg], "subdomains": len(subs),
                    "n": s0.n if cfg != 3 else "1029..14739", "m": s0.m if cfg != 3 else "654..4614",
-                   "precision": "fp64", "staircase": True, "reach": True, "panel_width": args.panel_width or 64,
-                   "graph": use_graph, "assembly": args.assembly},
+                   "precision": "fp64", "staircase": True, "reach": True,
+                   "panel_width": "per size class (autotune)" if classes64 else (args.panel_width or 64),
+                   "graph": use_graph, "assembly": args.assembly, "block_split": args.block_split},
         "autotune": tune,
         "useful_gflops": useful / (ms_per_step * 1e-3) / 1e9,
         "useful_gflop_per_step": useful / 1e9,
         "staircase_gflop_per_step": (st["trsm_useful"] + st["syrk_useful"]) / 1e9,
         **err_stats(errs.get("fp64", [])),
-        "relF_source": "cpu_baseline leg: FP64 oracle on its sample of subdomains (seeded 256-column "
-                       "subsets of the first two for n > 3000) against the kept GPU F",
+        "relF_source": "long-double oracle against the kept GPU F: the first 8 subdomains whole (small "
+                       "subdomains), the seeded 256-column subset F[S, S] of subdomain 0 (n > 3000)",
+        "relF_vs_fp64_oracle": errs64.get("fp64"),
         "prep_s": prep_s,
         "preprocessing": prep,
         "preprocessing_orig": prep_orig,
@@ -483,6 +579,7 @@ def main():
         "mixed": mixed,
         "pcpg": pcpg or None,
         "apply": extra,
+        "selection": selection,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -121,6 +121,40 @@ typedef struct {
  *                    block works on zero rows (the result is the same up to
  *                    the sign of zeros); 1 = visit every block from the
  *                    tile's first pivot on (the staircase of Sec. 3.2 alone)
+ *   block_split      GPU factor blocks (Sec. 3.2 factor splitting; the
+ *                    non-uniform splitting of the Sec. 4.1 footnote): 0
+ *                    (default) = uniform column ranges of panel_width
+ *                    columns; 1 = ranges that
+ *                    follow the supernodal elimination tree: a block is a
+ *                    whole subtree or the top part of one (never two
+ *                    unrelated subtrees), at most panel_width columns, so
+ *                    that the blocks of disjoint subtrees are independent
+ *                    (the implicit apply then solves them in parallel)
+ *   select_iters     per-subdomain choice between the explicit and the
+ *                    implicit approach (Sec. 5: the best approach depends on
+ *                    the subdomain size and the iteration count): 0 (default)
+ *                    = every subdomain explicit; k > 0 = the solver is
+ *                    expected to apply the operator k times, and a subdomain
+ *                    whose predicted amortisation point n* (sc_query_selection)
+ *                    exceeds k is applied implicitly: sc_assemble skips it,
+ *                    sc_apply and sc_pcpg apply it with the factor
+ *                    (eq. (11)), the others with F (eq. (12)).  The
+ *                    prediction: t_asm = structural flops / select_model[0]
+ *                    TFLOP/s, t_expl = stored F bytes / select_model[1] GB/s,
+ *                    t_impl = 16 nnz(L) / select_model[2] GB/s (two FP64
+ *                    sweeps), n* = t_asm / (t_impl - t_expl) (infinite when
+ *                    t_impl <= t_expl); zeros = rates measured on MI355X
+ *                    (FP64 42 / mixed 70 TFLOP/s, 5800 GB/s, and the implicit
+ *                    rate in kSelectImplGBps)
+ *   arena_cap_bytes  0 (default) = X (the temporary of the assembly, Sec. 3.1)
+ *                    resident for the whole batch; > 0 = temporary-memory
+ *                    waves: the batch is cut into waves of subdomains whose X
+ *                    slabs fit this many bytes (XCD-interleaved, largest
+ *                    first), sc_assemble runs TRSM + SYRK wave after wave on
+ *                    one X buffer of the largest wave's size.  sc_plan_create
+ *                    returns SC_ERR_OOM when one subdomain's X alone exceeds
+ *                    the cap (before touching the device), SC_ERR_UNSUPPORTED
+ *                    with assembly_kernels = 1
  */
 typedef struct {
     int32_t precision;
@@ -132,8 +166,35 @@ typedef struct {
     int32_t use_graph;
     int32_t assembly_kernels;
     int32_t disable_reach;
-    int32_t reserved[5];
+    int32_t block_split;
+    int32_t select_iters;
+    float select_model[3];
+    int64_t arena_cap_bytes;
+    const struct sc_tune_class_s* tune_classes;
+    int32_t ntune_classes;
+    int32_t reserved2;
 } sc_options_t;
+
+/*
+ * One size class of the autotuner (sc_autotune_classes): the settings used
+ * for every subdomain with n_lo <= n < n_hi.  Passed back to sc_plan_create
+ * through sc_options_t::tune_classes / ntune_classes (borrowed for that call
+ * only); a subdomain outside every class takes the plan-wide options.
+ *   panel_width   GPU factor block width, 16..64 (0 = plan option)
+ *   block_split   0 uniform, 1 elimination-tree ranges, -1 = plan option
+ *   syrk_kind     SYRK work items: 0 = by size (64 x 64 blocks up to 16384
+ *                 rows FP64 / 6144 mixed, 128 x 128 tiles above), 1 = 64 x
+ *                 64 blocks, 2 = 128 x 128 tiles
+ *   ms_per_sub    measured assembly time per subdomain of the class sample
+ *                 with these settings (output; informational)
+ */
+typedef struct sc_tune_class_s {
+    int32_t n_lo, n_hi;
+    int32_t panel_width;
+    int32_t block_split;
+    int32_t syrk_kind;
+    float ms_per_sub;
+} sc_tune_class_t;
 
 /* Initialisation stage (Sec. 2.2): ordering, symbolic factorisation, staircase
  * plan (Sec. 3, column pivots and stable sort), GPU block and tile lists, and
@@ -236,6 +297,14 @@ sc_status_t sc_get_F(sc_plan_t plan, int32_t sub, double* out, int32_t ld, int32
 sc_status_t sc_query(sc_plan_t plan, int32_t sub, int64_t* n, int64_t* m, int64_t* dual_offset,
                      int64_t* nnzL, double* useful_flops);
 
+/* The per-subdomain choice of select_iters: *implicit = 1 when subdomain
+ * `sub` is applied with the factor, 0 when assembled; the predicted times (ms)
+ * of its assembly, of one explicit and of one implicit application, and its
+ * amortisation point n* (+inf when the implicit application is not slower).
+ * Any out pointer may be NULL. */
+sc_status_t sc_query_selection(sc_plan_t plan, int32_t sub, int32_t* implicit, double* t_asm_ms,
+                               double* t_expl_ms, double* t_impl_ms, double* n_star);
+
 /* Plan-wide totals: number of subdomains, total dual length, useful TRSM and
  * SYRK flops (as in sc_query), the same counts without the staircase
  * ("orig"), the structural counts (the same sums with a(i) replaced by r(i),
@@ -253,7 +322,8 @@ sc_status_t sc_plan_stats(sc_plan_t plan, int32_t* nsub, int64_t* dual_total,
  * (synchronising on the recorded events):
  *   ms[0] staircase TRSM, ms[1] staircase SYRK + permute-back,
  *   ms[2] explicit apply (GEMV), ms[3] implicit apply,
- *   ms[4] overlapped assembly (first TRSM to last SYRK, assembly_kernels 1);
+ *   ms[4] assembly launched by groups (first TRSM to last SYRK:
+ *         assembly_kernels 1, or temporary-memory waves);
  *   counts[k] = number of launches of kernel k summed into ms[k].
  * `reset` != 0 clears the sums after reading.  Arrays hold 5 entries. */
 sc_status_t sc_set_timing(sc_plan_t plan, int32_t enable);
@@ -275,6 +345,31 @@ sc_status_t sc_autotune(const sc_subdomain_desc_t* sd, int32_t nsub, const sc_op
                         const double* const* kreg_vals, const int32_t* candidates, int32_t ncand,
                         int32_t sample, int32_t reps, void* stream, int32_t* best_width,
                         double* times_ms);
+
+/* Autotuner over size classes (Sec. 4.1 and Table 1: the best block size
+ * depends on the hardware and on the subdomain size).  The batch's
+ * subdomains are grouped by n into classes [2^k, 2^(k+1)) (the first from 0,
+ * the last open); for every class with subdomains, up to `sample` of them
+ * (evenly over the class, by n) are planned, factored and assembled for each
+ * candidate setting, and the fastest mean sc_assemble time wins, searched
+ * coordinate by coordinate: block split (uniform, etree) at width 64, then
+ * the width (32, 48, 64), then the SYRK work items (64 x 64 blocks, 128 x 128
+ * tiles).  With `cache_path` (may be NULL) the results are kept in a text
+ * file, one line per (device, precision, class): classes found there for this
+ * device and precision are not timed again, new ones are appended.
+ *   sd, nsub, base, kreg_vals   the batch and the options to tune, as for
+ *                               sc_plan_create / sc_factor
+ *   sample, reps                subdomains per class sample (>= 1), timed
+ *                               repetitions per candidate (>= 1)
+ *   classes[max_classes]        out: the tuned classes, increasing n
+ *   nclasses                    out: how many
+ * Allocates and frees temporary plans on the current device; errors as
+ * sc_plan_create / sc_factor, SC_ERR_INVALID_ARG when max_classes is too small,
+ * SC_ERR_DEVICE when the cache file cannot be written. */
+sc_status_t sc_autotune_classes(const sc_subdomain_desc_t* sd, int32_t nsub, const sc_options_t* base,
+                                const double* const* kreg_vals, int32_t sample, int32_t reps,
+                                const char* cache_path, void* stream, sc_tune_class_t* classes,
+                                int32_t max_classes, int32_t* nclasses);
 
 /* Release every device and host buffer of the plan, after waiting for the
  * device (work queued on any stream may still use them).  NULL is accepted. */

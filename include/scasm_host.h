@@ -32,6 +32,8 @@ typedef struct {
     int64_t stair_visits;  /* the same with the staircase alone (no reach)      */
     double trsm_reach, syrk_reach;     /* structural counts: a(i) replaced by
                                           r(i) = columns of X nonzero in row i */
+    double t_asm_ms, t_expl_ms, t_impl_ms, n_star;   /* the select_iters
+                                          prediction (sc_options_t) */
 } sc_host_info_t;
 
 /*

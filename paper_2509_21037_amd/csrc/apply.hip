@@ -254,7 +254,8 @@ __global__ __launch_bounds__(256) void pcpg_step(const SubDev* __restrict__ subs
     }
 }
 
-hipError_t launch_pcpg(const DevTables& t, const PcpgArgs& a, hipStream_t stream) {
+hipError_t launch_pcpg(const DevTables& t, const PcpgArgs& a, hipStream_t stream, const ImplicitLevels* lvh,
+                       const int64_t* xoff, double* xwork, int32_t nimpl) {
     PcpgDev D;
     D.G = a.G; D.g_off = a.g_off; D.kdim = a.kdim; D.GtGinv = a.GtGinv;
     D.r = a.r; D.w = a.w; D.pvec = a.p; D.q = a.q; D.ww = a.ww; D.hist = a.hist; D.nsub = a.nsub;
@@ -264,6 +265,8 @@ hipError_t launch_pcpg(const DevTables& t, const PcpgArgs& a, hipStream_t stream
     if (e != hipSuccess) return e;
     for (int it = 0; it < a.iters; ++it) {
         if ((e = launch_apply(t, a.p, a.q, stream, nullptr)) != hipSuccess) return e;
+        if (lvh && (e = launch_apply_implicit(t, *lvh, xoff, xwork, a.p, a.q, nimpl, stream, nullptr)) != hipSuccess)
+            return e;
         hipLaunchKernelGGL(pcpg_step, dim3((unsigned)a.nsub), dim3(256), 0, stream, t.subs, D, a.lambda, it);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
@@ -301,9 +304,9 @@ __device__ __forceinline__ double linv_at(const double* __restrict__ Lv, int r, 
 __global__ __launch_bounds__(256) void implicit_init(
     const SubDev* __restrict__ subs, const int32_t* __restrict__ piv, const int32_t* __restrict__ pi,
     const int8_t* __restrict__ sgn, const int64_t* __restrict__ xoff, const double* __restrict__ p,
-    double* __restrict__ xwork)
+    double* __restrict__ xwork, const int32_t* __restrict__ sub_list)
 {
-    const int sub = blockIdx.x;
+    const int sub = sub_list ? sub_list[blockIdx.x] : (int)blockIdx.x;
     const SubDev S = subs[sub];
     double* __restrict__ x = xwork + xoff[sub];
     const int32_t* __restrict__ pv = piv + S.col_off;
@@ -461,12 +464,12 @@ __global__ __launch_bounds__(kImplThreads) void implicit_sweeps(
     const SubDev* __restrict__ subs, const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows,
     const double* __restrict__ lval, const int64_t* __restrict__ rptr_off, const int32_t* __restrict__ rptr,
     const int32_t* __restrict__ rpos, const int64_t* __restrict__ xoff, double* __restrict__ xwork,
-    double* __restrict__ ubuf)
+    double* __restrict__ ubuf, const int32_t* __restrict__ sub_list)
 {
     __shared__ double sp[kImplParts][64];
     __shared__ double sx[64];
     __shared__ double sz[kImplThreads];
-    const int sub = blockIdx.x;
+    const int sub = sub_list ? sub_list[blockIdx.x] : (int)blockIdx.x;
     const SubDev S = subs[sub];
     double* __restrict__ x = xwork + xoff[sub];
     const int32_t* __restrict__ rp = rptr + rptr_off[sub];
@@ -485,40 +488,42 @@ __global__ __launch_bounds__(kImplThreads) void implicit_sweeps(
 __global__ __launch_bounds__(256) void implicit_gather(
     const SubDev* __restrict__ subs, const int32_t* __restrict__ piv, const int32_t* __restrict__ pi,
     const int8_t* __restrict__ sgn, const int64_t* __restrict__ xoff, const double* __restrict__ xwork,
-    double* __restrict__ q)
+    double* __restrict__ q, const int32_t* __restrict__ sub_list)
 {
-    const int sub = blockIdx.x;
+    const int sub = sub_list ? sub_list[blockIdx.x] : (int)blockIdx.x;
     const SubDev S = subs[sub];
     const double* __restrict__ x = xwork + xoff[sub];
     for (int a = threadIdx.x; a < S.m; a += 256)
         q[S.dual_off + pi[S.col_off + a]] = (double)sgn[S.col_off + a] * x[piv[S.col_off + a]];
 }
 
-hipError_t launch_implicit_init(const DevTables& t, const int64_t* xoff, double* xwork, const double* p, int32_t nsub,
-                                hipStream_t stream) {
-    if (nsub <= 0) return hipSuccess;
-    hipLaunchKernelGGL(implicit_init, dim3((unsigned)nsub), dim3(256), 0, stream, t.subs, t.piv, t.pi, t.sgn, xoff, p,
-                       xwork);
+hipError_t launch_implicit_init(const DevTables& t, const int64_t* xoff, double* xwork, const double* p,
+                                const int32_t* sub_list, int32_t count, hipStream_t stream) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(implicit_init, dim3((unsigned)count), dim3(256), 0, stream, t.subs, t.piv, t.pi, t.sgn, xoff, p,
+                       xwork, sub_list);
     return hipGetLastError();
 }
 
 hipError_t launch_implicit_sweeps(const DevTables& t, const ImplicitLevels& lv, const int64_t* xoff, double* xwork,
-                                  int32_t nsub, hipStream_t stream) {
-    if (nsub <= 0) return hipSuccess;
+                                  int32_t count, hipStream_t stream) {
+    if (count <= 0) return hipSuccess;
     hipError_t e = hipSuccess;
     if (lv.per_subdomain) {
-        hipLaunchKernelGGL(implicit_sweeps, dim3((unsigned)nsub), dim3(kImplThreads), 0, stream, t.subs, t.blocks,
-                           t.rows, t.lval, lv.rptr_off, lv.rptr, lv.rpos, xoff, xwork, lv.ubuf);
+        hipLaunchKernelGGL(implicit_sweeps, dim3((unsigned)count), dim3(kImplThreads), 0, stream, t.subs, t.blocks,
+                           t.rows, t.lval, lv.rptr_off, lv.rptr, lv.rpos, xoff, xwork, lv.ubuf, lv.subs);
         return hipGetLastError();
     }
     for (size_t l = 0; l + 1 < lv.fw_off.size(); ++l) {
         const int64_t cnt = lv.fw_off[l + 1] - lv.fw_off[l];
+        if (cnt <= 0) continue;
         hipLaunchKernelGGL(implicit_fwd, dim3((unsigned)cnt), dim3(kImplThreads), 0, stream, t.subs, t.blocks, t.lval,
                            lv.rptr_off, lv.rptr, lv.rpos, lv.fw_items + lv.fw_off[l], xoff, xwork, lv.ubuf);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     for (size_t l = 0; l + 1 < lv.bw_off.size(); ++l) {
         const int64_t cnt = lv.bw_off[l + 1] - lv.bw_off[l];
+        if (cnt <= 0) continue;
         hipLaunchKernelGGL(implicit_bwd, dim3((unsigned)cnt), dim3(kImplThreads), 0, stream, t.subs, t.blocks, t.rows,
                            t.lval, lv.bw_items + lv.bw_off[l], xoff, xwork);
         if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -527,20 +532,20 @@ hipError_t launch_implicit_sweeps(const DevTables& t, const ImplicitLevels& lv, 
 }
 
 hipError_t launch_implicit_gather(const DevTables& t, const int64_t* xoff, const double* xwork, double* q,
-                                  int32_t nsub, hipStream_t stream) {
-    if (nsub <= 0) return hipSuccess;
-    hipLaunchKernelGGL(implicit_gather, dim3((unsigned)nsub), dim3(256), 0, stream, t.subs, t.piv, t.pi, t.sgn, xoff,
-                       xwork, q);
+                                  const int32_t* sub_list, int32_t count, hipStream_t stream) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(implicit_gather, dim3((unsigned)count), dim3(256), 0, stream, t.subs, t.piv, t.pi, t.sgn, xoff,
+                       xwork, q, sub_list);
     return hipGetLastError();
 }
 
 hipError_t launch_apply_implicit(const DevTables& t, const ImplicitLevels& lv, const int64_t* xoff, double* xwork,
-                                 const double* p, double* q, int32_t nsub, hipStream_t stream, hipEvent_t* ev) {
+                                 const double* p, double* q, int32_t count, hipStream_t stream, hipEvent_t* ev) {
     hipError_t e = hipSuccess;
     if (ev && (e = hipEventRecord(ev[0], stream)) != hipSuccess) return e;
-    if ((e = launch_implicit_init(t, xoff, xwork, p, nsub, stream)) != hipSuccess) return e;
-    if ((e = launch_implicit_sweeps(t, lv, xoff, xwork, nsub, stream)) != hipSuccess) return e;
-    if ((e = launch_implicit_gather(t, xoff, xwork, q, nsub, stream)) != hipSuccess) return e;
+    if ((e = launch_implicit_init(t, xoff, xwork, p, lv.subs, count, stream)) != hipSuccess) return e;
+    if ((e = launch_implicit_sweeps(t, lv, xoff, xwork, count, stream)) != hipSuccess) return e;
+    if ((e = launch_implicit_gather(t, xoff, xwork, q, lv.subs, count, stream)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], stream)) != hipSuccess) return e;
     return hipSuccess;
 }

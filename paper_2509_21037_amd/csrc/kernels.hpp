@@ -70,8 +70,12 @@ struct PcpgArgs {
     int32_t iters;
 };
 
-// Projected CG on every subdomain, `iters` iterations (explicit F apply).
-hipError_t launch_pcpg(const DevTables& t, const PcpgArgs& a, hipStream_t stream);
+struct ImplicitLevels;
+// Projected CG on every subdomain, `iters` iterations: F applied explicitly
+// to the assembled subdomains, and, when lvh is given, with the factor to the
+// nimpl subdomains of lvh->subs (workspace xwork at xoff).
+hipError_t launch_pcpg(const DevTables& t, const PcpgArgs& a, hipStream_t stream, const ImplicitLevels* lvh,
+                       const int64_t* xoff, double* xwork, int32_t nimpl);
 
 // Level schedule of the blocked triangular solves of the implicit apply:
 // items (subdomain, block) grouped by level (host offsets, levels run in
@@ -89,6 +93,8 @@ struct ImplicitLevels {
     // true: one workgroup per subdomain runs both sweeps block by block (the
     // block DAGs are near chains); false: one launch per level
     bool per_subdomain = false;
+    // the subdomains covered (device list; null = all, in index order)
+    const int32_t* subs = nullptr;
 };
 
 // Implicit apply q = B P^T L^{-T} L^{-1} P B^T p; xwork holds n_i doubles per
@@ -96,14 +102,16 @@ struct ImplicitLevels {
 // three launches below in order: x = P B^T p (init), the two blocked
 // triangular sweeps on x in place (they read no caller pointer, so a captured
 // graph of them stays valid for any p and q), q = B P^T x (gather).
-hipError_t launch_implicit_init(const DevTables& t, const int64_t* xoff, double* xwork, const double* p, int32_t nsub,
-                                hipStream_t stream);
+// `count` subdomains: those of `sub_list` / lv.subs, or 0 .. count - 1 when
+// the list is null.
+hipError_t launch_implicit_init(const DevTables& t, const int64_t* xoff, double* xwork, const double* p,
+                                const int32_t* sub_list, int32_t count, hipStream_t stream);
 hipError_t launch_implicit_sweeps(const DevTables& t, const ImplicitLevels& lv, const int64_t* xoff, double* xwork,
-                                  int32_t nsub, hipStream_t stream);
+                                  int32_t count, hipStream_t stream);
 hipError_t launch_implicit_gather(const DevTables& t, const int64_t* xoff, const double* xwork, double* q,
-                                  int32_t nsub, hipStream_t stream);
+                                  const int32_t* sub_list, int32_t count, hipStream_t stream);
 hipError_t launch_apply_implicit(const DevTables& t, const ImplicitLevels& lv, const int64_t* xoff, double* xwork,
-                                 const double* p, double* q, int32_t nsub, hipStream_t stream, hipEvent_t* ev);
+                                 const double* p, double* q, int32_t count, hipStream_t stream, hipEvent_t* ev);
 
 // q = F p for every subdomain (FP32 F when t.F32 is set, else FP64 F), two
 // passes over the packed sorted F; optional events ev[0] before, ev[1] after.

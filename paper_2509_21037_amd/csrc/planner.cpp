@@ -501,16 +501,49 @@ std::string build_plan(const SubdomainInput& in, const PlanOptions& opt, SubPlan
         }
     }
 
-    // ---- GPU blocks: uniform column ranges of width bs; pruned rows = rows
-    // >= the block end that hold a nonzero in any of the block's columns
+    // ---- GPU blocks (Sec. 3.2, factor splitting): column ranges of at most bs
+    // columns, either uniform, or following the elimination tree (the
+    // non-uniform splitting of the Sec. 4.1 footnote): a block is a whole
+    // subtree or the top part of one (never two unrelated subtrees), so that
+    // the blocks of disjoint subtrees stay independent and a block's pruned
+    // rows are not the union of unrelated row structures; a supernode wider
+    // than bs is cut into bs-column panels.  Pruned rows = rows >= the block
+    // end that hold a nonzero in any of the block's columns.
     const int32_t bs = std::max(16, (opt.panel_width / 16) * 16);
     P.block_width = bs;
     P.block_of_row.assign(n, -1);
+    std::vector<int32_t> bstart;
+    if (opt.block_split == 0) {
+        for (int32_t c0 = 0; c0 < n; c0 += bs) bstart.push_back(c0);
+    } else {
+        // supernodal elimination tree (supernodes are in postorder); a range
+        // of columns [c0, c1) is closed when every supernode in it but the
+        // last has its parent in it (a subtree, or the top part of one): the
+        // largest closed range of at most bs columns becomes the next block
+        std::vector<int32_t> sparent(P.nsuper, -1);
+        for (int32_t s = 0; s < P.nsuper; ++s) {
+            const int32_t pc = P.parent[P.sfirst[s + 1] - 1];
+            if (pc >= 0) sparent[s] = P.col2super[pc];
+        }
+        for (int32_t c0 = 0; c0 < n;) {
+            bstart.push_back(c0);
+            int32_t best = -1, maxpar = -1;
+            for (int32_t t = P.col2super[c0]; t < P.nsuper; ++t) {
+                const int32_t e = P.sfirst[t + 1];
+                if (maxpar <= t) best = std::min(e, c0 + bs);   // [c0, min(e, c0 + bs)) is closed
+                if (e - c0 >= bs) break;
+                maxpar = std::max(maxpar, sparent[t] < 0 ? P.nsuper : sparent[t]);
+            }
+            c0 = best;
+        }
+    }
+    bstart.push_back(n);
     {
         std::vector<int32_t> mark(n, -1);
         int64_t voff = 0;
-        for (int32_t c0 = 0; c0 < n; c0 += bs) {
-            const int32_t c1 = std::min(n, c0 + bs);
+        for (size_t bi = 0; bi + 1 < bstart.size(); ++bi) {
+            const int32_t c0 = bstart[bi];
+            const int32_t c1 = bstart[bi + 1];
             const int32_t b = (int32_t)P.blocks.size();
             std::vector<int32_t> rows;
             for (int32_t s = P.col2super[c0]; s < P.nsuper && P.sfirst[s] < c1; ++s)

@@ -38,10 +38,14 @@ struct PlanOptions {
     int32_t panel_width = 64;         // GPU factor block width (uniform blocks)
     int32_t staircase = 1;            // 0 = every column treated as pivot 0 ("orig")
     int32_t reach = 1;                // 0 = a TRSM tile sweeps every block after its first pivot's
+    int32_t block_split = 0;          // 0 = uniform column ranges of panel_width; 1 = ranges that
+                                      // follow the supernodal elimination tree (a block is a subtree
+                                      // or the top part of one, at most panel_width columns)
 };
 
 // One GPU factor block (Sec. 3.2, factor splitting with pruning): the column
-// range [row0, row0 + w) of L, uniform width except the last.  Its values:
+// range [row0, row0 + w) of L (uniform width except the last, or following the
+// elimination tree: PlanOptions::block_split).  Its values:
 //   * the dense diagonal triangle, w x w column-major (leading dimension
 //     ld = w) at lval_off;
 //   * the `nbelow` non-empty rows of L[row0 + w :, block] (pruning), whose

@@ -9,6 +9,7 @@
 #include <climits>
 #include <cstdint>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -59,7 +60,50 @@ std::string to_plan_options(const sc_options_t& o, PlanOptions& po) {
     if (o.leaf_nodes) po.leaf_nodes = o.leaf_nodes;
     po.staircase = o.disable_staircase ? 0 : 1;
     po.reach = o.disable_reach ? 0 : 1;
+    if (o.block_split < 0 || o.block_split > 1) return "block_split must be 0 or 1";
+    if (o.arena_cap_bytes < 0) return "arena_cap_bytes must be >= 0";
+    if (o.select_iters < 0) return "select_iters must be >= 0";
+    for (int k = 0; k < 3; ++k)
+        if (!(o.select_model[k] >= 0.0f)) return "select_model rates must be >= 0";
+    if (o.ntune_classes < 0 || (o.ntune_classes > 0 && !o.tune_classes)) return "bad tune_classes";
+    for (int32_t c = 0; c < o.ntune_classes; ++c) {
+        const sc_tune_class_t& k = o.tune_classes[c];
+        if (k.n_lo < 0 || k.n_hi < k.n_lo) return "tune class: bad n range";
+        if (k.panel_width != 0 && (k.panel_width < 16 || k.panel_width > kMaxPanel))
+            return "tune class: panel_width must be 0 or in [16, 64]";
+        if (k.block_split < -1 || k.block_split > 1) return "tune class: block_split must be -1, 0 or 1";
+        if (k.syrk_kind < 0 || k.syrk_kind > 2) return "tune class: syrk_kind must be 0, 1 or 2";
+    }
+    po.block_split = o.block_split;
     return "";
+}
+
+// Per-subdomain explicit / implicit selection (select_iters): default rates
+// measured on MI355X -- structural assembly TFLOP/s (FP64, mixed), explicit
+// apply GB/s over the stored F, implicit apply GB/s over the two sweeps' 16
+// bytes per factor entry.
+constexpr double kSelectAsmTflops64 = 42.0;
+constexpr double kSelectAsmTflopsMixed = 70.0;
+constexpr double kSelectExplGBps = 5800.0;
+constexpr double kSelectImplGBps = 1000.0;
+
+struct Prediction {
+    double t_asm_ms = 0, t_expl_ms = 0, t_impl_ms = 0, n_star = 0;
+};
+
+// t_asm = structural flops / assembly rate; t_expl = stored F bytes / apply
+// rate; t_impl = 16 nnz(L) / implicit rate; n* = t_asm / (t_impl - t_expl).
+Prediction predict(const SubPlan& sp, bool mixed, const sc_options_t& o) {
+    const double r_asm = o.select_model[0] > 0 ? o.select_model[0] : (mixed ? kSelectAsmTflopsMixed : kSelectAsmTflops64);
+    const double r_expl = o.select_model[1] > 0 ? o.select_model[1] : kSelectExplGBps;
+    const double r_impl = o.select_model[2] > 0 ? o.select_model[2] : kSelectImplGBps;
+    const double nst = (double)((sp.m + kSyrkTile - 1) / kSyrkTile);
+    Prediction q;
+    q.t_asm_ms = (sp.trsm_reach + sp.syrk_reach) / (r_asm * 1e12) * 1e3;
+    q.t_expl_ms = nst * (nst + 1) / 2 * kFTileElems * (mixed ? 4.0 : 8.0) / (r_expl * 1e9) * 1e3;
+    q.t_impl_ms = 16.0 * (double)sp.nnzL / (r_impl * 1e9) * 1e3;
+    q.n_star = q.t_impl_ms > q.t_expl_ms ? q.t_asm_ms / (q.t_impl_ms - q.t_expl_ms) : HUGE_VAL;
+    return q;
 }
 
 #define HIP_TRY(expr)                                                                        \
@@ -145,8 +189,22 @@ struct sc_plan_s {
     DevBuf<int32_t> d_rptr, d_rpos;
     DevBuf<double> d_ubuf;
     ImplicitLevels ilv;
+    // the same schedule restricted to the subdomains applied implicitly in
+    // sc_apply / sc_pcpg (select_iters)
+    DevBuf<int2> d_ifw_h, d_ibw_h;
+    DevBuf<int32_t> d_impl_list;
+    ImplicitLevels ilv_h;
     bool mixed = false;
     bool factored = false, assembled = false;
+    // temporary-memory waves (arena_cap_bytes > 0): X elements the cap holds;
+    // the groups are then waves that reuse one X buffer one after the other
+    int64_t arena_elems = 0;
+    std::vector<int32_t> syrk_kind;             // per subdomain: 0 by size, 1 blocks, 2 tiles
+    // select_iters: per subdomain applied with the factor (not assembled),
+    // and the prediction behind the choice
+    std::vector<uint8_t> implicit_sub;
+    std::vector<Prediction> pred;
+    int32_t n_implicit = 0;
     hipGraphExec_t graph_exec = nullptr;        // captured assembly (use_graph)
     hipGraphExec_t impl_graph = nullptr;        // captured triangular sweeps of the implicit apply (use_graph)
     bool impl_ready = false;                    // implicit apply schedule and workspace built
@@ -188,7 +246,25 @@ struct sc_plan_s {
         if ((e = hipEventRecord(ov_events[ng], aux)) != hipSuccess) return e;
         return hipStreamWaitEvent(st, ov_events[ng], 0);
     }
+    // temporary-memory waves: TRSM then SYRK of each group in turn on `st`
+    // (the next wave's TRSM overwrites X only after this wave's SYRK)
+    hipError_t launch_waves(hipStream_t st) {
+        hipError_t e = hipSuccess;
+        const DevTables t = tables();
+        for (size_t g = 0; g < g_tcnt.size(); ++g) {
+            if ((e = launch_trsm(t, d_tile_order_g.p + g_toff[g], g_tcnt[g], st)) != hipSuccess) return e;
+            if ((e = launch_syrk(t, d_syrk_g.p + g_soff[g], g_stile[g], g_sblock[g], st)) != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
     hipError_t launch_assembly(hipStream_t st, hipEvent_t* ev) {
+        if (arena_elems > 0) {
+            hipError_t e = hipSuccess;
+            if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
+            if ((e = launch_waves(st)) != hipSuccess) return e;
+            if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
+            return hipSuccess;
+        }
         if (!overlapped()) return launch_assemble(tables(), st, ev);
         hipError_t e = hipSuccess;
         if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
@@ -237,7 +313,8 @@ struct sc_plan_s {
                          (d_lval.count + d_X.count + d_F.count) * 8 +
                          (d_lval32.count + d_X32.count + d_F32.count) * 4 +
                          (d_xwork.count + d_xoff.count) * 8 + (d_ifw.count + d_ibw.count) * sizeof(int2) +
-                         (d_rptr.count + d_rpos.count) * 4 + (d_rptr_off.count + d_ubuf.count) * 8);
+                         (d_rptr.count + d_rpos.count) * 4 + (d_rptr_off.count + d_ubuf.count) * 8 +
+                         (d_ifw_h.count + d_ibw_h.count) * sizeof(int2) + d_impl_list.count * 4);
     }
     void release() {
         d_subs.release(); d_tiles.release(); d_blocks.release(); d_syrk.release();
@@ -248,6 +325,7 @@ struct sc_plan_s {
         d_lval32.release(); d_X32.release(); d_F32.release();
         d_xwork.release(); d_xoff.release();
         d_ifw.release(); d_ibw.release(); d_rptr_off.release(); d_rptr.release(); d_rpos.release(); d_ubuf.release();
+        d_ifw_h.release(); d_ibw_h.release(); d_impl_list.release();
         if (h_lval) (void)hipHostFree(h_lval);
         h_lval = nullptr;
         if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
@@ -284,6 +362,47 @@ struct sc_plan_s {
     }
 };
 
+namespace {
+
+// Mean ms per sc_assemble of a temporary plan of `ns` subdomains with
+// options `o` (one warm-up call, then `reps` timed calls between events).
+sc_status_t time_candidate(const sc_subdomain_desc_t* sub, int32_t ns, const sc_options_t& o,
+                           const double* const* vals, int32_t reps, void* stream, hipEvent_t e0, hipEvent_t e1,
+                           double* ms_out) {
+    hipStream_t st = (hipStream_t)stream;
+    sc_plan_t P = nullptr;
+    sc_status_t status = sc_plan_create(sub, ns, &o, stream, &P);
+    if (status == SC_OK) status = sc_factor(P, vals, stream, nullptr, nullptr);
+    if (status == SC_OK) status = sc_assemble(P, stream);
+    float ms = 0.f;
+    if (status == SC_OK) {
+        hipError_t e = hipEventRecord(e0, st);
+        for (int32_t r = 0; r < reps && e == hipSuccess; ++r)
+            if (sc_assemble(P, stream) != SC_OK) e = hipErrorUnknown;
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) status = fail(SC_ERR_DEVICE, "autotune timing failed");
+    }
+    const std::string keep = g_last_error;
+    sc_plan_destroy(P);
+    g_last_error = keep;
+    *ms_out = ms / reps;
+    return status;
+}
+
+std::string device_key() {
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string k = std::string(prop.gcnArchName) + "|" + prop.name;
+    for (char& c : k)
+        if (c == ' ' || c == '\t' || c == '\n') c = '_';
+    return k;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* sc_last_error(void) { return g_last_error.c_str(); }
@@ -303,17 +422,37 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
         if (!err.empty()) return fail(SC_ERR_INVALID_ARG, err);
     }
     P->mixed = P->opt.precision == SC_PREC_MIXED;
+    if (P->opt.arena_cap_bytes > 0) {
+        if (P->opt.assembly_kernels == 1)
+            return fail(SC_ERR_UNSUPPORTED, "arena_cap_bytes with assembly_kernels = 1: the waves run one after "
+                                            "the other on one X buffer and cannot overlap");
+        P->arena_elems = std::max<int64_t>(1, P->opt.arena_cap_bytes / (P->mixed ? 4 : 8));
+    }
     P->nsub = nsub;
     P->plans.resize(nsub);
     P->kval_count.resize(nsub);
     std::vector<std::string> errs(nsub);
     std::vector<int> codes(nsub, 0);
     const int nthr = P->opt.n_threads > 0 ? P->opt.n_threads : omp_get_max_threads();
+    // per-subdomain settings from the autotuner's size classes
+    P->syrk_kind.assign(nsub, 0);
+    std::vector<PlanOptions> spo(nsub, po);
+    for (int32_t i = 0; i < nsub; ++i)
+        for (int32_t c = 0; c < P->opt.ntune_classes; ++c) {
+            const sc_tune_class_t& k = P->opt.tune_classes[c];
+            if (sd[i].n < k.n_lo || sd[i].n >= k.n_hi) continue;
+            if (k.panel_width) spo[i].panel_width = k.panel_width;
+            if (k.block_split >= 0) spo[i].block_split = k.block_split;
+            P->syrk_kind[i] = k.syrk_kind;
+            break;
+        }
+    P->opt.tune_classes = nullptr;          // borrowed for this call only
+    P->opt.ntune_classes = 0;
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthr)
     for (int32_t i = 0; i < nsub; ++i) {
         const SubdomainInput in = to_input(sd[i]);
         try {
-            errs[i] = build_plan(in, po, P->plans[i], codes[i]);
+            errs[i] = build_plan(in, spo[i], P->plans[i], codes[i]);
         } catch (const std::bad_alloc&) {
             errs[i] = "host allocation failed";
             codes[i] = 3;
@@ -332,9 +471,20 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
     // SYRK items per subdomain: 128 x 128 tiles (large subdomains) or 64 x 64
     // blocks
     std::vector<std::vector<SyrkItem>> sub_tiles(nsub), sub_blocks(nsub);
+    std::vector<int64_t> x_elems(nsub, 0);      // X slab elements of each subdomain
     int64_t blk = 0, rows = 0, lv = 0, colo = 0, xo = 0, fo = 0, dual = 0;
+    P->implicit_sub.assign(nsub, 0);
+    P->pred.resize(nsub);
+    for (int32_t i = 0; i < nsub; ++i) {
+        P->pred[i] = predict(P->plans[i], P->mixed, P->opt);
+        if (P->opt.select_iters > 0 && P->pred[i].n_star > (double)P->opt.select_iters) {
+            P->implicit_sub[i] = 1;
+            ++P->n_implicit;
+        }
+    }
     for (int32_t i = 0; i < nsub; ++i) {
         const SubPlan& sp = P->plans[i];
+        const bool impl = P->implicit_sub[i] != 0;
         SubDev s{};
         s.n = sp.n;
         s.m = sp.m;
@@ -357,6 +507,7 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
             T.kstart = po.staircase ? sp.piv[(size_t)t * kTile] : 0;
             T.x_off = xo;
             xo += (int64_t)(sp.n - T.kstart) * kTile;
+            x_elems[i] += (int64_t)(sp.n - T.kstart) * kTile;
             for (int w = 0; w < 4; ++w) {
                 const int c = t * kTile + w * kStripe;
                 if (w * kStripe >= T.ncols) T.start_block[w] = s.nblocks;
@@ -371,7 +522,7 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
         }
         const int32_t nst = (sp.m + kSyrkTile - 1) / kSyrkTile;
         s.ftile_off = (int64_t)P->h_ftiles.size();
-        for (int32_t I = 0; I < nst; ++I) {
+        for (int32_t I = 0; I < nst && !impl; ++I) {     // implicit subdomains: no F
             P->h_frows.push_back(make_int2(i, I));
             for (int32_t J = 0; J <= I; ++J) P->h_ftiles.push_back(SyrkItem{i, I, J, 0, 0});
         }
@@ -383,7 +534,9 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
             auto mask = [&](int32_t t64, int32_t q) -> uint64_t {
                 return t64 < s.ntiles ? sp.step_mask[(size_t)t64 * nw + q] : 0;
             };
-            if (sp.n <= (P->mixed ? kSyrkBlockMaxNMixed : kSyrkBlockMaxN)) {
+            const bool blocks = P->syrk_kind[i] == 1 ||
+                                (P->syrk_kind[i] == 0 && sp.n <= (P->mixed ? kSyrkBlockMaxNMixed : kSyrkBlockMaxN));
+            if (blocks) {
                 for (int32_t I = 0; I < s.ntiles; ++I)
                     for (int32_t J = 0; J <= I; ++J) {
                         SyrkItem it{i, I, J, 0, (int64_t)P->h_ksteps.size()};
@@ -395,7 +548,7 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
                             }
                         }
                         it.nsteps = (int32_t)(P->h_ksteps.size() - it.step_off);
-                        if (it.nsteps > 0) sub_blocks[i].push_back(it);
+                        if (it.nsteps > 0 && !impl) sub_blocks[i].push_back(it);
                     }
             } else {
                 for (int32_t I = 0; I < nst; ++I)
@@ -414,7 +567,7 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
                             }
                         }
                         it.nsteps = (int32_t)(P->h_ksteps.size() - it.step_off);
-                        if (it.nsteps > 0) sub_tiles[i].push_back(it);
+                        if (it.nsteps > 0 && !impl) sub_tiles[i].push_back(it);
                     }
             }
         }
@@ -432,6 +585,12 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
         P->trsm_r += sp.trsm_reach;
         P->syrk_r += sp.syrk_reach;
     }
+    if (P->arena_elems > 0)
+        for (int32_t i = 0; i < nsub; ++i)
+            if (x_elems[i] > P->arena_elems)
+                return fail(SC_ERR_OOM, "arena_cap_bytes = " + std::to_string(P->opt.arena_cap_bytes) +
+                                            " is below the X slabs of subdomain " + std::to_string(i) + " (" +
+                                            std::to_string(x_elems[i] * (P->mixed ? 4 : 8)) + " bytes)");
     // ---- XCD-aware work lists: subdomains go to XCDs by longest-processing-
     // time on their useful flops; XCD x receives workgroups x, x + 8, ...
     {
@@ -470,6 +629,7 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
         // the tiles of one subdomain in order of decreasing visit count, its
         // SYRK items in order of decreasing step count (long items first)
         auto push_tiles = [&](std::vector<int32_t>& list, int32_t i) {
+            if (P->implicit_sub[i]) return;           // applied with the factor: no tiles
             const SubDev& sd = P->h_subs[i];
             const size_t b0 = list.size();
             for (int32_t t = 0; t < sd.ntiles; ++t) list.push_back((int32_t)(sd.tile_off + t));
@@ -484,20 +644,48 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
         }
         std::vector<std::vector<int32_t>> xt(kNumXcd);
         // groups for the overlapped assembly
+        // groups of subdomains: without an arena cap every XCD's list cut in
+        // kOverlapGroups consecutive parts (overlapped assembly, pipelined
+        // preprocessing); with a cap (temporary-memory waves) the subdomains
+        // in XCD-interleaved order (largest first) packed greedily into waves
+        // whose X slabs fit the cap, each wave's slabs at the same offsets
+        std::vector<std::vector<int32_t>> groups;
+        std::vector<int32_t> xcd_of(nsub, 0);
+        for (int x = 0; x < kNumXcd; ++x)
+            for (int32_t i : xsub[x]) xcd_of[i] = x;
         {
             size_t lmax = 0;
             for (int x = 0; x < kNumXcd; ++x) lmax = std::max(lmax, xsub[x].size());
-            const int ng = (int)std::max<size_t>(1, std::min<size_t>(kOverlapGroups, lmax));
-            for (int gi = 0; gi < ng; ++gi) {
+            if (P->arena_elems > 0) {
+                groups.emplace_back();
+                int64_t cur = 0;
+                for (size_t k = 0; k < lmax; ++k)
+                    for (int x = 0; x < kNumXcd; ++x) {
+                        if (k >= xsub[x].size()) continue;
+                        const int32_t i = xsub[x][k];
+                        if (!groups.back().empty() && cur + x_elems[i] > P->arena_elems) {
+                            groups.emplace_back();
+                            cur = 0;
+                        }
+                        groups.back().push_back(i);
+                        cur += x_elems[i];
+                    }
+            } else {
+                const int ng = (int)std::max<size_t>(1, std::min<size_t>(kOverlapGroups, lmax));
+                for (int gi = 0; gi < ng; ++gi) {
+                    groups.emplace_back();
+                    for (int x = 0; x < kNumXcd; ++x) {
+                        const size_t L = xsub[x].size();
+                        for (size_t k = L * gi / ng; k < L * (gi + 1) / ng; ++k) groups.back().push_back(xsub[x][k]);
+                    }
+                }
+            }
+            for (const std::vector<int32_t>& grp : groups) {
                 std::vector<std::vector<int32_t>> gt(kNumXcd), gsub(kNumXcd);
+                for (int32_t i : grp) gsub[xcd_of[i]].push_back(i);
                 size_t lt = 0;
                 for (int x = 0; x < kNumXcd; ++x) {
-                    const size_t L = xsub[x].size();
-                    for (size_t k = L * gi / ng; k < L * (gi + 1) / ng; ++k) {
-                        const int32_t i = xsub[x][k];
-                        push_tiles(gt[x], i);
-                        gsub[x].push_back(i);
-                    }
+                    for (int32_t i : gsub[x]) push_tiles(gt[x], i);
                     lt = std::max(lt, gt[x].size());
                 }
                 P->g_sub_off.push_back((int64_t)P->g_sub.size());
@@ -536,6 +724,22 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
             P->g_lval.push_back(off);
             if (off != lv || (int64_t)P->g_sub.size() != nsub)
                 return fail(SC_ERR_INVALID_ARG, "internal: subdomain groups do not cover the batch");
+        }
+        if (P->arena_elems > 0) {
+            // temporary-memory waves: the X slabs of each wave start at 0
+            xo = 0;
+            for (const std::vector<int32_t>& grp : groups) {
+                int64_t off = 0;
+                for (int32_t i : grp) {
+                    const SubDev& sd = P->h_subs[i];
+                    for (int32_t t = 0; t < sd.ntiles; ++t) {
+                        TileDev& T = P->h_tiles[sd.tile_off + t];
+                        T.x_off = off;
+                        off += (int64_t)(sd.n - T.kstart) * kTile;
+                    }
+                }
+                xo = std::max(xo, off);
+            }
         }
         for (int x = 0; x < kNumXcd; ++x)
             for (int32_t i : xsub[x]) push_tiles(xt[x], i);
@@ -816,7 +1020,7 @@ sc_status_t sc_assemble(sc_plan_t P, void* stream) {
         evp = ev;
     }
     HIP_TRY(P->launch_assembly((hipStream_t)stream, evp));
-    if (evp && P->overlapped()) {
+    if (evp && (P->overlapped() || P->arena_elems > 0)) {
         P->pending.push_back({4, ev[0], ev[1]});
         P->event_pool.push_back(ev[2]);
         P->event_pool.push_back(ev[3]);
@@ -828,6 +1032,8 @@ sc_status_t sc_assemble(sc_plan_t P, void* stream) {
     return SC_OK;
 }
 
+static sc_status_t build_implicit(sc_plan_s* P, hipStream_t st);
+
 sc_status_t sc_apply(sc_plan_t P, const double* p_dev, double* q_dev, void* stream) {
     g_last_error.clear();
     if (!P) return fail(SC_ERR_INVALID_ARG, "plan is NULL");
@@ -835,14 +1041,27 @@ sc_status_t sc_apply(sc_plan_t P, const double* p_dev, double* q_dev, void* stre
     if (P->dual_total > 0 && (!p_dev || !q_dev)) return fail(SC_ERR_INVALID_ARG, "p or q is NULL");
     if (P->dual_total > 0 && p_dev == q_dev) return fail(SC_ERR_INVALID_ARG, "p and q must not alias");
     HIP_TRY(hipSetDevice(P->device));
+    hipStream_t st = (hipStream_t)stream;
+    if (P->n_implicit > 0 && !P->impl_ready) {
+        const sc_status_t s = build_implicit(P, st);
+        if (s != SC_OK) return s;
+    }
     hipEvent_t ev[2];
     hipEvent_t* evp = nullptr;
     if (P->timing) {
         HIP_TRY(P->take_events(2, ev));
         evp = ev;
     }
-    HIP_TRY(launch_apply(P->tables(), p_dev, q_dev, (hipStream_t)stream, evp));
-    if (evp) P->pending.push_back({2, ev[0], ev[1]});
+    const DevTables t = P->tables();
+    if (evp) HIP_TRY(hipEventRecord(ev[0], st));
+    HIP_TRY(launch_apply(t, p_dev, q_dev, st, nullptr));
+    // subdomains chosen for the implicit approach (select_iters)
+    if (P->n_implicit > 0)
+        HIP_TRY(launch_apply_implicit(t, P->ilv_h, P->d_xoff.p, P->d_xwork.p, p_dev, q_dev, P->n_implicit, st, nullptr));
+    if (evp) {
+        HIP_TRY(hipEventRecord(ev[1], st));
+        P->pending.push_back({2, ev[0], ev[1]});
+    }
     return SC_OK;
 }
 
@@ -902,6 +1121,10 @@ sc_status_t sc_pcpg(sc_plan_t P, const double* const* R_host, const int32_t* k_h
     }
     HIP_TRY(hipSetDevice(P->device));
     hipStream_t st = (hipStream_t)stream;
+    if (P->n_implicit > 0 && !P->impl_ready) {
+        const sc_status_t s = build_implicit(P, st);
+        if (s != SC_OK) return s;
+    }
     // workspace
     const size_t nd = (size_t)std::max<int64_t>(1, P->dual_total);
     DevBuf<double> dG, dGi, dwork, dww, dhist;
@@ -926,7 +1149,8 @@ sc_status_t sc_pcpg(sc_plan_t P, const double* const* R_host, const int32_t* k_h
         a.d = d_dev; a.lambda = lambda_dev;
         a.r = dwork.p; a.w = dwork.p + nd; a.p = dwork.p + 2 * nd; a.q = dwork.p + 3 * nd;
         a.ww = dww.p; a.hist = dhist.p; a.nsub = P->nsub; a.iters = iters;
-        e = launch_pcpg(P->tables(), a, st);
+        e = launch_pcpg(P->tables(), a, st, P->n_implicit > 0 ? &P->ilv_h : nullptr, P->d_xoff.p, P->d_xwork.p,
+                        P->n_implicit);
     }
     if (e == hipSuccess && wnorm_hist)
         e = hipMemcpyAsync(wnorm_hist, dhist.p, (size_t)(iters + 1) * P->nsub * 8, hipMemcpyDeviceToHost, st);
@@ -950,7 +1174,8 @@ static sc_status_t build_implicit(sc_plan_s* P, hipStream_t st) {
     std::vector<std::vector<int2>> fw, bw;
     std::vector<int64_t> rptr_off(P->nsub, 0);
     std::vector<int32_t> rptr, rpos;
-    int64_t nblocks_all = 0, nlevels_all = 0;
+    int64_t nblocks_all = 0, nlevels_all = 0, nlevels_sub_h = 0;
+    std::vector<int64_t> sub_levels(P->nsub, 0);
     for (int32_t i = 0; i < P->nsub; ++i) {
         const SubPlan& sp = P->plans[i];
         const SubDev& sd = P->h_subs[i];
@@ -969,7 +1194,8 @@ static sc_status_t build_implicit(sc_plan_s* P, hipStream_t st) {
                 lb[b] = std::max(lb[b], lb[sp.block_of_row[sp.brows[d.rows_off + q]]] + 1);
         }
         nblocks_all += nb;
-        nlevels_all += nb > 0 ? 1 + *std::max_element(lf.begin(), lf.end()) : 0;
+        sub_levels[i] = nb > 0 ? 1 + *std::max_element(lf.begin(), lf.end()) : 0;
+        nlevels_all += sub_levels[i];
         for (int32_t b = 0; b < nb; ++b) {
             if ((size_t)lf[b] >= fw.size()) fw.resize(lf[b] + 1);
             if ((size_t)lb[b] >= bw.size()) bw.resize(lb[b] + 1);
@@ -1000,13 +1226,38 @@ static sc_status_t build_implicit(sc_plan_s* P, hipStream_t st) {
     lv.bw_off.assign(1, 0);
     for (auto& l : fw) { fwi.insert(fwi.end(), l.begin(), l.end()); lv.fw_off.push_back((int64_t)fwi.size()); }
     for (auto& l : bw) { bwi.insert(bwi.end(), l.begin(), l.end()); lv.bw_off.push_back((int64_t)bwi.size()); }
+    // the subset applied implicitly next to the assembled subdomains
+    std::vector<int2> fwh, bwh;
+    std::vector<int32_t> impl_list;
+    ImplicitLevels lvh;
+    lvh.fw_off.assign(1, 0);
+    lvh.bw_off.assign(1, 0);
+    int64_t nblocks_h = 0;
+    for (int32_t i = 0; i < P->nsub; ++i)
+        if (P->implicit_sub[i]) {
+            impl_list.push_back(i);
+            nblocks_h += (int64_t)P->plans[i].blocks.size();
+            nlevels_sub_h += sub_levels[i];
+        }
+    auto subset = [&](const std::vector<std::vector<int2>>& lev, std::vector<int2>& out, std::vector<int64_t>& off) {
+        for (auto& l : lev) {
+            for (const int2& it : l)
+                if (P->implicit_sub[it.x]) out.push_back(it);
+            if ((int64_t)out.size() > off.back()) off.push_back((int64_t)out.size());
+        }
+    };
+    subset(fw, fwh, lvh.fw_off);
+    subset(bw, bwh, lvh.bw_off);
     DevBuf<double> xwork, ubuf;
     DevBuf<int64_t> xoff, rptr_off_d;
     DevBuf<int2> ifw, ibw;
     DevBuf<int32_t> rptr_d, rpos_d;
+    DevBuf<int2> ifwh, ibwh;
+    DevBuf<int32_t> ilist;
     auto release_all = [&]() {
         xwork.release(); ubuf.release(); xoff.release(); rptr_off_d.release();
         ifw.release(); ibw.release(); rptr_d.release(); rpos_d.release();
+        ifwh.release(); ibwh.release(); ilist.release();
     };
     hipError_t e = xwork.alloc((size_t)off[P->nsub]);
     if (e == hipSuccess) e = xoff.alloc(off.size());
@@ -1016,6 +1267,9 @@ static sc_status_t build_implicit(sc_plan_s* P, hipStream_t st) {
     if (e == hipSuccess) e = rptr_d.alloc(rptr.size());
     if (e == hipSuccess) e = rpos_d.alloc(std::max<size_t>(1, rpos.size()));
     if (e == hipSuccess) e = ubuf.alloc((size_t)P->nrows_total);
+    if (e == hipSuccess) e = ifwh.alloc(fwh.size());
+    if (e == hipSuccess) e = ibwh.alloc(bwh.size());
+    if (e == hipSuccess) e = ilist.alloc(impl_list.size());
     auto up = [&](void* d, const void* h, size_t bytes) -> hipError_t {
         return bytes ? hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, st) : hipSuccess;
     };
@@ -1025,6 +1279,9 @@ static sc_status_t build_implicit(sc_plan_s* P, hipStream_t st) {
     if (e == hipSuccess) e = up(rptr_off_d.p, rptr_off.data(), rptr_off.size() * 8);
     if (e == hipSuccess) e = up(rptr_d.p, rptr.data(), rptr.size() * 4);
     if (e == hipSuccess) e = up(rpos_d.p, rpos.data(), rpos.size() * 4);
+    if (e == hipSuccess) e = up(ifwh.p, fwh.data(), fwh.size() * sizeof(int2));
+    if (e == hipSuccess) e = up(ibwh.p, bwh.data(), bwh.size() * sizeof(int2));
+    if (e == hipSuccess) e = up(ilist.p, impl_list.data(), impl_list.size() * 4);
     if (e == hipSuccess) e = hipStreamSynchronize(st);    // the host tables go out of scope
     if (e != hipSuccess) {
         release_all();
@@ -1043,6 +1300,18 @@ static sc_status_t build_implicit(sc_plan_s* P, hipStream_t st) {
     P->d_xwork = xwork; P->d_xoff = xoff; P->d_ifw = ifw; P->d_ibw = ibw;
     P->d_rptr_off = rptr_off_d; P->d_rptr = rptr_d; P->d_rpos = rpos_d; P->d_ubuf = ubuf;
     P->ilv = lv;
+    lvh.fw_items = ifwh.p;
+    lvh.bw_items = ibwh.p;
+    lvh.rptr_off = lv.rptr_off;
+    lvh.rptr = lv.rptr;
+    lvh.rpos = lv.rpos;
+    lvh.ubuf = lv.ubuf;
+    lvh.subs = ilist.p;
+    // per-subdomain sweeps for the subset when its own block DAGs are near
+    // chains (the per-subdomain kernel reads the list)
+    lvh.per_subdomain = 2 * nblocks_h < 3 * nlevels_sub_h;
+    P->d_ifw_h = ifwh; P->d_ibw_h = ibwh; P->d_impl_list = ilist;
+    P->ilv_h = lvh;
     P->impl_ready = true;
     return SC_OK;
 }
@@ -1082,9 +1351,9 @@ sc_status_t sc_apply_implicit(sc_plan_t P, const double* p_dev, double* q_dev, v
             if (e != hipSuccess) return fail(SC_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
             P->impl_graph = ex;
         }
-        HIP_TRY(launch_implicit_init(t, P->d_xoff.p, P->d_xwork.p, p_dev, P->nsub, st));
+        HIP_TRY(launch_implicit_init(t, P->d_xoff.p, P->d_xwork.p, p_dev, nullptr, P->nsub, st));
         HIP_TRY(hipGraphLaunch(P->impl_graph, st));
-        HIP_TRY(launch_implicit_gather(t, P->d_xoff.p, P->d_xwork.p, q_dev, P->nsub, st));
+        HIP_TRY(launch_implicit_gather(t, P->d_xoff.p, P->d_xwork.p, q_dev, nullptr, P->nsub, st));
         return SC_OK;
     }
     hipEvent_t ev[2];
@@ -1103,6 +1372,9 @@ sc_status_t sc_get_F(sc_plan_t P, int32_t sub, double* out, int32_t ld, int32_t 
     if (!P) return fail(SC_ERR_INVALID_ARG, "plan is NULL");
     if (sub < 0 || sub >= P->nsub) return fail(SC_ERR_INVALID_ARG, "subdomain index out of range");
     if (!P->assembled) return fail(SC_ERR_STATE, "sc_get_F before sc_assemble");
+    if (P->implicit_sub[sub])
+        return fail(SC_ERR_STATE, "subdomain " + std::to_string(sub) + " is applied implicitly (select_iters): "
+                                  "its F is not assembled");
     const SubDev& s = P->h_subs[sub];
     if (s.m == 0) return SC_OK;
     if (!out || ld < s.m) return fail(SC_ERR_INVALID_ARG, "bad output buffer or ld");
@@ -1153,6 +1425,20 @@ sc_status_t sc_query(sc_plan_t P, int32_t sub, int64_t* n, int64_t* m, int64_t* 
     if (dual_offset) *dual_offset = P->h_subs[sub].dual_off;
     if (nnzL) *nnzL = sp.nnzL;
     if (useful_flops) *useful_flops = sp.trsm_useful + sp.syrk_useful;
+    return SC_OK;
+}
+
+sc_status_t sc_query_selection(sc_plan_t P, int32_t sub, int32_t* implicit, double* t_asm_ms, double* t_expl_ms,
+                               double* t_impl_ms, double* n_star) {
+    g_last_error.clear();
+    if (!P) return fail(SC_ERR_INVALID_ARG, "plan is NULL");
+    if (sub < 0 || sub >= P->nsub) return fail(SC_ERR_INVALID_ARG, "subdomain index out of range");
+    const Prediction& q = P->pred[sub];
+    if (implicit) *implicit = P->implicit_sub[sub];
+    if (t_asm_ms) *t_asm_ms = q.t_asm_ms;
+    if (t_expl_ms) *t_expl_ms = q.t_expl_ms;
+    if (t_impl_ms) *t_impl_ms = q.t_impl_ms;
+    if (n_star) *n_star = q.n_star;
     return SC_OK;
 }
 
@@ -1215,6 +1501,11 @@ sc_status_t sc_host_analyze(const sc_subdomain_desc_t* sd, const sc_options_t* o
         h.syrk_reach = sp.syrk_reach;
         h.trsm_visits = (int64_t)sp.visit.size();
         h.stair_visits = sp.visits_stair;
+        const Prediction q = predict(sp, o.precision == SC_PREC_MIXED, o);
+        h.t_asm_ms = q.t_asm_ms;
+        h.t_expl_ms = q.t_expl_ms;
+        h.t_impl_ms = q.t_impl_ms;
+        h.n_star = q.n_star;
         *info = h;
     }
     if (kreg_vals) {
@@ -1356,6 +1647,136 @@ sc_status_t sc_autotune(const sc_subdomain_desc_t* sd, int32_t nsub, const sc_op
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return status;
+}
+
+sc_status_t sc_autotune_classes(const sc_subdomain_desc_t* sd, int32_t nsub, const sc_options_t* base,
+                                const double* const* kreg_vals, int32_t sample, int32_t reps,
+                                const char* cache_path, void* stream, sc_tune_class_t* classes,
+                                int32_t max_classes, int32_t* nclasses) {
+    g_last_error.clear();
+    if (!sd || nsub <= 0 || !kreg_vals || sample < 1 || reps < 1 || !classes || max_classes < 1 || !nclasses)
+        return fail(SC_ERR_INVALID_ARG, "bad autotune arguments");
+    sc_options_t o0{};
+    if (base) o0 = *base;
+    o0.use_graph = 0;
+    o0.tune_classes = nullptr;
+    o0.ntune_classes = 0;
+    const char* prec = o0.precision == SC_PREC_MIXED ? "mixed" : "fp64";
+    // size classes [0, 1024), [1024, 2048), [2048, 4096), ...; the last one open
+    auto class_of = [](int32_t n) {
+        int c = 0;
+        while (c < 20 && n >= (1 << (c + 10))) ++c;
+        return c;
+    };
+    std::vector<std::vector<int32_t>> members(21);
+    for (int32_t i = 0; i < nsub; ++i) members[class_of(sd[i].n)].push_back(i);
+    std::vector<int> used;
+    for (int c = 0; c <= 20; ++c)
+        if (!members[c].empty()) used.push_back(c);
+    if ((int32_t)used.size() > max_classes)
+        return fail(SC_ERR_INVALID_ARG, "max_classes = " + std::to_string(max_classes) + " < " +
+                                            std::to_string(used.size()) + " size classes");
+    const std::string dev = device_key();
+    // cached classes
+    struct Cached { int32_t lo, hi, pw, split, syrk; float ms; };
+    std::vector<Cached> cached;
+    if (cache_path) {
+        FILE* f = std::fopen(cache_path, "r");
+        if (f) {
+            char line[512];
+            while (std::fgets(line, sizeof line, f)) {
+                if (line[0] == '#') continue;
+                char d[256], pr[16];
+                Cached k{};
+                if (std::sscanf(line, "%255s %15s %d %d %d %d %d %f", d, pr, &k.lo, &k.hi, &k.pw, &k.split, &k.syrk,
+                                &k.ms) == 8 &&
+                    dev == d && std::strcmp(pr, prec) == 0)
+                    cached.push_back(k);
+            }
+            std::fclose(f);
+        }
+    }
+    hipStream_t st = (hipStream_t)stream;
+    (void)st;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    sc_status_t status = SC_OK;
+    std::vector<std::string> fresh;
+    int32_t nc = 0;
+    for (size_t u = 0; u < used.size() && status == SC_OK; ++u) {
+        const int c = used[u];
+        const int32_t lo = c == 0 ? 0 : (1 << (c + 9));
+        const int32_t hi = u + 1 == used.size() ? INT32_MAX : (1 << (c + 10));
+        sc_tune_class_t out{lo, hi, 64, 0, 0, 0.f};
+        bool hit = false;
+        for (const Cached& k : cached)
+            if (k.lo == lo && k.hi == hi) {
+                out = sc_tune_class_t{lo, hi, k.pw, k.split, k.syrk, k.ms};
+                hit = true;
+                break;
+            }
+        if (!hit) {
+            std::vector<int32_t> idx = members[c];
+            std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) { return sd[a].n < sd[b].n; });
+            const int32_t ns = std::min<int32_t>(sample, (int32_t)idx.size());
+            std::vector<sc_subdomain_desc_t> sub(ns);
+            std::vector<const double*> vals(ns);
+            for (int32_t k = 0; k < ns; ++k) {
+                const int32_t i = idx[(int64_t)k * (int64_t)idx.size() / ns];
+                sub[k] = sd[i];
+                vals[k] = kreg_vals[i];
+            }
+            auto run = [&](int32_t pw, int32_t split, int32_t syrk, double* ms) {
+                sc_options_t o = o0;
+                sc_tune_class_t one{0, INT32_MAX, pw, split, syrk, 0.f};
+                o.tune_classes = &one;
+                o.ntune_classes = 1;
+                return time_candidate(sub.data(), ns, o, vals.data(), reps, stream, e0, e1, ms);
+            };
+            // SYRK kind the size rule gives this class's largest sample member
+            const int32_t nmax = sub[ns - 1].n;
+            const int32_t by_size = nmax <= (o0.precision == SC_PREC_MIXED ? kSyrkBlockMaxNMixed : kSyrkBlockMaxN) ? 1 : 2;
+            double best = 0.0, t = 0.0;
+            status = run(64, 0, by_size, &best);
+            out.panel_width = 64;
+            out.block_split = 0;
+            out.syrk_kind = by_size;
+            if (status == SC_OK && (status = run(64, 1, by_size, &t)) == SC_OK && t < best) {
+                best = t;
+                out.block_split = 1;
+            }
+            for (int32_t pw : {32, 48}) {
+                if (status != SC_OK) break;
+                if ((status = run(pw, out.block_split, by_size, &t)) == SC_OK && t < best) {
+                    best = t;
+                    out.panel_width = pw;
+                }
+            }
+            if (status == SC_OK && (status = run(out.panel_width, out.block_split, 3 - by_size, &t)) == SC_OK &&
+                t < best) {
+                best = t;
+                out.syrk_kind = 3 - by_size;
+            }
+            out.ms_per_sub = (float)(best / ns);
+            char line[512];
+            std::snprintf(line, sizeof line, "%s %s %d %d %d %d %d %.6g\n", dev.c_str(), prec, lo, hi,
+                          out.panel_width, out.block_split, out.syrk_kind, (double)out.ms_per_sub);
+            fresh.push_back(line);
+        }
+        classes[nc++] = out;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (status != SC_OK) return status;
+    *nclasses = nc;
+    if (cache_path && !fresh.empty()) {
+        FILE* f = std::fopen(cache_path, "a");
+        if (!f) return fail(SC_ERR_DEVICE, std::string("cannot write the autotune cache ") + cache_path);
+        for (const std::string& l : fresh) std::fputs(l.c_str(), f);
+        std::fclose(f);
+    }
+    return SC_OK;
 }
 
 sc_status_t sc_plan_destroy(sc_plan_t P) {

@@ -17,7 +17,7 @@ STATUS_NAMES = {0: "SC_OK", 1: "SC_ERR_INVALID_ARG", 2: "SC_ERR_NOT_SPD", 3: "SC
 
 EXPORTED = ["sc_plan_create", "sc_factor", "sc_assemble", "sc_apply", "sc_apply_implicit",
             "sc_get_F", "sc_query", "sc_plan_stats", "sc_plan_destroy", "sc_host_analyze",
-            "sc_host_tile_visits", "sc_set_timing", "sc_kernel_times", "sc_pcpg", "sc_autotune", "sc_preprocess",
+            "sc_host_tile_visits", "sc_set_timing", "sc_kernel_times", "sc_pcpg", "sc_autotune", "sc_autotune_classes", "sc_preprocess", "sc_query_selection",
             "sc_last_error"]
 
 
@@ -37,12 +37,23 @@ class SubdomainDesc(ctypes.Structure):
                 ("dofs_per_node", ctypes.c_int32)]
 
 
+class TuneClass(ctypes.Structure):
+    _fields_ = [("n_lo", ctypes.c_int32), ("n_hi", ctypes.c_int32), ("panel_width", ctypes.c_int32),
+                ("block_split", ctypes.c_int32), ("syrk_kind", ctypes.c_int32), ("ms_per_sub", ctypes.c_float)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("disable_staircase", ctypes.c_int32),
                 ("panel_width", ctypes.c_int32), ("relax_width", ctypes.c_int32),
                 ("leaf_nodes", ctypes.c_int32), ("n_threads", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("assembly_kernels", ctypes.c_int32),
-                ("disable_reach", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("disable_reach", ctypes.c_int32), ("block_split", ctypes.c_int32), ("select_iters", ctypes.c_int32),
+                ("select_model", ctypes.c_float * 3),
+                ("arena_cap_bytes", ctypes.c_int64), ("tune_classes", ctypes.POINTER(TuneClass)),
+                ("ntune_classes", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
 
 
 class HostInfo(ctypes.Structure):
@@ -53,7 +64,8 @@ class HostInfo(ctypes.Structure):
                 ("trsm_dense", ctypes.c_double), ("syrk_dense", ctypes.c_double),
                 ("factor_flops", ctypes.c_double), ("trsm_visits", ctypes.c_int64),
                 ("stair_visits", ctypes.c_int64), ("trsm_reach", ctypes.c_double),
-                ("syrk_reach", ctypes.c_double)]
+                ("syrk_reach", ctypes.c_double), ("t_asm_ms", ctypes.c_double), ("t_expl_ms", ctypes.c_double),
+                ("t_impl_ms", ctypes.c_double), ("n_star", ctypes.c_double)]
 
 
 _lib = None
@@ -86,6 +98,10 @@ def load():
         lib.sc_autotune.argtypes = [ctypes.POINTER(SubdomainDesc), i32, ctypes.POINTER(Options),
                                     ctypes.POINTER(vp), ctypes.POINTER(i32), i32, i32, i32, vp,
                                     ctypes.POINTER(i32), dp]
+        lib.sc_autotune_classes.argtypes = [ctypes.POINTER(SubdomainDesc), i32, ctypes.POINTER(Options),
+                                            ctypes.POINTER(vp), i32, i32, ctypes.c_char_p, vp,
+                                            ctypes.POINTER(TuneClass), i32, ctypes.POINTER(i32)]
+        lib.sc_query_selection.argtypes = [vp, i32, ctypes.POINTER(i32), dp, dp, dp, dp]
         lib.sc_set_timing.argtypes = [vp, i32]
         lib.sc_kernel_times.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), i32]
         lib.sc_last_error.argtypes = []
@@ -167,10 +183,29 @@ def check_dual_tensor(t, length: int, device_index: int, name: str):
         raise ScasmError(SC_ERR_INVALID_ARG, bad)
 
 
+BLOCK_SPLIT = {"uniform": 0, "etree": 1}
+
+
 def _options(precision="fp64", staircase=True, panel_width=0, relax_width=0, leaf_nodes=0, n_threads=0,
-             use_graph=False, assembly="default", reach=True):
+             use_graph=False, assembly="default", reach=True, block_split="uniform", arena_cap_bytes=0,
+             tune_classes=None, select_iters=0, select_model=(0.0, 0.0, 0.0)):
     opt = Options()
+    opt.arena_cap_bytes = int(arena_cap_bytes)
+    opt.select_iters = int(select_iters)
+    for k in range(3):
+        opt.select_model[k] = float(select_model[k])
+    if tune_classes:
+        arr = (TuneClass * len(tune_classes))()
+        for k, c in enumerate(tune_classes):
+            d = c.as_dict() if isinstance(c, TuneClass) else c
+            arr[k] = TuneClass(int(d["n_lo"]), int(d["n_hi"]), int(d.get("panel_width", 0)),
+                               int(d.get("block_split", -1)), int(d.get("syrk_kind", 0)),
+                               float(d.get("ms_per_sub", 0.0)))
+        opt.tune_classes = ctypes.cast(arr, ctypes.POINTER(TuneClass))
+        opt.ntune_classes = len(tune_classes)
+        opt._keep = arr                       # the array lives as long as the options
     opt.disable_reach = 0 if reach else 1
+    opt.block_split = BLOCK_SPLIT[block_split] if isinstance(block_split, str) else int(block_split)
     opt.use_graph = 1 if use_graph else 0
     opt.assembly_kernels = ASSEMBLY_KERNELS[assembly] if isinstance(assembly, str) else int(assembly)
     opt.precision = {"fp64": SC_PREC_FP64, "mixed": SC_PREC_MIXED}.get(precision, precision) \
@@ -254,6 +289,27 @@ def autotune(subdomains, candidates=(32, 48, 64), sample=64, reps=3, use_coords=
     return best.value, {c: times[i] for i, c in enumerate(candidates)}
 
 
+def autotune_classes(subdomains, sample=8, reps=2, cache_path=None, use_coords=True, stream=None, **opts):
+    """Per-size-class settings (sc_autotune_classes): returns a list of dicts
+    (n_lo, n_hi, panel_width, block_split, syrk_kind, ms_per_sub), to pass as
+    Plan(..., tune_classes=...)."""
+    lib = load()
+    keep = []
+    subs = list(subdomains)
+    descs = (SubdomainDesc * len(subs))()
+    for i, s in enumerate(subs):
+        _fill_desc(descs[i], s, keep, use_coords)
+    arrs = [np.ascontiguousarray(s.val, dtype=np.float64) for s in subs]
+    ptrs = (ctypes.c_void_p * len(arrs))(*[a.ctypes.data for a in arrs])
+    out = (TuneClass * 21)()
+    nc = ctypes.c_int32(0)
+    opt = _options(**opts)
+    _check(lib.sc_autotune_classes(descs, len(subs), ctypes.byref(opt), ptrs, int(sample), int(reps),
+                                   cache_path.encode() if cache_path else None, _stream_handle(stream), out, 21,
+                                   ctypes.byref(nc)))
+    return [out[k].as_dict() for k in range(nc.value)]
+
+
 class Plan:
     """A batch of subdomains (objects with n, rowptr, col, val, dof, sign and
     optional coords, dim, dofs_per_node, perm attributes)."""
@@ -261,7 +317,8 @@ class Plan:
     def __init__(self, subdomains: Sequence, precision: str = "fp64", staircase: bool = True,
                  panel_width: int = 0, relax_width: int = 0, leaf_nodes: int = 0, n_threads: int = 0,
                  use_coords: bool = True, use_graph: bool = False, assembly: str = "default", reach: bool = True,
-                 stream=None):
+                 block_split: str = "uniform", arena_cap_bytes: int = 0, tune_classes=None, select_iters: int = 0,
+                 select_model=(0.0, 0.0, 0.0), stream=None):
         lib = load()
         self._lib = lib
         self._h = ctypes.c_void_p(0)
@@ -272,7 +329,7 @@ class Plan:
         for i, s in enumerate(self.subdomains):
             _fill_desc(descs[i], s, keep, use_coords)
         opt = _options(precision, staircase, panel_width, relax_width, leaf_nodes, n_threads, use_graph, assembly,
-                       reach)
+                       reach, block_split, arena_cap_bytes, tune_classes, select_iters, select_model)
         _check(lib.sc_plan_create(descs, len(self.subdomains), ctypes.byref(opt), _stream_handle(stream),
                                   ctypes.byref(self._h)))
         del keep
@@ -377,6 +434,15 @@ class Plan:
                                   ctypes.byref(nnz), ctypes.byref(fl)))
         return {"n": n.value, "m": m.value, "dual_offset": off.value, "nnzL": nnz.value,
                 "useful_flops": fl.value}
+
+    def selection(self, i: int) -> dict:
+        """The select_iters choice for subdomain i and its prediction."""
+        imp = ctypes.c_int32()
+        ta, te, ti, ns = (ctypes.c_double() for _ in range(4))
+        _check(self._lib.sc_query_selection(self._h, i, ctypes.byref(imp), ctypes.byref(ta), ctypes.byref(te),
+                                            ctypes.byref(ti), ctypes.byref(ns)))
+        return {"implicit": bool(imp.value), "t_asm_ms": ta.value, "t_expl_ms": te.value, "t_impl_ms": ti.value,
+                "n_star": ns.value}
 
     def stats(self) -> dict:
         ns = ctypes.c_int32()

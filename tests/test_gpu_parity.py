@@ -142,6 +142,29 @@ def test_full_large_elasticity_512_columns_direct(precision):
     plan.destroy()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_etree_block_split_matches_oracle(precision):
+    """Factor blocks that follow the elimination tree (non-uniform widths,
+    Sec. 4.1 footnote) in the TRSM and SYRK: against the oracle, and equal to
+    the uniform split within rounding."""
+    subs = scgen.config_subdomains(2, count=2) + scgen.config_subdomains(3, count=4) + \
+        scgen.paper_subdomains(3, 14, count=1)
+    plan = _assemble(subs, precision=precision, block_split="etree")
+    uni = _assemble(subs, precision=precision)
+    tol = TOL_FP64 if precision == "fp64" else TOL_MIXED
+    for i, s in enumerate(subs):
+        F = plan.get_F(i)
+        assert np.array_equal(F, F.T)
+        assert oracle.relF(F, uni.get_F(i)) <= (1e-13 if precision == "fp64" else 1e-6)
+        if s.n <= 3000:
+            assert oracle.relF(F, oracle.schur(s)) <= tol, i
+        else:
+            sel = np.sort(np.random.default_rng(i).choice(s.m, size=min(128, s.m), replace=False))
+            assert oracle.relF(F[np.ix_(sel, sel)], oracle.schur(s, sel=sel)) <= tol, i
+    plan.destroy()
+    uni.destroy()
+
+
 def test_staircase_off_matches_on():
     subs = [scgen.config_subdomains(1)[0], scgen.box_subdomain("elasticity", (4, 3, 5), 0.25, seed=8)]
     on = _assemble(subs)
@@ -434,13 +457,14 @@ def test_pcpg_mixed_close_to_fp64():
 
 # ---------------------------------------------------------------- implicit apply
 
+@pytest.mark.parametrize("split", ["uniform", "etree"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_implicit_apply_matches_oracle(precision):
+def test_implicit_apply_matches_oracle(precision, split):
     base = scgen.box_subdomain("heat", (4, 4, 3), 0.25, seed=13)
     per_face = scgen.box_subdomain("elasticity", (3, 2, 3), 0.25, seed=15, gluing="per_face")
     subs = scgen.config_subdomains(1) + scgen.config_subdomains(3, count=3) + [base, per_face]
     _torch_init()
-    plan = P.Plan(subs, precision=precision)
+    plan = P.Plan(subs, precision=precision, block_split=split)
     plan.factor()
     p, q = _dual_vectors(plan, subs, seed=11)
     plan.apply_implicit(p, q)            # needs only the factor (before sc_assemble)
@@ -656,6 +680,93 @@ def test_overlapped_assembly_is_timed_in_its_own_slot():
     t = plan.kernel_times()
     assert t["assemble_overlap"][1] == 2 and t["assemble_overlap"][0] > 0
     assert t["trsm"][1] == 0 and t["syrk"][1] == 0
+
+
+def _median_n_star(subs, **kw):
+    ns = [P.host_analyze(s, values=False, **kw)["n_star"] for s in subs]
+    return ns, float(np.median(ns))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_hybrid_explicit_implicit_selection(precision):
+    """select_iters between the subdomains' predicted amortisation points:
+    the ones with n* above it are applied with the factor, the others with
+    the assembled F; sc_apply and sc_pcpg against the all-explicit plan."""
+    torch = _torch_init()
+    subs = scgen.config_subdomains(3, count=12)
+    ns, k = _median_n_star(subs, precision=precision)
+    k = int(k)
+    hyb = _assemble(subs, precision=precision, select_iters=k)
+    ref = _assemble(subs, precision=precision)
+    imp = [hyb.selection(i)["implicit"] for i in range(len(subs))]
+    assert imp == [n > k for n in ns] and any(imp) and not all(imp)
+    for i in range(len(subs)):
+        assert np.isclose(hyb.selection(i)["n_star"], ns[i])
+        if imp[i]:
+            with pytest.raises(P.ScasmError) as e:
+                hyb.get_F(i)
+            assert e.value.status == P.SC_ERR_STATE
+        else:
+            assert np.array_equal(hyb.get_F(i), ref.get_F(i))
+    p, _ = _dual_vectors(hyb, subs, seed=21)
+    q_h, q_r = torch.zeros_like(p), torch.zeros_like(p)
+    hyb.apply(p, q_h)
+    ref.apply(p, q_r)
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    for i, s in enumerate(subs):
+        o = hyb.query(i)["dual_offset"]
+        a, b = q_h[o:o + s.m].cpu().numpy(), q_r[o:o + s.m].cpu().numpy()
+        assert np.linalg.norm(a - b) <= tol * np.linalg.norm(b), i
+    d = torch.from_numpy(scgen.splitmix64_uniform(77, hyb.dual_total)).cuda()
+    lam_h, lam_r = torch.zeros_like(d), torch.zeros_like(d)
+    hyb.pcpg(d, lam_h, 60)
+    ref.pcpg(d, lam_r, 60)
+    assert float(torch.linalg.norm(lam_h - lam_r) / torch.linalg.norm(lam_r)) <= (1e-8 if precision == "fp64" else 1e-4)
+    hyb.destroy()
+    ref.destroy()
+
+
+def test_all_implicit_selection_equals_the_implicit_apply():
+    torch = _torch_init()
+    subs = scgen.config_subdomains(3, count=5) + scgen.config_subdomains(1)
+    plan = _assemble(subs, select_iters=1000, select_model=(10.0, 2000.0, 1e9))
+    assert all(plan.selection(i)["implicit"] for i in range(len(subs)))
+    p, _ = _dual_vectors(plan, subs, seed=5)
+    q1, q2 = torch.zeros_like(p), torch.zeros_like(p)
+    plan.apply(p, q1)
+    plan.apply_implicit(p, q2)
+    assert torch.equal(q1, q2)
+    plan.destroy()
+
+
+def test_autotune_classes_tune_cache_and_plan(tmp_path):
+    """Per-size-class autotuning (block split, width, SYRK work items) on
+    an uneven batch; the cache file returns the same classes without timing
+    again; a plan built with the classes matches the oracle."""
+    _torch_init()
+    subs = scgen.config_subdomains(3, count=40)
+    cache = str(tmp_path / "tune.txt")
+    cls = P.autotune_classes(subs, sample=2, reps=1, cache_path=cache)
+    ns = np.array([s.n for s in subs])
+    assert len(cls) >= 2
+    assert cls[0]["n_lo"] <= ns.min() and cls[-1]["n_hi"] > ns.max()
+    for a, b in zip(cls[:-1], cls[1:]):
+        assert a["n_hi"] <= b["n_lo"]
+    for c in cls:
+        assert c["panel_width"] in (32, 48, 64) and c["block_split"] in (0, 1) and c["syrk_kind"] in (1, 2)
+        assert c["ms_per_sub"] > 0
+    with open(cache) as f:
+        assert len([l for l in f if l.strip() and not l.startswith("#")]) == len(cls)
+    again = P.autotune_classes(subs, sample=2, reps=1, cache_path=cache)
+    assert [(c["n_lo"], c["n_hi"], c["panel_width"], c["block_split"], c["syrk_kind"]) for c in again] == \
+        [(c["n_lo"], c["n_hi"], c["panel_width"], c["block_split"], c["syrk_kind"]) for c in cls]
+    # every setting once, on a plan
+    mixed_cls = [dict(c, panel_width=pw, block_split=k % 2, syrk_kind=1 + (k // 2) % 2)
+                 for k, (c, pw) in enumerate(zip(cls, (32, 48, 64, 32, 48)))]
+    for tc in (cls, mixed_cls):
+        plan = _assemble(subs[:8], tune_classes=tc)
+        _check_against_oracle(plan, subs[:8], max_full=3000)
+        plan.destroy()
 
 
 def test_autotune_picks_a_candidate():

@@ -1,8 +1,10 @@
 """Pipelined preprocessing (sc_preprocess: host factorisation of later
 subdomain groups overlapped with the GPU assembly of earlier ones, Sec. 4.4)
-against the separated stages (sc_factor, then sc_assemble), and parity of the
-assembly on the paper's own element types (P1 triangles and tetrahedra,
-Sec. 4) with the oracle, staircase on and off."""
+against the separated stages (sc_factor, then sc_assemble); temporary-memory
+waves (the X temporary of Sec. 3.1 capped, the batch assembled wave by wave)
+against the resident X; parity of the assembly on the paper's own element
+types (P1 triangles and tetrahedra, Sec. 4) with the oracle, staircase on and
+off."""
 import numpy as np
 import pytest
 
@@ -67,6 +69,53 @@ def test_pipelined_preprocessing_equals_separate_stages(cfg, count, precision):
             assert oracle.relF(F_mix[i][np.ix_(sel, sel)], oracle.schur(s, sel=sel)) <= tol
     sep.destroy()
     mix.destroy()
+
+
+def _x_bytes(subs, precision):
+    """Bytes of the X slabs of each subdomain: per 64-column tile of the
+    sorted columns, rows [the tile's first pivot, n) x 64 columns."""
+    import numpy as np
+    out = []
+    for s in subs:
+        r = P.host_analyze(s, values=False)
+        piv = np.sort(r["piv"])
+        nt = (s.m + 63) // 64
+        out.append(sum((s.n - int(piv[64 * t])) * 64 for t in range(nt)) * (8 if precision == "fp64" else 4))
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_temporary_memory_waves_equal_resident_X(precision):
+    torch = _torch()
+    subs = scgen.config_subdomains(3, count=24)
+    xb = _x_bytes(subs, precision)
+    cap = 3 * max(xb)                     # several waves of a few subdomains
+    ref = P.Plan(subs, precision=precision)
+    ref.factor()
+    ref.assemble()
+    for graph in (False, True):
+        wav = P.Plan(subs, precision=precision, arena_cap_bytes=cap, use_graph=graph)
+        assert wav.stats()["device_bytes"] < ref.stats()["device_bytes"] - sum(xb) + 2 * cap
+        wav.factor()
+        wav.assemble()
+        wav.assemble()
+        for i in range(len(subs)):
+            assert np.array_equal(wav.get_F(i), ref.get_F(i)), (graph, i)
+        wav.destroy()
+    # pipelined preprocessing in waves
+    wav = P.Plan(subs, precision=precision, arena_cap_bytes=cap)
+    wav.preprocess()
+    for i in (0, 11, 23):
+        assert np.array_equal(wav.get_F(i), ref.get_F(i))
+    # the timed slot of a wave assembly
+    wav.set_timing(True)
+    wav.kernel_times(reset=True)
+    wav.assemble()
+    torch.cuda.synchronize()
+    kt = wav.kernel_times()
+    assert kt["assemble_overlap"][1] == 1 and kt["assemble_overlap"][0] > 0
+    wav.destroy()
+    ref.destroy()
 
 
 def test_pipelined_preprocessing_then_apply_and_assemble():

@@ -136,15 +136,16 @@ VISIT_CASES = [
 ]
 
 
+@pytest.mark.parametrize("split", ["uniform", "etree"])
 @pytest.mark.parametrize("name,make", VISIT_CASES)
-def test_trsm_visits_exactly_the_blocks_with_nonzero_rows_of_x(name, make):
+def test_trsm_visits_exactly_the_blocks_with_nonzero_rows_of_x(name, make, split):
     # X = L^{-1} P B^T solved densely: a tile must visit every block holding a
     # nonzero row of its columns (else the sweep would drop work), and with
     # random values nothing else (the reach has no cancellation)
     import scipy.linalg as sl
     s = make()
-    r = P.host_analyze(s, want_L=True)
-    row0, ptr, visit, masks = P.host_tile_visits(s, with_masks=True)
+    r = P.host_analyze(s, want_L=True, block_split=split)
+    row0, ptr, visit, masks = P.host_tile_visits(s, with_masks=True, block_split=split)
     L, piv, n, m = r["L"], r["piv"], s.n, s.m
     E = np.zeros((n, m))
     E[piv, np.arange(m)] = 1.0
@@ -183,11 +184,51 @@ def test_trsm_visits_exactly_the_blocks_with_nonzero_rows_of_x(name, make):
         assert r["trsm_visits"] < 0.6 * r["stair_visits"]
     # without the reach every block from the first pivot's on; without the
     # staircase every block
-    _, ptr2, visit2 = P.host_tile_visits(s, reach=False)
-    _, ptr3, visit3 = P.host_tile_visits(s, staircase=False)
+    _, ptr2, visit2 = P.host_tile_visits(s, reach=False, block_split=split)
+    _, ptr3, visit3 = P.host_tile_visits(s, staircase=False, block_split=split)
     for t in range(nt):
         assert np.array_equal(visit2[ptr2[t]:ptr2[t + 1]], np.arange(blk[piv[64 * t]], len(row0) - 1))
         assert np.array_equal(visit3[ptr3[t]:ptr3[t + 1]], np.arange(len(row0) - 1))
+
+
+def _block_dag_depth(L, row0):
+    """Levels of the block dependency DAG of the forward solve: block t
+    depends on block b when L[rows of t, columns of b] has a nonzero."""
+    nb = len(row0) - 1
+    blk = np.searchsorted(row0, np.arange(L.shape[0]), side="right") - 1
+    lev = np.zeros(nb, dtype=int)
+    for b in range(nb):
+        c0, c1 = row0[b], row0[b + 1]
+        rows = np.nonzero(np.abs(L[c1:, c0:c1]).max(axis=1) > 0)[0] + c1
+        for t in np.unique(blk[rows]):
+            lev[t] = max(lev[t], lev[b] + 1)
+    return int(lev.max()) + 1
+
+
+@pytest.mark.parametrize("name,make", VISIT_CASES)
+def test_etree_block_split(name, make):
+    # blocks of at most panel_width columns that never join unrelated
+    # subtrees: the block DAG of the forward solve keeps the elimination
+    # tree's parallelism (far fewer levels than the uniform ranges, whose
+    # blocks straddle subtrees and chain everything), and the factor is the
+    # same (the split does not touch the factorisation)
+    s = make()
+    for bs in (32, 64):
+        u = P.host_analyze(s, panel_width=bs, want_L=True)
+        e = P.host_analyze(s, panel_width=bs, block_split="etree", want_L=True)
+        row0, _, _ = P.host_tile_visits(s, panel_width=bs, block_split="etree")
+        row0u, _, _ = P.host_tile_visits(s, panel_width=bs)
+        w = np.diff(row0)
+        assert row0[0] == 0 and row0[-1] == s.n and np.all(w > 0) and np.all(w <= bs)
+        assert e["nblocks"] == len(w) >= u["nblocks"]
+        assert e["nnzL"] == u["nnzL"] and np.array_equal(e["perm"], u["perm"])
+        assert np.array_equal(e["L"], u["L"])
+        d_e, d_u = _block_dag_depth(e["L"], row0), _block_dag_depth(e["L"], row0u)
+        assert d_e <= d_u
+        if name == "heat12":
+            assert 3 * d_e < d_u and 4 * d_e <= len(w)
+    with pytest.raises(P.ScasmError):
+        P.host_analyze(s, block_split=2)
 
 
 def test_tile_visits_capacity_error():
@@ -290,6 +331,52 @@ def test_plan_create_validates_before_touching_the_device():
     assert lib.sc_assemble(None, None) == P.SC_ERR_INVALID_ARG
     assert lib.sc_plan_destroy(None) == P.SC_OK
     assert b"NULL" in lib.sc_last_error() or lib.sc_last_error() == b""
+
+
+def test_arena_cap_below_one_subdomain_is_oom_before_the_device():
+    # temporary-memory waves: a cap below the X slabs of one subdomain is
+    # refused with SC_ERR_OOM at plan creation, before any device call (this
+    # machine has no device); overlapped assembly cannot run in waves
+    subs = scgen.config_subdomains(3, count=2)
+    with pytest.raises(P.ScasmError) as e:
+        P.Plan(subs, arena_cap_bytes=4096)
+    assert e.value.status == P.SC_ERR_OOM and "arena_cap_bytes" in str(e.value)
+    with pytest.raises(P.ScasmError) as e:
+        P.Plan(subs, arena_cap_bytes=1 << 40, assembly="overlap")
+    assert e.value.status == P.SC_ERR_UNSUPPORTED
+    with pytest.raises(P.ScasmError) as e:
+        P.Plan(subs, arena_cap_bytes=-1)
+    assert e.value.status == P.SC_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("bad", [{"panel_width": 8}, {"block_split": 2}, {"syrk_kind": 3},
+                                 {"n_lo": 10, "n_hi": 5}])
+def test_tune_classes_are_validated_before_the_device(bad):
+    cls = {"n_lo": 0, "n_hi": 1 << 30, "panel_width": 32, "block_split": 1, "syrk_kind": 1}
+    cls.update(bad)
+    with pytest.raises(P.ScasmError) as e:
+        P.Plan(scgen.config_subdomains(1), tune_classes=[cls])
+    assert e.value.status == P.SC_ERR_INVALID_ARG and "tune class" in str(e.value)
+
+
+def test_selection_prediction_follows_its_model():
+    # per-subdomain explicit / implicit choice (select_iters): t_asm from the
+    # structural flops, t_expl from the stored F bytes, t_impl from 16 nnz(L)
+    # bytes, n* = t_asm / (t_impl - t_expl)
+    for s in (scgen.config_subdomains(2, count=1)[0], scgen.config_subdomains(3, count=1)[0]):
+        for prec, sF in (("fp64", 8), ("mixed", 4)):
+            r = P.host_analyze(s, values=False, precision=prec, select_model=(10.0, 2000.0, 500.0))
+            nst = (s.m + 127) // 128
+            assert np.isclose(r["t_asm_ms"], (r["trsm_reach"] + r["syrk_reach"]) / 10e12 * 1e3)
+            assert np.isclose(r["t_expl_ms"], nst * (nst + 1) / 2 * 128 * 128 * sF / 2000e9 * 1e3)
+            assert np.isclose(r["t_impl_ms"], 16 * r["nnzL"] / 500e9 * 1e3)
+            assert np.isclose(r["n_star"], r["t_asm_ms"] / (r["t_impl_ms"] - r["t_expl_ms"]))
+        fast = P.host_analyze(s, values=False, select_model=(10.0, 2000.0, 1e9))
+        assert fast["n_star"] == float("inf")          # the implicit apply never loses
+        d = P.host_analyze(s, values=False)            # default rates
+        assert d["t_asm_ms"] > 0 and d["t_impl_ms"] > 0
+    with pytest.raises(P.ScasmError):
+        P.host_analyze(s, values=False, select_iters=-1)
 
 
 def test_zero_multipliers_and_tiny_subdomain():
