@@ -255,6 +255,21 @@ sc_status_t sc_preprocess(sc_plan_t plan, const double* const* kreg_vals, void* 
  * and accumulated in FP64.  SC_ERR_STATE before sc_assemble. */
 sc_status_t sc_apply(sc_plan_t plan, const double* p_dev, double* q_dev, void* stream);
 
+/* Explicit apply that allocates nothing, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same result as sc_apply, bit for bit
+ * (same kernels, same summation order), with the partial sums of the stored
+ * tiles in a fixed device array of the library (32 MiB per GPU, held until
+ * the process ends) instead of the plan's buffer.  The batch runs in chunks
+ * of whole subdomains, one after the other on `stream`.  Limit: every
+ * subdomain needs m <= 23040 (its ceil(m/128)(ceil(m/128)+1)/2 stored tiles
+ * must fit the 16384 the array holds); SC_ERR_UNSUPPORTED otherwise, before
+ * anything is launched.  All calls on one GPU share its array: calls that
+ * overlap on one GPU (other streams, other threads) race and must be
+ * serialised by the caller.  Arguments and other errors as sc_apply; the call
+ * is not timed by sc_set_timing. */
+sc_status_t sc_apply_noalloc(sc_plan_t plan, const double* p_dev, double* q_dev, void* stream);
+
 /* Solution stage, implicit apply (eq. (11)): q_i = B_i P^T L^{-T} L^{-1} P B_i^T
  * p_i with two sparse triangular solves on the device, same vector layout as
  * sc_apply.  SC_ERR_STATE before sc_factor. */

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <mutex>
 
 #include "device.hpp"
 #include "kernels.hpp"
@@ -20,6 +21,9 @@ namespace scasm {
 // workgroup per 128-row block K of a subdomain, sums u of (K, J <= K) and v
 // of (I > K, K) in a fixed order and scatters the result to q in multiplier
 // order.  Deterministic; reads F once, about half of the dense m x m.
+// The partial sums of stored tile k live at part[(k - part_base) * 256]: the
+// plan-owned buffer holds every tile (part_base 0); the fixed scratch array of
+// the allocation-free apply holds one chunk of subdomains at a time.
 // ---------------------------------------------------------------------------
 template <class T>
 __device__ __forceinline__ void load8(const T* __restrict__ src, double (&t)[8]) {
@@ -45,7 +49,7 @@ __device__ __forceinline__ void load8(const T* __restrict__ src, double (&t)[8])
 template <class T>
 __global__ __launch_bounds__(256) void symv_tiles(
     const SubDev* __restrict__ subs, const SyrkItem* __restrict__ ftiles, const T* __restrict__ F,
-    const int32_t* __restrict__ pi, const double* __restrict__ p, double* __restrict__ part)
+    const int32_t* __restrict__ pi, const double* __restrict__ p, double* __restrict__ part, int64_t part_base)
 {
     __shared__ double sp[2][kSyrkTile];                 // p_s of the tile's columns (J) and rows (I)
     __shared__ double su[kSyrkTile][17];                // row sums per group of 8 columns
@@ -97,19 +101,19 @@ __global__ __launch_bounds__(256) void symv_tiles(
 #pragma unroll
         for (int g = 0; g < 16; ++g) acc += sv[k][g];
     }
-    part[((S.ftile_off + tile) << 8) + tid] = acc;
+    part[((S.ftile_off + tile - part_base) << 8) + tid] = acc;
 }
 
 __global__ __launch_bounds__(128) void symv_rows(
     const SubDev* __restrict__ subs, const int2* __restrict__ frows, const int32_t* __restrict__ pi,
-    const double* __restrict__ part, double* __restrict__ q)
+    const double* __restrict__ part, int64_t part_base, double* __restrict__ q)
 {
     const int2 it = frows[blockIdx.x];                  // (subdomain, row block K)
     const SubDev S = subs[it.x];
     const int K = it.y;
     const int r = threadIdx.x;
     const int nt = (S.m + kSyrkTile - 1) / kSyrkTile;
-    const double* __restrict__ P = part + (S.ftile_off << 8);
+    const double* __restrict__ P = part + ((S.ftile_off - part_base) << 8);
     double y = 0.0;
     for (int J = 0; J <= K; ++J) y += P[(((int64_t)K * (K + 1) / 2 + J) << 8) + r];
     for (int I = K + 1; I < nt; ++I) y += P[(((int64_t)I * (I + 1) / 2 + K) << 8) + 128 + r];
@@ -117,22 +121,72 @@ __global__ __launch_bounds__(128) void symv_rows(
     if (a < S.m) q[S.dual_off + pi[S.col_off + a]] = y;
 }
 
+// pass 1 over stored tiles [t0, t1), pass 2 over row blocks [r0, r1): the
+// tiles of whole subdomains, partial sums at part[(k - t0) * 256]
+static hipError_t apply_range(const DevTables& t, const double* p, double* q, double* part, int64_t t0, int64_t t1,
+                              int64_t r0, int64_t r1, hipStream_t stream) {
+    if (t1 <= t0) return hipSuccess;
+    if (t.F32)
+        hipLaunchKernelGGL(symv_tiles<float>, dim3((unsigned)(t1 - t0)), dim3(256), 0, stream, t.subs,
+                           t.ftiles + t0, (const float*)t.F32, t.pi, p, part, t0);
+    else
+        hipLaunchKernelGGL(symv_tiles<double>, dim3((unsigned)(t1 - t0)), dim3(256), 0, stream, t.subs,
+                           t.ftiles + t0, (const double*)t.F, t.pi, p, part, t0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(symv_rows, dim3((unsigned)(r1 - r0)), dim3(128), 0, stream, t.subs, t.frows + r0, t.pi,
+                       (const double*)part, t0, q);
+    return hipGetLastError();
+}
+
 hipError_t launch_apply(const DevTables& t, const double* p, double* q, hipStream_t stream, hipEvent_t* ev) {
     hipError_t e = hipSuccess;
     if (ev && (e = hipEventRecord(ev[0], stream)) != hipSuccess) return e;
-    if (t.nftiles > 0) {
-        if (t.F32)
-            hipLaunchKernelGGL(symv_tiles<float>, dim3((unsigned)t.nftiles), dim3(256), 0, stream, t.subs,
-                               t.ftiles, (const float*)t.F32, t.pi, p, t.part);
-        else
-            hipLaunchKernelGGL(symv_tiles<double>, dim3((unsigned)t.nftiles), dim3(256), 0, stream, t.subs,
-                               t.ftiles, (const double*)t.F, t.pi, p, t.part);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(symv_rows, dim3((unsigned)t.nfrows), dim3(128), 0, stream, t.subs, t.frows, t.pi,
-                           (const double*)t.part, q);
-    }
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = apply_range(t, p, q, t.part, 0, t.nftiles, 0, t.nfrows, stream)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], stream)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free explicit apply: the partial sums go to a fixed device array
+// (one per GPU, for the life of the process) instead of the plan's buffer;
+// the batch runs in chunks of whole subdomains whose stored tiles fit it, one
+// chunk after the other on the caller's stream.  Every call on a GPU shares
+// that GPU's array, so calls that overlap on one GPU race.  Nothing needs
+// clearing: pass 1 writes every partial sum that pass 2 of its chunk reads.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[kApplyScratchTiles * 256];
+
+namespace {
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t apply_scratch_init(int device, double** out) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;     // caller makes `device` current
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = (double*)ptr;
+    }
+    if (out) *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
+hipError_t launch_apply_chunked(const DevTables& t, const ApplyChunk* chunks, int64_t nchunks, double* scratch_ptr,
+                                const double* p, double* q, hipStream_t stream) {
+    for (int64_t c = 0; c < nchunks; ++c) {
+        const ApplyChunk& k = chunks[c];
+        if (k.t1 - k.t0 > kApplyScratchTiles) return hipErrorInvalidValue;
+        hipError_t e = apply_range(t, p, q, scratch_ptr, k.t0, k.t1, k.r0, k.r1, stream);
+        if (e != hipSuccess) return e;
+    }
     return hipSuccess;
 }
 

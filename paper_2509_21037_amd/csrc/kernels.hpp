@@ -117,4 +117,25 @@ hipError_t launch_apply_implicit(const DevTables& t, const ImplicitLevels& lv, c
 // passes over the packed sorted F; optional events ev[0] before, ev[1] after.
 hipError_t launch_apply(const DevTables& t, const double* p, double* q, hipStream_t stream, hipEvent_t* ev);
 
+// Allocation-free explicit apply.  Its partial sums live in a fixed device
+// array of kApplyScratchTiles stored tiles (256 doubles each: 32 MiB), one per
+// GPU for the life of the process.
+constexpr int64_t kApplyScratchTiles = 16384;
+// largest m whose nst (nst + 1) / 2 stored tiles (nst = ceil(m / 128)) fit
+constexpr int32_t kApplyMaxM = 180 * kSyrkTile;
+static_assert(180 * 181 / 2 <= kApplyScratchTiles && 181 * 182 / 2 > kApplyScratchTiles, "kApplyMaxM");
+constexpr int kMaxDevices = 64;
+// Whole subdomains whose stored tiles [t0, t1) fit the array; their row
+// blocks [r0, r1) (h_frows order).
+struct ApplyChunk {
+    int64_t t0, t1, r0, r1;
+};
+// Looks up (once per device, with `device` current) the device address of
+// the array; *out receives it.  Thread-safe.
+hipError_t apply_scratch_init(int device, double** out);
+// q = F p chunk by chunk on `stream`, partial sums in `scratch_ptr` (from
+// apply_scratch_init); no allocation.
+hipError_t launch_apply_chunked(const DevTables& t, const ApplyChunk* chunks, int64_t nchunks, double* scratch_ptr,
+                                const double* p, double* q, hipStream_t stream);
+
 }  // namespace scasm

@@ -176,6 +176,13 @@ struct sc_plan_s {
     DevBuf<SyrkItem> d_ftiles;
     DevBuf<int2> d_frows;
     DevBuf<double> d_part;                      // apply partial sums, 256 per stored F tile
+    // allocation-free apply: chunks of whole subdomains whose stored tiles fit
+    // the fixed scratch array, that array's device address on this plan's
+    // device, and the first subdomain too large for it (-1: none)
+    std::vector<ApplyChunk> h_chunks;
+    double* scratch = nullptr;
+    hipError_t scratch_err = hipSuccess;
+    int32_t noalloc_too_big = -1;
     DevBuf<int32_t> d_rows, d_piv, d_pi, d_visit, d_ksteps;
     DevBuf<uint64_t> d_vrows;
     DevBuf<int8_t> d_sgn;
@@ -759,9 +766,29 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
     P->X_total = xo;
     P->F_total = fo;
     P->dual_total = dual;
+    {
+        // chunks of the allocation-free apply: consecutive whole subdomains
+        ApplyChunk cur{0, 0, 0, 0};
+        for (int32_t i = 0; i < nsub; ++i) {
+            const int64_t nst = P->implicit_sub[i] ? 0 : ((int64_t)P->h_subs[i].m + kSyrkTile - 1) / kSyrkTile;
+            const int64_t nt = nst * (nst + 1) / 2;
+            if (nt > kApplyScratchTiles) {
+                if (P->noalloc_too_big < 0) P->noalloc_too_big = i;
+            } else if (cur.t1 - cur.t0 + nt > kApplyScratchTiles) {
+                P->h_chunks.push_back(cur);
+                cur = ApplyChunk{cur.t1, cur.t1, cur.r1, cur.r1};
+            }
+            cur.t1 += nt;
+            cur.r1 += nst;
+        }
+        if (cur.t1 > cur.t0) P->h_chunks.push_back(cur);
+    }
 
     hipStream_t st = (hipStream_t)stream;
     HIP_TRY(hipGetDevice(&P->device));
+    // device address of the fixed scratch array of the allocation-free apply
+    // (looked up once per device; an error is reported by that entry point)
+    P->scratch_err = apply_scratch_init(P->device, &P->scratch);
     sc_plan_s* p = P.get();
     auto cleanup_fail = [&](sc_status_t s, const std::string& m) { p->release(); return fail(s, m); };
 #define ALLOC(buf, n)                                                                        \
@@ -1062,6 +1089,30 @@ sc_status_t sc_apply(sc_plan_t P, const double* p_dev, double* q_dev, void* stre
         HIP_TRY(hipEventRecord(ev[1], st));
         P->pending.push_back({2, ev[0], ev[1]});
     }
+    return SC_OK;
+}
+
+sc_status_t sc_apply_noalloc(sc_plan_t P, const double* p_dev, double* q_dev, void* stream) {
+    g_last_error.clear();
+    if (!P) return fail(SC_ERR_INVALID_ARG, "plan is NULL");
+    if (!P->assembled) return fail(SC_ERR_STATE, "sc_apply_noalloc before sc_assemble");
+    if (P->dual_total > 0 && (!p_dev || !q_dev)) return fail(SC_ERR_INVALID_ARG, "p or q is NULL");
+    if (P->dual_total > 0 && p_dev == q_dev) return fail(SC_ERR_INVALID_ARG, "p and q must not alias");
+    if (P->n_implicit > 0)
+        return fail(SC_ERR_UNSUPPORTED, "sc_apply_noalloc: the plan applies some subdomains implicitly "
+                                        "(select_iters); use sc_apply");
+    if (P->noalloc_too_big >= 0)
+        return fail(SC_ERR_UNSUPPORTED,
+                    "sc_apply_noalloc: subdomain " + std::to_string(P->noalloc_too_big) + " has m = " +
+                        std::to_string(P->h_subs[P->noalloc_too_big].m) + "; the fixed scratch holds the partial " +
+                        "sums of " + std::to_string(kApplyScratchTiles) + " stored F tiles (m <= " +
+                        std::to_string(kApplyMaxM) + ")");
+    if (P->scratch_err != hipSuccess || !P->scratch)
+        return fail(SC_ERR_DEVICE, std::string("sc_apply_noalloc: scratch address: ") +
+                                       hipGetErrorString(P->scratch_err));
+    HIP_TRY(hipSetDevice(P->device));
+    HIP_TRY(launch_apply_chunked(P->tables(), P->h_chunks.data(), (int64_t)P->h_chunks.size(), P->scratch, p_dev,
+                                 q_dev, (hipStream_t)stream));
     return SC_OK;
 }
 

@@ -17,7 +17,7 @@ STATUS_NAMES = {0: "SC_OK", 1: "SC_ERR_INVALID_ARG", 2: "SC_ERR_NOT_SPD", 3: "SC
 
 EXPORTED = ["sc_plan_create", "sc_factor", "sc_assemble", "sc_apply", "sc_apply_implicit",
             "sc_get_F", "sc_query", "sc_plan_stats", "sc_plan_destroy", "sc_host_analyze",
-            "sc_host_tile_visits", "sc_set_timing", "sc_kernel_times", "sc_pcpg", "sc_autotune", "sc_autotune_classes", "sc_preprocess", "sc_query_selection",
+            "sc_host_tile_visits", "sc_set_timing", "sc_kernel_times", "sc_pcpg", "sc_autotune", "sc_autotune_classes", "sc_apply_noalloc", "sc_preprocess", "sc_query_selection",
             "sc_last_error"]
 
 
@@ -86,6 +86,7 @@ def load():
         lib.sc_preprocess.argtypes = [vp, ctypes.POINTER(vp), vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         lib.sc_apply.argtypes = [vp, vp, vp, vp]
         lib.sc_apply_implicit.argtypes = [vp, vp, vp, vp]
+        lib.sc_apply_noalloc.argtypes = [vp, vp, vp, vp]
         lib.sc_get_F.argtypes = [vp, i32, vp, i32, i32, vp]
         lib.sc_query.argtypes = [vp, i32, i64p, i64p, i64p, i64p, dp]
         lib.sc_plan_stats.argtypes = [vp, ctypes.POINTER(i32), i64p, dp, dp, dp, dp, dp, dp, i64p]
@@ -376,6 +377,13 @@ class Plan:
         """q = F p on device FP64 tensors of length dual_total."""
         pp, qp = self._dual(p, "p"), self._dual(q, "q")
         _check(self._lib.sc_apply(self._h, pp, qp, _stream_handle(stream)))
+        return q
+
+    def apply_noalloc(self, p, q, stream=None):
+        """q = F p like apply(), through the entry point that allocates
+        nothing (partial sums in the library's fixed per-GPU array)."""
+        pp, qp = self._dual(p, "p"), self._dual(q, "q")
+        _check(self._lib.sc_apply_noalloc(self._h, pp, qp, _stream_handle(stream)))
         return q
 
     def apply_implicit(self, p, q, stream=None):

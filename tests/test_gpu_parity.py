@@ -717,6 +717,9 @@ def test_hybrid_explicit_implicit_selection(precision):
         o = hyb.query(i)["dual_offset"]
         a, b = q_h[o:o + s.m].cpu().numpy(), q_r[o:o + s.m].cpu().numpy()
         assert np.linalg.norm(a - b) <= tol * np.linalg.norm(b), i
+    with pytest.raises(P.ScasmError) as e:
+        hyb.apply_noalloc(p, q_h)
+    assert e.value.status == P.SC_ERR_UNSUPPORTED
     d = torch.from_numpy(scgen.splitmix64_uniform(77, hyb.dual_total)).cuda()
     lam_h, lam_r = torch.zeros_like(d), torch.zeros_like(d)
     hyb.pcpg(d, lam_h, 60)
