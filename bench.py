@@ -75,6 +75,25 @@ def measured_traffic(workload, precision, kernel):
     return None if k is None else k["fetch_bytes"] + k["write_bytes"]
 
 
+def blended_peak(workload):
+    """Peak of the mixed-precision assembly weighted by its own flop split
+    (FP64 MFMA for the diagonal blocks at 78.6 TFLOP/s, FP32 MFMA for the rest
+    at 157.3): total / (f64 / peak64 + f32 / peak32), with the MFMA flops the
+    counter summary of the mixed TRSM and SYRK launches recorded, or None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}_mixed.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    ks = t.get("kernels", {})
+    f64 = sum(k.get("mfma_f64_flops", 0.0) for k in ks.values())
+    f32 = sum(k.get("mfma_f32_flops", 0.0) for k in ks.values())
+    if f64 + f32 <= 0:
+        return None
+    return {"tflops": (f64 + f32) / (f64 / PEAK_TFLOPS["fp64"] + f32 / PEAK_TFLOPS["fp32"]),
+            "fp64_share": f64 / (f64 + f32)}
+
+
 def time_assembly(torch, plan, steps, warmup, graph=False):
     """Wall-clock ms per sc_assemble over `steps` synchronised steps, and the
     mean per-kernel ms from HIP events (an extra eager pass when the plan
@@ -360,7 +379,7 @@ def main():
         # per size class: block split, block width, SYRK work items (FP64 and
         # mixed tuned separately), on samples of each class; not timed
         t0 = time.perf_counter()
-        smp = 8 if cfg == 3 else 4
+        smp = 8 if cfg == 3 else 16
         classes64 = P.autotune_classes(subs, sample=smp, reps=2, cache_path=args.tune_cache)
         classes32 = None if args.no_mixed else \
             P.autotune_classes(subs, sample=smp, reps=2, cache_path=args.tune_cache, precision="mixed")
@@ -506,7 +525,10 @@ def main():
                  "useful_gflops": useful / (ms_m * 1e-3) / 1e9, "kernel_ms": kms_m,
                  "kernel_tflops": {k: flops[k] / (kms_m[k] * 1e-3) / 1e12 for k in kms_m},
                  "frac_of_fp32_mfma_peak": useful / (ms_m * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"],
+                 "blended_peak": blended_peak(args.workload),
                  "relF_vs_fp64_gpu_max": max(rel_diff(kept["mixed"][i], kept["fp64"][i]) for i in ids)}
+        if mixed["blended_peak"]:
+            mixed["frac_of_blended_peak"] = useful / (ms_m * 1e-3) / 1e12 / mixed["blended_peak"]["tflops"]
         extra["explicit_fp32F_ms"] = apply32
         extra["explicit_fp32F_GBps"] = f_bytes64 / 2 / (apply32 * 1e-3) / 1e9
         if args.pcpg:

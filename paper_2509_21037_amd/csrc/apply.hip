@@ -562,6 +562,10 @@ hipError_t launch_implicit_init(const DevTables& t, const int64_t* xoff, double*
 hipError_t launch_implicit_sweeps(const DevTables& t, const ImplicitLevels& lv, const int64_t* xoff, double* xwork,
                                   int32_t count, hipStream_t stream) {
     if (count <= 0) return hipSuccess;
+    // every table and workspace the sweeps dereference must be in place
+    if (!xoff || !xwork || !lv.ubuf || !lv.rptr_off || !lv.rptr || !lv.rpos) return hipErrorInvalidValue;
+    if (!lv.per_subdomain && ((lv.fw_off.size() > 1 && !lv.fw_items) || (lv.bw_off.size() > 1 && !lv.bw_items)))
+        return hipErrorInvalidValue;
     hipError_t e = hipSuccess;
     if (lv.per_subdomain) {
         hipLaunchKernelGGL(implicit_sweeps, dim3((unsigned)count), dim3(kImplThreads), 0, stream, t.subs, t.blocks,
