@@ -194,6 +194,32 @@ def time_selection(torch, subs, iters, panel_width, use_graph):
     return out
 
 
+def paper_curves(torch, cap_gb=32.0, dims=(2, 3)):
+    """The paper's own workloads (Sec. 4: heat transfer on P1 triangles and
+    tetrahedra, the subdomain sizes of its figures, batches of about 8.4 M (2D)
+    / 1.1 M (3D) unknowns): FP64 assembly time per subdomain without the
+    staircase ("orig", Sec. 3.1), with the staircase alone (Sec. 3.2-3.3) and
+    with the staircase restricted to the elimination-tree reach, one plan at a
+    time, the X temporary capped at cap_gb (waves) so that every size fits."""
+    import scgen
+    out = []
+    for dim in dims:
+        for nodes in scgen.PAPER_NODES[dim]:
+            subs = scgen.paper_subdomains(dim, nodes)
+            row = {"dim": dim, "nodes_per_side": nodes, "n": subs[0].n, "m": subs[0].m, "subdomains": len(subs)}
+            for name, kw in (("orig", {"staircase": False}), ("staircase", {"reach": False}), ("reach", {})):
+                plan = P_mod().Plan(subs, arena_cap_bytes=int(cap_gb * 2 ** 30), **kw)
+                plan.factor()
+                ms, _ = time_assembly(torch, plan, 2, 1)
+                row[f"{name}_ms_per_subdomain"] = ms / len(subs)
+                plan.destroy()
+            row["speedup_staircase"] = row["orig_ms_per_subdomain"] / row["staircase_ms_per_subdomain"]
+            row["speedup_reach"] = row["orig_ms_per_subdomain"] / row["reach_ms_per_subdomain"]
+            log(f"bench: paper workload {row}")
+            out.append(row)
+    return out
+
+
 def P_mod():
     import paper_2509_21037_amd as P
     return P
@@ -336,6 +362,9 @@ def main():
     ap.add_argument("--compare-assembly", action="store_true",
                     help="also time the FP64 assembly in the other mode (overlap / separate)")
     ap.add_argument("--tune-cache", default=None, help="autotune cache file (read, and appended to)")
+    ap.add_argument("--paper-curves", action="store_true",
+                    help="also time the paper's P1 triangle / tetrahedron heat workloads at its figure sizes, "
+                         "without the staircase, with it, and with the reach (FP64, ms per subdomain)")
     ap.add_argument("--select", type=int, default=0,
                     help="also time K applications with per-subdomain explicit / implicit selection for K "
                          "iterations, against all-explicit and all-implicit (FP64)")
@@ -506,6 +535,7 @@ def main():
         extra["implicit_hbm_floor_ms"] = 2 * 8 * nnzl / (PEAK_HBM_GBS * 1e9) * 1e3
         extra["implicit_frac_of_floor"] = extra["implicit_hbm_floor_ms"] / extra["implicit_ms"]
 
+    curves = paper_curves(torch) if args.paper_curves else None
     selection = None
     if args.select:
         selection = time_selection(torch, subs, args.select, args.panel_width, use_graph)
@@ -602,6 +632,7 @@ def main():
         "pcpg": pcpg or None,
         "apply": extra,
         "selection": selection,
+        "paper_curves": curves,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

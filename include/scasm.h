@@ -138,14 +138,17 @@ typedef struct {
  *                    whose predicted amortisation point n* (sc_query_selection)
  *                    exceeds k is applied implicitly: sc_assemble skips it,
  *                    sc_apply and sc_pcpg apply it with the factor
- *                    (eq. (11)), the others with F (eq. (12)).  The
- *                    prediction: t_asm = structural flops / select_model[0]
- *                    TFLOP/s, t_expl = stored F bytes / select_model[1] GB/s,
- *                    t_impl = 16 nnz(L) / select_model[2] GB/s (two FP64
- *                    sweeps), n* = t_asm / (t_impl - t_expl) (infinite when
- *                    t_impl <= t_expl); zeros = rates measured on MI355X
- *                    (FP64 42 / mixed 70 TFLOP/s, 5800 GB/s, and the implicit
- *                    rate in kSelectImplGBps)
+ *                    (eq. (11)), the others with F (eq. (12)); the first
+ *                    such call builds the implicit schedule and workspace
+ *                    (device allocations, as sc_apply_implicit's first call
+ *                    does).  The prediction: t_asm = structural flops /
+ *                    select_model[0] TFLOP/s, t_expl = stored F bytes /
+ *                    select_model[1] GB/s, t_impl = 16 nnz(L) /
+ *                    select_model[2] GB/s (two FP64 sweeps), n* = t_asm /
+ *                    (t_impl - t_expl) (infinite when t_impl <= t_expl);
+ *                    zeros = rates measured on MI355X (assembly FP64 42 /
+ *                    mixed 70 TFLOP/s, explicit apply 5800 GB/s, implicit
+ *                    apply 1900 GB/s)
  *   arena_cap_bytes  0 (default) = X (the temporary of the assembly, Sec. 3.1)
  *                    resident for the whole batch; > 0 = temporary-memory
  *                    waves: the batch is cut into waves of subdomains whose X
