@@ -61,7 +61,8 @@ typedef enum {
  * One subdomain (paper, Sec. 3: "the input for the algorithm is B^T together
  * with the factor L", L of the fill-reduced K_reg).
  *   n              DOFs (> 0)
- *   kreg_rowptr    [n+1] int64 CSR row pointers of K_reg (both triangles)
+ *   kreg_rowptr    [n+1] int64 CSR row pointers of K_reg (both triangles, or
+ *                  the lower one with sc_options_t::lower_only_csr)
  *   kreg_col       column indices; the pattern is fixed for the plan's life
  *   m              multipliers = columns of B^T (>= 0)
  *   bt_dof         [m] DOF (original numbering) of column j's single nonzero
@@ -149,6 +150,18 @@ typedef struct {
  *                    zeros = rates measured on MI355X (assembly FP64 42 /
  *                    mixed 70 TFLOP/s, explicit apply 5800 GB/s, implicit
  *                    apply 1900 GB/s)
+ *   tune_classes, ntune_classes  settings per size class from
+ *                    sc_autotune_classes (see sc_tune_class_t), borrowed for
+ *                    the sc_plan_create call
+ *   lower_only_csr   0 (default) = kreg_rowptr / kreg_col hold both triangles
+ *                    of K_reg; 1 = only the entries on and below the diagonal
+ *                    (col <= row; SC_ERR_INVALID_ARG otherwise), and the
+ *                    value arrays of sc_factor / sc_preprocess follow that
+ *                    pattern
+ *   syrk_kind        SYRK work items for every subdomain a tune class does
+ *                    not cover: 0 (default) = by size (64 x 64 blocks up to
+ *                    16384 rows FP64 / 6144 mixed, 128 x 128 tiles above),
+ *                    1 = 64 x 64 blocks, 2 = 128 x 128 tiles
  *   arena_cap_bytes  0 (default) = X (the temporary of the assembly, Sec. 3.1)
  *                    resident for the whole batch; > 0 = temporary-memory
  *                    waves: the batch is cut into waves of subdomains whose X
@@ -175,6 +188,8 @@ typedef struct {
     int64_t arena_cap_bytes;
     const struct sc_tune_class_s* tune_classes;
     int32_t ntune_classes;
+    int32_t lower_only_csr;
+    int32_t syrk_kind;
     int32_t reserved2;
 } sc_options_t;
 

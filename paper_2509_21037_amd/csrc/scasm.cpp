@@ -48,6 +48,58 @@ SubdomainInput to_input(const sc_subdomain_desc_t& d) {
     return in;
 }
 
+// Plans one subdomain.  With lower_only the caller's CSR holds only the
+// entries on and below the diagonal (col <= row): the pattern is mirrored for
+// the ordering and the symbolic factorisation, and the map from CSR entries
+// to factor slots is folded back onto the caller's entries, so sc_factor
+// takes the caller's (lower) value arrays unchanged.
+std::string plan_subdomain(const sc_subdomain_desc_t& d, const PlanOptions& po, bool lower_only, SubPlan& sp,
+                           int& code) {
+    SubdomainInput in = to_input(d);
+    if (!lower_only) return build_plan(in, po, sp, code);
+    code = 1;
+    if (d.n <= 0 || !d.kreg_rowptr || !d.kreg_col) return "K_reg pattern missing";
+    const int32_t n = d.n;
+    if (d.kreg_rowptr[0] != 0) return "rowptr[0] must be 0";
+    std::vector<int64_t> cnt(n + 1, 0);
+    for (int32_t r = 0; r < n; ++r) {
+        if (d.kreg_rowptr[r + 1] < d.kreg_rowptr[r]) return "rowptr not monotone";
+        for (int64_t p = d.kreg_rowptr[r]; p < d.kreg_rowptr[r + 1]; ++p) {
+            const int32_t c = d.kreg_col[p];
+            if (c < 0 || c >= n) return "column index out of range";
+            if (c > r) return "lower_only_csr: entry above the diagonal in row " + std::to_string(r);
+            ++cnt[r + 1];
+            if (c != r) ++cnt[c + 1];
+        }
+    }
+    for (int32_t r = 0; r < n; ++r) cnt[r + 1] += cnt[r];
+    std::vector<int64_t> rowptr(cnt.begin(), cnt.end());
+    std::vector<int32_t> col((size_t)cnt[n]);
+    std::vector<int64_t> src((size_t)cnt[n]);
+    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+    for (int32_t r = 0; r < n; ++r)
+        for (int64_t p = d.kreg_rowptr[r]; p < d.kreg_rowptr[r + 1]; ++p) {
+            const int32_t c = d.kreg_col[p];
+            col[fill[r]] = c;
+            src[fill[r]++] = p;
+            if (c != r) {
+                col[fill[c]] = r;
+                src[fill[c]++] = p;
+            }
+        }
+    in.rowptr = rowptr.data();
+    in.col = col.data();
+    std::string err = build_plan(in, po, sp, code);
+    if (!err.empty()) return err;
+    // each caller entry has exactly one mirrored copy on the stored (lower,
+    // permuted) side; fold its slot back
+    std::vector<int64_t> kmap((size_t)d.kreg_rowptr[n], -1);
+    for (size_t e = 0; e < sp.kmap.size(); ++e)
+        if (sp.kmap[e] >= 0) kmap[(size_t)src[e]] = sp.kmap[e];
+    sp.kmap.swap(kmap);
+    return "";
+}
+
 // Fills `po` from the ABI options; returns "" or an error message.
 std::string to_plan_options(const sc_options_t& o, PlanOptions& po) {
     if (o.precision != SC_PREC_FP64 && o.precision != SC_PREC_MIXED) return "unknown precision";
@@ -63,6 +115,8 @@ std::string to_plan_options(const sc_options_t& o, PlanOptions& po) {
     if (o.block_split < 0 || o.block_split > 1) return "block_split must be 0 or 1";
     if (o.arena_cap_bytes < 0) return "arena_cap_bytes must be >= 0";
     if (o.select_iters < 0) return "select_iters must be >= 0";
+    if (o.lower_only_csr < 0 || o.lower_only_csr > 1) return "lower_only_csr must be 0 or 1";
+    if (o.syrk_kind < 0 || o.syrk_kind > 2) return "syrk_kind must be 0, 1 or 2";
     for (int k = 0; k < 3; ++k)
         if (!(o.select_model[k] >= 0.0f)) return "select_model rates must be >= 0";
     if (o.ntune_classes < 0 || (o.ntune_classes > 0 && !o.tune_classes)) return "bad tune_classes";
@@ -442,7 +496,7 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
     std::vector<int> codes(nsub, 0);
     const int nthr = P->opt.n_threads > 0 ? P->opt.n_threads : omp_get_max_threads();
     // per-subdomain settings from the autotuner's size classes
-    P->syrk_kind.assign(nsub, 0);
+    P->syrk_kind.assign(nsub, P->opt.syrk_kind);
     std::vector<PlanOptions> spo(nsub, po);
     for (int32_t i = 0; i < nsub; ++i)
         for (int32_t c = 0; c < P->opt.ntune_classes; ++c) {
@@ -457,9 +511,8 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
     P->opt.ntune_classes = 0;
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthr)
     for (int32_t i = 0; i < nsub; ++i) {
-        const SubdomainInput in = to_input(sd[i]);
         try {
-            errs[i] = build_plan(in, spo[i], P->plans[i], codes[i]);
+            errs[i] = plan_subdomain(sd[i], spo[i], P->opt.lower_only_csr != 0, P->plans[i], codes[i]);
         } catch (const std::bad_alloc&) {
             errs[i] = "host allocation failed";
             codes[i] = 3;
@@ -1524,7 +1577,7 @@ sc_status_t sc_host_analyze(const sc_subdomain_desc_t* sd, const sc_options_t* o
     SubPlan sp;
     int code = 0;
     try {
-        err = build_plan(to_input(*sd), po, sp, code);
+        err = plan_subdomain(*sd, po, o.lower_only_csr != 0, sp, code);
     } catch (const std::bad_alloc&) {
         return fail(SC_ERR_OOM, "host allocation failed");
     }
@@ -1595,7 +1648,7 @@ sc_status_t sc_host_tile_visits(const sc_subdomain_desc_t* sd, const sc_options_
     SubPlan sp;
     int code = 0;
     try {
-        err = build_plan(to_input(*sd), po, sp, code);
+        err = plan_subdomain(*sd, po, o.lower_only_csr != 0, sp, code);
     } catch (const std::bad_alloc&) {
         return fail(SC_ERR_OOM, "host allocation failed");
     }

@@ -165,6 +165,25 @@ def test_etree_block_split_matches_oracle(precision):
     uni.destroy()
 
 
+def test_lower_only_csr_and_plan_wide_syrk_kind():
+    """A plan fed the lower triangle of K_reg (lower_only_csr) assembles the
+    F of the full-pattern plan to rounding; the SYRK as 64 x 64 blocks or as
+    128 x 128 tiles for every subdomain gives the same F to rounding."""
+    from test_planner_abi import _lower_only
+    subs = scgen.config_subdomains(3, count=3) + scgen.config_subdomains(1)
+    full = _assemble(subs)
+    low = _assemble([_lower_only(s) for s in subs], lower_only_csr=True)
+    for i, s in enumerate(subs):
+        assert oracle.relF(low.get_F(i), full.get_F(i)) <= 1e-13
+    for kind in (1, 2):
+        k = _assemble(subs, syrk_kind=kind)
+        for i in range(len(subs)):
+            assert oracle.relF(k.get_F(i), full.get_F(i)) <= 1e-13, (kind, i)
+        k.destroy()
+    full.destroy()
+    low.destroy()
+
+
 def test_staircase_off_matches_on():
     subs = [scgen.config_subdomains(1)[0], scgen.box_subdomain("elasticity", (4, 3, 5), 0.25, seed=8)]
     on = _assemble(subs)

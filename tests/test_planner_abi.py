@@ -379,6 +379,65 @@ def test_selection_prediction_follows_its_model():
         P.host_analyze(s, values=False, select_iters=-1)
 
 
+def _lower_only(s):
+    """The same subdomain with only the CSR entries on and below the diagonal."""
+    import copy
+    keep = np.repeat(np.arange(s.n), np.diff(s.rowptr)) >= s.col
+    t = copy.copy(s)
+    t.col = s.col[keep]
+    t.val = s.val[keep]
+    t.rowptr = np.concatenate([[0], np.cumsum(np.add.reduceat(keep.astype(np.int64), s.rowptr[:-1])
+                                               * (np.diff(s.rowptr) > 0))]).astype(np.int64)
+    assert t.rowptr[-1] == keep.sum()
+    return t
+
+
+@pytest.mark.parametrize("make", [lambda: scgen.config_subdomains(1)[0],
+                                  lambda: scgen.box_subdomain("elasticity", (4, 3, 5), 0.25, seed=8),
+                                  lambda: scgen.paper_subdomains(3, 9, count=1)[0]])
+def test_lower_only_csr_gives_the_same_plan_and_factor(make):
+    s = make()
+    lo = _lower_only(s)
+    assert len(lo.col) < len(s.col)
+    full = P.host_analyze(s, want_L=True)
+    low = P.host_analyze(lo, want_L=True, lower_only_csr=True)
+    assert np.array_equal(full["perm"], low["perm"]) and np.array_equal(full["piv"], low["piv"])
+    assert full["nnzL"] == low["nnzL"] and full["nblocks"] == low["nblocks"]
+    # the same pattern; the values agree to rounding (a full CSR assembled
+    # in floating point is symmetric only to rounding, and the full-pattern
+    # run takes each pair's entry from the row that comes later in the order)
+    assert np.array_equal(full["L"] != 0, low["L"] != 0)
+    assert np.abs(full["L"] - low["L"]).max() <= 1e-13 * np.abs(full["L"]).max()
+    # an entry above the diagonal is refused in that mode
+    with pytest.raises(P.ScasmError) as e:
+        P.host_analyze(s, values=False, lower_only_csr=True)
+    assert e.value.status == P.SC_ERR_INVALID_ARG and "above the diagonal" in str(e.value)
+
+
+def test_options_struct_matches_the_c_header(tmp_path):
+    # ctypes layout of sc_options_t, sc_subdomain_desc_t and sc_tune_class_t
+    # against the C compiler's (sizes and field offsets)
+    import ctypes
+    from paper_2509_21037_amd.scasm import Options, SubdomainDesc, TuneClass
+    fields = {"sc_options_t": Options, "sc_subdomain_desc_t": SubdomainDesc, "sc_tune_class_t": TuneClass}
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "scasm.h"', "int main(void) {"]
+    for cname, py in fields.items():
+        src.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            src.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    src.append("return 0; }")
+    c = tmp_path / "abi.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "abi"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)])
+    got = dict(line.split() for line in subprocess.run([str(exe)], stdout=subprocess.PIPE, text=True,
+                                                       check=True).stdout.splitlines())
+    for cname, py in fields.items():
+        assert int(got[cname]) == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
+
+
 def test_zero_multipliers_and_tiny_subdomain():
     s = scgen.box_subdomain("heat", (1, 1), 1.0, seed=1)
     r = P.host_analyze(s, want_L=True)
