@@ -314,6 +314,18 @@ def test_full_large_elasticity_workload_sampled(precision):
         d = (subs[k].sign.astype(np.float64) * subs[0].sign)[sel]
         F = plan.get_F(k)[np.ix_(sel, sel)]
         assert oracle.relF(F, d[:, None] * F0 * d[None, :]) <= tol, k
+    if precision == "fp64":
+        # the implicit apply of the whole batch (its bottom levels hold
+        # thousands of blocks) against the explicit apply of the checked F
+        torch = _torch_init()
+        p, _ = _dual_vectors(plan, subs, seed=23)
+        qi, qe = torch.zeros_like(p), torch.zeros_like(p)
+        plan.apply(p, qe)
+        plan.apply_implicit(p, qi)
+        for k in range(len(subs)):
+            o = plan.query(k)["dual_offset"]
+            a, b = qi[o:o + subs[k].m], qe[o:o + subs[k].m]
+            assert float(torch.linalg.norm(a - b) / torch.linalg.norm(b)) <= 1e-12, k
     plan.destroy()
 
 
@@ -558,6 +570,27 @@ def test_implicit_apply_level_launches_on_a_forest():
     for i, s in enumerate(subs):
         o = plan.query(i)["dual_offset"]
         ref = oracle.schur(s) @ ph[o:o + s.m]
+        assert np.linalg.norm(qh[o:o + s.m] - ref) <= 1e-12 * np.linalg.norm(ref), i
+    plan.destroy()
+
+
+def test_implicit_apply_wide_levels_match_a_sparse_solve():
+    """Levels with thousands of blocks (3 x 700 independent 48 x 48
+    components, three 16-column blocks each, pruned rows below the first two)
+    in the one-launch-per-level sweeps; against B K^-1 B^T p from a sparse
+    direct solve."""
+    import scipy.sparse.linalg as spla
+    _torch_init()
+    subs = [_block_diagonal_subdomain(700, 48, 96, seed=41 + k) for k in range(3)]
+    plan = P.Plan(subs, panel_width=16, use_coords=False)
+    plan.factor()
+    p, q = _dual_vectors(plan, subs, seed=17)
+    plan.apply_implicit(p, q)
+    qh, ph = q.cpu().numpy(), p.cpu().numpy()
+    for i, s in enumerate(subs):
+        o = plan.query(i)["dual_offset"]
+        Bt = s.Bt_dense()
+        ref = Bt.T @ spla.spsolve(s.Kreg_csr().tocsc(), Bt @ ph[o:o + s.m])
         assert np.linalg.norm(qh[o:o + s.m] - ref) <= 1e-12 * np.linalg.norm(ref), i
     plan.destroy()
 
