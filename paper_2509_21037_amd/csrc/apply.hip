@@ -384,6 +384,12 @@ __global__ __launch_bounds__(256) void implicit_init(
 // dependent sums over many threads.
 constexpr int kImplThreads = 1024;
 constexpr int kImplParts = kImplThreads / 64;
+// factor tiles each wavefront has in flight in the off-diagonal products:
+// 16 where a launch has fewer workgroups than compute units (the step's
+// latency is the level's time), 8 on wide levels (two workgroups per CU
+// share the memory system)
+constexpr int kImplBatchNarrow = 16, kImplBatchWide = 8;
+constexpr int64_t kImplNarrowBelow = 256;
 
 __device__ __forceinline__ double sum_parts(const double (*sp)[64], int r) {
     double v = 0.0;
@@ -394,6 +400,7 @@ __device__ __forceinline__ double sum_parts(const double (*sp)[64], int r) {
 
 // forward step of block bd of subdomain S: x_b <- L_bb^{-1}(x_b - updates),
 // then its updates L[R_b, b] x_b into its entries of ubuf
+template <int NB>
 __device__ __forceinline__ void implicit_fwd_block(
     const SubDev& S, const BlockDev& bd, const double* __restrict__ lval, const int32_t* __restrict__ rp,
     const int32_t* __restrict__ rpos, double* __restrict__ x, double* __restrict__ ubuf,
@@ -418,8 +425,14 @@ __device__ __forceinline__ void implicit_fwd_block(
     // y_b = L_bb^{-1} x_b: k split in kImplParts ranges of 4
     const double* __restrict__ Lv = L + bd.linv_off;
     double y = 0.0;
-    if (r < w)
-        for (int k = 4 * part; k < min(4 * part + 4, r + 1); ++k) y += linv_at(Lv, r, k) * sx[k];
+    if (r < w) {
+        double a[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = 4 * part + i <= r ? linv_at(Lv, r, 4 * part + i) : 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (4 * part + i <= r) y += a[i] * sx[4 * part + i];
+    }
     sp[part][r] = y;
     __syncthreads();
     if (tid < 64) {
@@ -428,22 +441,33 @@ __device__ __forceinline__ void implicit_fwd_block(
         if (tid < w) x[bd.row0 + tid] = yb;
     }
     __syncthreads();
-    // u_b = L[R_b, b] y_b: four threads per pruned row (16 k each), adjacent lanes
+    // u_b = L[R_b, b] y_b: wavefront `part` takes row tiles part, part +
+    // kImplParts, ...; lane l the products L[16 t + l % 16, 4 s + l / 16]
+    // y[4 s + l / 16] over the k-slices s of row tile t, each wavefront load
+    // one whole 512-byte A tile, NB in flight at a time; then the four
+    // lanes of a row combine (y is zero past w, the tiles' padding is zero)
     const double* __restrict__ At = L + bd.aoff;
     const int nks = (w + 3) >> 2;
+    const int nrt = (bd.nbelow + 15) >> 4;
     double* __restrict__ u = ubuf + S.rows_off + bd.rows_off;
-    const int kq = tid & 3;
-    for (int q0 = 0; q0 < bd.nbelow; q0 += kImplThreads / 4) {
-        const int q = q0 + (tid >> 2);
-        double t = 0.0;
-        if (q < bd.nbelow)
-            for (int k = 16 * kq; k < min(16 * kq + 16, w); ++k) t += tile_at(At, nks, q, k) * sx[k];
-        t += __shfl_xor(t, 1, 64);
-        t += __shfl_xor(t, 2, 64);
-        if (q < bd.nbelow && kq == 0) u[q] = t;
+    for (int t = part; t < nrt; t += kImplParts) {
+        const double* __restrict__ Tt = At + (int64_t)t * nks * 64 + r;
+        double acc = 0.0;
+        for (int s0 = 0; s0 < nks; s0 += NB) {
+            double a[NB];
+#pragma unroll
+            for (int i = 0; i < NB; ++i) a[i] = s0 + i < nks ? Tt[(s0 + i) * 64] : 0.0;
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+                if (s0 + i < nks) acc += a[i] * sx[4 * (s0 + i) + (r >> 4)];
+        }
+        acc += __shfl_xor(acc, 16, 64);
+        acc += __shfl_xor(acc, 32, 64);
+        if (r < 16 && 16 * t + r < bd.nbelow) u[16 * t + r] = acc;
     }
 }
 
+template <int NB>
 __global__ __launch_bounds__(kImplThreads) void implicit_fwd(
     const SubDev* __restrict__ subs, const BlockDev* __restrict__ blocks, const double* __restrict__ lval,
     const int64_t* __restrict__ rptr_off, const int32_t* __restrict__ rptr, const int32_t* __restrict__ rpos,
@@ -455,10 +479,11 @@ __global__ __launch_bounds__(kImplThreads) void implicit_fwd(
     const int2 it = items[blockIdx.x];
     const SubDev S = subs[it.x];
     const BlockDev bd = blocks[S.blk_off + it.y];
-    implicit_fwd_block(S, bd, lval, rptr + rptr_off[it.x], rpos, xwork + xoff[it.x], ubuf, sp, sx);
+    implicit_fwd_block<NB>(S, bd, lval, rptr + rptr_off[it.x], rpos, xwork + xoff[it.x], ubuf, sp, sx);
 }
 
 // backward step of block bd: z_b <- L_bb^{-T}(y_b - L[R_b, b]^T z[R_b])
+template <int NB>
 __device__ __forceinline__ void implicit_bwd_block(
     const SubDev& S, const BlockDev& bd, const int32_t* __restrict__ rows, const double* __restrict__ lval,
     double* __restrict__ x, double (*sp)[64], double* sz, double* sv)
@@ -470,32 +495,60 @@ __device__ __forceinline__ void implicit_bwd_block(
     const int part = tid >> 6;
     const int w = bd.w, nb = bd.nbelow, nks = (w + 3) >> 2;
     const double* __restrict__ At = L + bd.aoff;
-    // y_b - L[R_b, b]^T z[R_b]: pruned rows in groups of kImplThreads, part p
-    // of the threads takes rows p, p + kImplParts, ... of a group
-    double v = 0.0;
+    // y_b - L[R_b, b]^T z[R_b]: pruned rows in groups of kImplThreads;
+    // wavefront `part` takes k-slice `part` (columns 4 part .. 4 part + 3),
+    // lane l the products L[16 t + l % 16, 4 part + l / 16] z[16 t + l % 16]
+    // over the row tiles t: each wavefront load is one whole 512-byte A tile,
+    // NB in flight at a time.  Rows past nb read the tiles' zero padding
+    // against zero z entries.
+    double acc = 0.0;
     for (int c0 = 0; c0 < nb; c0 += kImplThreads) {
         __syncthreads();
         sz[tid] = c0 + tid < nb ? x[rw[c0 + tid]] : 0.0;   // z of the pruned rows: final
         __syncthreads();
-        const int cn = min(kImplThreads, nb - c0);
-        if (r < w)
-            for (int qq = part; qq < cn; qq += kImplParts) v -= tile_at(At, nks, c0 + qq, r) * sz[qq];
+        if (part < nks) {
+            const int nrt = (min(kImplThreads, nb - c0) + 15) >> 4;
+            const double* __restrict__ Ts = At + ((int64_t)(c0 >> 4) * nks + part) * 64 + r;
+            for (int t0 = 0; t0 < nrt; t0 += NB) {
+                double a[NB];
+#pragma unroll
+                for (int i = 0; i < NB; ++i) a[i] = t0 + i < nrt ? Ts[(int64_t)(t0 + i) * nks * 64] : 0.0;
+#pragma unroll
+                for (int i = 0; i < NB; ++i)
+                    if (t0 + i < nrt) acc += a[i] * sz[16 * (t0 + i) + (r & 15)];
+            }
+        }
     }
-    if (part == 0 && r < w) v += x[bd.row0 + r];
-    sp[part][r] = v;
-    __syncthreads();
-    if (tid < 64) sv[tid] = tid < w ? sum_parts(sp, tid) : 0.0;
+    // column 4 part + l / 16: the sum over its 16 lanes
+    acc += __shfl_xor(acc, 1, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    acc += __shfl_xor(acc, 4, 64);
+    acc += __shfl_xor(acc, 8, 64);
+    if (part < nks && (r & 15) == 0 && 4 * part + (r >> 4) < w)
+        sv[4 * part + (r >> 4)] = x[bd.row0 + 4 * part + (r >> 4)] - acc;
     __syncthreads();
     // z_b = L_bb^{-T} v: k split in kImplParts ranges of 4
     const double* __restrict__ Lv = L + bd.linv_off;
     double z = 0.0;
-    if (r < w)
-        for (int k = max(r, 4 * part); k < min(4 * part + 4, w); ++k) z += linv_at(Lv, k, r) * sv[k];
+    if (r < w) {
+        double a[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = 4 * part + i;
+            a[i] = k >= r && k < w ? linv_at(Lv, k, r) : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = 4 * part + i;
+            if (k >= r && k < w) z += a[i] * sv[k];
+        }
+    }
     sp[part][r] = z;
     __syncthreads();
     if (tid < w) x[bd.row0 + tid] = sum_parts(sp, tid);
 }
 
+template <int NB>
 __global__ __launch_bounds__(kImplThreads) void implicit_bwd(
     const SubDev* __restrict__ subs, const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows,
     const double* __restrict__ lval, const int2* __restrict__ items, const int64_t* __restrict__ xoff,
@@ -507,7 +560,7 @@ __global__ __launch_bounds__(kImplThreads) void implicit_bwd(
     const int2 it = items[blockIdx.x];
     const SubDev S = subs[it.x];
     const BlockDev bd = blocks[S.blk_off + it.y];
-    implicit_bwd_block(S, bd, rows, lval, xwork + xoff[it.x], sp, sz, sv);
+    implicit_bwd_block<NB>(S, bd, rows, lval, xwork + xoff[it.x], sp, sz, sv);
 }
 
 // Both sweeps of one subdomain in one workgroup: its blocks in increasing
@@ -529,12 +582,12 @@ __global__ __launch_bounds__(kImplThreads) void implicit_sweeps(
     const int32_t* __restrict__ rp = rptr + rptr_off[sub];
     for (int b = 0; b < S.nblocks; ++b) {
         const BlockDev bd = blocks[S.blk_off + b];
-        implicit_fwd_block(S, bd, lval, rp, rpos, x, ubuf, sp, sx);
+        implicit_fwd_block<kImplBatchNarrow>(S, bd, lval, rp, rpos, x, ubuf, sp, sx);
         __syncthreads();
     }
     for (int b = S.nblocks - 1; b >= 0; --b) {
         const BlockDev bd = blocks[S.blk_off + b];
-        implicit_bwd_block(S, bd, rows, lval, x, sp, sz, sx);
+        implicit_bwd_block<kImplBatchNarrow>(S, bd, rows, lval, x, sp, sz, sx);
         __syncthreads();
     }
 }
@@ -575,15 +628,25 @@ hipError_t launch_implicit_sweeps(const DevTables& t, const ImplicitLevels& lv, 
     for (size_t l = 0; l + 1 < lv.fw_off.size(); ++l) {
         const int64_t cnt = lv.fw_off[l + 1] - lv.fw_off[l];
         if (cnt <= 0) continue;
-        hipLaunchKernelGGL(implicit_fwd, dim3((unsigned)cnt), dim3(kImplThreads), 0, stream, t.subs, t.blocks, t.lval,
-                           lv.rptr_off, lv.rptr, lv.rpos, lv.fw_items + lv.fw_off[l], xoff, xwork, lv.ubuf);
+        if (cnt < kImplNarrowBelow)
+            hipLaunchKernelGGL(implicit_fwd<kImplBatchNarrow>, dim3((unsigned)cnt), dim3(kImplThreads), 0, stream,
+                               t.subs, t.blocks, t.lval, lv.rptr_off, lv.rptr, lv.rpos, lv.fw_items + lv.fw_off[l],
+                               xoff, xwork, lv.ubuf);
+        else
+            hipLaunchKernelGGL(implicit_fwd<kImplBatchWide>, dim3((unsigned)cnt), dim3(kImplThreads), 0, stream,
+                               t.subs, t.blocks, t.lval, lv.rptr_off, lv.rptr, lv.rpos, lv.fw_items + lv.fw_off[l],
+                               xoff, xwork, lv.ubuf);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     for (size_t l = 0; l + 1 < lv.bw_off.size(); ++l) {
         const int64_t cnt = lv.bw_off[l + 1] - lv.bw_off[l];
         if (cnt <= 0) continue;
-        hipLaunchKernelGGL(implicit_bwd, dim3((unsigned)cnt), dim3(kImplThreads), 0, stream, t.subs, t.blocks, t.rows,
-                           t.lval, lv.bw_items + lv.bw_off[l], xoff, xwork);
+        if (cnt < kImplNarrowBelow)
+            hipLaunchKernelGGL(implicit_bwd<kImplBatchNarrow>, dim3((unsigned)cnt), dim3(kImplThreads), 0, stream,
+                               t.subs, t.blocks, t.rows, t.lval, lv.bw_items + lv.bw_off[l], xoff, xwork);
+        else
+            hipLaunchKernelGGL(implicit_bwd<kImplBatchWide>, dim3((unsigned)cnt), dim3(kImplThreads), 0, stream,
+                               t.subs, t.blocks, t.rows, t.lval, lv.bw_items + lv.bw_off[l], xoff, xwork);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
