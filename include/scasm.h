@@ -149,7 +149,7 @@ typedef struct {
  *                    (t_impl - t_expl) (infinite when t_impl <= t_expl);
  *                    zeros = rates measured on MI355X (assembly FP64 42 /
  *                    mixed 70 TFLOP/s, explicit apply 5800 GB/s, implicit
- *                    apply 1900 GB/s)
+ *                    apply 3070 GB/s)
  *   tune_classes, ntune_classes  settings per size class from
  *                    sc_autotune_classes (see sc_tune_class_t), borrowed for
  *                    the sc_plan_create call

@@ -139,7 +139,7 @@ std::string to_plan_options(const sc_options_t& o, PlanOptions& po) {
 constexpr double kSelectAsmTflops64 = 42.0;
 constexpr double kSelectAsmTflopsMixed = 70.0;
 constexpr double kSelectExplGBps = 5800.0;
-constexpr double kSelectImplGBps = 1900.0;
+constexpr double kSelectImplGBps = 3070.0;
 
 struct Prediction {
     double t_asm_ms = 0, t_expl_ms = 0, t_impl_ms = 0, n_star = 0;
