@@ -802,10 +802,15 @@ def test_hybrid_explicit_implicit_selection(precision):
     ref.destroy()
 
 
-def test_all_implicit_selection_equals_the_implicit_apply():
+@pytest.mark.parametrize("split", ["uniform", "etree"])
+def test_all_implicit_selection_equals_the_implicit_apply(split):
+    """Every subdomain selected for the implicit approach: sc_apply (the
+    schedule over the listed subdomains) equals sc_apply_implicit bit for bit;
+    with etree blocks both run level launches and the per-subdomain tail of
+    the top levels."""
     torch = _torch_init()
     subs = scgen.config_subdomains(3, count=5) + scgen.config_subdomains(1)
-    plan = _assemble(subs, select_iters=1000, select_model=(10.0, 2000.0, 1e9))
+    plan = _assemble(subs, select_iters=1000, select_model=(10.0, 2000.0, 1e9), block_split=split)
     assert all(plan.selection(i)["implicit"] for i in range(len(subs)))
     p, _ = _dual_vectors(plan, subs, seed=5)
     q1, q2 = torch.zeros_like(p), torch.zeros_like(p)
