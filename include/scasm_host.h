@@ -34,6 +34,12 @@ typedef struct {
                                           r(i) = columns of X nonzero in row i */
     double t_asm_ms, t_expl_ms, t_impl_ms, n_star;   /* the select_iters
                                           prediction (sc_options_t) */
+    int64_t merge_pairs;   /* factor block pairs whose TRSM updates below merge
+                              (0 with disable_pair_merge)                 */
+    int64_t merged_rows;   /* pruned-row updates the merging saves: over the
+                              column tiles, the second block's pruned rows
+                              for every visit of a pair's first block that
+                              the second follows                          */
 } sc_host_info_t;
 
 /*

@@ -67,6 +67,16 @@ __device__ __forceinline__ v4f mfma_f32(float a, float b, v4f c) {
 // itself in program order.
 // Mixed precision: the same with FP32 X and FP32 A tiles / MFMA for step 2;
 // step 1 stays FP64 (the block rows are widened, solved, rounded back).
+// Merged pairs: two consecutive blocks b, b + 1 of one supernode that a tile
+// visits one after the other (BlockDev::flags, set by the host) share the
+// rows below them: R_b = rows(b + 1) followed by R_{b+1}.  Block b then
+// updates only the rows of b + 1; its solved rows -X[b] wait in LDS (one 64 x
+// 16 slot per wavefront); block b + 1 updates R_{b+1} once with both:
+// X[R] -= L[R, b] X[b] + L[R, b + 1] X[b + 1], two chunk steps per row group
+// (the A tiles of b, then those of b + 1), one gather and one scatter.  The
+// sums run in the same order as two separate updates (a read-modify-write in
+// the X precision is exact), so X and F are bit for bit the same; the rows
+// below are read and written once instead of twice.
 // ---------------------------------------------------------------------------
 // a chunk: the 40 lower tiles of a 64 x 64 diagonal inverse (20 KB), or 16 KB
 // of pruned-row tiles
@@ -131,26 +141,56 @@ __device__ __forceinline__ BlockLite block_lite(const BlockDev* __restrict__ B, 
 template <class TA>
 constexpr int kPruneTiles = sizeof(TA) == 8 ? 2 : 4;
 
-// Chunk c of a block: c = 0 is the inverse of the diagonal block (its lower
-// tiles), the rest groups of kPruneTiles pruned row tiles (TA = precision of
-// the update's A tiles).  The first chunk carries the row indices of pruned chunk 0, pruned
-// chunk p those of pruned chunk p + 1: they are gathered while the chunk is
-// in use.
+// Role of a visit in a merged pair (see above): 0 = alone, 1 = first block
+// (updates only the rows of the next block), 2 = second block (its update of
+// the rows below also applies the first block's).
+__device__ __forceinline__ int visit_role(const BlockDev* __restrict__ B, const int32_t* __restrict__ V, int k,
+                                          int nv, int prev_role) {
+    if (prev_role == 1) return 2;
+    return (k + 1 < nv && B[V[k]].flags != 0 && V[k + 1] == V[k] + 1) ? 1 : 0;
+}
+
+// Rows the update of a visit covers: the rows of the next block (role 1,
+// whole 16-row tiles), else the block's pruned rows.
+__device__ __forceinline__ int update_rows(const BlockDev* __restrict__ B, const int32_t* __restrict__ V, int k,
+                                           int role, int nb) {
+    return role == 1 ? B[V[k] + 1].w : nb;
+}
+
+// Chunk c of a visit (block bd, role, `urows` rows in its update; prev = the
+// first block of the pair for role 2): c = 0 is the inverse of the diagonal
+// block (its lower tiles), the rest groups of kPruneTiles pruned row tiles
+// (TA = precision of the update's A tiles); role 2 alternates the first
+// block's A tiles of a row group (its pruned rows from the second block's
+// width on) with the second block's.  The diagonal chunk carries the row
+// indices of the first row group, the (second) chunk of row group p those of
+// group p + 1: they are gathered while the chunk is in use.
 template <class TA>
-__device__ __forceinline__ ChunkSrc chunk_src(const BlockLite& bd, int c, const double* __restrict__ L,
-                                              const TA* __restrict__ LA, const int32_t* __restrict__ R) {
+__device__ __forceinline__ ChunkSrc chunk_src(const BlockLite& bd, int prev_w, int64_t prev_aoff, int role, int urows,
+                                              int c, const double* __restrict__ L, const TA* __restrict__ LA,
+                                              const int32_t* __restrict__ R) {
     const int nks = (bd.w + 3) >> 2;
     const int nrt_d = (bd.w + 15) >> 4;
     constexpr int PT = kPruneTiles<TA>;
-    const int np = (((bd.nb + 15) >> 4) + PT - 1) / PT;
+    const int nrt = (urows + 15) >> 4;
+    const int np = (nrt + PT - 1) / PT;
     if (c == 0)
         return {reinterpret_cast<const char*>(L + bd.linv_off), (2 * (nrt_d - 1) * nrt_d + nks) * 64 * 8, np > 0,
                 R + bd.rows_off};
-    const int p = c - 1;
-    const int nt = min(PT, ((bd.nb + 15) >> 4) - PT * p);
+    const int p = role == 2 ? (c - 1) >> 1 : c - 1;
+    const int nt = min(PT, nrt - PT * p);
+    if (role == 2 && ((c - 1) & 1) == 0) {
+        const int nks1 = (prev_w + 3) >> 2;
+        return {reinterpret_cast<const char*>(LA + prev_aoff + (int64_t)((bd.w >> 4) + PT * p) * nks1 * 64),
+                nt * nks1 * 64 * (int)sizeof(TA), false, R};
+    }
     return {reinterpret_cast<const char*>(LA + bd.aoff + (int64_t)PT * p * nks * 64),
             nt * nks * 64 * (int)sizeof(TA), p + 1 < np, R + bd.rows_off + 16 * PT * min(p + 1, np - 1)};
 }
+
+// LDS slot of the first block's solved rows: 16 values per lane and wavefront.
+template <class TX>
+constexpr int kSlotBytes = 4 * 16 * 64 * (int)sizeof(TX);
 
 template <bool MIXED>
 __device__ __forceinline__ void trsm_tile(
@@ -210,22 +250,34 @@ __device__ __forceinline__ void trsm_tile(
     if (nv <= 0) return;
 
     BlockLite bd = block_lite(B, V[0]);
+    TX* __restrict__ slot = reinterpret_cast<TX*>(smem + kTrsmSmem) + wv * 16 * 64;
     // prefetch cursor over the flattened chunk stream: chunk s+2 is loaded
     // into registers at the start of step s, chunk s+1 goes to LDS at its end
     int pk = 0, pc = 0;
     BlockLite pbd = bd;
-    auto nchunks = [](const BlockLite& x) { return 1 + (((x.nb + 15) >> 4) + PT - 1) / PT; };
-    int pnch = nchunks(pbd);
+    int pprev_w = 0;
+    int64_t pprev_aoff = 0;
+    int prole = visit_role(B, V, 0, nv, 0);
+    int purows = update_rows(B, V, 0, prole, pbd.nb);
+    auto nchunks = [](int role, int urows) {
+        const int np = (((urows + 15) >> 4) + PT - 1) / PT;
+        return 1 + (role == 2 ? 2 * np : np);
+    };
+    int pnch = nchunks(prole, purows);
     auto take = [&]() {
         ChunkSrc c{reinterpret_cast<const char*>(L), 0, false, R};
         if (pk < nv) {
-            c = chunk_src(pbd, pc, L, LA, R);
+            c = chunk_src(pbd, pprev_w, pprev_aoff, prole, purows, pc, L, LA, R);
             if (++pc >= pnch) {
                 ++pk;
                 pc = 0;
                 if (pk < nv) {
+                    pprev_w = pbd.w;
+                    pprev_aoff = pbd.aoff;
                     pbd = block_lite(B, V[pk]);
-                    pnch = nchunks(pbd);
+                    prole = visit_role(B, V, pk, nv, prole);
+                    purows = update_rows(B, V, pk, prole, pbd.nb);
+                    pnch = nchunks(prole, purows);
                 }
             }
         }
@@ -264,12 +316,15 @@ __device__ __forceinline__ void trsm_tile(
         a0 = b0; a1 = b1; a2 = b2; a3 = b3; a4 = b4; ai = bi;
         sa_p = sb_p; sa_bytes = sb_bytes; sa_idx = sb_idx; sa_ip = sb_ip;
     };
+    int role = 0;
+    int nks_prev = 0;                            // k-slices of the pair's first block (role 2)
     for (int k = 0; k < nv; ++k) {
         const int b = V[k];
         const uint64_t on = VR[k] >> g;          // bit 16t + 4r: row 16t + 4r + g of the block
         const int w = bd.w;
         const int row0 = B[b].row0;
-        const int nb = bd.nb;
+        role = visit_role(B, V, k, nv, role);
+        const int nb = update_rows(B, V, k, role, bd.nb);   // rows this visit's update covers
         const int nks = (w + 3) >> 2;
         const int nrt_d = (w + 15) >> 4;
         const int nrt = (nb + 15) >> 4;
@@ -343,22 +398,67 @@ __device__ __forceinline__ void trsm_tile(
                         xb[t][r] = -v;
                     }
             }
+            // the first block of a pair keeps its solved rows for the second
+            // (zero for a wavefront that starts at the second)
+            if (role == 1) {
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) slot[(4 * t + r) * 64 + lane] = act ? xb[t][r] : TX(0);
+            }
         }
 
         // ---- 2. X[R_b] -= L[R_b, b] X[b], pruned row tiles PT p .. PT p + PT - 1
+        // (role 2: first the pair's first block's A tiles with its solved
+        // rows from LDS, then this block's, one gather and one scatter)
+        VX acc[PT];
+        int off[PT][4];
         for (int p = 0; p < np; ++p) {
+            if (role == 2) {
+                if constexpr (MIXED) step_begin();
+                if (act) {
+#pragma unroll
+                    for (int u = 0; u < PT; ++u) {
+                        acc[u] = accn[u];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) off[u][r] = offn[u][r];
+                    }
+                }
+                if constexpr (!MIXED) step_begin();
+                if (act) {
+                    const TX* __restrict__ sA = reinterpret_cast<const TX*>(smem + buf * kBufBytes);
+                    const int nt = min(PT, nrt - PT * p);
+#pragma unroll
+                    for (int u = 0; u < PT; ++u) {
+                        if (u < nt) {
+#pragma unroll
+                            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                                for (int s = 0; s < 4; ++s) {
+                                    const int ks = 4 * t + s;
+                                    if (ks < nks_prev) {
+                                        const TX xv = slot[ks * 64 + lane];
+                                        if constexpr (MIXED) acc[u] = mfma_f32(sA[(u * nks_prev + ks) * 64 + lane], xv, acc[u]);
+                                        else acc[u] = mfma_f64(sA[(u * nks_prev + ks) * 64 + lane], xv, acc[u]);
+                                    }
+                                }
+                        }
+                    }
+                }
+                step_end();
+            }
             // FP64: the next gather is issued before the next chunk's loads, so
             // that waiting for it a step later does not wait for them as well
             // (the mixed kernel has no registers left for that order)
-            VX acc[PT];
-            int off[PT][4];
             if constexpr (MIXED) step_begin();
             if (act) {
+                if (role != 2) {
 #pragma unroll
-                for (int u = 0; u < PT; ++u) {
-                    acc[u] = accn[u];
+                    for (int u = 0; u < PT; ++u) {
+                        acc[u] = accn[u];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) off[u][r] = offn[u][r];
+                        for (int r = 0; r < 4; ++r) off[u][r] = offn[u][r];
+                    }
                 }
                 if (p + 1 < np) gather(p + 1);
             }
@@ -389,6 +489,7 @@ __device__ __forceinline__ void trsm_tile(
             }
             step_end();
         }
+        nks_prev = nks;
         bd = bn;
     }
 }
@@ -399,7 +500,7 @@ __global__ __launch_bounds__(256, 2) void trsm_stair_f64(
     const uint64_t* __restrict__ vrows, const double* __restrict__ lval, const int32_t* __restrict__ piv,
     const int8_t* __restrict__ sgn, const int32_t* __restrict__ order, double* __restrict__ X)
 {
-    __shared__ __align__(16) char smem[kTrsmSmem];
+    __shared__ __align__(16) char smem[kTrsmSmem + kSlotBytes<double>];
     const int ti = order[blockIdx.x];
     if (ti < 0) return;
     trsm_tile<false>(subs, tiles, blocks, rows, visit, vrows, lval, nullptr, piv, sgn, X, ti, smem);
@@ -412,7 +513,7 @@ __global__ __launch_bounds__(256, 2) void trsm_stair_mixed(
     const int32_t* __restrict__ piv,
     const int8_t* __restrict__ sgn, const int32_t* __restrict__ order, float* __restrict__ X)
 {
-    __shared__ __align__(16) char smem[kTrsmSmem];
+    __shared__ __align__(16) char smem[kTrsmSmem + kSlotBytes<float>];
     const int ti = order[blockIdx.x];
     if (ti < 0) return;
     trsm_tile<true>(subs, tiles, blocks, rows, visit, vrows, lval, lval32, piv, sgn, X, ti, smem);

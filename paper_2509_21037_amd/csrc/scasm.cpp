@@ -117,6 +117,7 @@ std::string to_plan_options(const sc_options_t& o, PlanOptions& po) {
     if (o.select_iters < 0) return "select_iters must be >= 0";
     if (o.lower_only_csr < 0 || o.lower_only_csr > 1) return "lower_only_csr must be 0 or 1";
     if (o.syrk_kind < 0 || o.syrk_kind > 2) return "syrk_kind must be 0, 1 or 2";
+    if (o.disable_pair_merge < 0 || o.disable_pair_merge > 1) return "disable_pair_merge must be 0 or 1";
     for (int k = 0; k < 3; ++k)
         if (!(o.select_model[k] >= 0.0f)) return "select_model rates must be >= 0";
     if (o.ntune_classes < 0 || (o.ntune_classes > 0 && !o.tune_classes)) return "bad tune_classes";
@@ -557,8 +558,16 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
         s.tile_off = (int64_t)P->h_tiles.size();
         s.F_off = fo;
         s.dual_off = dual;
-        for (const BlockDesc& b : sp.blocks)
-            P->h_blocks.push_back(BlockDev{b.row0, b.w, b.nbelow, b.ld, b.lval_off, b.rows_off, b.aoff, b.linv_off});
+        {
+            // merged pairs of the TRSM's updates below (unless disabled)
+            const std::vector<int32_t> pair =
+                P->opt.disable_pair_merge ? std::vector<int32_t>(sp.blocks.size(), 0) : merge_pairs(sp);
+            for (size_t k = 0; k < sp.blocks.size(); ++k) {
+                const BlockDesc& b = sp.blocks[k];
+                P->h_blocks.push_back(
+                    BlockDev{b.row0, b.w, b.nbelow, pair[k], b.lval_off, b.rows_off, b.aoff, b.linv_off});
+            }
+        }
         for (int32_t t = 0; t < s.ntiles; ++t) {
             TileDev T{};
             T.sub = i;
@@ -1610,6 +1619,16 @@ sc_status_t sc_host_analyze(const sc_subdomain_desc_t* sd, const sc_options_t* o
         h.t_expl_ms = q.t_expl_ms;
         h.t_impl_ms = q.t_impl_ms;
         h.n_star = q.n_star;
+        if (!o.disable_pair_merge) {
+            const std::vector<int32_t> pair = merge_pairs(sp);
+            for (int32_t f : pair) h.merge_pairs += f;
+            const int32_t ntile = (sp.m + kTile - 1) / kTile;
+            for (int32_t t = 0; t < ntile; ++t)
+                for (int64_t k = sp.visit_ptr[t]; k + 1 < sp.visit_ptr[t + 1]; ++k) {
+                    const int32_t b = sp.visit[k];
+                    if (pair[b] && sp.visit[k + 1] == b + 1) h.merged_rows += sp.blocks[b + 1].nbelow;
+                }
+        }
         *info = h;
     }
     if (kreg_vals) {

@@ -54,7 +54,7 @@ class Options(ctypes.Structure):
                 ("select_model", ctypes.c_float * 3),
                 ("arena_cap_bytes", ctypes.c_int64), ("tune_classes", ctypes.POINTER(TuneClass)),
                 ("ntune_classes", ctypes.c_int32), ("lower_only_csr", ctypes.c_int32), ("syrk_kind", ctypes.c_int32),
-                ("reserved2", ctypes.c_int32)]
+                ("disable_pair_merge", ctypes.c_int32)]
 
 
 class HostInfo(ctypes.Structure):
@@ -66,7 +66,8 @@ class HostInfo(ctypes.Structure):
                 ("factor_flops", ctypes.c_double), ("trsm_visits", ctypes.c_int64),
                 ("stair_visits", ctypes.c_int64), ("trsm_reach", ctypes.c_double),
                 ("syrk_reach", ctypes.c_double), ("t_asm_ms", ctypes.c_double), ("t_expl_ms", ctypes.c_double),
-                ("t_impl_ms", ctypes.c_double), ("n_star", ctypes.c_double)]
+                ("t_impl_ms", ctypes.c_double), ("n_star", ctypes.c_double),
+                ("merge_pairs", ctypes.c_int64), ("merged_rows", ctypes.c_int64)]
 
 
 _lib = None
@@ -190,10 +191,12 @@ BLOCK_SPLIT = {"uniform": 0, "etree": 1}
 
 def _options(precision="fp64", staircase=True, panel_width=0, relax_width=0, leaf_nodes=0, n_threads=0,
              use_graph=False, assembly="default", reach=True, block_split="uniform", arena_cap_bytes=0,
-             tune_classes=None, select_iters=0, select_model=(0.0, 0.0, 0.0), lower_only_csr=False, syrk_kind=0):
+             tune_classes=None, select_iters=0, select_model=(0.0, 0.0, 0.0), lower_only_csr=False, syrk_kind=0,
+             pair_merge=True):
     opt = Options()
     opt.lower_only_csr = 1 if lower_only_csr else 0
     opt.syrk_kind = int(syrk_kind)
+    opt.disable_pair_merge = 0 if pair_merge else 1
     opt.arena_cap_bytes = int(arena_cap_bytes)
     opt.select_iters = int(select_iters)
     for k in range(3):
@@ -322,7 +325,8 @@ class Plan:
                  panel_width: int = 0, relax_width: int = 0, leaf_nodes: int = 0, n_threads: int = 0,
                  use_coords: bool = True, use_graph: bool = False, assembly: str = "default", reach: bool = True,
                  block_split: str = "uniform", arena_cap_bytes: int = 0, tune_classes=None, select_iters: int = 0,
-                 select_model=(0.0, 0.0, 0.0), lower_only_csr: bool = False, syrk_kind: int = 0, stream=None):
+                 select_model=(0.0, 0.0, 0.0), lower_only_csr: bool = False, syrk_kind: int = 0,
+                 pair_merge: bool = True, stream=None):
         lib = load()
         self._lib = lib
         self._h = ctypes.c_void_p(0)
@@ -334,7 +338,7 @@ class Plan:
             _fill_desc(descs[i], s, keep, use_coords)
         opt = _options(precision, staircase, panel_width, relax_width, leaf_nodes, n_threads, use_graph, assembly,
                        reach, block_split, arena_cap_bytes, tune_classes, select_iters, select_model,
-                       lower_only_csr, syrk_kind)
+                       lower_only_csr, syrk_kind, pair_merge)
         _check(lib.sc_plan_create(descs, len(self.subdomains), ctypes.byref(opt), _stream_handle(stream),
                                   ctypes.byref(self._h)))
         del keep

@@ -670,6 +670,46 @@ def test_reach_restricted_sweep_matches_full_staircase_sweep(precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_pair_merged_updates_match_separate_updates(precision):
+    """The TRSM's merged updates below pairs of factor blocks of one
+    supernode (the default) give F bit for bit equal to one update per block
+    (disable_pair_merge): a 20^3 elasticity pair of subdomains (42 pairs
+    each), uneven elasticity subdomains and scattered interior multipliers,
+    with uniform and etree blocks, the staircase alone, no staircase,
+    temporary-memory waves, the overlapped assembly and the pipelined
+    preprocessing."""
+    _torch_init()
+    big = scgen.config_subdomains(5, count=2)
+    assert P.host_analyze(big[0], values=False)["merge_pairs"] > 0
+    subs = scgen.config_subdomains(3, count=8)
+    s = scgen.box_subdomain("elasticity", (10, 10, 10), 0.1, seed=24)
+    dof = np.sort(np.random.default_rng(25).choice(s.n, size=333, replace=False)).astype(np.int32)
+    subs.append(s.with_columns(dof, scgen.rng.signs_from_seed(26, 333)))
+    elem = 8 if precision == "fp64" else 4
+    xmax = max(x.n * 64 * ((x.m + 63) // 64) * elem for x in subs)
+    cases = [(big, {}), (big, {"block_split": "etree"}), (subs, {}), (subs, {"block_split": "etree"}),
+             (subs, {"reach": False}), (subs, {"staircase": False}), (subs, {"arena_cap_bytes": 2 * xmax}),
+             (subs, {"assembly": "overlap"}), (subs, {"preprocess": True})]
+    for batch, kw in cases:
+        kw = dict(kw)
+        prep = kw.pop("preprocess", False)
+        plans = []
+        for merge in (True, False):
+            _torch_init()
+            plan = P.Plan(batch, precision=precision, pair_merge=merge, **kw)
+            if prep:
+                plan.preprocess()
+            else:
+                plan.factor()
+                plan.assemble()
+            plans.append(plan)
+        for i in range(len(batch)):
+            assert np.array_equal(plans[0].get_F(i), plans[1].get_F(i)), (kw, prep, i)
+        for plan in plans:
+            plan.destroy()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_scattered_interior_columns(precision):
     """Multipliers on random interior DOFs (pivots spread over the whole
     elimination tree, so the visit lists and step lists have gaps everywhere)

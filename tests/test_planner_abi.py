@@ -415,12 +415,13 @@ def test_lower_only_csr_gives_the_same_plan_and_factor(make):
 
 
 def test_options_struct_matches_the_c_header(tmp_path):
-    # ctypes layout of sc_options_t, sc_subdomain_desc_t and sc_tune_class_t
-    # against the C compiler's (sizes and field offsets)
+    # ctypes layout of sc_options_t, sc_subdomain_desc_t, sc_tune_class_t and
+    # sc_host_info_t against the C compiler's (sizes and field offsets)
     import ctypes
-    from paper_2509_21037_amd.scasm import Options, SubdomainDesc, TuneClass
-    fields = {"sc_options_t": Options, "sc_subdomain_desc_t": SubdomainDesc, "sc_tune_class_t": TuneClass}
-    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "scasm.h"', "int main(void) {"]
+    from paper_2509_21037_amd.scasm import HostInfo, Options, SubdomainDesc, TuneClass
+    fields = {"sc_options_t": Options, "sc_subdomain_desc_t": SubdomainDesc, "sc_tune_class_t": TuneClass,
+              "sc_host_info_t": HostInfo}
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "scasm_host.h"', "int main(void) {"]
     for cname, py in fields.items():
         src.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
         for f, _ in py._fields_:
@@ -436,6 +437,25 @@ def test_options_struct_matches_the_c_header(tmp_path):
         assert int(got[cname]) == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert int(got[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
+
+
+def test_merged_block_pairs_of_the_trsm():
+    """Pairs of factor blocks whose TRSM updates below merge: present where
+    supernodes span several blocks (the 20^3 elasticity subdomain, both
+    splits), none when disabled or where no supernode spans two blocks; the
+    saved updates are at most the pruned rows of the blocks the tiles visit."""
+    s = scgen.config_subdomains(5, count=1)[0]
+    for split in ("uniform", "etree"):
+        h = P.host_analyze(s, values=False, block_split=split)
+        assert h["merge_pairs"] > 10 and h["merged_rows"] > 0
+        off = P.host_analyze(s, values=False, block_split=split, pair_merge=False)
+        assert off["merge_pairs"] == 0 and off["merged_rows"] == 0
+        # every pair saves at most one update of the second block's pruned
+        # rows per column tile
+        tiles = (s.m + 63) // 64
+        assert h["merged_rows"] <= tiles * h["sum_below"]
+    tiny = scgen.config_subdomains(1)[0]
+    assert P.host_analyze(tiny, values=False)["merge_pairs"] == 0
 
 
 def test_zero_multipliers_and_tiny_subdomain():
