@@ -40,6 +40,9 @@ typedef struct {
                               column tiles, the second block's pruned rows
                               for every visit of a pair's first block that
                               the second follows                          */
+    int64_t pruned_updates;  /* pruned-row updates of the TRSM without merging:
+                              over the column tiles, the pruned rows of every
+                              visited block                                */
 } sc_host_info_t;
 
 /*

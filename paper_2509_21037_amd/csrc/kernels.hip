@@ -192,7 +192,7 @@ __device__ __forceinline__ ChunkSrc chunk_src(const BlockLite& bd, int prev_w, i
 template <class TX>
 constexpr int kSlotBytes = 4 * 16 * 64 * (int)sizeof(TX);
 
-template <bool MIXED>
+template <bool MIXED, bool MERGE>
 __device__ __forceinline__ void trsm_tile(
     const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
     const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows,
@@ -257,7 +257,7 @@ __device__ __forceinline__ void trsm_tile(
     BlockLite pbd = bd;
     int pprev_w = 0;
     int64_t pprev_aoff = 0;
-    int prole = visit_role(B, V, 0, nv, 0);
+    int prole = MERGE ? visit_role(B, V, 0, nv, 0) : 0;
     int purows = update_rows(B, V, 0, prole, pbd.nb);
     auto nchunks = [](int role, int urows) {
         const int np = (((urows + 15) >> 4) + PT - 1) / PT;
@@ -275,7 +275,7 @@ __device__ __forceinline__ void trsm_tile(
                     pprev_w = pbd.w;
                     pprev_aoff = pbd.aoff;
                     pbd = block_lite(B, V[pk]);
-                    prole = visit_role(B, V, pk, nv, prole);
+                    prole = MERGE ? visit_role(B, V, pk, nv, prole) : 0;
                     purows = update_rows(B, V, pk, prole, pbd.nb);
                     pnch = nchunks(prole, purows);
                 }
@@ -323,7 +323,7 @@ __device__ __forceinline__ void trsm_tile(
         const uint64_t on = VR[k] >> g;          // bit 16t + 4r: row 16t + 4r + g of the block
         const int w = bd.w;
         const int row0 = B[b].row0;
-        role = visit_role(B, V, k, nv, role);
+        role = MERGE ? visit_role(B, V, k, nv, role) : 0;
         const int nb = update_rows(B, V, k, role, bd.nb);   // rows this visit's update covers
         const int nks = (w + 3) >> 2;
         const int nrt_d = (w + 15) >> 4;
@@ -494,18 +494,22 @@ __device__ __forceinline__ void trsm_tile(
     }
 }
 
+// MERGE: with the merged pairs (BlockDev::flags); without, the flags are
+// ignored and the merged code paths compile away.
+template <bool MERGE>
 __global__ __launch_bounds__(256, 2) void trsm_stair_f64(
     const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
     const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows, const int32_t* __restrict__ visit,
     const uint64_t* __restrict__ vrows, const double* __restrict__ lval, const int32_t* __restrict__ piv,
     const int8_t* __restrict__ sgn, const int32_t* __restrict__ order, double* __restrict__ X)
 {
-    __shared__ __align__(16) char smem[kTrsmSmem + kSlotBytes<double>];
+    __shared__ __align__(16) char smem[kTrsmSmem + (MERGE ? kSlotBytes<double> : 0)];
     const int ti = order[blockIdx.x];
     if (ti < 0) return;
-    trsm_tile<false>(subs, tiles, blocks, rows, visit, vrows, lval, nullptr, piv, sgn, X, ti, smem);
+    trsm_tile<false, MERGE>(subs, tiles, blocks, rows, visit, vrows, lval, nullptr, piv, sgn, X, ti, smem);
 }
 
+template <bool MERGE>
 __global__ __launch_bounds__(256, 2) void trsm_stair_mixed(
     const SubDev* __restrict__ subs, const TileDev* __restrict__ tiles,
     const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows, const int32_t* __restrict__ visit,
@@ -513,12 +517,11 @@ __global__ __launch_bounds__(256, 2) void trsm_stair_mixed(
     const int32_t* __restrict__ piv,
     const int8_t* __restrict__ sgn, const int32_t* __restrict__ order, float* __restrict__ X)
 {
-    __shared__ __align__(16) char smem[kTrsmSmem + kSlotBytes<float>];
+    __shared__ __align__(16) char smem[kTrsmSmem + (MERGE ? kSlotBytes<float> : 0)];
     const int ti = order[blockIdx.x];
     if (ti < 0) return;
-    trsm_tile<true>(subs, tiles, blocks, rows, visit, vrows, lval, lval32, piv, sgn, X, ti, smem);
+    trsm_tile<true, MERGE>(subs, tiles, blocks, rows, visit, vrows, lval, lval32, piv, sgn, X, ti, smem);
 }
-
 
 // ---------------------------------------------------------------------------
 // Staircase SYRK, F = X^T X (Sec. 3.3, output splitting): one workgroup per
@@ -947,12 +950,21 @@ __global__ __launch_bounds__(256) void syrk_tile_f32(
 // ---------------------------------------------------------------------------
 hipError_t launch_trsm(const DevTables& t, const int32_t* order, int64_t count, hipStream_t stream) {
     if (count <= 0) return hipSuccess;
-    if (t.X32)
-        hipLaunchKernelGGL(trsm_stair_mixed, dim3((unsigned)count), dim3(256), 0, stream, t.subs, t.tiles,
-                           t.blocks, t.rows, t.visit, t.vrows, t.lval, t.lval32, t.piv, t.sgn, order, t.X32);
-    else
-        hipLaunchKernelGGL(trsm_stair_f64, dim3((unsigned)count), dim3(256), 0, stream, t.subs, t.tiles,
-                           t.blocks, t.rows, t.visit, t.vrows, t.lval, t.piv, t.sgn, order, t.X);
+    if (t.X32) {
+        if (t.trsm_merge)
+            hipLaunchKernelGGL(trsm_stair_mixed<true>, dim3((unsigned)count), dim3(256), 0, stream, t.subs, t.tiles,
+                               t.blocks, t.rows, t.visit, t.vrows, t.lval, t.lval32, t.piv, t.sgn, order, t.X32);
+        else
+            hipLaunchKernelGGL(trsm_stair_mixed<false>, dim3((unsigned)count), dim3(256), 0, stream, t.subs, t.tiles,
+                               t.blocks, t.rows, t.visit, t.vrows, t.lval, t.lval32, t.piv, t.sgn, order, t.X32);
+    } else {
+        if (t.trsm_merge)
+            hipLaunchKernelGGL(trsm_stair_f64<true>, dim3((unsigned)count), dim3(256), 0, stream, t.subs, t.tiles,
+                               t.blocks, t.rows, t.visit, t.vrows, t.lval, t.piv, t.sgn, order, t.X);
+        else
+            hipLaunchKernelGGL(trsm_stair_f64<false>, dim3((unsigned)count), dim3(256), 0, stream, t.subs, t.tiles,
+                               t.blocks, t.rows, t.visit, t.vrows, t.lval, t.piv, t.sgn, order, t.X);
+    }
     return hipGetLastError();
 }
 

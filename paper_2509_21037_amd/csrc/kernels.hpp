@@ -34,6 +34,7 @@ struct DevTables {
     const int2* frows = nullptr;           // (subdomain, 128-row block): symmetric apply pass 2
     double* part = nullptr;                // 256 partial sums per stored F tile
     int64_t ntiles = 0;          // TRSM workgroups (length of tile_order)
+    bool trsm_merge = false;     // TRSM with the merged pairs of BlockDev::flags
     int64_t nsyrk = 0;           // SYRK workgroups (items with sub < 0 are idle)
     int64_t nsyrk_tile = 0;      // the first nsyrk_tile of them are 128 x 128 tiles, the rest 64 x 64 blocks
     int64_t nftiles = 0;

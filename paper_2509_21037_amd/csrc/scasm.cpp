@@ -142,6 +142,12 @@ constexpr double kSelectAsmTflopsMixed = 70.0;
 constexpr double kSelectExplGBps = 5800.0;
 constexpr double kSelectImplGBps = 3070.0;
 
+// Share of a batch's TRSM pruned-row updates the merged pairs must save for
+// the merge-capable TRSM kernel to be launched (the 12^3 heat batch saves 5%
+// and ran 2% slower with it, the uneven elasticity batch 4% faster, the 20^3
+// batch, 36% saved, 12% faster).
+constexpr double kMergeMinShare = 0.10;
+
 struct Prediction {
     double t_asm_ms = 0, t_expl_ms = 0, t_impl_ms = 0, n_star = 0;
 };
@@ -262,6 +268,10 @@ struct sc_plan_s {
     // the groups are then waves that reuse one X buffer one after the other
     int64_t arena_elems = 0;
     std::vector<int32_t> syrk_kind;             // per subdomain: 0 by size, 1 blocks, 2 tiles
+    // the TRSM kernel with the merged pairs: when they save at least
+    // kMergeMinShare of the batch's pruned-row updates (below that, the
+    // merge-capable kernel's extra scalar state costs more than it saves)
+    bool trsm_merge = false;
     // select_iters: per subdomain applied with the factor (not assembled),
     // and the prediction behind the choice
     std::vector<uint8_t> implicit_sub;
@@ -415,6 +425,7 @@ struct sc_plan_s {
         t.frows = d_frows.p;
         t.part = d_part.p;
         t.tile_order = d_tile_order.p;
+        t.trsm_merge = trsm_merge;
         t.ntiles = (int64_t)h_tile_order.size();
         t.nsyrk = (int64_t)h_syrk.size();
         t.nsyrk_tile = nsyrk_tile;
@@ -534,6 +545,7 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
     std::vector<std::vector<SyrkItem>> sub_tiles(nsub), sub_blocks(nsub);
     std::vector<int64_t> x_elems(nsub, 0);      // X slab elements of each subdomain
     int64_t blk = 0, rows = 0, lv = 0, colo = 0, xo = 0, fo = 0, dual = 0;
+    int64_t upd_rows = 0, merged_rows = 0;      // TRSM pruned-row updates, and those the merged pairs save
     P->implicit_sub.assign(nsub, 0);
     P->pred.resize(nsub);
     for (int32_t i = 0; i < nsub; ++i) {
@@ -559,7 +571,8 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
         s.F_off = fo;
         s.dual_off = dual;
         {
-            // merged pairs of the TRSM's updates below (unless disabled)
+            // merged pairs of the TRSM's updates below (unless disabled), and
+            // the pruned-row updates of the tiles' visits they save
             const std::vector<int32_t> pair =
                 P->opt.disable_pair_merge ? std::vector<int32_t>(sp.blocks.size(), 0) : merge_pairs(sp);
             for (size_t k = 0; k < sp.blocks.size(); ++k) {
@@ -567,6 +580,14 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
                 P->h_blocks.push_back(
                     BlockDev{b.row0, b.w, b.nbelow, pair[k], b.lval_off, b.rows_off, b.aoff, b.linv_off});
             }
+            if (!impl)
+                for (int32_t t = 0; t + 1 < (int32_t)sp.visit_ptr.size(); ++t)
+                    for (int64_t k = sp.visit_ptr[t]; k < sp.visit_ptr[t + 1]; ++k) {
+                        const int32_t b = sp.visit[k];
+                        upd_rows += sp.blocks[b].nbelow;
+                        if (pair[b] && k + 1 < sp.visit_ptr[t + 1] && sp.visit[k + 1] == b + 1)
+                            merged_rows += sp.blocks[b + 1].nbelow;
+                    }
         }
         for (int32_t t = 0; t < s.ntiles; ++t) {
             TileDev T{};
@@ -822,6 +843,7 @@ sc_status_t sc_plan_create(const sc_subdomain_desc_t* sd, int32_t nsub, const sc
         syrk_list(xsub, P->h_syrk, P->nsyrk_tile, nb);
     }
     P->nval_total = lv;
+    P->trsm_merge = merged_rows > 0 && (double)merged_rows >= kMergeMinShare * (double)upd_rows;
     rows += 64;                            // the TRSM reads whole 64-entry groups of a row list
     P->nrows_total = rows;
     P->ncol_total = colo;
@@ -1619,6 +1641,7 @@ sc_status_t sc_host_analyze(const sc_subdomain_desc_t* sd, const sc_options_t* o
         h.t_expl_ms = q.t_expl_ms;
         h.t_impl_ms = q.t_impl_ms;
         h.n_star = q.n_star;
+        for (int64_t k = 0; k < (int64_t)sp.visit.size(); ++k) h.pruned_updates += sp.blocks[sp.visit[k]].nbelow;
         if (!o.disable_pair_merge) {
             const std::vector<int32_t> pair = merge_pairs(sp);
             for (int32_t f : pair) h.merge_pairs += f;

@@ -67,7 +67,8 @@ class HostInfo(ctypes.Structure):
                 ("stair_visits", ctypes.c_int64), ("trsm_reach", ctypes.c_double),
                 ("syrk_reach", ctypes.c_double), ("t_asm_ms", ctypes.c_double), ("t_expl_ms", ctypes.c_double),
                 ("t_impl_ms", ctypes.c_double), ("n_star", ctypes.c_double),
-                ("merge_pairs", ctypes.c_int64), ("merged_rows", ctypes.c_int64)]
+                ("merge_pairs", ctypes.c_int64), ("merged_rows", ctypes.c_int64),
+                ("pruned_updates", ctypes.c_int64)]
 
 
 _lib = None

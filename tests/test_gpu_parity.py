@@ -685,6 +685,11 @@ def test_pair_merged_updates_match_separate_updates(precision):
     s = scgen.box_subdomain("elasticity", (10, 10, 10), 0.1, seed=24)
     dof = np.sort(np.random.default_rng(25).choice(s.n, size=333, replace=False)).astype(np.int32)
     subs.append(s.with_columns(dof, scgen.rng.signs_from_seed(26, 333)))
+    # both batches save more than the 10% of their pruned-row updates above
+    # which the plan launches the merge-capable TRSM kernel
+    for batch in (big, subs):
+        st = [P.host_analyze(x, values=False) for x in batch]
+        assert sum(h["merged_rows"] for h in st) >= 0.1 * sum(h["pruned_updates"] for h in st)
     elem = 8 if precision == "fp64" else 4
     xmax = max(x.n * 64 * ((x.m + 63) // 64) * elem for x in subs)
     cases = [(big, {}), (big, {"block_split": "etree"}), (subs, {}), (subs, {"block_split": "etree"}),
