@@ -355,7 +355,11 @@ __device__ __forceinline__ double linv_at(const double* __restrict__ Lv, int r, 
     return Lv[(2 * rt * (rt + 1) + (k >> 2)) * 64 + (r & 15) + 16 * (k & 3)];
 }
 
-__global__ __launch_bounds__(256) void implicit_init(
+// one 1024-thread workgroup per subdomain (x has n_i entries: ~30k on the
+// 20^3 subdomains)
+constexpr int kInitThreads = 1024;
+
+__global__ __launch_bounds__(kInitThreads) void implicit_init(
     const SubDev* __restrict__ subs, const int32_t* __restrict__ piv, const int32_t* __restrict__ pi,
     const int8_t* __restrict__ sgn, const int64_t* __restrict__ xoff, const double* __restrict__ p,
     double* __restrict__ xwork, const int32_t* __restrict__ sub_list)
@@ -367,9 +371,9 @@ __global__ __launch_bounds__(256) void implicit_init(
     const int32_t* __restrict__ pis = pi + S.col_off;
     const int8_t* __restrict__ sg = sgn + S.col_off;
     const double* __restrict__ ps = p + S.dual_off;
-    for (int i = threadIdx.x; i < S.n; i += 256) x[i] = 0.0;
+    for (int i = threadIdx.x; i < S.n; i += kInitThreads) x[i] = 0.0;
     __syncthreads();
-    for (int a = threadIdx.x; a < S.m; a += 256) {
+    for (int a = threadIdx.x; a < S.m; a += kInitThreads) {
         if (a > 0 && pv[a - 1] == pv[a]) continue;
         double v = 0.0;
         for (int b = a; b < S.m && pv[b] == pv[a]; ++b) v += (double)sg[b] * ps[pis[b]];
@@ -390,6 +394,7 @@ constexpr int kImplParts = kImplThreads / 64;
 // share the memory system)
 constexpr int kImplBatchNarrow = 16, kImplBatchWide = 8;
 constexpr int64_t kImplNarrowBelow = 256;
+constexpr int kImplSplit = 4;
 
 __device__ __forceinline__ double sum_parts(const double (*sp)[64], int r) {
     double v = 0.0;
@@ -403,8 +408,8 @@ __device__ __forceinline__ double sum_parts(const double (*sp)[64], int r) {
 template <int NB>
 __device__ __forceinline__ void implicit_fwd_block(
     const SubDev& S, const BlockDev& bd, const double* __restrict__ lval, const int32_t* __restrict__ rp,
-    const int32_t* __restrict__ rpos, double* __restrict__ x, double* __restrict__ ubuf,
-    double (*sp)[64], double* sx)
+    const int32_t* __restrict__ rpos, const double* __restrict__ x, double* __restrict__ yo,
+    double* __restrict__ ubuf, double (*sp)[64], double* sx, int g = 0, int G = 1)
 {
     const double* __restrict__ L = lval + S.lval_off;
     const int tid = threadIdx.x;
@@ -438,7 +443,7 @@ __device__ __forceinline__ void implicit_fwd_block(
     if (tid < 64) {
         const double yb = sum_parts(sp, tid);
         sx[tid] = tid < w ? yb : 0.0;
-        if (tid < w) x[bd.row0 + tid] = yb;
+        if (g == 0 && tid < w) yo[bd.row0 + tid] = yb;   // one writer of the G copies
     }
     __syncthreads();
     // u_b = L[R_b, b] y_b: wavefront `part` takes row tiles part, part +
@@ -450,7 +455,7 @@ __device__ __forceinline__ void implicit_fwd_block(
     const int nks = (w + 3) >> 2;
     const int nrt = (bd.nbelow + 15) >> 4;
     double* __restrict__ u = ubuf + S.rows_off + bd.rows_off;
-    for (int t = part; t < nrt; t += kImplParts) {
+    for (int t = part + kImplParts * g; t < nrt; t += kImplParts * G) {
         const double* __restrict__ Tt = At + (int64_t)t * nks * 64 + r;
         double acc = 0.0;
         for (int s0 = 0; s0 < nks; s0 += NB) {
@@ -472,21 +477,22 @@ __global__ __launch_bounds__(kImplThreads) void implicit_fwd(
     const SubDev* __restrict__ subs, const BlockDev* __restrict__ blocks, const double* __restrict__ lval,
     const int64_t* __restrict__ rptr_off, const int32_t* __restrict__ rptr, const int32_t* __restrict__ rpos,
     const int2* __restrict__ items, const int64_t* __restrict__ xoff, double* __restrict__ xwork,
-    double* __restrict__ ubuf)
+    double* __restrict__ ywork, double* __restrict__ ubuf, int G)
 {
     __shared__ double sp[kImplParts][64];
     __shared__ double sx[64];
-    const int2 it = items[blockIdx.x];
+    const int2 it = items[blockIdx.x / G];
     const SubDev S = subs[it.x];
     const BlockDev bd = blocks[S.blk_off + it.y];
-    implicit_fwd_block<NB>(S, bd, lval, rptr + rptr_off[it.x], rpos, xwork + xoff[it.x], ubuf, sp, sx);
+    implicit_fwd_block<NB>(S, bd, lval, rptr + rptr_off[it.x], rpos, xwork + xoff[it.x], ywork + xoff[it.x], ubuf,
+                           sp, sx, (int)(blockIdx.x % G), G);
 }
 
 // backward step of block bd: z_b <- L_bb^{-T}(y_b - L[R_b, b]^T z[R_b])
 template <int NB>
 __device__ __forceinline__ void implicit_bwd_block(
     const SubDev& S, const BlockDev& bd, const int32_t* __restrict__ rows, const double* __restrict__ lval,
-    double* __restrict__ x, double (*sp)[64], double* sz, double* sv)
+    const double* __restrict__ yi, double* __restrict__ x, double (*sp)[64], double* sz, double* sv)
 {
     const double* __restrict__ L = lval + S.lval_off;
     const int32_t* __restrict__ rw = rows + S.rows_off + bd.rows_off;
@@ -525,7 +531,7 @@ __device__ __forceinline__ void implicit_bwd_block(
     acc += __shfl_xor(acc, 4, 64);
     acc += __shfl_xor(acc, 8, 64);
     if (part < nks && (r & 15) == 0 && 4 * part + (r >> 4) < w)
-        sv[4 * part + (r >> 4)] = x[bd.row0 + 4 * part + (r >> 4)] - acc;
+        sv[4 * part + (r >> 4)] = yi[bd.row0 + 4 * part + (r >> 4)] - acc;
     __syncthreads();
     // z_b = L_bb^{-T} v: k split in kImplParts ranges of 4
     const double* __restrict__ Lv = L + bd.linv_off;
@@ -552,7 +558,7 @@ template <int NB>
 __global__ __launch_bounds__(kImplThreads) void implicit_bwd(
     const SubDev* __restrict__ subs, const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows,
     const double* __restrict__ lval, const int2* __restrict__ items, const int64_t* __restrict__ xoff,
-    double* __restrict__ xwork)
+    const double* __restrict__ ywork, double* __restrict__ xwork)
 {
     __shared__ double sp[kImplParts][64];
     __shared__ double sz[kImplThreads];
@@ -560,7 +566,7 @@ __global__ __launch_bounds__(kImplThreads) void implicit_bwd(
     const int2 it = items[blockIdx.x];
     const SubDev S = subs[it.x];
     const BlockDev bd = blocks[S.blk_off + it.y];
-    implicit_bwd_block<NB>(S, bd, rows, lval, xwork + xoff[it.x], sp, sz, sv);
+    implicit_bwd_block<NB>(S, bd, rows, lval, ywork + xoff[it.x], xwork + xoff[it.x], sp, sz, sv);
 }
 
 // Both sweeps of one subdomain in one workgroup: its blocks in increasing
@@ -571,7 +577,7 @@ __global__ __launch_bounds__(kImplThreads) void implicit_sweeps(
     const SubDev* __restrict__ subs, const BlockDev* __restrict__ blocks, const int32_t* __restrict__ rows,
     const double* __restrict__ lval, const int64_t* __restrict__ rptr_off, const int32_t* __restrict__ rptr,
     const int32_t* __restrict__ rpos, const int64_t* __restrict__ xoff, double* __restrict__ xwork,
-    double* __restrict__ ubuf, const int32_t* __restrict__ sub_list)
+    double* __restrict__ ywork, double* __restrict__ ubuf, const int32_t* __restrict__ sub_list)
 {
     __shared__ double sp[kImplParts][64];
     __shared__ double sx[64];
@@ -579,20 +585,21 @@ __global__ __launch_bounds__(kImplThreads) void implicit_sweeps(
     const int sub = sub_list ? sub_list[blockIdx.x] : (int)blockIdx.x;
     const SubDev S = subs[sub];
     double* __restrict__ x = xwork + xoff[sub];
+    double* __restrict__ y = ywork + xoff[sub];
     const int32_t* __restrict__ rp = rptr + rptr_off[sub];
     for (int b = 0; b < S.nblocks; ++b) {
         const BlockDev bd = blocks[S.blk_off + b];
-        implicit_fwd_block<kImplBatchNarrow>(S, bd, lval, rp, rpos, x, ubuf, sp, sx);
+        implicit_fwd_block<kImplBatchNarrow>(S, bd, lval, rp, rpos, x, y, ubuf, sp, sx);
         __syncthreads();
     }
     for (int b = S.nblocks - 1; b >= 0; --b) {
         const BlockDev bd = blocks[S.blk_off + b];
-        implicit_bwd_block<kImplBatchNarrow>(S, bd, rows, lval, x, sp, sz, sx);
+        implicit_bwd_block<kImplBatchNarrow>(S, bd, rows, lval, y, x, sp, sz, sx);
         __syncthreads();
     }
 }
 
-__global__ __launch_bounds__(256) void implicit_gather(
+__global__ __launch_bounds__(kInitThreads) void implicit_gather(
     const SubDev* __restrict__ subs, const int32_t* __restrict__ piv, const int32_t* __restrict__ pi,
     const int8_t* __restrict__ sgn, const int64_t* __restrict__ xoff, const double* __restrict__ xwork,
     double* __restrict__ q, const int32_t* __restrict__ sub_list)
@@ -600,15 +607,15 @@ __global__ __launch_bounds__(256) void implicit_gather(
     const int sub = sub_list ? sub_list[blockIdx.x] : (int)blockIdx.x;
     const SubDev S = subs[sub];
     const double* __restrict__ x = xwork + xoff[sub];
-    for (int a = threadIdx.x; a < S.m; a += 256)
+    for (int a = threadIdx.x; a < S.m; a += kInitThreads)
         q[S.dual_off + pi[S.col_off + a]] = (double)sgn[S.col_off + a] * x[piv[S.col_off + a]];
 }
 
 hipError_t launch_implicit_init(const DevTables& t, const int64_t* xoff, double* xwork, const double* p,
                                 const int32_t* sub_list, int32_t count, hipStream_t stream) {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(implicit_init, dim3((unsigned)count), dim3(256), 0, stream, t.subs, t.piv, t.pi, t.sgn, xoff, p,
-                       xwork, sub_list);
+    hipLaunchKernelGGL(implicit_init, dim3((unsigned)count), dim3(kInitThreads), 0, stream, t.subs, t.piv, t.pi, t.sgn,
+                       xoff, p, xwork, sub_list);
     return hipGetLastError();
 }
 
@@ -616,26 +623,29 @@ hipError_t launch_implicit_sweeps(const DevTables& t, const ImplicitLevels& lv, 
                                   int32_t count, hipStream_t stream) {
     if (count <= 0) return hipSuccess;
     // every table and workspace the sweeps dereference must be in place
-    if (!xoff || !xwork || !lv.ubuf || !lv.rptr_off || !lv.rptr || !lv.rpos) return hipErrorInvalidValue;
+    if (!xoff || !xwork || !lv.ywork || !lv.ubuf || !lv.rptr_off || !lv.rptr || !lv.rpos) return hipErrorInvalidValue;
     if (!lv.per_subdomain && ((lv.fw_off.size() > 1 && !lv.fw_items) || (lv.bw_off.size() > 1 && !lv.bw_items)))
         return hipErrorInvalidValue;
     hipError_t e = hipSuccess;
     if (lv.per_subdomain) {
         hipLaunchKernelGGL(implicit_sweeps, dim3((unsigned)count), dim3(kImplThreads), 0, stream, t.subs, t.blocks,
-                           t.rows, t.lval, lv.rptr_off, lv.rptr, lv.rpos, xoff, xwork, lv.ubuf, lv.subs);
+                           t.rows, t.lval, lv.rptr_off, lv.rptr, lv.rpos, xoff, xwork, lv.ywork, lv.ubuf, lv.subs);
         return hipGetLastError();
     }
     for (size_t l = 0; l + 1 < lv.fw_off.size(); ++l) {
         const int64_t cnt = lv.fw_off[l + 1] - lv.fw_off[l];
         if (cnt <= 0) continue;
+        // narrow levels: kImplSplit workgroups per block, each repeating the
+        // update sums and the diagonal product and taking every kImplSplit-th
+        // group of row tiles of the product below
         if (cnt < kImplNarrowBelow)
-            hipLaunchKernelGGL(implicit_fwd<kImplBatchNarrow>, dim3((unsigned)cnt), dim3(kImplThreads), 0, stream,
-                               t.subs, t.blocks, t.lval, lv.rptr_off, lv.rptr, lv.rpos, lv.fw_items + lv.fw_off[l],
-                               xoff, xwork, lv.ubuf);
+            hipLaunchKernelGGL(implicit_fwd<kImplBatchNarrow>, dim3((unsigned)(cnt * kImplSplit)), dim3(kImplThreads),
+                               0, stream, t.subs, t.blocks, t.lval, lv.rptr_off, lv.rptr, lv.rpos,
+                               lv.fw_items + lv.fw_off[l], xoff, xwork, lv.ywork, lv.ubuf, kImplSplit);
         else
             hipLaunchKernelGGL(implicit_fwd<kImplBatchWide>, dim3((unsigned)cnt), dim3(kImplThreads), 0, stream,
                                t.subs, t.blocks, t.lval, lv.rptr_off, lv.rptr, lv.rpos, lv.fw_items + lv.fw_off[l],
-                               xoff, xwork, lv.ubuf);
+                               xoff, xwork, lv.ywork, lv.ubuf, 1);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     for (size_t l = 0; l + 1 < lv.bw_off.size(); ++l) {
@@ -643,10 +653,12 @@ hipError_t launch_implicit_sweeps(const DevTables& t, const ImplicitLevels& lv, 
         if (cnt <= 0) continue;
         if (cnt < kImplNarrowBelow)
             hipLaunchKernelGGL(implicit_bwd<kImplBatchNarrow>, dim3((unsigned)cnt), dim3(kImplThreads), 0, stream,
-                               t.subs, t.blocks, t.rows, t.lval, lv.bw_items + lv.bw_off[l], xoff, xwork);
+                               t.subs, t.blocks, t.rows, t.lval, lv.bw_items + lv.bw_off[l], xoff, lv.ywork,
+                               xwork);
         else
             hipLaunchKernelGGL(implicit_bwd<kImplBatchWide>, dim3((unsigned)cnt), dim3(kImplThreads), 0, stream,
-                               t.subs, t.blocks, t.rows, t.lval, lv.bw_items + lv.bw_off[l], xoff, xwork);
+                               t.subs, t.blocks, t.rows, t.lval, lv.bw_items + lv.bw_off[l], xoff, lv.ywork,
+                               xwork);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
@@ -655,8 +667,8 @@ hipError_t launch_implicit_sweeps(const DevTables& t, const ImplicitLevels& lv, 
 hipError_t launch_implicit_gather(const DevTables& t, const int64_t* xoff, const double* xwork, double* q,
                                   const int32_t* sub_list, int32_t count, hipStream_t stream) {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(implicit_gather, dim3((unsigned)count), dim3(256), 0, stream, t.subs, t.piv, t.pi, t.sgn, xoff,
-                       xwork, q, sub_list);
+    hipLaunchKernelGGL(implicit_gather, dim3((unsigned)count), dim3(kInitThreads), 0, stream, t.subs, t.piv, t.pi,
+                       t.sgn, xoff, xwork, q, sub_list);
     return hipGetLastError();
 }
 

@@ -90,6 +90,10 @@ struct ImplicitLevels {
     const int32_t* rptr = nullptr;
     const int32_t* rpos = nullptr;
     double* ubuf = nullptr;
+    // y = L^{-1} x of the forward sweep (n_i doubles per subdomain at the
+    // xwork offsets): kept apart from x so that several workgroups of one
+    // forward block step read x while one of them writes y
+    double* ywork = nullptr;
     std::vector<int64_t> fw_off, bw_off;
     // true: one workgroup per subdomain runs both sweeps block by block (the
     // block DAGs are near chains); false: one launch per level

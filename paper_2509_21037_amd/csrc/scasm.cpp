@@ -249,7 +249,7 @@ struct sc_plan_s {
     DevBuf<int8_t> d_sgn;
     DevBuf<double> d_lval, d_X, d_F;
     DevBuf<float> d_lval32, d_X32, d_F32;
-    DevBuf<double> d_xwork;                   // implicit apply: n_i doubles per subdomain
+    DevBuf<double> d_xwork, d_ywork;          // implicit apply: n_i doubles per subdomain each
     DevBuf<int64_t> d_xoff;
     // implicit apply level schedule (built with the workspace, on first use)
     DevBuf<int2> d_ifw, d_ibw;
@@ -384,7 +384,7 @@ struct sc_plan_s {
                          (d_rows.count + d_piv.count + d_pi.count + d_visit.count + d_ksteps.count) * 4 + d_vrows.count * 8 + d_sgn.count +
                          (d_lval.count + d_X.count + d_F.count) * 8 +
                          (d_lval32.count + d_X32.count + d_F32.count) * 4 +
-                         (d_xwork.count + d_xoff.count) * 8 + (d_ifw.count + d_ibw.count) * sizeof(int2) +
+                         (d_xwork.count + d_ywork.count + d_xoff.count) * 8 + (d_ifw.count + d_ibw.count) * sizeof(int2) +
                          (d_rptr.count + d_rpos.count) * 4 + (d_rptr_off.count + d_ubuf.count) * 8 +
                          (d_ifw_h.count + d_ibw_h.count) * sizeof(int2) + d_impl_list.count * 4);
     }
@@ -395,7 +395,7 @@ struct sc_plan_s {
         d_rows.release(); d_piv.release(); d_pi.release(); d_visit.release(); d_ksteps.release(); d_vrows.release(); d_sgn.release();
         d_lval.release(); d_X.release(); d_F.release();
         d_lval32.release(); d_X32.release(); d_F32.release();
-        d_xwork.release(); d_xoff.release();
+        d_xwork.release(); d_ywork.release(); d_xoff.release();
         d_ifw.release(); d_ibw.release(); d_rptr_off.release(); d_rptr.release(); d_rpos.release(); d_ubuf.release();
         d_ifw_h.release(); d_ibw_h.release(); d_impl_list.release();
         if (h_lval) (void)hipHostFree(h_lval);
@@ -1383,18 +1383,19 @@ static sc_status_t build_implicit(sc_plan_s* P, hipStream_t st) {
     };
     subset(fw, fwh, lvh.fw_off);
     subset(bw, bwh, lvh.bw_off);
-    DevBuf<double> xwork, ubuf;
+    DevBuf<double> xwork, ywork, ubuf;
     DevBuf<int64_t> xoff, rptr_off_d;
     DevBuf<int2> ifw, ibw;
     DevBuf<int32_t> rptr_d, rpos_d;
     DevBuf<int2> ifwh, ibwh;
     DevBuf<int32_t> ilist;
     auto release_all = [&]() {
-        xwork.release(); ubuf.release(); xoff.release(); rptr_off_d.release();
+        xwork.release(); ywork.release(); ubuf.release(); xoff.release(); rptr_off_d.release();
         ifw.release(); ibw.release(); rptr_d.release(); rpos_d.release();
         ifwh.release(); ibwh.release(); ilist.release();
     };
     hipError_t e = xwork.alloc((size_t)off[P->nsub]);
+    if (e == hipSuccess) e = ywork.alloc((size_t)off[P->nsub]);
     if (e == hipSuccess) e = xoff.alloc(off.size());
     if (e == hipSuccess) e = ifw.alloc(std::max<size_t>(1, fwi.size()));
     if (e == hipSuccess) e = ibw.alloc(std::max<size_t>(1, bwi.size()));
@@ -1429,10 +1430,11 @@ static sc_status_t build_implicit(sc_plan_s* P, hipStream_t st) {
     lv.rptr = rptr_d.p;
     lv.rpos = rpos_d.p;
     lv.ubuf = ubuf.p;
+    lv.ywork = ywork.p;
     // near-chain block DAGs (fewer than 1.5 blocks per level): a level
     // launch would carry one block per subdomain
     lv.per_subdomain = 2 * nblocks_all < 3 * nlevels_all;
-    P->d_xwork = xwork; P->d_xoff = xoff; P->d_ifw = ifw; P->d_ibw = ibw;
+    P->d_xwork = xwork; P->d_ywork = ywork; P->d_xoff = xoff; P->d_ifw = ifw; P->d_ibw = ibw;
     P->d_rptr_off = rptr_off_d; P->d_rptr = rptr_d; P->d_rpos = rpos_d; P->d_ubuf = ubuf;
     P->ilv = lv;
     lvh.fw_items = ifwh.p;
@@ -1441,6 +1443,7 @@ static sc_status_t build_implicit(sc_plan_s* P, hipStream_t st) {
     lvh.rptr = lv.rptr;
     lvh.rpos = lv.rpos;
     lvh.ubuf = lv.ubuf;
+    lvh.ywork = lv.ywork;
     lvh.subs = ilist.p;
     // per-subdomain sweeps for the subset when its own block DAGs are near
     // chains (the per-subdomain kernel reads the list)
