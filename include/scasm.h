@@ -147,9 +147,9 @@ typedef struct {
  *                    select_model[1] GB/s, t_impl = 16 nnz(L) /
  *                    select_model[2] GB/s (two FP64 sweeps), n* = t_asm /
  *                    (t_impl - t_expl) (infinite when t_impl <= t_expl);
- *                    zeros = rates measured on MI355X (assembly FP64 42 /
- *                    mixed 70 TFLOP/s, explicit apply 5800 GB/s, implicit
- *                    apply 3070 GB/s)
+ *                    zeros = rates measured on MI355X (assembly FP64 45.6 /
+ *                    mixed 75.7 TFLOP/s, explicit apply 5800 GB/s, implicit
+ *                    apply 3190 GB/s)
  *   tune_classes, ntune_classes  settings per size class from
  *                    sc_autotune_classes (see sc_tune_class_t), borrowed for
  *                    the sc_plan_create call

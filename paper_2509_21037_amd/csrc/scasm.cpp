@@ -137,10 +137,10 @@ std::string to_plan_options(const sc_options_t& o, PlanOptions& po) {
 // measured on MI355X -- structural assembly TFLOP/s (FP64, mixed), explicit
 // apply GB/s over the stored F, implicit apply GB/s over the two sweeps' 16
 // bytes per factor entry.
-constexpr double kSelectAsmTflops64 = 42.0;
-constexpr double kSelectAsmTflopsMixed = 70.0;
+constexpr double kSelectAsmTflops64 = 45.6;
+constexpr double kSelectAsmTflopsMixed = 75.7;
 constexpr double kSelectExplGBps = 5800.0;
-constexpr double kSelectImplGBps = 3070.0;
+constexpr double kSelectImplGBps = 3190.0;
 
 // Share of a batch's TRSM pruned-row updates the merged pairs must save for
 // the merge-capable TRSM kernel to be launched (the 12^3 heat batch saves 5%
