@@ -354,7 +354,8 @@ def main():
                     help="also time the FP64 assembly with the TRSM sweeping every block after the first pivot")
     ap.add_argument("--panel-width", type=int, default=0, help="GPU factor block width (0 = library default)")
     ap.add_argument("--autotune", choices=("auto", "on", "off"), default="auto",
-                    help="pick the factor block width with sc_autotune (auto: on for the elasticity batches)")
+                    help="per-size-class autotuner (block split, width, SYRK kind; auto: on unless "
+                         "--panel-width is given)")
     ap.add_argument("--graph", choices=("auto", "on", "off"), default="auto",
                     help="replay the assembly as a captured HIP graph (auto: on for the elasticity batches)")
     ap.add_argument("--assembly", choices=("overlap", "separate"), default="separate",
@@ -404,7 +405,7 @@ def main():
     ids = sample_ids(subs, big)
     use_graph = args.graph == "on" or (args.graph == "auto" and cfg != 2)
     tune, classes64, classes32 = None, None, None
-    if args.autotune == "on" or (args.autotune == "auto" and cfg != 2 and not args.panel_width):
+    if args.autotune == "on" or (args.autotune == "auto" and not args.panel_width):
         # per size class: block split, block width, SYRK work items (FP64 and
         # mixed tuned separately), on samples of each class; not timed
         t0 = time.perf_counter()
