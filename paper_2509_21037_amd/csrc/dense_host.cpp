@@ -1,8 +1,9 @@
-// Dense kernels of the host factorisation: C += sign * A B^T with an 8 x 4
-// register tile (two 4-wide AVX2 vectors per column of C, eight accumulators:
-// enough independent FMA chains to cover the FMA latency on two ports), over
-// panels of A and B packed 256 columns of K at a time so that the inner loop
-// reads both contiguously.
+// Dense kernels of the host factorisation: C += sign * A B^T with a register
+// tile of MR x 4 (two vectors per column of C, eight accumulators: enough
+// independent FMA chains to cover the FMA latency on two ports), over panels
+// of A and B packed 256 columns of K at a time so that the inner loop reads
+// both contiguously.  Two instantiations: AVX2 (4-wide, MR = 8) and, on CPUs
+// that have it (checked at run time), AVX-512 (8-wide, MR = 16).
 #include "dense_host.hpp"
 
 #include <immintrin.h>
@@ -13,7 +14,6 @@
 namespace scasm {
 namespace {
 
-constexpr int kMR = 8;      // rows of C per micro-tile
 constexpr int kNR = 4;      // columns of C per micro-tile
 constexpr int64_t kKC = 256;
 
@@ -21,6 +21,7 @@ constexpr int64_t kKC = 256;
 // padded past mr / nr)
 inline void micro_8x4(int64_t kc, const double* __restrict__ pa, const double* __restrict__ pb, double* C,
                       int64_t ldc, int mr, int nr, double sign) {
+    constexpr int kMR = 8;
     __m256d c00 = _mm256_setzero_pd(), c01 = _mm256_setzero_pd();
     __m256d c10 = _mm256_setzero_pd(), c11 = _mm256_setzero_pd();
     __m256d c20 = _mm256_setzero_pd(), c21 = _mm256_setzero_pd();
@@ -70,6 +71,142 @@ inline void micro_8x4(int64_t kc, const double* __restrict__ pa, const double* _
         for (int i = 0; i < mr; ++i) C[i + j * ldc] += sign * t[j][i];
 }
 
+// The same with 8-wide vectors: a 16 x 4 tile.
+__attribute__((target("avx512f"))) inline void micro_16x4(int64_t kc, const double* __restrict__ pa,
+                                                          const double* __restrict__ pb, double* C, int64_t ldc,
+                                                          int mr, int nr, double sign) {
+    constexpr int kMR = 16;
+    __m512d c00 = _mm512_setzero_pd(), c01 = _mm512_setzero_pd();
+    __m512d c10 = _mm512_setzero_pd(), c11 = _mm512_setzero_pd();
+    __m512d c20 = _mm512_setzero_pd(), c21 = _mm512_setzero_pd();
+    __m512d c30 = _mm512_setzero_pd(), c31 = _mm512_setzero_pd();
+    for (int64_t k = 0; k < kc; ++k) {
+        const __m512d a0 = _mm512_loadu_pd(pa + 16 * k);
+        const __m512d a1 = _mm512_loadu_pd(pa + 16 * k + 8);
+        __m512d b = _mm512_set1_pd(pb[4 * k]);
+        c00 = _mm512_fmadd_pd(a0, b, c00);
+        c01 = _mm512_fmadd_pd(a1, b, c01);
+        b = _mm512_set1_pd(pb[4 * k + 1]);
+        c10 = _mm512_fmadd_pd(a0, b, c10);
+        c11 = _mm512_fmadd_pd(a1, b, c11);
+        b = _mm512_set1_pd(pb[4 * k + 2]);
+        c20 = _mm512_fmadd_pd(a0, b, c20);
+        c21 = _mm512_fmadd_pd(a1, b, c21);
+        b = _mm512_set1_pd(pb[4 * k + 3]);
+        c30 = _mm512_fmadd_pd(a0, b, c30);
+        c31 = _mm512_fmadd_pd(a1, b, c31);
+    }
+    const __m512d s = _mm512_set1_pd(sign);
+    if (mr == kMR && nr == kNR) {
+        double* c0 = C;
+        double* c1 = C + ldc;
+        double* c2 = C + 2 * ldc;
+        double* c3 = C + 3 * ldc;
+        _mm512_storeu_pd(c0, _mm512_fmadd_pd(s, c00, _mm512_loadu_pd(c0)));
+        _mm512_storeu_pd(c0 + 8, _mm512_fmadd_pd(s, c01, _mm512_loadu_pd(c0 + 8)));
+        _mm512_storeu_pd(c1, _mm512_fmadd_pd(s, c10, _mm512_loadu_pd(c1)));
+        _mm512_storeu_pd(c1 + 8, _mm512_fmadd_pd(s, c11, _mm512_loadu_pd(c1 + 8)));
+        _mm512_storeu_pd(c2, _mm512_fmadd_pd(s, c20, _mm512_loadu_pd(c2)));
+        _mm512_storeu_pd(c2 + 8, _mm512_fmadd_pd(s, c21, _mm512_loadu_pd(c2 + 8)));
+        _mm512_storeu_pd(c3, _mm512_fmadd_pd(s, c30, _mm512_loadu_pd(c3)));
+        _mm512_storeu_pd(c3 + 8, _mm512_fmadd_pd(s, c31, _mm512_loadu_pd(c3 + 8)));
+        return;
+    }
+    alignas(64) double t[kNR][kMR];
+    _mm512_store_pd(&t[0][0], c00);
+    _mm512_store_pd(&t[0][8], c01);
+    _mm512_store_pd(&t[1][0], c10);
+    _mm512_store_pd(&t[1][8], c11);
+    _mm512_store_pd(&t[2][0], c20);
+    _mm512_store_pd(&t[2][8], c21);
+    _mm512_store_pd(&t[3][0], c30);
+    _mm512_store_pd(&t[3][8], c31);
+    for (int j = 0; j < nr; ++j)
+        for (int i = 0; i < mr; ++i) C[i + j * ldc] += sign * t[j][i];
+}
+
+// Packed panels: B per block of kNR columns, k-major (kNR values per k); A
+// per block of MR rows, k-major (MR values per k), full blocks copied with
+// whole-vector moves.
+inline void pack_b(const double* B, int64_t ldb, int64_t N, int64_t k0, int64_t kc, double* pb) {
+    const int64_t nblk = (N + kNR - 1) / kNR;
+    for (int64_t jb = 0; jb < nblk; ++jb) {
+        double* dst = pb + jb * kNR * kc;
+        const int64_t j0 = jb * kNR;
+        const int nr = (int)std::min<int64_t>(kNR, N - j0);
+        for (int64_t k = 0; k < kc; ++k) {
+            const double* src = B + j0 + (k0 + k) * ldb;
+            int jj = 0;
+            for (; jj < nr; ++jj) dst[k * kNR + jj] = src[jj];
+            for (; jj < kNR; ++jj) dst[k * kNR + jj] = 0.0;
+        }
+    }
+}
+
+template <int MR>
+inline void pack_a(const double* A, int64_t lda, int mr, int64_t i0, int64_t k0, int64_t kc, double* dst) {
+    if (mr == MR) {
+        for (int64_t k = 0; k < kc; ++k) {
+            const double* src = A + i0 + (k0 + k) * lda;
+            for (int ii = 0; ii < MR; ++ii) dst[k * MR + ii] = src[ii];
+        }
+        return;
+    }
+    for (int64_t k = 0; k < kc; ++k) {
+        const double* src = A + i0 + (k0 + k) * lda;
+        int ii = 0;
+        for (; ii < mr; ++ii) dst[k * MR + ii] = src[ii];
+        for (; ii < MR; ++ii) dst[k * MR + ii] = 0.0;
+    }
+}
+
+void gemm_blocked_avx2(int64_t M, int64_t N, int64_t K, double sign, const double* A, int64_t lda,
+                       const double* B, int64_t ldb, double* C, int64_t ldc) {
+    constexpr int kMR = 8;
+    thread_local std::vector<double> pa, pb;
+    const int64_t nblk = (N + kNR - 1) / kNR;
+    pa.resize((size_t)kMR * kKC);
+    pb.resize((size_t)nblk * kNR * kKC);
+    for (int64_t k0 = 0; k0 < K; k0 += kKC) {
+        const int64_t kc = std::min(kKC, K - k0);
+        pack_b(B, ldb, N, k0, kc, pb.data());
+        for (int64_t i0 = 0; i0 < M; i0 += kMR) {
+            const int mr = (int)std::min<int64_t>(kMR, M - i0);
+            pack_a<kMR>(A, lda, mr, i0, k0, kc, pa.data());
+            for (int64_t jb = 0; jb < nblk; ++jb) {
+                const int64_t j0 = jb * kNR;
+                const int nr = (int)std::min<int64_t>(kNR, N - j0);
+                micro_8x4(kc, pa.data(), pb.data() + jb * kNR * kc, C + i0 + j0 * ldc, ldc, mr, nr, sign);
+            }
+        }
+    }
+}
+
+__attribute__((target("avx512f"))) void gemm_blocked_avx512(int64_t M, int64_t N, int64_t K, double sign,
+                                                            const double* A, int64_t lda, const double* B,
+                                                            int64_t ldb, double* C, int64_t ldc) {
+    constexpr int kMR = 16;
+    thread_local std::vector<double> pa, pb;
+    const int64_t nblk = (N + kNR - 1) / kNR;
+    pa.resize((size_t)kMR * kKC);
+    pb.resize((size_t)nblk * kNR * kKC);
+    for (int64_t k0 = 0; k0 < K; k0 += kKC) {
+        const int64_t kc = std::min(kKC, K - k0);
+        pack_b(B, ldb, N, k0, kc, pb.data());
+        for (int64_t i0 = 0; i0 < M; i0 += kMR) {
+            const int mr = (int)std::min<int64_t>(kMR, M - i0);
+            pack_a<kMR>(A, lda, mr, i0, k0, kc, pa.data());
+            for (int64_t jb = 0; jb < nblk; ++jb) {
+                const int64_t j0 = jb * kNR;
+                const int nr = (int)std::min<int64_t>(kNR, N - j0);
+                micro_16x4(kc, pa.data(), pb.data() + jb * kNR * kc, C + i0 + j0 * ldc, ldc, mr, nr, sign);
+            }
+        }
+    }
+}
+
+const bool g_avx512 = __builtin_cpu_supports("avx512f");
+
 }  // namespace
 
 void gemm_nt(int64_t M, int64_t N, int64_t K, double sign, const double* A, int64_t lda, const double* B,
@@ -86,40 +223,8 @@ void gemm_nt(int64_t M, int64_t N, int64_t K, double sign, const double* A, int6
         }
         return;
     }
-    thread_local std::vector<double> pa, pb;
-    const int64_t nblk = (N + kNR - 1) / kNR;
-    pa.resize((size_t)kMR * kKC);
-    pb.resize((size_t)nblk * kNR * kKC);
-    for (int64_t k0 = 0; k0 < K; k0 += kKC) {
-        const int64_t kc = std::min(kKC, K - k0);
-        // B panel: per block of kNR columns, k-major (kNR values per k)
-        for (int64_t jb = 0; jb < nblk; ++jb) {
-            double* dst = pb.data() + jb * kNR * kc;
-            const int64_t j0 = jb * kNR;
-            const int nr = (int)std::min<int64_t>(kNR, N - j0);
-            for (int64_t k = 0; k < kc; ++k) {
-                const double* src = B + j0 + (k0 + k) * ldb;
-                int jj = 0;
-                for (; jj < nr; ++jj) dst[k * kNR + jj] = src[jj];
-                for (; jj < kNR; ++jj) dst[k * kNR + jj] = 0.0;
-            }
-        }
-        for (int64_t i0 = 0; i0 < M; i0 += kMR) {
-            const int mr = (int)std::min<int64_t>(kMR, M - i0);
-            double* dst = pa.data();
-            for (int64_t k = 0; k < kc; ++k) {
-                const double* src = A + i0 + (k0 + k) * lda;
-                int ii = 0;
-                for (; ii < mr; ++ii) dst[k * kMR + ii] = src[ii];
-                for (; ii < kMR; ++ii) dst[k * kMR + ii] = 0.0;
-            }
-            for (int64_t jb = 0; jb < nblk; ++jb) {
-                const int64_t j0 = jb * kNR;
-                const int nr = (int)std::min<int64_t>(kNR, N - j0);
-                micro_8x4(kc, pa.data(), pb.data() + jb * kNR * kc, C + i0 + j0 * ldc, ldc, mr, nr, sign);
-            }
-        }
-    }
+    if (g_avx512) gemm_blocked_avx512(M, N, K, sign, A, lda, B, ldb, C, ldc);
+    else gemm_blocked_avx2(M, N, K, sign, A, lda, B, ldb, C, ldc);
 }
 
 }  // namespace scasm
