@@ -1,9 +1,9 @@
 // Dense kernels of the host factorisation: C += sign * A B^T with a register
-// tile of MR x 4 (two vectors per column of C, eight accumulators: enough
+// tile (two vectors per column of C, at least eight accumulators: enough
 // independent FMA chains to cover the FMA latency on two ports), over panels
 // of A and B packed 256 columns of K at a time so that the inner loop reads
-// both contiguously.  Two instantiations: AVX2 (4-wide, MR = 8) and, on CPUs
-// that have it (checked at run time), AVX-512 (8-wide, MR = 16).
+// both contiguously.  Two versions: AVX2 (4-wide, 8 x 4 tiles) and, on CPUs
+// that have it (checked at run time), AVX-512 (8-wide, 16 x 8 tiles).
 #include "dense_host.hpp"
 
 #include <immintrin.h>
@@ -71,56 +71,44 @@ inline void micro_8x4(int64_t kc, const double* __restrict__ pa, const double* _
         for (int i = 0; i < mr; ++i) C[i + j * ldc] += sign * t[j][i];
 }
 
-// The same with 8-wide vectors: a 16 x 4 tile.
-__attribute__((target("avx512f"))) inline void micro_16x4(int64_t kc, const double* __restrict__ pa,
+// The same with 8-wide vectors: a 16 x 8 tile (sixteen accumulators; the
+// AVX-512 register file holds them with the two A vectors and a broadcast).
+__attribute__((target("avx512f"))) inline void micro_16x8(int64_t kc, const double* __restrict__ pa,
                                                           const double* __restrict__ pb, double* C, int64_t ldc,
                                                           int mr, int nr, double sign) {
-    constexpr int kMR = 16;
-    __m512d c00 = _mm512_setzero_pd(), c01 = _mm512_setzero_pd();
-    __m512d c10 = _mm512_setzero_pd(), c11 = _mm512_setzero_pd();
-    __m512d c20 = _mm512_setzero_pd(), c21 = _mm512_setzero_pd();
-    __m512d c30 = _mm512_setzero_pd(), c31 = _mm512_setzero_pd();
+    constexpr int kMR = 16, kNB = 8;
+    __m512d c0[kNB], c1[kNB];
+#pragma unroll
+    for (int j = 0; j < kNB; ++j) {
+        c0[j] = _mm512_setzero_pd();
+        c1[j] = _mm512_setzero_pd();
+    }
     for (int64_t k = 0; k < kc; ++k) {
         const __m512d a0 = _mm512_loadu_pd(pa + 16 * k);
         const __m512d a1 = _mm512_loadu_pd(pa + 16 * k + 8);
-        __m512d b = _mm512_set1_pd(pb[4 * k]);
-        c00 = _mm512_fmadd_pd(a0, b, c00);
-        c01 = _mm512_fmadd_pd(a1, b, c01);
-        b = _mm512_set1_pd(pb[4 * k + 1]);
-        c10 = _mm512_fmadd_pd(a0, b, c10);
-        c11 = _mm512_fmadd_pd(a1, b, c11);
-        b = _mm512_set1_pd(pb[4 * k + 2]);
-        c20 = _mm512_fmadd_pd(a0, b, c20);
-        c21 = _mm512_fmadd_pd(a1, b, c21);
-        b = _mm512_set1_pd(pb[4 * k + 3]);
-        c30 = _mm512_fmadd_pd(a0, b, c30);
-        c31 = _mm512_fmadd_pd(a1, b, c31);
+#pragma unroll
+        for (int j = 0; j < kNB; ++j) {
+            const __m512d b = _mm512_set1_pd(pb[kNB * k + j]);
+            c0[j] = _mm512_fmadd_pd(a0, b, c0[j]);
+            c1[j] = _mm512_fmadd_pd(a1, b, c1[j]);
+        }
     }
     const __m512d s = _mm512_set1_pd(sign);
-    if (mr == kMR && nr == kNR) {
-        double* c0 = C;
-        double* c1 = C + ldc;
-        double* c2 = C + 2 * ldc;
-        double* c3 = C + 3 * ldc;
-        _mm512_storeu_pd(c0, _mm512_fmadd_pd(s, c00, _mm512_loadu_pd(c0)));
-        _mm512_storeu_pd(c0 + 8, _mm512_fmadd_pd(s, c01, _mm512_loadu_pd(c0 + 8)));
-        _mm512_storeu_pd(c1, _mm512_fmadd_pd(s, c10, _mm512_loadu_pd(c1)));
-        _mm512_storeu_pd(c1 + 8, _mm512_fmadd_pd(s, c11, _mm512_loadu_pd(c1 + 8)));
-        _mm512_storeu_pd(c2, _mm512_fmadd_pd(s, c20, _mm512_loadu_pd(c2)));
-        _mm512_storeu_pd(c2 + 8, _mm512_fmadd_pd(s, c21, _mm512_loadu_pd(c2 + 8)));
-        _mm512_storeu_pd(c3, _mm512_fmadd_pd(s, c30, _mm512_loadu_pd(c3)));
-        _mm512_storeu_pd(c3 + 8, _mm512_fmadd_pd(s, c31, _mm512_loadu_pd(c3 + 8)));
+    if (mr == kMR && nr == kNB) {
+#pragma unroll
+        for (int j = 0; j < kNB; ++j) {
+            double* cj = C + j * ldc;
+            _mm512_storeu_pd(cj, _mm512_fmadd_pd(s, c0[j], _mm512_loadu_pd(cj)));
+            _mm512_storeu_pd(cj + 8, _mm512_fmadd_pd(s, c1[j], _mm512_loadu_pd(cj + 8)));
+        }
         return;
     }
-    alignas(64) double t[kNR][kMR];
-    _mm512_store_pd(&t[0][0], c00);
-    _mm512_store_pd(&t[0][8], c01);
-    _mm512_store_pd(&t[1][0], c10);
-    _mm512_store_pd(&t[1][8], c11);
-    _mm512_store_pd(&t[2][0], c20);
-    _mm512_store_pd(&t[2][8], c21);
-    _mm512_store_pd(&t[3][0], c30);
-    _mm512_store_pd(&t[3][8], c31);
+    alignas(64) double t[kNB][kMR];
+#pragma unroll
+    for (int j = 0; j < kNB; ++j) {
+        _mm512_store_pd(&t[j][0], c0[j]);
+        _mm512_store_pd(&t[j][8], c1[j]);
+    }
     for (int j = 0; j < nr; ++j)
         for (int i = 0; i < mr; ++i) C[i + j * ldc] += sign * t[j][i];
 }
@@ -128,17 +116,18 @@ __attribute__((target("avx512f"))) inline void micro_16x4(int64_t kc, const doub
 // Packed panels: B per block of kNR columns, k-major (kNR values per k); A
 // per block of MR rows, k-major (MR values per k), full blocks copied with
 // whole-vector moves.
+template <int NR>
 inline void pack_b(const double* B, int64_t ldb, int64_t N, int64_t k0, int64_t kc, double* pb) {
-    const int64_t nblk = (N + kNR - 1) / kNR;
+    const int64_t nblk = (N + NR - 1) / NR;
     for (int64_t jb = 0; jb < nblk; ++jb) {
-        double* dst = pb + jb * kNR * kc;
-        const int64_t j0 = jb * kNR;
-        const int nr = (int)std::min<int64_t>(kNR, N - j0);
+        double* dst = pb + jb * NR * kc;
+        const int64_t j0 = jb * NR;
+        const int nr = (int)std::min<int64_t>(NR, N - j0);
         for (int64_t k = 0; k < kc; ++k) {
             const double* src = B + j0 + (k0 + k) * ldb;
             int jj = 0;
-            for (; jj < nr; ++jj) dst[k * kNR + jj] = src[jj];
-            for (; jj < kNR; ++jj) dst[k * kNR + jj] = 0.0;
+            for (; jj < nr; ++jj) dst[k * NR + jj] = src[jj];
+            for (; jj < NR; ++jj) dst[k * NR + jj] = 0.0;
         }
     }
 }
@@ -169,7 +158,7 @@ void gemm_blocked_avx2(int64_t M, int64_t N, int64_t K, double sign, const doubl
     pb.resize((size_t)nblk * kNR * kKC);
     for (int64_t k0 = 0; k0 < K; k0 += kKC) {
         const int64_t kc = std::min(kKC, K - k0);
-        pack_b(B, ldb, N, k0, kc, pb.data());
+        pack_b<kNR>(B, ldb, N, k0, kc, pb.data());
         for (int64_t i0 = 0; i0 < M; i0 += kMR) {
             const int mr = (int)std::min<int64_t>(kMR, M - i0);
             pack_a<kMR>(A, lda, mr, i0, k0, kc, pa.data());
@@ -185,21 +174,21 @@ void gemm_blocked_avx2(int64_t M, int64_t N, int64_t K, double sign, const doubl
 __attribute__((target("avx512f"))) void gemm_blocked_avx512(int64_t M, int64_t N, int64_t K, double sign,
                                                             const double* A, int64_t lda, const double* B,
                                                             int64_t ldb, double* C, int64_t ldc) {
-    constexpr int kMR = 16;
+    constexpr int kMR = 16, kNB = 8;
     thread_local std::vector<double> pa, pb;
-    const int64_t nblk = (N + kNR - 1) / kNR;
+    const int64_t nblk = (N + kNB - 1) / kNB;
     pa.resize((size_t)kMR * kKC);
-    pb.resize((size_t)nblk * kNR * kKC);
+    pb.resize((size_t)nblk * kNB * kKC);
     for (int64_t k0 = 0; k0 < K; k0 += kKC) {
         const int64_t kc = std::min(kKC, K - k0);
-        pack_b(B, ldb, N, k0, kc, pb.data());
+        pack_b<kNB>(B, ldb, N, k0, kc, pb.data());
         for (int64_t i0 = 0; i0 < M; i0 += kMR) {
             const int mr = (int)std::min<int64_t>(kMR, M - i0);
             pack_a<kMR>(A, lda, mr, i0, k0, kc, pa.data());
             for (int64_t jb = 0; jb < nblk; ++jb) {
-                const int64_t j0 = jb * kNR;
-                const int nr = (int)std::min<int64_t>(kNR, N - j0);
-                micro_16x4(kc, pa.data(), pb.data() + jb * kNR * kc, C + i0 + j0 * ldc, ldc, mr, nr, sign);
+                const int64_t j0 = jb * kNB;
+                const int nr = (int)std::min<int64_t>(kNB, N - j0);
+                micro_16x8(kc, pa.data(), pb.data() + jb * kNB * kc, C + i0 + j0 * ldc, ldc, mr, nr, sign);
             }
         }
     }
