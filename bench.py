@@ -55,21 +55,29 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# Sources that fix what an assembly launch reads and writes: the kernels and
+# the planner that lays out their blocks, tiles and merged pairs.
+PROFILED_SOURCES = ("kernels.hip", "planner.cpp")
+
+
 def kernels_digest():
     import hashlib
-    with open(os.path.join(ROOT, "paper_2509_21037_amd", "csrc", "kernels.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for name in PROFILED_SOURCES:
+        with open(os.path.join(ROOT, "paper_2509_21037_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def measured_traffic(workload, precision, kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None when it was taken on other kernel sources."""
+    summary, or None when it was taken on other kernel or planner sources."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{precision}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("kernels_sha256") != kernels_digest():
+    if t.get("sources_sha256") != kernels_digest():
         return None
     k = t.get("kernels", {}).get(kernel)
     return None if k is None else k["fetch_bytes"] + k["write_bytes"]

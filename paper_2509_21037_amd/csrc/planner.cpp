@@ -722,9 +722,7 @@ std::vector<int32_t> merge_pairs(const SubPlan& P) {
         if (b > 0 && flag[b - 1]) continue;           // b is the second block of a pair
         const BlockDesc& x = P.blocks[b];
         const BlockDesc& y = P.blocks[b + 1];
-        const int32_t s = P.col2super[x.row0];
-        if (P.sfirst[s] > x.row0 || P.col2super[y.row0 + y.w - 1] != s || y.w % 16 != 0) continue;
-        if (x.nbelow != y.w + y.nbelow) continue;
+        if (y.w % 16 != 0 || x.nbelow != y.w + y.nbelow) continue;
         bool same = true;
         for (int32_t q = 0; q < y.w && same; ++q) same = P.brows[x.rows_off + q] == y.row0 + q;
         for (int32_t q = 0; q < y.nbelow && same; ++q) same = P.brows[x.rows_off + y.w + q] == P.brows[y.rows_off + q];

@@ -129,10 +129,11 @@ int64_t factor_numeric(const SubPlan& plan, const double* kvals, double* vals);
 void repack_blocks(const SubPlan& plan, const double* vals, double* bvals);
 
 // Blocks whose update of the rows below the TRSM merges with the next
-// block's (flag 1 per block): b and b + 1 inside one supernode, b + 1 a whole
-// number of 16-row tiles wide, and the pruned rows of b exactly the rows of
-// b + 1 followed by the pruned rows of b + 1; paired greedily from the first
-// block, so a block is in at most one pair.
+// block's (flag 1 per block): b + 1 a whole number of 16-row tiles wide and
+// the pruned rows of b exactly the rows of b + 1 followed by the pruned rows
+// of b + 1 (the panels of one supernode, or a child whose structure is its
+// parent's); paired greedily from the first block, so a block is in at most
+// one pair.
 std::vector<int32_t> merge_pairs(const SubPlan& plan);
 
 }  // namespace scasm

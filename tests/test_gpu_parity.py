@@ -671,10 +671,10 @@ def test_reach_restricted_sweep_matches_full_staircase_sweep(precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_pair_merged_updates_match_separate_updates(precision):
-    """The TRSM's merged updates below pairs of factor blocks of one
-    supernode (the default) give F bit for bit equal to one update per block
-    (disable_pair_merge): a 20^3 elasticity pair of subdomains (42 pairs
-    each), uneven elasticity subdomains and scattered interior multipliers,
+    """The TRSM's merged updates below pairs of consecutive factor blocks
+    (the default) give F bit for bit equal to one update per block
+    (disable_pair_merge): a 20^3 elasticity pair of subdomains (65 pairs
+    each with uniform blocks, 98 with etree blocks), uneven elasticity subdomains and scattered interior multipliers,
     with uniform and etree blocks, the staircase alone, no staircase,
     temporary-memory waves, the overlapped assembly and the pipelined
     preprocessing."""

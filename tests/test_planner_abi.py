@@ -440,10 +440,12 @@ def test_options_struct_matches_the_c_header(tmp_path):
 
 
 def test_merged_block_pairs_of_the_trsm():
-    """Pairs of factor blocks whose TRSM updates below merge: present where
-    supernodes span several blocks (the 20^3 elasticity subdomain, both
-    splits), none when disabled or where no supernode spans two blocks; the
-    saved updates are at most the pruned rows of the blocks the tiles visit."""
+    """Pairs of factor blocks whose TRSM updates below merge (the first
+    block's rows below are the second block's rows followed by its rows
+    below): present on the 20^3 elasticity subdomain with both splits, none
+    when disabled or on the 16 x 16 heat subdomain (5 blocks, no consecutive
+    two of them nested that way); the saved updates are
+    at most half the pruned rows of the blocks the tiles visit."""
     s = scgen.config_subdomains(5, count=1)[0]
     for split in ("uniform", "etree"):
         h = P.host_analyze(s, values=False, block_split=split)
