@@ -163,9 +163,11 @@ typedef struct {
  *                    16384 rows FP64 / 6144 mixed, 128 x 128 tiles above),
  *                    1 = 64 x 64 blocks, 2 = 128 x 128 tiles
  *   disable_pair_merge  0 (default) = the TRSM updates the rows below two
- *                    consecutive factor blocks of one supernode once for both
- *                    (Sec. 3.2: fewer read-modify-writes of X; the result is
- *                    bit for bit the same); 1 = one update per block
+ *                    consecutive factor blocks once for both where the
+ *                    first's rows below are the second's rows followed by
+ *                    the second's rows below (Sec. 3.2: fewer
+ *                    read-modify-writes of X; the result is bit for bit the
+ *                    same); 1 = one update per block
  *   arena_cap_bytes  0 (default) = X (the temporary of the assembly, Sec. 3.1)
  *                    resident for the whole batch; > 0 = temporary-memory
  *                    waves: the batch is cut into waves of subdomains whose X

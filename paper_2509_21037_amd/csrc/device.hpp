@@ -66,7 +66,7 @@ constexpr int kStepRowMask = (1 << kStepSlabShift) - 1;   // rows below 2^27 (ch
 
 struct BlockDev {
     int32_t row0, w, nbelow;
-    int32_t flags;       // bit 0: merged with the next block in the TRSM's updates below (same supernode)
+    int32_t flags;       // bit 0: merged with the next block in the TRSM's updates below
     int64_t lval_off;    // diagonal block (w x w, column-major), relative to the subdomain's lval_off
     int64_t rows_off;    // relative to the subdomain's rows_off
     int64_t aoff;        // pruned rows as MFMA A tiles, relative to the subdomain's lval_off

@@ -67,9 +67,10 @@ __device__ __forceinline__ v4f mfma_f32(float a, float b, v4f c) {
 // itself in program order.
 // Mixed precision: the same with FP32 X and FP32 A tiles / MFMA for step 2;
 // step 1 stays FP64 (the block rows are widened, solved, rounded back).
-// Merged pairs: two consecutive blocks b, b + 1 of one supernode that a tile
-// visits one after the other (BlockDev::flags, set by the host) share the
-// rows below them: R_b = rows(b + 1) followed by R_{b+1}.  Block b then
+// Merged pairs: two consecutive blocks b, b + 1 that a tile visits one after
+// the other and whose rows below nest, R_b = rows(b + 1) followed by R_{b+1}
+// (BlockDev::flags, set by the host: two panels of one supernode, or a child
+// block with its parent's structure).  Block b then
 // updates only the rows of b + 1; its solved rows -X[b] wait in LDS (one 64 x
 // 16 slot per wavefront); block b + 1 updates R_{b+1} once with both:
 // X[R] -= L[R, b] X[b] + L[R, b + 1] X[b + 1], two chunk steps per row group
