@@ -417,7 +417,10 @@ def main():
         # per size class: block split, block width, SYRK work items (FP64 and
         # mixed tuned separately), on samples of each class; not timed
         t0 = time.perf_counter()
-        smp = 8 if cfg == 3 else 16
+        # the sample of a class must fill the chip the way the batch does
+        # (12^3 heat: 14 column tiles per subdomain, 128 of them ~1800
+        # workgroups); 8 per class of the uneven batch, 16 of the 20^3 ones
+        smp = {2: 128, 3: 8}.get(cfg, 16)
         classes64 = P.autotune_classes(subs, sample=smp, reps=2, cache_path=args.tune_cache)
         classes32 = None if args.no_mixed else \
             P.autotune_classes(subs, sample=smp, reps=2, cache_path=args.tune_cache, precision="mixed")
