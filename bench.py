@@ -371,6 +371,8 @@ def main():
     ap.add_argument("--compare-assembly", action="store_true",
                     help="also time the FP64 assembly in the other mode (overlap / separate)")
     ap.add_argument("--tune-cache", default=None, help="autotune cache file (read, and appended to)")
+    ap.add_argument("--tune-sample", type=int, default=0,
+                    help="autotune subdomains per size class (default: 128 heat, 8 uneven elasticity, 16 20^3)")
     ap.add_argument("--paper-curves", action="store_true",
                     help="also time the paper's P1 triangle / tetrahedron heat workloads at its figure sizes, "
                          "without the staircase, with it, and with the reach (FP64, ms per subdomain)")
@@ -420,7 +422,7 @@ def main():
         # the sample of a class must fill the chip the way the batch does
         # (12^3 heat: 14 column tiles per subdomain, 128 of them ~1800
         # workgroups); 8 per class of the uneven batch, 16 of the 20^3 ones
-        smp = {2: 128, 3: 8}.get(cfg, 16)
+        smp = args.tune_sample or {2: 128, 3: 8}.get(cfg, 16)
         classes64 = P.autotune_classes(subs, sample=smp, reps=2, cache_path=args.tune_cache)
         classes32 = None if args.no_mixed else \
             P.autotune_classes(subs, sample=smp, reps=2, cache_path=args.tune_cache, precision="mixed")
